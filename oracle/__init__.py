@@ -1,0 +1,221 @@
+"""FP64 CPU oracle of the WSKP per-frame path (test infrastructure only).
+
+Only the tests, the package's smoke check and the benchmark's CPU-baseline
+leg may import this package.  The product library never loads it, and it
+shares no code with the HIP path: the arithmetic lives in
+``wskp_oracle.c`` (plain loops in double precision); this module only
+marshals NumPy arrays into it.
+
+Functions take and return NumPy arrays in NHWC layout without a batch axis
+unless stated.  Inputs may be float32; everything is widened to float64.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Dict, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "wskp_oracle.c")
+_LIB = os.path.join(_HERE, "libwskp_oracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_fp = ctypes.POINTER(ctypes.c_float)
+_ip = ctypes.POINTER(ctypes.c_int)
+_L = ctypes.c_long
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle into ``libwskp_oracle.so`` next to its source."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O3", "-fopenmp", "-shared", "-fPIC", "-std=c99", _SRC,
+               "-o", _LIB + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        lib.wo_preprocess.argtypes = [_L, _L, _fp, _fp, _fp, _fp, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      _dp, _dp, _dp]
+        lib.wo_conv3x3.argtypes = [_L, _L, _L, _L, _dp, _dp, _dp, ctypes.c_int, _dp]
+        lib.wo_avgpool2.argtypes = [_L, _L, _L, _dp, _dp]
+        lib.wo_upsample2.argtypes = [_L, _L, _L, _dp, _dp]
+        lib.wo_unet.argtypes = [_L, _L, ctypes.c_int, _ip, ctypes.c_int, ctypes.c_int, _fp,
+                                _dp, _dp]
+        lib.wo_unet.restype = ctypes.c_int
+        lib.wo_activate.argtypes = [_L, ctypes.c_int, ctypes.c_int, _dp, _dp]
+        lib.wo_decode.argtypes = [_L, _L, ctypes.c_int, _ip, _dp, _dp, _dp, ctypes.c_double,
+                                  _dp, _dp, _dp]
+        lib.wo_decode_vjp.argtypes = [_L, _L, ctypes.c_int, _ip, _dp, _dp, _dp,
+                                      ctypes.c_double, _dp, _dp, _dp]
+        lib.wo_l1.argtypes = [_L, _dp, _dp, _dp]
+        lib.wo_l1.restype = ctypes.c_double
+        _lib = lib
+    return _lib
+
+
+def _d(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _f(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _ptr(a: np.ndarray, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+def _ints(seq: Sequence[int]):
+    arr = (ctypes.c_int * len(seq))(*[int(s) for s in seq])
+    return arr
+
+
+def set_threads(n: int) -> None:
+    """Set the OpenMP thread count used by the C oracle."""
+    lib = _load()
+    try:
+        omp = ctypes.CDLL("libgomp.so.1")
+        omp.omp_set_num_threads(int(n))
+    except OSError:  # pragma: no cover - libgomp always present with gcc
+        os.environ["OMP_NUM_THREADS"] = str(n)
+    del lib
+
+
+def preprocess(radiance, albedo, normal, depth, gamma=2.2, near=1.0, far=10.0,
+               eps_albedo=1e-3) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Network input X [H,W,10], irradiance c [H,W,3] and mod = a + eps [H,W,3]."""
+    r, a, n, d = _f(radiance), _f(albedo), _f(normal), _f(depth)
+    H, W = r.shape[:2]
+    X = np.empty((H, W, 10))
+    c = np.empty((H, W, 3))
+    mod = np.empty((H, W, 3))
+    _load().wo_preprocess(H, W, _ptr(r, _fp), _ptr(a, _fp), _ptr(n, _fp), _ptr(d, _fp),
+                          gamma, near, far, eps_albedo, _ptr(X), _ptr(c), _ptr(mod))
+    return X, c, mod
+
+
+def conv3x3(x, w, b, relu: bool) -> np.ndarray:
+    """3x3 cross-correlation, zero pad 1, + bias; x [H,W,Cin], w [Cout,Cin,3,3]."""
+    x, w, b = _d(x), _d(w), _d(b)
+    H, W, Cin = x.shape
+    Cout = w.shape[0]
+    assert w.shape == (Cout, Cin, 3, 3) and b.shape == (Cout,)
+    out = np.empty((H, W, Cout))
+    _load().wo_conv3x3(H, W, Cin, Cout, _ptr(x), _ptr(w), _ptr(b), int(relu), _ptr(out))
+    return out
+
+
+def avgpool2(x) -> np.ndarray:
+    x = _d(x)
+    H, W, C = x.shape
+    out = np.empty((H // 2, W // 2, C))
+    _load().wo_avgpool2(H, W, C, _ptr(x), _ptr(out))
+    return out
+
+
+def upsample2(x) -> np.ndarray:
+    x = _d(x)
+    H, W, C = x.shape
+    out = np.empty((2 * H, 2 * W, C))
+    _load().wo_upsample2(H, W, C, _ptr(x), _ptr(out))
+    return out
+
+
+def unet(X, blob, levels: int, channels: Sequence[int], out_channels: int) -> np.ndarray:
+    """Raw network output h [H,W,out_channels] for input X [H,W,Cin]."""
+    X = _d(X)
+    blob = _f(blob)
+    H, W, Cin = X.shape
+    h = np.empty((H, W, out_channels))
+    rc = _load().wo_unet(H, W, levels, _ints(channels), Cin, out_channels, _ptr(blob, _fp),
+                         _ptr(X), _ptr(h))
+    if rc != 0:
+        raise ValueError(f"wo_unet failed ({rc}): H, W must be multiples of 2^(L-1)")
+    return h
+
+
+def activate(h, M: int, act: str = "softplus") -> np.ndarray:
+    """Head record: act(h[..., :M]) then raw logits h[..., M:2M]."""
+    h = _d(h)
+    head = np.empty_like(h)
+    P = h.size // (2 * M)
+    _load().wo_activate(P, M, 1 if act == "exp" else 0, _ptr(h), _ptr(head))
+    return head
+
+
+def decode(head, c, mod, kernel_sizes: Sequence[int], eps: float = 1e-10,
+           diagnostics: bool = False):
+    """Decode + fusion + remodulation of one frame: y [H,W,3].
+
+    With ``diagnostics`` also returns the per-size filtered images
+    [H,W,M,3] and the fusion weights [H,W,M].
+    """
+    head, c = _d(head), _d(c)
+    H, W, twoM = head.shape
+    M = twoM // 2
+    assert M == len(kernel_sizes) and c.shape == (H, W, 3)
+    modp = None
+    if mod is not None:
+        mod = _d(mod)
+        modp = _ptr(mod)
+    y = np.empty((H, W, 3))
+    outs = np.empty((H, W, M, 3)) if diagnostics else None
+    alpha = np.empty((H, W, M)) if diagnostics else None
+    _load().wo_decode(H, W, M, _ints(kernel_sizes), _ptr(head), _ptr(c), modp, eps, _ptr(y),
+                      _ptr(outs) if diagnostics else None, _ptr(alpha) if diagnostics else None)
+    if diagnostics:
+        return y, outs, alpha
+    return y
+
+
+def decode_vjp(head, c, mod, kernel_sizes: Sequence[int], g, eps: float = 1e-10):
+    """(dL/dhead [H,W,2M], dL/dc [H,W,3]) for cotangent g = dL/dy [H,W,3]."""
+    head, c, g = _d(head), _d(c), _d(g)
+    H, W, twoM = head.shape
+    M = twoM // 2
+    modp = None
+    if mod is not None:
+        mod = _d(mod)
+        modp = _ptr(mod)
+    dhead = np.empty((H, W, twoM))
+    dc = np.empty((H, W, 3))
+    _load().wo_decode_vjp(H, W, M, _ints(kernel_sizes), _ptr(head), _ptr(c), modp, eps,
+                          _ptr(g), _ptr(dhead), _ptr(dc))
+    return dhead, dc
+
+
+def l1(y, t):
+    """(mean |y - t|, gradient sign(y - t) / n)."""
+    y, t = _d(y), _d(t)
+    g = np.empty_like(y)
+    v = _load().wo_l1(y.size, _ptr(y), _ptr(t), _ptr(g))
+    return v, g
+
+
+def denoise(frame: Dict[str, np.ndarray], blob, cfg, return_all: bool = False):
+    """Whole per-frame path for one frame: y [H,W,3] in float64.
+
+    ``cfg`` carries levels, channels, kernel_sizes, eps_norm, eps_albedo,
+    gamma, depth_near, depth_far and weight_act.  With ``return_all`` the
+    intermediates (X, c, mod, h, head) come back in a dict as well.
+    """
+    X, c, mod = preprocess(frame["radiance"], frame["albedo"], frame["normal"], frame["depth"],
+                           cfg.gamma, cfg.depth_near, cfg.depth_far, cfg.eps_albedo)
+    h = unet(X, blob, cfg.levels, cfg.channels, 2 * len(cfg.kernel_sizes))
+    head = activate(h, len(cfg.kernel_sizes), cfg.weight_act)
+    y = decode(head, c, mod, cfg.kernel_sizes, cfg.eps_norm)
+    if return_all:
+        return y, {"X": X, "c": c, "mod": mod, "h": h, "head": head}
+    return y
