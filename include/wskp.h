@@ -1,0 +1,213 @@
+/*
+ * wskp.h -- C ABI of the MI355X (gfx950) weight-sharing kernel-prediction
+ * (WSKP) Monte Carlo denoiser.
+ *
+ * Method: Fan, Wang, Huo, Bao, "Real-time Monte Carlo Denoising with Weight
+ * Sharing Kernel Prediction Network" (EGSR 2021).  A convolutional network
+ * (Sec. 4.1, Eq. 2) predicts one scalar weight per pixel for each of M
+ * filter sizes plus M per-pixel fusion logits.  Every pixel's k x k kernel
+ * is built from its neighbours' scalars and normalised over the window
+ * (Eq. 3), applied to the albedo-demodulated irradiance (Eq. 4, Sec. 4.2),
+ * the M filtered images are blended with softmax weights (Eq. 5) and the
+ * albedo is multiplied back (Sec. 4.2, last paragraph).
+ *
+ * Conventions shared by every entry point:
+ *  - Images are NHWC float32, channels innermost, rows of W pixels, fully
+ *    contiguous.  A batch of N frames of one size is N images back to back.
+ *  - Every tensor pointer is a DEVICE pointer owned by the caller.  It must
+ *    stay valid until the work queued on `stream` has completed.  The
+ *    library never frees or retains caller memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    All work is queued asynchronously on it; no call synchronises the
+ *    device except wskp_create / wskp_destroy.
+ *  - Calls validate their arguments synchronously and return a status; no
+ *    exception crosses the ABI.  A failed call queues no work.  Faults that
+ *    happen later on the device surface at the caller's next
+ *    synchronisation.  wskp_last_error() gives a thread-local message for
+ *    the last failing call.
+ *  - A handle may be used from several host threads at once only with
+ *    distinct streams and distinct workspaces.
+ */
+#ifndef WSKP_H
+#define WSKP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wskp_ctx *wskp_handle_t;
+
+typedef enum {
+    WSKP_OK = 0,
+    WSKP_E_INVALID_ARG = -1, /* NULL pointer, bad config value, weight count mismatch */
+    WSKP_E_SHAPE = -2,       /* H or W < 1, or not a multiple of 2^(levels-1) for the net */
+    WSKP_E_UNSUPPORTED = -3, /* valid request this build does not implement */
+    WSKP_E_DEVICE = -4,      /* no usable gfx950 device, or a HIP runtime error */
+    WSKP_E_OOM = -5,         /* device or pinned-host allocation failed */
+    WSKP_E_BUDGET = -6,      /* workspace too small for the request */
+    WSKP_E_LAUNCH = -7,      /* a kernel launch was rejected by the runtime */
+    WSKP_E_INTERNAL = -8
+} wskp_status_t;
+
+/* Arithmetic of the convolutions.  Decode, normalisation and fusion are
+ * always float32. */
+typedef enum {
+    WSKP_PREC_FP32 = 0,    /* fp32 operands, fp32 MFMA accumulate */
+    WSKP_PREC_BF16 = 1,    /* bf16 operands (round to nearest even), fp32 accumulate */
+    WSKP_PREC_FP8_E4M3 = 2 /* OCP e4m3 operands with scales, fp32 accumulate */
+} wskp_precision_t;
+
+/* Map from the network's raw output h to the positive per-pixel weight W. */
+typedef enum {
+    WSKP_ACT_SOFTPLUS = 0, /* W = log(1 + e^h) */
+    WSKP_ACT_EXP = 1       /* W = e^h: the numerator of the window softmax, Eq. 3 */
+} wskp_weight_act_t;
+
+#define WSKP_MAX_LEVELS 6
+#define WSKP_MAX_KERNELS 8
+#define WSKP_MAX_KERNEL_SIZE 15
+
+/* Network and filter configuration.
+ *  levels         U-Net depth L (1..6); frame sides must be multiples of 2^(L-1)
+ *  channels[l]    width of level l, multiples of 16 (level 0 = full resolution)
+ *  num_kernels    M, number of filter sizes (1..8); the net outputs 2M channels
+ *  kernel_sizes   odd sizes k_i (1..15), one per weight map (Sec. 4.2, "Kernel
+ *                 Fusion": k_i = k_b + i k_s)
+ *  precision      wskp_precision_t of the convolutions
+ *  weight_act     wskp_weight_act_t
+ *  eps_norm       floor of the window sum: out = N / max(S, eps_norm)
+ *  eps_albedo     c = r / (a + eps_albedo); the same factor remodulates
+ *  gamma          tone map of the network's radiance input: clamp(r,0,1)^(1/gamma)
+ *  depth_near/far depth scaled as clamp((d - near)/(far - near), 0, 1)
+ * Network input channels (Sec. 5.1): [tonemapped r (3), albedo (3),
+ * (normal + 1)/2 (3), scaled depth (1)]. */
+typedef struct {
+    uint32_t struct_size; /* sizeof(wskp_config_t) */
+    int32_t levels;
+    int32_t channels[8];
+    int32_t num_kernels;
+    int32_t kernel_sizes[8];
+    int32_t precision;
+    int32_t weight_act;
+    float eps_norm;
+    float eps_albedo;
+    float gamma;
+    float depth_near;
+    float depth_far;
+} wskp_config_t;
+
+/* One frame of a batch.  Device pointers, NHWC float32:
+ * radiance/albedo/normal [H,W,3], depth [H,W,1], out [H,W,3]. */
+typedef struct {
+    int32_t H, W;
+    const float *radiance;
+    const float *albedo;
+    const float *normal;
+    const float *depth;
+    float *out;
+} wskp_frame_t;
+
+/* Number of float32 values in the weight blob for `cfg`.  Blob order:
+ * enc0..enc_{L-1}, dec_{L-2}..dec_0, head; each conv is w[C_out][C_in][3][3]
+ * followed by b[C_out].  enc0 has C_in = 10, enc_l has C_in = C_{l-1},
+ * dec_l has C_in = C_{l+1} + C_l (upsampled coarse features first), head
+ * has C_in = C_0 and C_out = 2M (M weight channels, then M logits).
+ * Returns 0 for an invalid config. */
+size_t wskp_num_weights(const wskp_config_t *cfg);
+
+/* Creates a handle on HIP device `device`: validates cfg, copies the host
+ * weight blob (n_weights floats, owned by the caller, not retained) to the
+ * device in the layout the kernels read.  host_act_scales: FP8 activation
+ * scales, one per conv in blob order (NULL for other precisions, or to use
+ * scales derived from the weights).  Synchronous. */
+wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host_weights, size_t n_weights,
+                          const float *host_act_scales, int device, wskp_handle_t *out);
+
+/* Releases the handle's device memory.  Synchronises the device first. */
+wskp_status_t wskp_destroy(wskp_handle_t h);
+
+/* Bytes of device workspace that wskp_denoise (n = 1) or
+ * wskp_denoise_batch needs for n frames of sizes H[i] x W[i]. */
+wskp_status_t wskp_workspace_size(wskp_handle_t h, int n, const int *H, const int *W,
+                                  size_t *bytes);
+
+/* Denoises one frame (the problem of Sec. 3: noisy radiance plus albedo,
+ * normal and depth in, denoised radiance out).  Inputs as wskp_frame_t;
+ * `out` [H,W,3] receives albedo * fused filtered irradiance.  `ws` is a
+ * device workspace of ws_bytes >= wskp_workspace_size(h, 1, &H, &W);
+ * its content is scratch (the intermediate feature maps and the
+ * [H,W,2M] head record: weights W_i, then logits).  H and W must be
+ * multiples of 2^(levels-1). */
+wskp_status_t wskp_denoise(wskp_handle_t h, void *stream, int H, int W, const float *radiance,
+                           const float *albedo, const float *normal, const float *depth,
+                           float *out, void *ws, size_t ws_bytes);
+
+#define WSKP_BATCH_REVERSE_TILES 1u /* walk tiles in reverse order (result must not change) */
+
+/* Denoises n independent frames of possibly different sizes with one
+ * launch per network layer.  `frames` is a HOST array of n descriptors
+ * (read during the call only).  Each frame's result is the same as that of
+ * wskp_denoise on it alone: no arithmetic crosses frames.  Workspace from
+ * wskp_workspace_size(h, n, H, W). */
+wskp_status_t wskp_denoise_batch(wskp_handle_t h, void *stream, int n, const wskp_frame_t *frames,
+                                 uint32_t flags, void *ws, size_t ws_bytes);
+
+/* Decode + fusion + remodulation alone (Eq. 3, 4, 5), for N frames of
+ * H x W.  head [N,H,W,2M]: channels 0..M-1 are the positive weight maps
+ * W_i (already activated), M..2M-1 the fusion logits.  c [N,H,W,3] is the
+ * irradiance to filter, mod [N,H,W,3] the remodulation factor (NULL = 1).
+ * out [N,H,W,3] = mod * sum_i softmax(logits)_i * (box_i(W_i c) /
+ * max(box_i(W_i), eps_norm)), with windows truncated at the border.  Any
+ * H, W >= 1. */
+wskp_status_t wskp_decode(wskp_handle_t h, void *stream, int N, int H, int W, const float *head,
+                          const float *c, const float *mod, float *out);
+
+/* Vector-Jacobian product of wskp_decode: given grad_out = dL/dout
+ * [N,H,W,3], writes grad_head = dL/dhead [N,H,W,2M] (weights, then
+ * logits) and grad_c = dL/dc [N,H,W,3] (mod is treated as a constant).
+ * Both outputs are overwritten, not accumulated.  ws is a device scratch
+ * buffer of ws_bytes >= wskp_backward_workspace_size(h, N, H, W). */
+wskp_status_t wskp_backward(wskp_handle_t h, void *stream, int N, int H, int W, const float *head,
+                            const float *c, const float *mod, const float *grad_out,
+                            float *grad_head, float *grad_c, void *ws, size_t ws_bytes);
+
+/* Bytes of device scratch wskp_backward needs for N frames of H x W
+ * (16 * M bytes per pixel: per-centre adjoint terms of every kernel size). */
+wskp_status_t wskp_backward_workspace_size(wskp_handle_t h, int N, int H, int W, size_t *bytes);
+
+/* Location of an intermediate tensor of frame `frame` inside the workspace
+ * of the last-planned batch layout for frames of sizes H[i] x W[i]: which =
+ * 0..L-1 for encoder output e_l, 100 + l for decoder output u_l, 200 for
+ * the head record.  Returns byte offset, shape and element size (4 = fp32,
+ * 2 = bf16).  For debugging and layer-by-layer checks. */
+wskp_status_t wskp_workspace_tensor(wskp_handle_t h, int n, const int *H, const int *W, int frame,
+                                    int which, size_t *offset, int *th, int *tw, int *tc,
+                                    int *elem_bytes);
+
+/* Launch timing, for benchmarks.  wskp_timing_enable(h, k) makes the next
+ * k calls of wskp_denoise / wskp_denoise_batch record a HIP event on the
+ * call's stream before the first launch and after each launch (k = 0 turns
+ * it off and frees the events).  wskp_timing_read waits for those events and
+ * returns in ms_sum[i] the elapsed milliseconds of launch i summed over the
+ * recorded calls, the number of launches per call and the number of calls.
+ * Launch i is named by wskp_launch_name(h, i): "enc0".."enc5",
+ * "dec0".."dec5", "head", "decode". */
+wskp_status_t wskp_timing_enable(wskp_handle_t h, int max_calls);
+wskp_status_t wskp_timing_read(wskp_handle_t h, int max, float *ms_sum, int *n_launches,
+                               int *n_calls);
+const char *wskp_launch_name(wskp_handle_t h, int i);
+
+/* Static text for a status code. */
+const char *wskp_status_string(wskp_status_t s);
+
+/* Thread-local detail of the last failing call on this thread ("" if none). */
+const char *wskp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WSKP_H */

@@ -219,3 +219,38 @@ def denoise(frame: Dict[str, np.ndarray], blob, cfg, return_all: bool = False):
     if return_all:
         return y, {"X": X, "c": c, "mod": mod, "h": h, "head": head}
     return y
+
+
+def unet_layers(X, blob, cfg) -> Dict[str, np.ndarray]:
+    """Every intermediate map of the U-Net: e0..e_{L-1}, u_{L-2}..u0, h.
+
+    The same steps as ``unet`` composed from the single-op routines, for
+    layer-by-layer comparisons.
+    """
+    blob = _f(blob)
+    L, ch = cfg.levels, cfg.channels
+    convs = []
+    off = 0
+    cin = [X.shape[-1]] + [ch[l - 1] for l in range(1, L)] + \
+          [ch[l + 1] + ch[l] for l in range(L - 2, -1, -1)] + [ch[0]]
+    cout = [ch[l] for l in range(L)] + [ch[l] for l in range(L - 2, -1, -1)] + \
+           [2 * len(cfg.kernel_sizes)]
+    for ci, co in zip(cin, cout):
+        w = blob[off:off + co * ci * 9].reshape(co, ci, 3, 3)
+        off += co * ci * 9
+        b = blob[off:off + co]
+        off += co
+        convs.append((w, b))
+    out = {}
+    e = conv3x3(X, *convs[0], relu=True)
+    out["e0"] = e
+    for l in range(1, L):
+        e = conv3x3(avgpool2(e), *convs[l], relu=True)
+        out[f"e{l}"] = e
+    u = out[f"e{L - 1}"]
+    for j, l in enumerate(range(L - 2, -1, -1)):
+        cat = np.concatenate([upsample2(u), out[f"e{l}"]], axis=-1)
+        u = conv3x3(cat, *convs[L + j], relu=True)
+        out[f"u{l}"] = u
+    out["h"] = conv3x3(u, *convs[-1], relu=False)
+    return out

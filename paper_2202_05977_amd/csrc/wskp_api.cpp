@@ -1,0 +1,613 @@
+// C ABI of libwskp: argument validation, weight packing, workspace layout
+// and the launch sequence of one denoising pass.  Every arithmetic step of
+// the path runs in the HIP kernels (conv3x3.hip, decode.hip); this file
+// only plans and launches.
+#include "wskp.h"
+#include "wskp_internal.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+using namespace wskp;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+wskp_status_t fail(wskp_status_t s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+wskp_status_t hip_fail(hipError_t e, const char *what, wskp_status_t s = WSKP_E_DEVICE)
+{
+    return fail(s, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct LayerPlan {
+    ConvLayer L;
+    int mode;
+    int epi;
+    int Cin;
+    size_t w_off, b_off;  // byte offsets into the device weight buffer
+};
+
+// Host round-to-nearest-even to bf16 (the usual bit-level method).
+uint16_t host_bf16(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+}  // namespace
+
+struct wskp_ctx {
+    wskp_config_t cfg;
+    int device = 0;
+    int prec = 0;
+    int act_bytes = 4;
+    std::vector<LayerPlan> layers;
+    void *dweights = nullptr;
+    DecodeCfg dc{};
+    // pinned host staging for batch frame tables
+    std::mutex mu;
+    FrameDesc *ring = nullptr;
+    std::vector<hipEvent_t> ring_ev;
+    int ring_next = 0;
+    // launch timing (diagnostics): events recorded around every launch
+    std::vector<hipEvent_t> tev;
+    int t_max_calls = 0, t_calls = 0;
+};
+
+static constexpr int kRingSlots = 8;
+static constexpr int kMaxBatch = 1024;
+
+// ---------------------------------------------------------------------------
+static wskp_status_t check_config(const wskp_config_t *c)
+{
+    if (!c) return fail(WSKP_E_INVALID_ARG, "config is NULL");
+    if (c->struct_size != sizeof(wskp_config_t))
+        return fail(WSKP_E_INVALID_ARG, "config.struct_size != sizeof(wskp_config_t)");
+    if (c->levels < 1 || c->levels > WSKP_MAX_LEVELS)
+        return fail(WSKP_E_INVALID_ARG, "levels must be in 1..6");
+    for (int l = 0; l < c->levels; ++l)
+        if (c->channels[l] < 16 || c->channels[l] > 256 || c->channels[l] % 16)
+            return fail(WSKP_E_INVALID_ARG, "channels[l] must be a multiple of 16 in 16..256");
+    if (c->num_kernels < 1 || c->num_kernels > WSKP_MAX_KERNELS)
+        return fail(WSKP_E_INVALID_ARG, "num_kernels must be in 1..8");
+    for (int i = 0; i < c->num_kernels; ++i) {
+        const int k = c->kernel_sizes[i];
+        if (k < 1 || k > WSKP_MAX_KERNEL_SIZE || k % 2 == 0)
+            return fail(WSKP_E_INVALID_ARG, "kernel sizes must be odd, 1..15");
+    }
+    if (c->precision < WSKP_PREC_FP32 || c->precision > WSKP_PREC_FP8_E4M3)
+        return fail(WSKP_E_INVALID_ARG, "unknown precision");
+    if (c->weight_act != WSKP_ACT_SOFTPLUS && c->weight_act != WSKP_ACT_EXP)
+        return fail(WSKP_E_INVALID_ARG, "unknown weight activation");
+    if (!(c->eps_norm > 0.f) || !(c->eps_albedo >= 0.f) || !(c->gamma > 0.f) ||
+        !(c->depth_far > c->depth_near))
+        return fail(WSKP_E_INVALID_ARG, "eps_norm > 0, eps_albedo >= 0, gamma > 0, far > near");
+    return WSKP_OK;
+}
+
+// (Cin, Cout) of each conv in blob order.
+static void conv_dims(const wskp_config_t *c, std::vector<std::pair<int, int>> &d)
+{
+    const int L = c->levels;
+    d.clear();
+    d.push_back({10, c->channels[0]});
+    for (int l = 1; l < L; ++l) d.push_back({c->channels[l - 1], c->channels[l]});
+    for (int l = L - 2; l >= 0; --l) d.push_back({c->channels[l + 1] + c->channels[l], c->channels[l]});
+    d.push_back({c->channels[0], 2 * c->num_kernels});
+}
+
+extern "C" size_t wskp_num_weights(const wskp_config_t *cfg)
+{
+    if (check_config(cfg) != WSKP_OK) return 0;
+    std::vector<std::pair<int, int>> d;
+    conv_dims(cfg, d);
+    size_t n = 0;
+    for (auto &p : d) n += (size_t)p.second * p.first * 9 + p.second;
+    return n;
+}
+
+// Packs OIHW fp32 weights into the order the kernels read (see conv3x3.hip).
+static void pack_layer(int prec, const LayerPlan &lp, const float *w, std::vector<char> &out)
+{
+    const ConvLayer &L = lp.L;
+    const int CK = L.CK, nch = L.Cin_pad / CK, Cin = lp.Cin, Cout = L.Cout;
+    auto W = [&](int co, int ci, int tap) -> float {
+        if (co >= Cout || ci >= Cin) return 0.f;
+        return w[((size_t)co * Cin + ci) * 9 + tap];
+    };
+    if (prec == WSKP_PREC_FP32) {
+        // [chunk][tap][c][Cout_pad]
+        out.assign((size_t)nch * 9 * CK * L.Cout_pad * 4, 0);
+        float *o = reinterpret_cast<float *>(out.data());
+        for (int cc = 0; cc < nch; ++cc)
+            for (int tap = 0; tap < 9; ++tap)
+                for (int c = 0; c < CK; ++c)
+                    for (int co = 0; co < L.Cout_pad; ++co)
+                        o[(((size_t)cc * 9 + tap) * CK + c) * L.Cout_pad + co] = W(co, cc * CK + c, tap);
+    } else {
+        // [chunk][Cout_pad][NK*32], K = tap*CK + c, zero padded
+        const int NK = (9 * CK + 31) / 32, KR = NK * 32;
+        out.assign((size_t)nch * L.Cout_pad * KR * 2, 0);
+        uint16_t *o = reinterpret_cast<uint16_t *>(out.data());
+        for (int cc = 0; cc < nch; ++cc)
+            for (int co = 0; co < L.Cout_pad; ++co)
+                for (int k = 0; k < 9 * CK; ++k) {
+                    const int tap = k / CK, c = k % CK;
+                    o[((size_t)cc * L.Cout_pad + co) * KR + k] = host_bf16(W(co, cc * CK + c, tap));
+                }
+    }
+}
+
+extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host_weights,
+                                     size_t n_weights, const float *host_act_scales, int device,
+                                     wskp_handle_t *out)
+{
+    (void)host_act_scales;
+    if (!out) return fail(WSKP_E_INVALID_ARG, "out handle pointer is NULL");
+    *out = nullptr;
+    wskp_status_t st = check_config(cfg);
+    if (st != WSKP_OK) return st;
+    if (cfg->precision == WSKP_PREC_FP8_E4M3)
+        return fail(WSKP_E_UNSUPPORTED, "FP8 convolutions are not available in this build");
+    if (!host_weights) return fail(WSKP_E_INVALID_ARG, "weights pointer is NULL");
+    if (n_weights != wskp_num_weights(cfg))
+        return fail(WSKP_E_INVALID_ARG, "weight count does not match wskp_num_weights(cfg)");
+
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0) return fail(WSKP_E_DEVICE, "no HIP device available");
+    if (device < 0 || device >= ndev) return fail(WSKP_E_DEVICE, "device index out of range");
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess)
+        return hip_fail(e, "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(WSKP_E_DEVICE, std::string("device is ") + prop.gcnArchName + ", need gfx950");
+    if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+
+    wskp_ctx *h = new wskp_ctx();
+    h->cfg = *cfg;
+    h->device = device;
+    h->prec = cfg->precision;
+    h->act_bytes = h->prec == WSKP_PREC_FP32 ? 4 : 2;
+
+    // ---- layer plan
+    const int L = cfg->levels, M = cfg->num_kernels;
+    std::vector<std::pair<int, int>> dims;
+    conv_dims(cfg, dims);
+    auto add = [&](int mode, int level, int s0kind, int s0, int s1, int C0, int C1, int Cin, int Cout,
+                   int okind, int oidx) {
+        LayerPlan lp{};
+        ConvLayer &c = lp.L;
+        c.level = level;
+        c.src0_kind = s0kind;
+        c.src0_idx = s0;
+        c.src1_idx = s1;
+        c.C0 = C0;
+        c.C1 = C1;
+        c.CK = conv_chunk(h->prec, mode, Cin, C0);
+        c.Cin_pad = (Cin + c.CK - 1) / c.CK * c.CK;
+        c.Cout = Cout;
+        const int nblk = (Cout + 15) / 16;
+        c.NB = (nblk % 2 == 0) ? 2 : 1;
+        c.groups = nblk / c.NB;
+        c.Cout_pad = nblk * 16;
+        c.out_kind = okind;
+        c.out_idx = oidx;
+        c.M = M;
+        c.inv_gamma = 1.f / cfg->gamma;
+        c.dnear = cfg->depth_near;
+        c.dinv = 1.f / (cfg->depth_far - cfg->depth_near);
+        lp.mode = mode;
+        lp.epi = okind == 2 ? (cfg->weight_act == WSKP_ACT_EXP ? EPI_HEAD_EXP : EPI_HEAD_SOFTPLUS)
+                            : EPI_RELU;
+        lp.Cin = Cin;
+        h->layers.push_back(lp);
+    };
+    const int *ch = cfg->channels;
+    add(CONV_PACK, 0, 0, 0, 0, 10, 0, 10, ch[0], 0, 0);
+    for (int l = 1; l < L; ++l) add(CONV_POOL, l, 0, l - 1, 0, ch[l - 1], 0, ch[l - 1], ch[l], 0, l);
+    for (int l = L - 2; l >= 0; --l)
+        add(CONV_CAT, l, 1, l + 1, l, ch[l + 1], ch[l], ch[l + 1] + ch[l], ch[l], 1, l);
+    add(CONV_PLAIN, 0, 1, 0, 0, ch[0], 0, ch[0], 2 * M, 2, 0);
+
+    // ---- pack weights into one device buffer
+    std::vector<char> blob;
+    size_t src = 0;
+    for (size_t i = 0; i < h->layers.size(); ++i) {
+        LayerPlan &lp = h->layers[i];
+        const int Cin = dims[i].first, Cout = dims[i].second;
+        std::vector<char> pk;
+        pack_layer(h->prec, lp, host_weights + src, pk);
+        src += (size_t)Cout * Cin * 9;
+        lp.w_off = align_up(blob.size());
+        blob.resize(lp.w_off + pk.size());
+        std::memcpy(blob.data() + lp.w_off, pk.data(), pk.size());
+        lp.b_off = align_up(blob.size());
+        blob.resize(lp.b_off + (size_t)Cout * 4);
+        std::memcpy(blob.data() + lp.b_off, host_weights + src, (size_t)Cout * 4);
+        src += Cout;
+    }
+    if ((e = hipMalloc(&h->dweights, blob.size())) != hipSuccess) {
+        delete h;
+        return hip_fail(e, "hipMalloc(weights)", WSKP_E_OOM);
+    }
+    if ((e = hipMemcpy(h->dweights, blob.data(), blob.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+        (void)hipFree(h->dweights);
+        delete h;
+        return hip_fail(e, "hipMemcpy(weights)");
+    }
+    for (auto &lp : h->layers) {
+        lp.L.w = static_cast<char *>(h->dweights) + lp.w_off;
+        lp.L.bias = reinterpret_cast<const float *>(static_cast<char *>(h->dweights) + lp.b_off);
+    }
+
+    // ---- decode configuration
+    h->dc.M = M;
+    h->dc.R = 0;
+    for (int i = 0; i < M; ++i) {
+        h->dc.radius[i] = (cfg->kernel_sizes[i] - 1) / 2;
+        if (h->dc.radius[i] > h->dc.R) h->dc.R = h->dc.radius[i];
+    }
+    h->dc.eps_norm = cfg->eps_norm;
+    h->dc.eps_albedo = cfg->eps_albedo;
+    *out = h;
+    return WSKP_OK;
+}
+
+extern "C" wskp_status_t wskp_destroy(wskp_handle_t h)
+{
+    if (!h) return fail(WSKP_E_INVALID_ARG, "handle is NULL");
+    (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();
+    for (auto ev : h->ring_ev) (void)hipEventDestroy(ev);
+    for (auto ev : h->tev) (void)hipEventDestroy(ev);
+    if (h->ring) (void)hipHostFree(h->ring);
+    if (h->dweights) (void)hipFree(h->dweights);
+    delete h;
+    return WSKP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Workspace: [frame table][frame 0][frame 1]...; per frame e_0..e_{L-1},
+// u_0..u_{L-2}, head, each 256-byte aligned.
+static size_t frame_bytes(const wskp_ctx *h, int H, int W, size_t *off_e, size_t *off_u,
+                          size_t *off_head)
+{
+    const int L = h->cfg.levels;
+    size_t o = 0;
+    for (int l = 0; l < L; ++l) {
+        if (off_e) off_e[l] = o;
+        o += align_up((size_t)(H >> l) * (W >> l) * h->cfg.channels[l] * h->act_bytes);
+    }
+    for (int l = 0; l < L - 1; ++l) {
+        if (off_u) off_u[l] = o;
+        o += align_up((size_t)(H >> l) * (W >> l) * h->cfg.channels[l] * h->act_bytes);
+    }
+    if (off_head) *off_head = o;
+    o += align_up((size_t)H * W * 2 * h->cfg.num_kernels * 4);
+    return o;
+}
+
+static size_t table_bytes(int n) { return align_up((size_t)n * sizeof(FrameDesc)); }
+
+static wskp_status_t check_frame_size(const wskp_ctx *h, int H, int W)
+{
+    const int a = 1 << (h->cfg.levels - 1);
+    if (H < 1 || W < 1) return fail(WSKP_E_SHAPE, "H and W must be >= 1");
+    if (H % a || W % a)
+        return fail(WSKP_E_SHAPE, "H and W must be multiples of 2^(levels-1) = " + std::to_string(a));
+    if ((long)H * W > (1L << 28)) return fail(WSKP_E_SHAPE, "frame too large");
+    return WSKP_OK;
+}
+
+extern "C" wskp_status_t wskp_workspace_size(wskp_handle_t h, int n, const int *H, const int *W,
+                                             size_t *bytes)
+{
+    if (!h || !H || !W || !bytes) return fail(WSKP_E_INVALID_ARG, "NULL argument");
+    if (n < 1 || n > kMaxBatch) return fail(WSKP_E_INVALID_ARG, "n must be in 1..1024");
+    size_t tot = table_bytes(n);
+    for (int i = 0; i < n; ++i) {
+        wskp_status_t st = check_frame_size(h, H[i], W[i]);
+        if (st != WSKP_OK) return st;
+        tot += frame_bytes(h, H[i], W[i], nullptr, nullptr, nullptr);
+    }
+    *bytes = tot;
+    return WSKP_OK;
+}
+
+extern "C" wskp_status_t wskp_workspace_tensor(wskp_handle_t h, int n, const int *H, const int *W,
+                                               int frame, int which, size_t *offset, int *th,
+                                               int *tw, int *tc, int *elem_bytes)
+{
+    if (!h || !H || !W || !offset) return fail(WSKP_E_INVALID_ARG, "NULL argument");
+    if (n < 1 || frame < 0 || frame >= n) return fail(WSKP_E_INVALID_ARG, "frame out of range");
+    const int L = h->cfg.levels;
+    size_t base = table_bytes(n);
+    for (int i = 0; i < frame; ++i) base += frame_bytes(h, H[i], W[i], nullptr, nullptr, nullptr);
+    size_t oe[kMaxLevels], ou[kMaxLevels], oh;
+    frame_bytes(h, H[frame], W[frame], oe, ou, &oh);
+    int l, c, eb = h->act_bytes;
+    size_t o;
+    if (which >= 0 && which < L) {
+        l = which; o = oe[l]; c = h->cfg.channels[l];
+    } else if (which >= 100 && which < 100 + L) {
+        l = which - 100;
+        o = (l == L - 1) ? oe[l] : ou[l];
+        c = h->cfg.channels[l];
+    } else if (which == 200) {
+        l = 0; o = oh; c = 2 * h->cfg.num_kernels; eb = 4;
+    } else {
+        return fail(WSKP_E_INVALID_ARG, "unknown tensor id");
+    }
+    *offset = base + o;
+    if (th) *th = H[frame] >> l;
+    if (tw) *tw = W[frame] >> l;
+    if (tc) *tc = c;
+    if (elem_bytes) *elem_bytes = eb;
+    return WSKP_OK;
+}
+
+static void fill_frame(const wskp_ctx *h, FrameDesc &fd, char *fbase, const wskp_frame_t &f)
+{
+    size_t oe[kMaxLevels], ou[kMaxLevels], oh;
+    frame_bytes(h, f.H, f.W, oe, ou, &oh);
+    const int L = h->cfg.levels;
+    std::memset(&fd, 0, sizeof(fd));
+    fd.H = f.H;
+    fd.W = f.W;
+    fd.r = f.radiance;
+    fd.a = f.albedo;
+    fd.n = f.normal;
+    fd.d = f.depth;
+    fd.out = f.out;
+    for (int l = 0; l < L; ++l) fd.e[l] = fbase + oe[l];
+    for (int l = 0; l < L - 1; ++l) fd.u[l] = fbase + ou[l];
+    fd.u[L - 1] = fd.e[L - 1];
+    fd.head = reinterpret_cast<float *>(fbase + oh);
+}
+
+static wskp_status_t set_device(const wskp_ctx *h)
+{
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess || cur != h->device) {
+        hipError_t e = hipSetDevice(h->device);
+        if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    }
+    return WSKP_OK;
+}
+
+static int n_launches(const wskp_ctx *h) { return (int)h->layers.size() + 1; }
+
+// Queues the whole network and the decode for the frames of `fa`.
+static wskp_status_t run_frames(wskp_ctx *h, const FrameArg &fa, int n, const int *Hs, const int *Ws,
+                                hipStream_t s)
+{
+    hipEvent_t *ev = nullptr;
+    if (h->t_max_calls > 0 && h->t_calls < h->t_max_calls)
+        ev = h->tev.data() + (size_t)h->t_calls++ * (n_launches(h) + 1);
+    int k = 0;
+    if (ev) (void)hipEventRecord(ev[k], s);
+    for (const LayerPlan &lp : h->layers) {
+        const int blocks = conv_grid(lp.L, n, Hs, Ws);
+        hipError_t e = launch_conv(lp.L, lp.mode, lp.epi, h->prec, fa, blocks, s);
+        if (e != hipSuccess) return hip_fail(e, "conv launch", WSKP_E_LAUNCH);
+        if (ev) (void)hipEventRecord(ev[++k], s);
+    }
+    hipError_t e = launch_decode_frames(h->dc, fa, decode_grid(n, Hs, Ws), s);
+    if (e != hipSuccess) return hip_fail(e, "decode launch", WSKP_E_LAUNCH);
+    if (ev) (void)hipEventRecord(ev[++k], s);
+    return WSKP_OK;
+}
+
+extern "C" wskp_status_t wskp_timing_enable(wskp_handle_t h, int max_calls)
+{
+    if (!h || max_calls < 0) return fail(WSKP_E_INVALID_ARG, "bad argument");
+    wskp_status_t st = set_device(h);
+    if (st != WSKP_OK) return st;
+    (void)hipDeviceSynchronize();
+    for (auto ev : h->tev) (void)hipEventDestroy(ev);
+    h->tev.clear();
+    h->t_calls = 0;
+    h->t_max_calls = 0;
+    if (max_calls == 0) return WSKP_OK;
+    h->tev.resize((size_t)max_calls * (n_launches(h) + 1));
+    for (auto &ev : h->tev) {
+        hipError_t e = hipEventCreate(&ev);
+        if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+    h->t_max_calls = max_calls;
+    return WSKP_OK;
+}
+
+extern "C" wskp_status_t wskp_timing_read(wskp_handle_t h, int max, float *ms_sum, int *n_launch,
+                                          int *n_calls)
+{
+    if (!h || !ms_sum || !n_launch || !n_calls) return fail(WSKP_E_INVALID_ARG, "NULL argument");
+    const int nl = n_launches(h);
+    if (max < nl) return fail(WSKP_E_INVALID_ARG, "ms_sum too short");
+    for (int i = 0; i < nl; ++i) ms_sum[i] = 0.f;
+    for (int c = 0; c < h->t_calls; ++c) {
+        hipEvent_t *ev = h->tev.data() + (size_t)c * (nl + 1);
+        hipError_t e = hipEventSynchronize(ev[nl]);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        for (int i = 0; i < nl; ++i) {
+            float ms = 0.f;
+            if ((e = hipEventElapsedTime(&ms, ev[i], ev[i + 1])) != hipSuccess)
+                return hip_fail(e, "hipEventElapsedTime");
+            ms_sum[i] += ms;
+        }
+    }
+    *n_launch = nl;
+    *n_calls = h->t_calls;
+    return WSKP_OK;
+}
+
+extern "C" const char *wskp_launch_name(wskp_handle_t h, int i)
+{
+    static const char *enc[] = {"enc0", "enc1", "enc2", "enc3", "enc4", "enc5"};
+    static const char *dec[] = {"dec0", "dec1", "dec2", "dec3", "dec4", "dec5"};
+    if (!h || i < 0 || i > (int)h->layers.size()) return "";
+    if (i == (int)h->layers.size()) return "decode";
+    const LayerPlan &lp = h->layers[i];
+    if (lp.L.out_kind == 2) return "head";
+    return lp.L.out_kind == 0 ? enc[lp.L.out_idx] : dec[lp.L.out_idx];
+}
+
+extern "C" wskp_status_t wskp_denoise(wskp_handle_t h, void *stream, int H, int W,
+                                      const float *radiance, const float *albedo,
+                                      const float *normal, const float *depth, float *out,
+                                      void *ws, size_t ws_bytes)
+{
+    if (!h) return fail(WSKP_E_INVALID_ARG, "handle is NULL");
+    if (!radiance || !albedo || !normal || !depth || !out || !ws)
+        return fail(WSKP_E_INVALID_ARG, "NULL tensor or workspace pointer");
+    wskp_status_t st = check_frame_size(h, H, W);
+    if (st != WSKP_OK) return st;
+    const size_t need = table_bytes(1) + frame_bytes(h, H, W, nullptr, nullptr, nullptr);
+    if (ws_bytes < need)
+        return fail(WSKP_E_BUDGET, "workspace too small: need " + std::to_string(need) + " bytes");
+    if ((st = set_device(h)) != WSKP_OK) return st;
+    wskp_frame_t f{H, W, radiance, albedo, normal, depth, out};
+    FrameArg fa{};
+    fa.table = nullptr;
+    fa.n = 1;
+    fa.reverse = 0;
+    fill_frame(h, fa.one, static_cast<char *>(ws) + table_bytes(1), f);
+    return run_frames(h, fa, 1, &H, &W, static_cast<hipStream_t>(stream));
+}
+
+extern "C" wskp_status_t wskp_denoise_batch(wskp_handle_t h, void *stream, int n,
+                                            const wskp_frame_t *frames, uint32_t flags, void *ws,
+                                            size_t ws_bytes)
+{
+    if (!h || !frames || !ws) return fail(WSKP_E_INVALID_ARG, "NULL argument");
+    if (n < 1 || n > kMaxBatch) return fail(WSKP_E_INVALID_ARG, "n must be in 1..1024");
+    std::vector<int> Hs(n), Ws(n);
+    for (int i = 0; i < n; ++i) {
+        const wskp_frame_t &f = frames[i];
+        if (!f.radiance || !f.albedo || !f.normal || !f.depth || !f.out)
+            return fail(WSKP_E_INVALID_ARG, "NULL tensor pointer in frame " + std::to_string(i));
+        wskp_status_t st = check_frame_size(h, f.H, f.W);
+        if (st != WSKP_OK) return st;
+        Hs[i] = f.H;
+        Ws[i] = f.W;
+    }
+    size_t need;
+    wskp_status_t st = wskp_workspace_size(h, n, Hs.data(), Ws.data(), &need);
+    if (st != WSKP_OK) return st;
+    if (ws_bytes < need)
+        return fail(WSKP_E_BUDGET, "workspace too small: need " + std::to_string(need) + " bytes");
+    if ((st = set_device(h)) != WSKP_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    std::lock_guard<std::mutex> lock(h->mu);
+    hipError_t e;
+    if (!h->ring) {
+        if ((e = hipHostMalloc(reinterpret_cast<void **>(&h->ring),
+                               sizeof(FrameDesc) * kMaxBatch * kRingSlots, hipHostMallocDefault)) !=
+            hipSuccess)
+            return hip_fail(e, "hipHostMalloc(frame table ring)", WSKP_E_OOM);
+        h->ring_ev.resize(kRingSlots);
+        for (auto &ev : h->ring_ev)
+            if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+                return hip_fail(e, "hipEventCreate");
+        for (auto &ev : h->ring_ev) (void)hipEventRecord(ev, s);
+    }
+    const int slot = h->ring_next;
+    h->ring_next = (h->ring_next + 1) % kRingSlots;
+    // the slot's previous copy must have left host memory before it is rewritten
+    if ((e = hipEventSynchronize(h->ring_ev[slot])) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    FrameDesc *tab = h->ring + (size_t)slot * kMaxBatch;
+    char *base = static_cast<char *>(ws) + table_bytes(n);
+    for (int i = 0; i < n; ++i) {
+        fill_frame(h, tab[i], base, frames[i]);
+        base += frame_bytes(h, Hs[i], Ws[i], nullptr, nullptr, nullptr);
+    }
+    if ((e = hipMemcpyAsync(ws, tab, sizeof(FrameDesc) * n, hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_fail(e, "hipMemcpyAsync(frame table)");
+    if ((e = hipEventRecord(h->ring_ev[slot], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    FrameArg fa{};
+    fa.table = static_cast<const FrameDesc *>(ws);
+    fa.n = n;
+    fa.reverse = (flags & WSKP_BATCH_REVERSE_TILES) ? 1 : 0;
+    return run_frames(h, fa, n, Hs.data(), Ws.data(), s);
+}
+
+extern "C" wskp_status_t wskp_decode(wskp_handle_t h, void *stream, int N, int H, int W,
+                                     const float *head, const float *c, const float *mod, float *out)
+{
+    if (!h) return fail(WSKP_E_INVALID_ARG, "handle is NULL");
+    if (!head || !c || !out) return fail(WSKP_E_INVALID_ARG, "NULL tensor pointer");
+    if (N < 1 || H < 1 || W < 1 || (long)N * H * W > (1L << 30))
+        return fail(WSKP_E_SHAPE, "N, H, W must be >= 1");
+    wskp_status_t st = set_device(h);
+    if (st != WSKP_OK) return st;
+    hipError_t e = launch_decode_tensors(h->dc, N, H, W, head, c, mod, out,
+                                         static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "decode launch", WSKP_E_LAUNCH);
+    return WSKP_OK;
+}
+
+extern "C" wskp_status_t wskp_backward_workspace_size(wskp_handle_t h, int N, int H, int W,
+                                                      size_t *bytes)
+{
+    if (!h || !bytes) return fail(WSKP_E_INVALID_ARG, "NULL argument");
+    if (N < 1 || H < 1 || W < 1) return fail(WSKP_E_SHAPE, "N, H, W must be >= 1");
+    *bytes = decode_backward_scratch_bytes(h->dc, N, H, W);
+    return WSKP_OK;
+}
+
+extern "C" wskp_status_t wskp_backward(wskp_handle_t h, void *stream, int N, int H, int W,
+                                       const float *head, const float *c, const float *mod,
+                                       const float *grad_out, float *grad_head, float *grad_c,
+                                       void *ws, size_t ws_bytes)
+{
+    if (!h) return fail(WSKP_E_INVALID_ARG, "handle is NULL");
+    if (!head || !c || !grad_out || !grad_head || !grad_c || !ws)
+        return fail(WSKP_E_INVALID_ARG, "NULL tensor or workspace pointer");
+    if (N < 1 || H < 1 || W < 1 || (long)N * H * W > (1L << 30))
+        return fail(WSKP_E_SHAPE, "N, H, W must be >= 1");
+    const size_t need = decode_backward_scratch_bytes(h->dc, N, H, W);
+    if (ws_bytes < need)
+        return fail(WSKP_E_BUDGET, "workspace too small: need " + std::to_string(need) + " bytes");
+    wskp_status_t st = set_device(h);
+    if (st != WSKP_OK) return st;
+    hipError_t e = launch_decode_backward(h->dc, N, H, W, head, c, mod, grad_out, grad_head, grad_c,
+                                          ws, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "backward launch", WSKP_E_LAUNCH);
+    return WSKP_OK;
+}
+
+extern "C" const char *wskp_status_string(wskp_status_t s)
+{
+    switch (s) {
+    case WSKP_OK: return "ok";
+    case WSKP_E_INVALID_ARG: return "invalid argument";
+    case WSKP_E_SHAPE: return "unsupported shape";
+    case WSKP_E_UNSUPPORTED: return "unsupported";
+    case WSKP_E_DEVICE: return "device error";
+    case WSKP_E_OOM: return "out of memory";
+    case WSKP_E_BUDGET: return "workspace too small";
+    case WSKP_E_LAUNCH: return "kernel launch failed";
+    case WSKP_E_INTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *wskp_last_error(void) { return g_last_error.c_str(); }

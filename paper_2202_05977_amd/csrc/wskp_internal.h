@@ -1,0 +1,108 @@
+// Internal declarations shared by the HIP kernels and the C ABI layer of
+// libwskp.  Not part of the public interface (include/wskp.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace wskp {
+
+constexpr int kMaxLevels = 6;
+constexpr int kMaxKernels = 8;
+constexpr int kThreads = 256;  // every kernel runs 4 wave64s per workgroup
+
+// Everything one frame's layers need: its size, the caller's input and
+// output buffers, and where its intermediate maps sit in the workspace.
+struct FrameDesc {
+    int H, W;
+    const float *r, *a, *n, *d;  // radiance, albedo, normal [H,W,3]; depth [H,W,1]
+    float *out;                  // [H,W,3]
+    void *e[kMaxLevels];         // encoder outputs e_l  [H>>l, W>>l, C_l]
+    void *u[kMaxLevels];         // decoder outputs u_l  [H>>l, W>>l, C_l]; u[L-1] == e[L-1]
+    float *head;                 // [H,W,2M]: weights W_i then logits
+};
+
+// A batch of frames for one launch: either one frame passed by value or a
+// device-resident table of n frames.
+struct FrameArg {
+    const FrameDesc *table;  // device pointer, or nullptr to use `one`
+    int n;
+    int reverse;             // walk tiles in reverse order
+    FrameDesc one;
+};
+
+__device__ __forceinline__ const FrameDesc &frame_at(const FrameArg &fa, int f)
+{
+    return fa.table ? fa.table[f] : fa.one;
+}
+
+// Spread consecutive logical tile ids over one XCD.  The hardware deals
+// workgroups round-robin to the 8 XCDs (block b runs on XCD b % 8); this
+// bijection gives each XCD a contiguous run of logical ids so that tiles
+// that share halos (and output-channel groups that share an input tile)
+// share that XCD's L2.
+__device__ __forceinline__ int xcd_logical_id(int b, int nb)
+{
+    const int x = b & 7, i = b >> 3;
+    const int q = nb >> 3, rmd = nb & 7;
+    return x * q + (x < rmd ? x : rmd) + i;
+}
+
+enum ConvMode { CONV_PACK = 0, CONV_POOL = 1, CONV_CAT = 2, CONV_PLAIN = 3 };
+enum ConvEpi { EPI_RELU = 0, EPI_HEAD_SOFTPLUS = 1, EPI_HEAD_EXP = 2 };
+enum ActType { ACT_F32 = 0, ACT_BF16 = 1 };
+
+// One 3x3 conv layer as the kernels see it.
+struct ConvLayer {
+    int level;         // output resolution level (H >> level, W >> level)
+    int src0_kind;     // 0: e[src0_idx], 1: u[src0_idx]
+    int src0_idx;
+    int src1_idx;      // CAT: skip e[src1_idx]
+    int C0, C1;        // channels of source 0 / source 1 (CAT: up, skip)
+    int Cin_pad;       // virtual input channels padded to the chunk size
+    int Cout;          // real output channels
+    int Cout_pad;      // padded to 16 * NB * groups
+    int groups;        // output-channel groups (one workgroup each)
+    int out_kind;      // 0: e[out_idx], 1: u[out_idx], 2: head
+    int out_idx;
+    int M;             // head: channels 0..M-1 get the weight activation
+    int CK;            // input channels per reduction chunk (weights packed to match)
+    int NB;            // 16-channel output blocks per workgroup
+    const void *w;     // packed weights
+    const float *bias; // [Cout]
+    float inv_gamma, dnear, dinv;  // CONV_PACK preprocessing constants
+};
+
+struct DecodeCfg {
+    int M;
+    int R;                    // max radius
+    int radius[kMaxKernels];  // (k_i - 1)/2
+    float eps_norm;
+    float eps_albedo;
+};
+
+// ---- launchers (defined in the .hip files) --------------------------------
+// Launches one conv layer over `blocks` workgroups (conv_grid of the batch;
+// a larger count is allowed: surplus workgroups exit at once).
+hipError_t launch_conv(const ConvLayer &L, int mode, int epi, int prec, const FrameArg &fa,
+                       int blocks, hipStream_t s);
+int conv_grid(const ConvLayer &L, int n, const int *H, const int *W);
+int conv_chunk(int prec, int mode, int Cin, int C0);
+// Decode + fusion + remodulation over frames of fa (denoise mode: c and mod
+// derive from r, a) -- or over plain tensors (decode mode).
+hipError_t launch_decode_frames(const DecodeCfg &dc, const FrameArg &fa, int blocks, hipStream_t s);
+int decode_grid(int n, const int *H, const int *W);
+hipError_t launch_decode_tensors(const DecodeCfg &dc, int N, int H, int W, const float *head,
+                                 const float *c, const float *mod, float *out, hipStream_t s);
+hipError_t launch_decode_backward(const DecodeCfg &dc, int N, int H, int W, const float *head,
+                                  const float *c, const float *mod, const float *g,
+                                  float *grad_head, float *grad_c, void *scratch,
+                                  hipStream_t s);
+size_t decode_backward_scratch_bytes(const DecodeCfg &dc, int N, int H, int W);
+
+// Tile geometry of the conv kernels (host and device agree on these).
+constexpr int kConvTW = 32;  // output columns per tile (two 16-pixel MFMA blocks)
+int conv_tile_rows(int prec);
+
+}  // namespace wskp

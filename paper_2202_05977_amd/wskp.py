@@ -1,0 +1,347 @@
+"""Python binding of libwskp (argument marshalling only).
+
+Every function here has the name of the C entry point it calls (see
+include/wskp.h) and does no arithmetic of its own: it checks that tensors
+are contiguous float32 CUDA (HIP) tensors, passes their device pointers and
+the current stream, and turns a failing status into ``WskpError``.  The
+library is loaded after ``import torch`` so that it binds to the HIP runtime
+torch already loaded.  There is no fallback: if libwskp.so is missing or
+the device is not gfx950, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from .synth import NetConfig
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwskp.so")
+
+PREC = {"fp32": 0, "bf16": 1, "fp8": 2}
+ACT = {"softplus": 0, "exp": 1}
+BATCH_REVERSE_TILES = 1
+
+_lib = None
+
+
+class WskpError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where} failed: status {status} ({detail})")
+        self.status = status
+
+
+class wskp_config_t(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("levels", ctypes.c_int32),
+        ("channels", ctypes.c_int32 * 8),
+        ("num_kernels", ctypes.c_int32),
+        ("kernel_sizes", ctypes.c_int32 * 8),
+        ("precision", ctypes.c_int32),
+        ("weight_act", ctypes.c_int32),
+        ("eps_norm", ctypes.c_float),
+        ("eps_albedo", ctypes.c_float),
+        ("gamma", ctypes.c_float),
+        ("depth_near", ctypes.c_float),
+        ("depth_far", ctypes.c_float),
+    ]
+
+
+class wskp_frame_t(ctypes.Structure):
+    _fields_ = [
+        ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+        ("radiance", ctypes.c_void_p), ("albedo", ctypes.c_void_p),
+        ("normal", ctypes.c_void_p), ("depth", ctypes.c_void_p),
+        ("out", ctypes.c_void_p),
+    ]
+
+
+def lib():
+    """The loaded library (loads it on first use; raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.wskp_num_weights.argtypes = [ctypes.POINTER(wskp_config_t)]
+        L.wskp_num_weights.restype = sz
+        L.wskp_create.argtypes = [ctypes.POINTER(wskp_config_t), vp, sz, vp, i32,
+                                  ctypes.POINTER(vp)]
+        L.wskp_destroy.argtypes = [vp]
+        L.wskp_workspace_size.argtypes = [vp, i32, ip, ip, ctypes.POINTER(sz)]
+        L.wskp_denoise.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, sz]
+        L.wskp_denoise_batch.argtypes = [vp, vp, i32, ctypes.POINTER(wskp_frame_t),
+                                         ctypes.c_uint32, vp, sz]
+        L.wskp_decode.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp]
+        L.wskp_backward.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, sz]
+        L.wskp_backward_workspace_size.argtypes = [vp, i32, i32, i32, ctypes.POINTER(sz)]
+        L.wskp_workspace_tensor.argtypes = [vp, i32, ip, ip, i32, i32, ctypes.POINTER(sz),
+                                            ip, ip, ip, ip]
+        L.wskp_timing_enable.argtypes = [vp, i32]
+        L.wskp_timing_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_float), ip, ip]
+        L.wskp_launch_name.argtypes = [vp, i32]
+        L.wskp_launch_name.restype = ctypes.c_char_p
+        L.wskp_status_string.argtypes = [i32]
+        L.wskp_status_string.restype = ctypes.c_char_p
+        L.wskp_last_error.argtypes = []
+        L.wskp_last_error.restype = ctypes.c_char_p
+        for name in ("wskp_create", "wskp_destroy", "wskp_workspace_size", "wskp_denoise",
+                     "wskp_denoise_batch", "wskp_decode", "wskp_backward",
+                     "wskp_backward_workspace_size", "wskp_workspace_tensor",
+                     "wskp_timing_enable", "wskp_timing_read"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        L = lib()
+        detail = L.wskp_last_error().decode() or L.wskp_status_string(status).decode()
+        raise WskpError(status, where, detail)
+
+
+def _ptr(t: Optional[torch.Tensor], name: str, shape: Optional[Sequence[int]] = None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float32")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def make_config(cfg: NetConfig, precision: str = "fp32") -> wskp_config_t:
+    c = wskp_config_t()
+    c.struct_size = ctypes.sizeof(wskp_config_t)
+    c.levels = cfg.levels
+    for i, ch in enumerate(cfg.channels[:8]):
+        c.channels[i] = ch
+    c.num_kernels = cfg.M          # the library rejects M > 8
+    for i, k in enumerate(cfg.kernel_sizes[:8]):
+        c.kernel_sizes[i] = k
+    c.precision = PREC[precision]
+    c.weight_act = ACT[cfg.weight_act]
+    c.eps_norm = cfg.eps_norm
+    c.eps_albedo = cfg.eps_albedo
+    c.gamma = cfg.gamma
+    c.depth_near = cfg.depth_near
+    c.depth_far = cfg.depth_far
+    return c
+
+
+# ---------------------------------------------------------------- entry points
+def wskp_num_weights(cfg: NetConfig) -> int:
+    c = make_config(cfg)
+    return int(lib().wskp_num_weights(ctypes.byref(c)))
+
+
+def wskp_create(cfg: NetConfig, weights: np.ndarray, precision: str = "fp32",
+                act_scales: Optional[np.ndarray] = None, device: int = 0) -> ctypes.c_void_p:
+    c = make_config(cfg, precision)
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    sc = None
+    if act_scales is not None:
+        sc = np.ascontiguousarray(act_scales, dtype=np.float32)
+    h = ctypes.c_void_p()
+    _check(lib().wskp_create(ctypes.byref(c), w.ctypes.data, w.size,
+                             None if sc is None else sc.ctypes.data, device, ctypes.byref(h)),
+           "wskp_create")
+    return h
+
+
+def wskp_destroy(h) -> None:
+    _check(lib().wskp_destroy(h), "wskp_destroy")
+
+
+def wskp_workspace_size(h, Hs: Sequence[int], Ws: Sequence[int]) -> int:
+    n = len(Hs)
+    a = (ctypes.c_int * n)(*Hs)
+    b = (ctypes.c_int * n)(*Ws)
+    out = ctypes.c_size_t()
+    _check(lib().wskp_workspace_size(h, n, a, b, ctypes.byref(out)), "wskp_workspace_size")
+    return out.value
+
+
+def wskp_workspace_tensor(h, Hs, Ws, frame: int, which: int):
+    n = len(Hs)
+    a = (ctypes.c_int * n)(*Hs)
+    b = (ctypes.c_int * n)(*Ws)
+    off = ctypes.c_size_t()
+    th, tw, tc, eb = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().wskp_workspace_tensor(h, n, a, b, frame, which, ctypes.byref(off),
+                                       ctypes.byref(th), ctypes.byref(tw), ctypes.byref(tc),
+                                       ctypes.byref(eb)), "wskp_workspace_tensor")
+    return off.value, (th.value, tw.value, tc.value), eb.value
+
+
+def wskp_denoise(h, radiance, albedo, normal, depth, out, ws, stream=None) -> None:
+    H, W = radiance.shape[:2]
+    _check(lib().wskp_denoise(h, _stream(stream), H, W,
+                              _ptr(radiance, "radiance", (H, W, 3)),
+                              _ptr(albedo, "albedo", (H, W, 3)),
+                              _ptr(normal, "normal", (H, W, 3)),
+                              _ptr(depth, "depth", (H, W, 1)),
+                              _ptr(out, "out", (H, W, 3)),
+                              ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size()),
+           "wskp_denoise")
+
+
+def wskp_denoise_batch(h, frames: List[Dict[str, torch.Tensor]], ws, flags: int = 0,
+                       stream=None) -> None:
+    n = len(frames)
+    arr = (wskp_frame_t * n)()
+    for i, f in enumerate(frames):
+        H, W = f["radiance"].shape[:2]
+        arr[i].H, arr[i].W = H, W
+        arr[i].radiance = _ptr(f["radiance"], "radiance", (H, W, 3)).value
+        arr[i].albedo = _ptr(f["albedo"], "albedo", (H, W, 3)).value
+        arr[i].normal = _ptr(f["normal"], "normal", (H, W, 3)).value
+        arr[i].depth = _ptr(f["depth"], "depth", (H, W, 1)).value
+        arr[i].out = _ptr(f["out"], "out", (H, W, 3)).value
+    _check(lib().wskp_denoise_batch(h, _stream(stream), n, arr, flags,
+                                    ctypes.c_void_p(ws.data_ptr()),
+                                    ws.numel() * ws.element_size()), "wskp_denoise_batch")
+
+
+def wskp_decode(h, head, c, mod, out, stream=None) -> None:
+    N, H, W, twoM = head.shape
+    _check(lib().wskp_decode(h, _stream(stream), N, H, W, _ptr(head, "head"),
+                             _ptr(c, "c", (N, H, W, 3)),
+                             _ptr(mod, "mod", (N, H, W, 3)),
+                             _ptr(out, "out", (N, H, W, 3))), "wskp_decode")
+
+
+def wskp_backward_workspace_size(h, N: int, H: int, W: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().wskp_backward_workspace_size(h, N, H, W, ctypes.byref(out)),
+           "wskp_backward_workspace_size")
+    return out.value
+
+
+def wskp_backward(h, head, c, mod, grad_out, grad_head, grad_c, ws, stream=None) -> None:
+    N, H, W, twoM = head.shape
+    _check(lib().wskp_backward(h, _stream(stream), N, H, W, _ptr(head, "head"),
+                               _ptr(c, "c", (N, H, W, 3)), _ptr(mod, "mod", (N, H, W, 3)),
+                               _ptr(grad_out, "grad_out", (N, H, W, 3)),
+                               _ptr(grad_head, "grad_head", (N, H, W, twoM)),
+                               _ptr(grad_c, "grad_c", (N, H, W, 3)),
+                               ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size()),
+           "wskp_backward")
+
+
+def wskp_timing_enable(h, max_calls: int) -> None:
+    _check(lib().wskp_timing_enable(h, max_calls), "wskp_timing_enable")
+
+
+def wskp_timing_read(h):
+    """{launch name: (ms summed over calls)}, number of calls."""
+    ms = (ctypes.c_float * 64)()
+    nl, nc = ctypes.c_int(), ctypes.c_int()
+    _check(lib().wskp_timing_read(h, 64, ms, ctypes.byref(nl), ctypes.byref(nc)),
+           "wskp_timing_read")
+    names = [lib().wskp_launch_name(h, i).decode() for i in range(nl.value)]
+    return {n: float(ms[i]) for i, n in enumerate(names)}, nc.value
+
+
+# ---------------------------------------------------------------- conveniences
+class Denoiser:
+    """Owns a handle and a workspace; ``__call__`` denoises one frame."""
+
+    def __init__(self, cfg: NetConfig, weights: np.ndarray, precision: str = "fp32",
+                 device: int = 0, act_scales: Optional[np.ndarray] = None):
+        self.cfg = cfg
+        self.precision = precision
+        self.device = torch.device("cuda", device)
+        self.h = wskp_create(cfg, weights, precision, act_scales, device)
+        self._ws = None
+
+    def workspace(self, Hs, Ws) -> torch.Tensor:
+        need = wskp_workspace_size(self.h, Hs, Ws)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    def __call__(self, frame: Dict[str, torch.Tensor], out: Optional[torch.Tensor] = None,
+                 stream=None) -> torch.Tensor:
+        H, W = frame["radiance"].shape[:2]
+        if out is None:
+            out = torch.empty((H, W, 3), dtype=torch.float32, device=self.device)
+        ws = self.workspace([H], [W])
+        wskp_denoise(self.h, frame["radiance"], frame["albedo"], frame["normal"], frame["depth"],
+                     out, ws, stream)
+        return out
+
+    def batch(self, frames: List[Dict[str, torch.Tensor]], flags: int = 0, stream=None):
+        Hs = [f["radiance"].shape[0] for f in frames]
+        Ws = [f["radiance"].shape[1] for f in frames]
+        ws = self.workspace(Hs, Ws)
+        wskp_denoise_batch(self.h, frames, ws, flags, stream)
+
+    def intermediate(self, Hs, Ws, frame: int, which: int) -> torch.Tensor:
+        """View of an intermediate map in the current workspace (debugging)."""
+        off, (th, tw, tc), eb = wskp_workspace_tensor(self.h, Hs, Ws, frame, which)
+        ws = self._ws
+        raw = ws[off:off + th * tw * tc * eb]
+        if eb == 4:
+            return raw.view(torch.float32).view(th, tw, tc)
+        return raw.view(torch.bfloat16).view(th, tw, tc)
+
+    def close(self):
+        if self.h is not None:
+            wskp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class WskpDecode(torch.autograd.Function):
+    """Decode + fusion + remodulation with the hand-written adjoint.
+
+    forward(head [N,H,W,2M], c [N,H,W,3], mod [N,H,W,3] or None) -> y.
+    Gradients flow to head (weights and logits) and c; mod is a constant.
+    """
+
+    @staticmethod
+    def forward(ctx, handle, head, c, mod):
+        head = head.contiguous()
+        c = c.contiguous()
+        mod = None if mod is None else mod.contiguous()
+        out = torch.empty(c.shape, dtype=torch.float32, device=c.device)
+        wskp_decode(handle, head, c, mod, out)
+        ctx.handle = handle
+        ctx.save_for_backward(head, c, mod if mod is not None else torch.empty(0))
+        ctx.has_mod = mod is not None
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        head, c, mod = ctx.saved_tensors
+        mod = mod if ctx.has_mod else None
+        N, H, W, _ = head.shape
+        g = g.contiguous()
+        gh = torch.empty_like(head)
+        gc = torch.empty_like(c)
+        ws = torch.empty(wskp_backward_workspace_size(ctx.handle, N, H, W), dtype=torch.uint8,
+                         device=head.device)
+        wskp_backward(ctx.handle, head, c, mod, g, gh, gc, ws)
+        return None, gh, gc, None

@@ -1,0 +1,26 @@
+"""Shared helpers for the GPU parity tests (no method arithmetic here)."""
+import numpy as np
+
+
+def rel_l2(a, b) -> float:
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def max_rel(a, b) -> float:
+    """||a - b||_inf / ||b||_inf."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def to_dev(frame, device="cuda"):
+    import torch
+    return {k: torch.from_numpy(np.ascontiguousarray(v)).to(device) for k, v in frame.items()}
+
+
+# FP32 path vs the FP64 oracle: relative L2 and relative max-norm.
+TOL_FP32 = 1e-5
+# BF16 convolutions vs the FP64 oracle: relative L2.
+TOL_BF16 = 1e-2

@@ -1,0 +1,89 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point the public header declares, validates configurations and
+fails cleanly when no gfx950 device is present."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2202_05977_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "wskp.h")
+
+
+def _wskp():
+    pytest.importorskip("torch")
+    from paper_2202_05977_amd import wskp
+    if not os.path.exists(wskp.LIB_PATH):
+        pytest.skip("libwskp.so not built")
+    return wskp
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(wskp_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for n in ("wskp_create", "wskp_destroy", "wskp_denoise", "wskp_denoise_batch",
+              "wskp_decode", "wskp_backward", "wskp_workspace_size", "wskp_num_weights"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    wskp = _wskp()
+    lib = wskp.lib()
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+
+
+def test_num_weights_matches_blob():
+    wskp = _wskp()
+    for cfg in synth.CONFIGS.values():
+        assert wskp.wskp_num_weights(cfg) == synth.num_weights(cfg) == synth.make_weights(cfg).size
+
+
+def test_config_validation():
+    wskp = _wskp()
+    import dataclasses
+    bad = [
+        dataclasses.replace(synth.SMALL, kernel_sizes=(3, 4)),       # even size
+        dataclasses.replace(synth.SMALL, kernel_sizes=(17,)),        # too large
+        dataclasses.replace(synth.SMALL, channels=(16, 24, 64)),     # not a multiple of 16
+        dataclasses.replace(synth.SMALL, kernel_sizes=tuple(range(1, 19, 2))),  # M = 9
+    ]
+    for cfg in bad:
+        assert wskp.wskp_num_weights(cfg) == 0
+        with pytest.raises(wskp.WskpError) as ei:
+            wskp.wskp_create(cfg, np.zeros(10, np.float32))
+        assert ei.value.status == -1
+
+
+def test_weight_count_mismatch_is_rejected():
+    wskp = _wskp()
+    blob = synth.make_weights(synth.SMALL)
+    with pytest.raises(wskp.WskpError) as ei:
+        wskp.wskp_create(synth.SMALL, blob[:-1])
+    assert ei.value.status == -1
+
+
+def test_status_strings():
+    wskp = _wskp()
+    lib = wskp.lib()
+    for s in range(0, -9, -1):
+        assert lib.wskp_status_string(s)
+    assert lib.wskp_status_string(-99) == b"unknown status"
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="a GPU driver is present")
+def test_create_without_device_fails_cleanly():
+    wskp = _wskp()
+    blob = synth.make_weights(synth.SMALL)
+    with pytest.raises(wskp.WskpError) as ei:
+        wskp.wskp_create(synth.SMALL, blob)
+    assert ei.value.status == -4

@@ -1,0 +1,154 @@
+"""GPU parity of the fused decode + fusion + remodulation kernel (Eq. 3-5)
+and of its hand-written adjoint, against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_05977_amd import synth
+from _helpers import rel_l2, max_rel, TOL_FP32
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _handle(kernel_sizes, act="softplus"):
+    from paper_2202_05977_amd import wskp
+    import dataclasses
+    cfg = dataclasses.replace(synth.SMALL, kernel_sizes=tuple(kernel_sizes), weight_act=act)
+    return wskp.wskp_create(cfg, synth.make_weights(cfg), "fp32")
+
+
+def _case(seed, N, H, W, M, spread=1.0):
+    rng = np.random.default_rng(seed)
+    head = synth.make_head(seed, N, H, W, M, spread)
+    c = rng.gamma(0.5, 2.0, size=(N, H, W, 3)).astype(np.float32)
+    mod = rng.uniform(0.05, 1.0, size=(N, H, W, 3)).astype(np.float32)
+    return head, c, mod
+
+
+def _gpu_decode(h, head, c, mod):
+    from paper_2202_05977_amd import wskp
+    d = lambda a: None if a is None else torch.from_numpy(a).cuda()
+    out = torch.empty(c.shape, dtype=torch.float32, device="cuda")
+    wskp.wskp_decode(h, d(head), d(c), d(mod), out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("ks,shape", [
+    ((3, 5, 7), (1, 8, 8)),
+    ((3, 5, 7), (2, 37, 53)),          # ragged: several tiles plus tails in x and y
+    ((3, 5, 7, 9, 11), (1, 45, 70)),
+    ((3, 5, 7, 9, 11), (1, 5, 3)),     # windows larger than the image
+    ((1, 3), (1, 17, 33)),
+    ((13, 15), (1, 40, 40)),
+])
+def test_decode_matches_oracle(ks, shape):
+    N, H, W = shape
+    h = _handle(ks)
+    head, c, mod = _case(sum(shape) + len(ks), N, H, W, len(ks))
+    y = _gpu_decode(h, head, c, mod)
+    for n in range(N):
+        ref = oracle.decode(head[n], c[n], mod[n], ks)
+        assert rel_l2(y[n], ref) <= TOL_FP32
+        assert max_rel(y[n], ref) <= TOL_FP32
+
+
+def test_decode_without_mod_and_invariants():
+    ks = (3, 5, 7, 9, 11)
+    h = _handle(ks)
+    head, c, _ = _case(5, 1, 33, 47, 5, spread=2.0)
+    y = _gpu_decode(h, head, c, None)
+    ref = oracle.decode(head[0], c[0], None, ks)
+    assert rel_l2(y[0], ref) <= TOL_FP32
+    # constant irradiance is preserved exactly up to rounding, borders included
+    cc = np.broadcast_to(np.array([0.5, 2.0, 7.0], np.float32), c.shape).copy()
+    y = _gpu_decode(h, head, cc, None)
+    np.testing.assert_allclose(y, cc, rtol=2e-6)
+    # all-zero weights hit the eps floor: output 0
+    hz = head.copy()
+    hz[..., :5] = 0.0
+    assert np.all(_gpu_decode(h, hz, c, None) == 0.0)
+
+
+def test_decode_k1_identity():
+    h = _handle((1,))
+    head, c, mod = _case(3, 1, 20, 24, 1)
+    y = _gpu_decode(h, head, c, mod)
+    np.testing.assert_allclose(y, c * mod, rtol=1e-6)
+
+
+def test_decode_repeatable_bitwise():
+    ks = (3, 5, 7, 9, 11)
+    h = _handle(ks)
+    head, c, mod = _case(8, 1, 96, 160, 5)
+    a = _gpu_decode(h, head, c, mod)
+    b = _gpu_decode(h, head, c, mod)
+    assert np.array_equal(a, b)
+
+
+def test_decode_720p_against_oracle():
+    """Full 1280x720 frame in the configuration the benchmark times."""
+    ks = synth.HD.kernel_sizes
+    h = _handle(ks)
+    head, c, mod = _case(1, 1, 720, 1280, len(ks))
+    y = _gpu_decode(h, head, c, mod)
+    ref = oracle.decode(head[0], c[0], mod[0], ks)
+    assert rel_l2(y[0], ref) <= TOL_FP32
+    assert max_rel(y[0], ref) <= TOL_FP32
+
+
+# ------------------------------------------------------------------ adjoint
+def _gpu_backward(h, head, c, mod, g):
+    from paper_2202_05977_amd import wskp
+    N, H, W, twoM = head.shape
+    d = lambda a: None if a is None else torch.from_numpy(a).cuda()
+    gh = torch.empty((N, H, W, twoM), dtype=torch.float32, device="cuda")
+    gc = torch.empty((N, H, W, 3), dtype=torch.float32, device="cuda")
+    ws = torch.empty(wskp.wskp_backward_workspace_size(h, N, H, W), dtype=torch.uint8,
+                     device="cuda")
+    wskp.wskp_backward(h, d(head), d(c), d(mod), d(g), gh, gc, ws)
+    torch.cuda.synchronize()
+    return gh.cpu().numpy(), gc.cpu().numpy()
+
+
+@pytest.mark.parametrize("shape", [(1, 16, 16), (2, 37, 45), (1, 64, 96)])
+def test_backward_matches_oracle_vjp(shape):
+    ks = (3, 5, 7, 9, 11)
+    N, H, W = shape
+    h = _handle(ks)
+    head, c, mod = _case(11 + H, N, H, W, 5)
+    g = np.random.default_rng(H).normal(size=(N, H, W, 3)).astype(np.float32)
+    gh, gc = _gpu_backward(h, head, c, mod, g)
+    for n in range(N):
+        rh, rc = oracle.decode_vjp(head[n], c[n], mod[n], ks, g[n])
+        assert rel_l2(gh[n, ..., :5], rh[..., :5]) <= TOL_FP32
+        assert rel_l2(gh[n, ..., 5:], rh[..., 5:]) <= TOL_FP32
+        assert rel_l2(gc[n], rc) <= TOL_FP32
+
+
+def test_autograd_function_l1_training_batch():
+    """8 crops of 256x256 with clean targets: the L1 cotangent
+    sign(y - t)/n (taken from the oracle's y) is pushed through the
+    autograd Function; gradients vs the oracle VJP."""
+    from paper_2202_05977_amd import wskp
+    ks = synth.HD.kernel_sizes
+    h = _handle(ks)
+    N, H, W = 8, 256, 256
+    fr = synth.make_frame_batch(range(2000, 2000 + N), H, W)
+    head, _, _ = _case(4, N, H, W, len(ks))
+    c = fr["radiance"] / (fr["albedo"] + np.float32(1e-3))
+    mod = fr["albedo"] + np.float32(1e-3)
+    g = np.empty_like(c)
+    for n in range(N):
+        yref = oracle.decode(head[n], c[n], mod[n], ks)
+        g[n] = oracle.l1(yref, fr["clean"][n])[1] / N
+    th = torch.from_numpy(head).cuda().requires_grad_(True)
+    tc = torch.from_numpy(c).cuda().requires_grad_(True)
+    y = wskp.WskpDecode.apply(h, th, tc, torch.from_numpy(mod).cuda())
+    torch.autograd.backward(y, grad_tensors=torch.from_numpy(g).cuda())
+    for n in (0, N - 1):
+        rh, rc = oracle.decode_vjp(head[n], c[n], mod[n], ks, g[n])
+        assert rel_l2(th.grad[n].cpu().numpy(), rh) <= TOL_FP32
+        assert rel_l2(tc.grad[n].cpu().numpy(), rc) <= TOL_FP32

@@ -1,0 +1,108 @@
+"""GPU parity of the whole per-frame path (prediction network on MFMA +
+fused decode) against the FP64 oracle, layer by layer and end to end."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2202_05977_amd import synth
+from _helpers import rel_l2, max_rel, to_dev, TOL_FP32, TOL_BF16
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _denoiser(cfg, prec):
+    from paper_2202_05977_amd import wskp
+    return wskp.Denoiser(cfg, synth.make_weights(cfg, 0), prec)
+
+
+def _run(dn, fr):
+    out = dn(to_dev(fr))
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+_ORACLE_CACHE = {}
+
+
+def _oracle(cfg_name, seed, H, W):
+    key = (cfg_name, seed, H, W)
+    if key not in _ORACLE_CACHE:
+        cfg = synth.CONFIGS[cfg_name]
+        fr = synth.make_frame(seed, H, W)
+        y, it = oracle.denoise(fr, synth.make_weights(cfg, 0), cfg, return_all=True)
+        _ORACLE_CACHE[key] = (fr, y, it)
+    return _ORACLE_CACHE[key]
+
+
+@pytest.mark.parametrize("shape", [(128, 128), (72, 104)])
+def test_small_fp32_layer_by_layer(shape):
+    H, W = shape
+    cfg = synth.SMALL
+    fr, y, it = _oracle("small", 1, H, W)
+    layers = oracle.unet_layers(it["X"], synth.make_weights(cfg, 0), cfg)
+    dn = _denoiser(cfg, "fp32")
+    out = _run(dn, fr)
+    L = cfg.levels
+    for l in range(L):
+        g = dn.intermediate([H], [W], 0, l).float().cpu().numpy()
+        assert rel_l2(g, layers[f"e{l}"]) <= TOL_FP32, f"e{l}"
+    for l in range(L - 1):
+        g = dn.intermediate([H], [W], 0, 100 + l).float().cpu().numpy()
+        assert rel_l2(g, layers[f"u{l}"]) <= TOL_FP32, f"u{l}"
+    head = dn.intermediate([H], [W], 0, 200).cpu().numpy()
+    assert rel_l2(head, it["head"]) <= TOL_FP32
+    assert rel_l2(out, y) <= TOL_FP32
+    assert max_rel(out, y) <= TOL_FP32
+
+
+def test_hd_fp32_720p_end_to_end():
+    fr, y, _ = _oracle("hd", 1, 720, 1280)
+    out = _run(_denoiser(synth.HD, "fp32"), fr)
+    assert np.all(np.isfinite(out))
+    assert rel_l2(out, y) <= TOL_FP32
+    assert max_rel(out, y) <= TOL_FP32
+
+
+def test_hd_bf16_720p_end_to_end():
+    fr, y, _ = _oracle("hd", 1, 720, 1280)
+    out = _run(_denoiser(synth.HD, "bf16"), fr)
+    err = rel_l2(out, y)
+    print(f"bf16 720p rel-L2 vs FP64 oracle: {err:.3e}, max-rel {max_rel(out, y):.3e}")
+    assert err <= TOL_BF16
+
+
+def test_small_bf16_ragged():
+    fr, y, _ = _oracle("small", 1, 72, 104)
+    out = _run(_denoiser(synth.SMALL, "bf16"), fr)
+    assert rel_l2(out, y) <= TOL_BF16
+
+
+def test_batch_mixed_sizes_equals_single_frames():
+    """Each frame alone == in a mixed-resolution batch == with tiles walked in
+    reverse (bitwise)."""
+    from paper_2202_05977_amd import wskp
+    cfg = synth.SMALL
+    dn = _denoiser(cfg, "fp32")
+    sizes = [(64, 64), (128, 96), (32, 160), (72, 104)]
+    frames = [to_dev(synth.make_frame(10 + i, H, W)) for i, (H, W) in enumerate(sizes)]
+    singles = []
+    for f in frames:
+        singles.append(dn(f).clone())
+    for flags in (0, wskp.BATCH_REVERSE_TILES):
+        for f in frames:
+            f["out"] = torch.full_like(f["radiance"], float("nan"))
+        dn.batch(frames, flags=flags)
+        torch.cuda.synchronize()
+        for f, s in zip(frames, singles):
+            assert torch.equal(f["out"], s)
+
+
+def test_shape_errors():
+    from paper_2202_05977_amd import wskp
+    dn = _denoiser(synth.HD, "fp32")
+    fr = to_dev(synth.make_frame(1, 36, 64))     # 36 is not a multiple of 8
+    with pytest.raises(wskp.WskpError) as ei:
+        dn(fr)
+    assert ei.value.status == -2
