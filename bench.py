@@ -118,6 +118,9 @@ def main():
                     help="first one is the headline value")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (no error or CPU figures)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="only run a plain device copy of MB megabytes 5 times (reference "
+                         "kernel for scaling HBM traffic counters) and exit")
     ap.add_argument("--height", type=int, default=720)
     ap.add_argument("--width", type=int, default=1280)
     args = ap.parse_args()
@@ -128,6 +131,16 @@ def main():
 
     import torch
     from paper_2202_05977_amd import synth, wskp  # noqa: F401
+
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 5}))
+        return
 
     H, W = args.height, args.width
     cfg = synth.HD

@@ -25,6 +25,8 @@
 //   Both accumulate in fp32.
 #include "wskp_internal.h"
 
+#include <type_traits>
+
 namespace wskp {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -95,48 +97,26 @@ __device__ __forceinline__ bool conv_locate(const ConvLayer &L, const FrameArg &
     return false;
 }
 
-// Four consecutive virtual input channels c..c+3 at pixel (gy, gx) of the
-// layer's resolution, produced by the fused input operation.
-template <int MODE, typename SrcT>
-__device__ __forceinline__ void fetch4(const ConvLayer &L, const FrameDesc &fd, const SrcT *s0,
-                                       const SrcT *s1, int gy, int gx, int Wl, int c, float v[4])
+// ---- fast transcendental helpers -------------------------------------------
+// v_exp_f32 / v_log_f32 compute 2^x and log2(x) to about 1 ulp for normal
+// inputs.  log1p uses the compensated form log(u) * t / (u - 1), u = 1 + t,
+// which removes the rounding of 1 + t (Goldberg's method), so the result keeps
+// full relative accuracy for small t.
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
+
+__device__ __forceinline__ float log1p_small(float t)
 {
-    if (MODE == CONV_PLAIN) {
-        Elem<SrcT>::load4(s0 + ((size_t)gy * Wl + gx) * L.C0 + c, v);
-    } else if (MODE == CONV_POOL) {
-        const int W0 = Wl * 2;
-        const SrcT *b = s0 + ((size_t)(2 * gy) * W0 + 2 * gx) * L.C0 + c;
-        float p0[4], p1[4], p2[4], p3[4];
-        Elem<SrcT>::load4(b, p0);
-        Elem<SrcT>::load4(b + L.C0, p1);
-        Elem<SrcT>::load4(b + (size_t)W0 * L.C0, p2);
-        Elem<SrcT>::load4(b + (size_t)W0 * L.C0 + L.C0, p3);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) v[j] = 0.25f * (p0[j] + p1[j] + p2[j] + p3[j]);
-    } else if (MODE == CONV_CAT) {
-        if (c < L.C0)
-            Elem<SrcT>::load4(s0 + ((size_t)(gy >> 1) * (Wl >> 1) + (gx >> 1)) * L.C0 + c, v);
-        else
-            Elem<SrcT>::load4(s1 + ((size_t)gy * Wl + gx) * L.C1 + (c - L.C0), v);
-    } else {  // CONV_PACK: [T(r) 3, a 3, (n+1)/2 3, depth 1, zero padding]
-        const size_t pix = (size_t)gy * Wl + gx;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int ch = c + j;
-            float x = 0.f;
-            if (ch < 3) {
-                const float r = fd.r[pix * 3 + ch];
-                x = powf(fminf(fmaxf(r, 0.f), 1.f), L.inv_gamma);
-            } else if (ch < 6) {
-                x = fd.a[pix * 3 + ch - 3];
-            } else if (ch < 9) {
-                x = (fd.n[pix * 3 + ch - 6] + 1.f) * 0.5f;
-            } else if (ch == 9) {
-                x = fminf(fmaxf((fd.d[pix] - L.dnear) * L.dinv, 0.f), 1.f);
-            }
-            v[j] = x;
-        }
-    }
+    const float u = 1.f + t;
+    if (u == 1.f) return t;
+    return fast_log2(u) * 0.69314718055994531f * (t / (u - 1.f));
+}
+
+// softplus(x) = max(x, 0) + log(1 + e^{-|x|})
+__device__ __forceinline__ float softplus_f(float x)
+{
+    const float t = fast_exp2(-fabsf(x) * 1.4426950408889634f);
+    return fmaxf(x, 0.f) + log1p_small(t);
 }
 
 template <int EPI>
@@ -145,7 +125,7 @@ __device__ __forceinline__ float epilogue(float v, int co, int M)
     if (EPI == EPI_RELU) return fmaxf(v, 0.f);
     if (co < M) {
         if (EPI == EPI_HEAD_EXP) return expf(v);
-        return fmaxf(v, 0.f) + log1pf(expf(-fabsf(v)));
+        return softplus_f(v);
     }
     return v;
 }
@@ -157,65 +137,240 @@ __device__ __forceinline__ OutT *conv_dst(const ConvLayer &L, const FrameDesc &f
     return reinterpret_cast<OutT *>(L.out_kind ? fd.u[L.out_idx] : fd.e[L.out_idx]);
 }
 
+__device__ __forceinline__ unsigned pack2(float a, float b)
+{
+    return (unsigned)f32_to_bf16(a) | ((unsigned)f32_to_bf16(b) << 16);
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) const u32x4 g_u32x4;
+// 16-byte load through a global-address-space pointer (a global_load
+// instead of a flat load).
+__device__ __forceinline__ uint4 gload16(const void *p)
+{
+    const u32x4 v = *(g_u32x4 *)(p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+// Network input of Sec. 5.1 at one pixel: [T(r) 3, a 3, (n+1)/2 3, depth 1],
+// T(x) = clamp(x,0,1)^(1/gamma) = 2^(log2(x)/gamma), depth scaled to [0,1]
+// and clamped.
+__device__ __forceinline__ void pack_input(const ConvLayer &L, const FrameDesc &fd, size_t pix,
+                                           float x[10])
+{
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        const float r = fminf(fmaxf(fd.r[pix * 3 + ch], 0.f), 1.f);
+        x[ch] = fast_exp2(fast_log2(r) * L.inv_gamma);
+        x[3 + ch] = fd.a[pix * 3 + ch];
+        x[6 + ch] = (fd.n[pix * 3 + ch] + 1.f) * 0.5f;
+    }
+    x[9] = fminf(fmaxf((fd.d[pix] - L.dnear) * L.dinv, 0.f), 1.f);
+}
+
 // =============================================================================
-// fp32 form
+// Staging of one reduction chunk: the (TH+2) x 34 input halo (virtual
+// channels [cc*CK, cc*CK+CK)) and the weight slice.  init() computes each
+// item's source offsets once; fetch() only issues global loads into
+// registers (and, for pooling, averages them); commit() writes the registers
+// to LDS.  The main loop fetches chunk cc+1 while the MFMAs of chunk cc run.
 // =============================================================================
-template <int TH, int CK, int NB>
-struct F32Geom {
+template <int PREC, int MODE, int CK, int TH, int NB, typename SrcT>
+struct Stage {
+    static constexpr bool BF = PREC != 0;
     static constexpr int TW = kConvTW, HP = TH + 2, WP = TW + 2;
-    static constexpr int PL = ((HP * WP - 16 + 31) / 32) * 32 + 16;  // plane stride = 16 mod 32
-    static constexpr int BS = NB * 16 + ((NB % 2 == 0) ? 16 : 0);     // weight row stride
-    static constexpr int MB = TH / 2;                                  // 16-px blocks per wave
+    // input items: a 16-byte run of one pixel's channels (PACK: one pixel)
+    static constexpr int G = (MODE == CONV_PACK) ? CK : 16 / (int)sizeof(SrcT);
+    static constexpr int NG = CK / G;
+    static constexpr int TOT = HP * WP * NG;
+    static constexpr int IT = (TOT + kThreads - 1) / kThreads;
+    static constexpr int RW = (MODE == CONV_PACK) ? (BF ? 2 : 3) : 1;   // 16-byte words per item
+    // LDS geometry
+    static constexpr int PL = ((HP * WP - 16 + 31) / 32) * 32 + 16;     // fp32 plane stride
+    static constexpr int PS = CK + 8;                                    // bf16 pixel stride
+    static constexpr int KE = 9 * CK;
+    static constexpr int NK = BF ? (KE + 31) / 32 : KE / 4;              // MFMAs per chunk
+    static constexpr int BS = NB * 16 + ((NB % 2 == 0) ? 16 : 0);        // fp32 weight row stride
+    static constexpr int BSK = NK * 32 + 8;                              // bf16 weight row stride
+    static constexpr int A_BYTES = (BF ? HP * WP * PS * 2 : CK * PL * 4);
+    static constexpr int B_BYTES = (BF ? NB * 16 * BSK * 2 : KE * BS * 4);
+    // weight items: 16 bytes of the packed chunk
+    static constexpr int WTOT = BF ? NB * 16 * (NK * 32 / 8) : KE * NB * 4;
+    static constexpr int WIT = (WTOT + kThreads - 1) / kThreads;
+    static constexpr int WCHUNK = BF ? NK * 32 : KE;   // per-chunk stride factor (x Cout_pad)
+
+    uint4 in[IT][RW];
+    uint4 w[WIT];
+    int off0[IT], off1[IT];   // element offsets of the item in source 0 / source 1
+    unsigned live;            // bit k: item k lies inside the image
+    int woff[WIT];            // element offset of weight item k in chunk 0
+
+    __device__ __forceinline__ void init(const ConvLayer &L, int g, int x0, int y0, int Hl, int Wl)
+    {
+        const int tid = threadIdx.x;
+        live = 0;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int it = tid + k * kThreads;
+            const int p = it / NG, cg = it - p * NG;
+            const int ly = p / WP, lx = p - ly * WP;
+            const int gy = y0 - 1 + ly, gx = x0 - 1 + lx;
+            off0[k] = off1[k] = 0;
+            if (it < TOT && gy >= 0 && gy < Hl && gx >= 0 && gx < Wl) {
+                live |= 1u << k;
+                if constexpr (MODE == CONV_PACK) {
+                    off0[k] = gy * Wl + gx;                                    // pixel index
+                } else if constexpr (MODE == CONV_PLAIN) {
+                    off0[k] = (gy * Wl + gx) * L.C0 + cg * G;
+                } else if constexpr (MODE == CONV_CAT) {
+                    off0[k] = ((gy >> 1) * (Wl >> 1) + (gx >> 1)) * L.C0 + cg * G;
+                    off1[k] = (gy * Wl + gx) * L.C1 + cg * G;
+                } else {  // POOL: top-left of the 2x2 window in the finer level
+                    off0[k] = ((2 * gy) * (2 * Wl) + 2 * gx) * L.C0 + cg * G;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < WIT; ++k) {
+            const int it = tid + k * kThreads;
+            woff[k] = 0;
+            if (it < WTOT) {
+                if constexpr (BF) {
+                    constexpr int KV = NK * 32 / 8;
+                    const int co = it / KV, q = it - co * KV;
+                    woff[k] = (g * NB * 16 + co) * (NK * 32) + q * 8;
+                } else {
+                    const int e = it / (NB * 4), q = it - e * (NB * 4);
+                    woff[k] = e * L.Cout_pad + g * NB * 16 + q * 4;
+                }
+            }
+        }
+    }
+
+    __device__ __forceinline__ void fetch(const ConvLayer &L, const FrameDesc &fd, const SrcT *s0,
+                                          const SrcT *s1, int cc, int Wl)
+    {
+        const int tid = threadIdx.x;
+        const int c0 = cc * CK;
+        // decoder input: the whole chunk comes from one source (CK divides C0)
+        const bool from_up = (MODE != CONV_CAT) || c0 < L.C0;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+#pragma unroll
+            for (int q = 0; q < RW; ++q) in[k][q] = make_uint4(0, 0, 0, 0);
+            if (!((live >> k) & 1u)) continue;
+            if constexpr (MODE == CONV_PACK) {
+                float x[10];
+                pack_input(L, fd, (size_t)off0[k], x);
+                if constexpr (BF) {
+                    in[k][0] = make_uint4(pack2(x[0], x[1]), pack2(x[2], x[3]), pack2(x[4], x[5]),
+                                          pack2(x[6], x[7]));
+                    in[k][1] = make_uint4(pack2(x[8], x[9]), 0, 0, 0);
+                } else {
+                    in[k][0] = make_uint4(__float_as_uint(x[0]), __float_as_uint(x[1]),
+                                          __float_as_uint(x[2]), __float_as_uint(x[3]));
+                    in[k][1] = make_uint4(__float_as_uint(x[4]), __float_as_uint(x[5]),
+                                          __float_as_uint(x[6]), __float_as_uint(x[7]));
+                    in[k][2] = make_uint4(__float_as_uint(x[8]), __float_as_uint(x[9]), 0, 0);
+                }
+            } else if constexpr (MODE == CONV_PLAIN) {
+                in[k][0] = gload16(s0 + off0[k] + c0);
+            } else if constexpr (MODE == CONV_CAT) {
+                in[k][0] = from_up ? gload16(s0 + off0[k] + c0) : gload16(s1 + off1[k] + (c0 - L.C0));
+            } else {  // CONV_POOL: 2x2 mean of the finer level
+                const SrcT *b = s0 + off0[k] + c0;
+                const size_t rs = (size_t)(2 * Wl) * L.C0;
+                const uint4 q0 = gload16(b);
+                const uint4 q1 = gload16(b + L.C0);
+                const uint4 q2 = gload16(b + rs);
+                const uint4 q3 = gload16(b + rs + L.C0);
+                if constexpr (BF) {
+                    const unsigned *a0 = &q0.x, *a1 = &q1.x, *a2 = &q2.x, *a3 = &q3.x;
+                    unsigned o[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const float lo = 0.25f * (bf16_to_f32(a0[j] & 0xffff) + bf16_to_f32(a1[j] & 0xffff) +
+                                                  bf16_to_f32(a2[j] & 0xffff) + bf16_to_f32(a3[j] & 0xffff));
+                        const float hi = 0.25f * (bf16_to_f32(a0[j] >> 16) + bf16_to_f32(a1[j] >> 16) +
+                                                  bf16_to_f32(a2[j] >> 16) + bf16_to_f32(a3[j] >> 16));
+                        o[j] = pack2(lo, hi);
+                    }
+                    in[k][0] = make_uint4(o[0], o[1], o[2], o[3]);
+                } else {
+                    const float *f0 = reinterpret_cast<const float *>(&q0), *f1 = reinterpret_cast<const float *>(&q1);
+                    const float *f2 = reinterpret_cast<const float *>(&q2), *f3 = reinterpret_cast<const float *>(&q3);
+                    float o[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) o[j] = 0.25f * (f0[j] + f1[j] + f2[j] + f3[j]);
+                    in[k][0] = make_uint4(__float_as_uint(o[0]), __float_as_uint(o[1]),
+                                          __float_as_uint(o[2]), __float_as_uint(o[3]));
+                }
+            }
+        }
+        // weight slice of this chunk
+        using WT = typename std::conditional<BF, unsigned short, float>::type;
+        const WT *wsrc = reinterpret_cast<const WT *>(L.w) + (size_t)cc * WCHUNK * L.Cout_pad;
+#pragma unroll
+        for (int k = 0; k < WIT; ++k)
+            if (tid + k * kThreads < WTOT) w[k] = gload16(wsrc + woff[k]);
+    }
+
+    __device__ __forceinline__ void commit(void *As_, void *Bs_) const
+    {
+        const int tid = threadIdx.x;
+#pragma unroll
+        for (int k = 0; k < IT; ++k) {
+            const int it = tid + k * kThreads;
+            if (it >= TOT) continue;
+            const int p = it / NG, cg = it - p * NG;
+            if constexpr (BF) {
+                unsigned short *As = static_cast<unsigned short *>(As_);
+#pragma unroll
+                for (int q = 0; q < RW; ++q)
+                    *reinterpret_cast<uint4 *>(&As[p * PS + cg * G + q * 8]) = in[k][q];
+            } else {
+                float *As = static_cast<float *>(As_);
+#pragma unroll
+                for (int q = 0; q < RW; ++q) {
+                    const unsigned *v = &in[k][q].x;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int ch = cg * G + q * 4 + j;
+                        if (ch < CK) As[ch * PL + p] = __uint_as_float(v[j]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < WIT; ++k) {
+            const int it = tid + k * kThreads;
+            if (it >= WTOT) continue;
+            if constexpr (BF) {
+                constexpr int KV = NK * 32 / 8;
+                const int co = it / KV, q = it - co * KV;
+                *reinterpret_cast<uint4 *>(static_cast<unsigned short *>(Bs_) + co * BSK + q * 8) = w[k];
+            } else {
+                const int e = it / (NB * 4), q = it - e * (NB * 4);
+                *reinterpret_cast<uint4 *>(static_cast<float *>(Bs_) + e * BS + q * 4) = w[k];
+            }
+        }
+    }
 };
 
-template <int MODE, int EPI, int TH, int CK, int NB, typename SrcT, typename OutT>
-__global__ __launch_bounds__(kThreads) void conv3x3_f32_kernel(ConvLayer L, FrameArg fa)
+// One chunk's MFMAs.  fp32: 9*CK/4 steps of v_mfma_f32_16x16x4f32 (K order
+// tap, channel); bf16: NK steps of v_mfma_f32_16x16x32_bf16, each covering
+// 32 consecutive K values as 4 runs of 8 channels (a run never crosses a tap
+// because CK is a multiple of 8; for CK = 16 one MFMA spans two taps).
+template <int PREC, int MODE, int CK, int TH, int NB, typename SrcT>
+__device__ __forceinline__ void chunk_mfma(const void *As_, const void *Bs_, f32x4 (*acc)[NB])
 {
-    using G = F32Geom<TH, CK, NB>;
-    __shared__ float As[CK * G::PL];
-    __shared__ float Bs[9 * CK * G::BS];
-
-    int f, g, x0, y0, Hl, Wl;
-    if (!conv_locate<TH>(L, fa, f, g, x0, y0, Hl, Wl)) return;
-    const FrameDesc &fd = frame_at(fa, f);
-    const SrcT *s0 = reinterpret_cast<const SrcT *>(L.src0_kind ? fd.u[L.src0_idx] : fd.e[L.src0_idx]);
-    const SrcT *s1 = reinterpret_cast<const SrcT *>(fd.e[L.src1_idx]);
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int lj = lane & 15, lk = lane >> 4;
-
-    f32x4 acc[G::MB][NB];
-#pragma unroll
-    for (int i = 0; i < G::MB; ++i)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[i][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    const int nchunks = L.Cin_pad / CK;
-    for (int cc = 0; cc < nchunks; ++cc) {
-        if (cc) __syncthreads();
-        // input halo of this chunk -> channel planes
-        constexpr int NG = CK / 4;
-        for (int it = tid; it < G::HP * G::WP * NG; it += kThreads) {
-            const int p = it / NG, cg = it - p * NG;
-            const int ly = p / G::WP, lx = p - ly * G::WP;
-            const int gy = y0 - 1 + ly, gx = x0 - 1 + lx;
-            float v[4] = {0.f, 0.f, 0.f, 0.f};
-            if (gy >= 0 && gy < Hl && gx >= 0 && gx < Wl)
-                fetch4<MODE, SrcT>(L, fd, s0, s1, gy, gx, Wl, cc * CK + cg * 4, v);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) As[(cg * 4 + j) * G::PL + p] = v[j];
-        }
-        // weight slice [9*CK][16*NB]
-        const float *wsrc = reinterpret_cast<const float *>(L.w) +
-                            (size_t)cc * 9 * CK * L.Cout_pad + g * NB * 16;
-        for (int it = tid; it < 9 * CK * NB * 4; it += kThreads) {
-            const int e = it / (NB * 4), q = it - e * (NB * 4);
-            const float4 v = *reinterpret_cast<const float4 *>(wsrc + (size_t)e * L.Cout_pad + q * 4);
-            float *d = &Bs[e * G::BS + q * 4];
-            d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
-        }
-        __syncthreads();
-
+    using S = Stage<PREC, MODE, CK, TH, NB, SrcT>;
+    constexpr int MB = TH / 2;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lj = lane & 15, lq = lane >> 4;
+    if constexpr (PREC == 0) {
+        const float *As = static_cast<const float *>(As_);
+        const float *Bs = static_cast<const float *>(Bs_);
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int dy = tap / 3, dx = tap % 3;
@@ -223,131 +378,35 @@ __global__ __launch_bounds__(kThreads) void conv3x3_f32_kernel(ConvLayer L, Fram
             for (int c4 = 0; c4 < CK / 4; ++c4) {
                 float b[NB];
 #pragma unroll
-                for (int nb = 0; nb < NB; ++nb)
-                    b[nb] = Bs[(tap * CK + c4 * 4 + lk) * G::BS + nb * 16 + lj];
+                for (int nb = 0; nb < NB; ++nb) b[nb] = Bs[(tap * CK + c4 * 4 + lq) * S::BS + nb * 16 + lj];
 #pragma unroll
-                for (int i = 0; i < G::MB; ++i) {
-                    const int blk = wave * G::MB + i, row = blk >> 1, cb = blk & 1;
-                    const float a = As[(c4 * 4 + lk) * G::PL + (row + dy) * G::WP + cb * 16 + lj + dx];
+                for (int i = 0; i < MB; ++i) {
+                    const int blk = wave * MB + i, row = blk >> 1, cb = blk & 1;
+                    const float a = As[(c4 * 4 + lq) * S::PL + (row + dy) * S::WP + cb * 16 + lj + dx];
 #pragma unroll
                     for (int nb = 0; nb < NB; ++nb)
                         acc[i][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[nb], acc[i][nb], 0, 0, 0);
                 }
             }
         }
-    }
-
-    // epilogue: lane holds channel lj of pixels 4*lk + v of each 16-px block
-    OutT *dst = conv_dst<OutT>(L, fd);
+    } else {
+        const unsigned short *As = static_cast<const unsigned short *>(As_);
+        const unsigned short *Bs = static_cast<const unsigned short *>(Bs_);
 #pragma unroll
-    for (int i = 0; i < G::MB; ++i) {
-        const int blk = wave * G::MB + i, row = blk >> 1, cb = blk & 1;
-        const int y = y0 + row;
-        if (y >= Hl) continue;
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const int co = g * NB * 16 + nb * 16 + lj;
-            if (co >= L.Cout) continue;
-            const float bias = L.bias[co];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int x = x0 + cb * 16 + lk * 4 + v;
-                if (x >= Wl) continue;
-                const float val = epilogue<EPI>(acc[i][nb][v] + bias, co, L.M);
-                Elem<OutT>::store(dst + ((size_t)y * Wl + x) * L.Cout + co, val);
-            }
-        }
-    }
-}
-
-// =============================================================================
-// bf16 form
-// =============================================================================
-// LDS input: pixel-major rows of CK bf16 channels plus 8 padding channels,
-// so the byte stride of a pixel is 2*(CK+8): for CK = 32 that is 80 bytes,
-// which spreads the 16-byte fragment reads of 8 consecutive pixels over all
-// banks.  A fragment for 16x16x32: lane (i = l%16, q = l/16) holds 8
-// consecutive K values; the K order inside a chunk is (tap, channel) with the
-// channel fastest, and each MFMA covers 32 consecutive K values: 4 runs of 8
-// channels.  For CK = 16 (the 10-channel network input padded) one MFMA
-// spans two taps.
-template <int TH, int CK, int NB>
-struct BF16Geom {
-    static constexpr int TW = kConvTW, HP = TH + 2, WP = TW + 2;
-    static constexpr int PS = CK + 8;                 // pixel stride (bf16 elements)
-    static constexpr int KE = 9 * CK;                 // K values per chunk
-    static constexpr int NK = (KE + 31) / 32;         // MFMAs per chunk (K padded)
-    static constexpr int BSK = NK * 32 + 8;           // weight: per output channel, K run + pad
-    static constexpr int MB = TH / 2;
-};
-
-template <int MODE, int EPI, int TH, int CK, int NB, typename SrcT, typename OutT>
-__global__ __launch_bounds__(kThreads) void conv3x3_bf16_kernel(ConvLayer L, FrameArg fa)
-{
-    using G = BF16Geom<TH, CK, NB>;
-    __shared__ __attribute__((aligned(16))) unsigned short As[G::HP * G::WP * G::PS];
-    __shared__ __attribute__((aligned(16))) unsigned short Bs[NB * 16 * G::BSK];
-
-    int f, g, x0, y0, Hl, Wl;
-    if (!conv_locate<TH>(L, fa, f, g, x0, y0, Hl, Wl)) return;
-    const FrameDesc &fd = frame_at(fa, f);
-    const SrcT *s0 = reinterpret_cast<const SrcT *>(L.src0_kind ? fd.u[L.src0_idx] : fd.e[L.src0_idx]);
-    const SrcT *s1 = reinterpret_cast<const SrcT *>(fd.e[L.src1_idx]);
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int lj = lane & 15, lq = lane >> 4;
-
-    f32x4 acc[G::MB][NB];
-#pragma unroll
-    for (int i = 0; i < G::MB; ++i)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) acc[i][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    const int nchunks = L.Cin_pad / CK;
-    for (int cc = 0; cc < nchunks; ++cc) {
-        if (cc) __syncthreads();
-        constexpr int NG = CK / 4;
-        for (int it = tid; it < G::HP * G::WP * NG; it += kThreads) {
-            const int p = it / NG, cg = it - p * NG;
-            const int ly = p / G::WP, lx = p - ly * G::WP;
-            const int gy = y0 - 1 + ly, gx = x0 - 1 + lx;
-            float v[4] = {0.f, 0.f, 0.f, 0.f};
-            if (gy >= 0 && gy < Hl && gx >= 0 && gx < Wl)
-                fetch4<MODE, SrcT>(L, fd, s0, s1, gy, gx, Wl, cc * CK + cg * 4, v);
-            uint2 pk;
-            pk.x = (unsigned)f32_to_bf16(v[0]) | ((unsigned)f32_to_bf16(v[1]) << 16);
-            pk.y = (unsigned)f32_to_bf16(v[2]) | ((unsigned)f32_to_bf16(v[3]) << 16);
-            *reinterpret_cast<uint2 *>(&As[p * G::PS + cg * 4]) = pk;
-        }
-        // weights: packed per chunk as [Cout_pad][NK*32] bf16 (K fastest)
-        const unsigned short *wsrc = reinterpret_cast<const unsigned short *>(L.w) +
-                                     ((size_t)cc * L.Cout_pad + g * NB * 16) * (G::NK * 32);
-        constexpr int KV = G::NK * 32 / 8;  // 16-byte vectors per channel row
-        for (int it = tid; it < NB * 16 * KV; it += kThreads) {
-            const int co = it / KV, q = it - co * KV;
-            const uint4 v = *reinterpret_cast<const uint4 *>(wsrc + (size_t)co * (G::NK * 32) + q * 8);
-            *reinterpret_cast<uint4 *>(&Bs[co * G::BSK + q * 8]) = v;
-        }
-        __syncthreads();
-
-#pragma unroll
-        for (int s = 0; s < G::NK; ++s) {
-            // this lane's run of 8 K values: k = s*32 + lq*8 .. +7 -> (tap, c0)
+        for (int s = 0; s < S::NK; ++s) {
             const int k0 = s * 32 + lq * 8;
             const int tap = k0 / CK, c0 = k0 - tap * CK;
             const bool live = tap < 9;
             const int dy = live ? tap / 3 : 0, dx = live ? tap % 3 : 0;
             bf16x8 b[NB];
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb) {
-                const u16x8 q = *reinterpret_cast<const u16x8 *>(&Bs[(nb * 16 + lj) * G::BSK + k0]);
-                b[nb] = __builtin_bit_cast(bf16x8, q);
-            }
+            for (int nb = 0; nb < NB; ++nb)
+                b[nb] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(&Bs[(nb * 16 + lj) * S::BSK + k0]));
 #pragma unroll
-            for (int i = 0; i < G::MB; ++i) {
-                const int blk = wave * G::MB + i, row = blk >> 1, cb = blk & 1;
-                const int p = (row + dy) * G::WP + cb * 16 + lj + dx;
-                u16x8 q = *reinterpret_cast<const u16x8 *>(&As[p * G::PS + (live ? c0 : 0)]);
+            for (int i = 0; i < MB; ++i) {
+                const int blk = wave * MB + i, row = blk >> 1, cb = blk & 1;
+                const int p = (row + dy) * S::WP + cb * 16 + lj + dx;
+                u16x8 q = *reinterpret_cast<const u16x8 *>(&As[p * S::PS + (live ? c0 : 0)]);
                 if (!live) q = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
                 const bf16x8 a = __builtin_bit_cast(bf16x8, q);
 #pragma unroll
@@ -356,24 +415,95 @@ __global__ __launch_bounds__(kThreads) void conv3x3_bf16_kernel(ConvLayer L, Fra
             }
         }
     }
+}
 
-    OutT *dst = conv_dst<OutT>(L, fd);
+template <int PREC, int MODE, int EPI, int TH, int CK, int NB, typename SrcT, typename OutT>
+#ifndef WSKP_CONV_MIN_WG
+#define WSKP_CONV_MIN_WG 1
+#endif
+__global__ __launch_bounds__(kThreads, WSKP_CONV_MIN_WG) void conv3x3_kernel(ConvLayer L, FrameArg fa)
+{
+    using S = Stage<PREC, MODE, CK, TH, NB, SrcT>;
+    constexpr int MB = TH / 2;
+    constexpr int NC = NB * 16;                 // output channels of this workgroup
+    constexpr int OS = NC + 1;                  // LDS row stride of the output tile (floats)
+    constexpr int OUT_BYTES = TH * kConvTW * OS * 4;
+    constexpr int LDS_BYTES = (S::A_BYTES + S::B_BYTES > OUT_BYTES) ? S::A_BYTES + S::B_BYTES : OUT_BYTES;
+    __shared__ __attribute__((aligned(16))) unsigned char smem[LDS_BYTES];
+    void *As = smem;
+    void *Bs = smem + S::A_BYTES;
+
+    int f, g, x0, y0, Hl, Wl;
+    if (!conv_locate<TH>(L, fa, f, g, x0, y0, Hl, Wl)) return;
+    const FrameDesc &fd = frame_at(fa, f);
+    const SrcT *s0 = reinterpret_cast<const SrcT *>(L.src0_kind ? fd.u[L.src0_idx] : fd.e[L.src0_idx]);
+    const SrcT *s1 = reinterpret_cast<const SrcT *>(fd.e[L.src1_idx]);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lj = lane & 15, lq = lane >> 4;
+
+    f32x4 acc[MB][NB];
 #pragma unroll
-    for (int i = 0; i < G::MB; ++i) {
-        const int blk = wave * G::MB + i, row = blk >> 1, cb = blk & 1;
-        const int y = y0 + row;
-        if (y >= Hl) continue;
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[i][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    S st;
+    st.init(L, g, x0, y0, Hl, Wl);
+    const int nchunks = L.Cin_pad / CK;
+    st.fetch(L, fd, s0, s1, 0, Wl);
+    for (int cc = 0; cc < nchunks; ++cc) {
+        if (cc) __syncthreads();
+        st.commit(As, Bs);
+        __syncthreads();
+        if (cc + 1 < nchunks) st.fetch(L, fd, s0, s1, cc + 1, Wl);
+        chunk_mfma<PREC, MODE, CK, TH, NB, SrcT>(As, Bs, acc);
+    }
+
+    // epilogue, phase 1: bias + activation into an LDS tile [TH*32][NC]
+    // (lane holds channel lj of pixels 4*lq + v of each 16-px block)
+    __syncthreads();
+    float *Ot = reinterpret_cast<float *>(smem);
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        const int blk = wave * MB + i, row = blk >> 1, cb = blk & 1;
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            const int co = g * NB * 16 + nb * 16 + lj;
-            if (co >= L.Cout) continue;
-            const float bias = L.bias[co];
+            const int cl = nb * 16 + lj, co = g * NC + cl;
+            const float bias = co < L.Cout ? L.bias[co] : 0.f;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int x = x0 + cb * 16 + lq * 4 + v;
-                if (x >= Wl) continue;
-                const float val = epilogue<EPI>(acc[i][nb][v] + bias, co, L.M);
-                Elem<OutT>::store(dst + ((size_t)y * Wl + x) * L.Cout + co, val);
+                const int px = row * kConvTW + cb * 16 + lq * 4 + v;
+                Ot[px * OS + cl] = epilogue<EPI>(acc[i][nb][v] + bias, co, L.M);
+            }
+        }
+    }
+    __syncthreads();
+    // phase 2: coalesced stores of runs of V channels per pixel
+    OutT *dst = conv_dst<OutT>(L, fd);
+    const int ncw = min(NC, L.Cout - g * NC);      // channels this workgroup writes
+    if constexpr (std::is_same<OutT, float>::value) {
+        // fp32 (head record): float2 runs (channel counts are even)
+        const int nv = ncw >> 1;
+        for (int it = tid; it < TH * kConvTW * nv; it += kThreads) {
+            const int px = it / nv, c2 = (it - px * nv) * 2;
+            const int y = y0 + px / kConvTW, x = x0 + px % kConvTW;
+            if (y < Hl && x < Wl) {
+                float2 v = make_float2(Ot[px * OS + c2], Ot[px * OS + c2 + 1]);
+                *reinterpret_cast<float2 *>(dst + ((size_t)y * Wl + x) * L.Cout + g * NC + c2) = v;
+            }
+        }
+    } else {
+        // bf16: runs of 4 channels (8 bytes)
+        const int nv = ncw >> 2;
+        for (int it = tid; it < TH * kConvTW * nv; it += kThreads) {
+            const int px = it / nv, c4 = (it - px * nv) * 4;
+            const int y = y0 + px / kConvTW, x = x0 + px % kConvTW;
+            if (y < Hl && x < Wl) {
+                const float *o = &Ot[px * OS + c4];
+                uint2 v;
+                v.x = pack2(o[0], o[1]);
+                v.y = pack2(o[2], o[3]);
+                *reinterpret_cast<uint2 *>(dst + ((size_t)y * Wl + x) * L.Cout + g * NC + c4) = v;
             }
         }
     }
@@ -382,7 +512,12 @@ __global__ __launch_bounds__(kThreads) void conv3x3_bf16_kernel(ConvLayer L, Fra
 // =============================================================================
 // dispatch
 // =============================================================================
-constexpr int kTH = 8;
+// Output rows per conv tile and the minimum number of workgroups per CU the
+// register allocation must allow (build-time tuning knobs).
+#ifndef WSKP_CONV_TH
+#define WSKP_CONV_TH 8
+#endif
+constexpr int kTH = WSKP_CONV_TH;
 int conv_tile_rows(int) { return kTH; }
 
 int conv_chunk(int prec, int mode, int Cin, int C0)
@@ -402,69 +537,60 @@ int conv_grid(const ConvLayer &L, int n, const int *H, const int *W)
     return (int)total;
 }
 
-template <int MODE, int EPI, int CK, int NB, typename SrcT, typename OutT>
-static void launch_one(int prec, const ConvLayer &L, const FrameArg &fa, int blocks, hipStream_t s)
+template <int PREC, int MODE, int EPI, int CK, int NB, typename OutT>
+static void launch_one(const ConvLayer &L, const FrameArg &fa, int blocks, hipStream_t s)
 {
-    if (prec == 0)
-        hipLaunchKernelGGL((conv3x3_f32_kernel<MODE, EPI, kTH, CK, NB, SrcT, OutT>), dim3(blocks),
-                           dim3(kThreads), 0, s, L, fa);
-    else
-        hipLaunchKernelGGL((conv3x3_bf16_kernel<MODE, EPI, kTH, CK, NB, SrcT, OutT>), dim3(blocks),
-                           dim3(kThreads), 0, s, L, fa);
+    // fp32 activations travel with the fp32 MFMA form, bf16 with the bf16 form
+    using SrcT = typename std::conditional<PREC == 0, float, unsigned short>::type;
+    hipLaunchKernelGGL((conv3x3_kernel<PREC, MODE, EPI, kTH, CK, NB, SrcT, OutT>), dim3(blocks),
+                       dim3(kThreads), 0, s, L, fa);
 }
 
-template <int MODE, int EPI, typename SrcT, typename OutT>
-static bool launch_ck_nb(int prec, const ConvLayer &L, const FrameArg &fa, int blocks, hipStream_t s)
+// Chunk sizes: fp32 uses CK = 12 (network input) or 16; bf16 uses 16 (input
+// padded from 10) or 32 where the channel counts allow it.
+template <int PREC, int MODE, int EPI, typename OutT>
+static bool launch_ck_nb(const ConvLayer &L, const FrameArg &fa, int blocks, hipStream_t s)
 {
 #define WSKP_CASE(ck, nb)                                                   \
     if (L.CK == ck && L.NB == nb) {                                         \
-        launch_one<MODE, EPI, ck, nb, SrcT, OutT>(prec, L, fa, blocks, s); \
+        launch_one<PREC, MODE, EPI, ck, nb, OutT>(L, fa, blocks, s);       \
         return true;                                                        \
     }
-    if (MODE == CONV_PACK) {
-        if (prec == 0) { WSKP_CASE(12, 1) WSKP_CASE(12, 2) }
+    if constexpr (MODE == CONV_PACK) {
+        if constexpr (PREC == 0) { WSKP_CASE(12, 1) WSKP_CASE(12, 2) }
         else { WSKP_CASE(16, 1) WSKP_CASE(16, 2) }
-        return false;
+    } else {
+        WSKP_CASE(16, 1)
+        WSKP_CASE(16, 2)
+        if constexpr (PREC != 0) { WSKP_CASE(32, 1) WSKP_CASE(32, 2) }
     }
-    WSKP_CASE(16, 1)
-    WSKP_CASE(16, 2)
-    if (prec != 0) { WSKP_CASE(32, 1) WSKP_CASE(32, 2) }
 #undef WSKP_CASE
     return false;
 }
 
-template <typename SrcT, typename OutT>
-static bool dispatch_typed(const ConvLayer &L, int mode, int prec, const FrameArg &fa, int blocks,
-                           hipStream_t s)
+template <int PREC>
+static bool dispatch(const ConvLayer &L, int mode, int epi, const FrameArg &fa, int blocks,
+                     hipStream_t s)
 {
+    using ActT = typename std::conditional<PREC == 0, float, unsigned short>::type;
     switch (mode) {
-    case CONV_PACK: return launch_ck_nb<CONV_PACK, EPI_RELU, SrcT, OutT>(prec, L, fa, blocks, s);
-    case CONV_POOL: return launch_ck_nb<CONV_POOL, EPI_RELU, SrcT, OutT>(prec, L, fa, blocks, s);
-    case CONV_CAT: return launch_ck_nb<CONV_CAT, EPI_RELU, SrcT, OutT>(prec, L, fa, blocks, s);
+    case CONV_PACK: return launch_ck_nb<PREC, CONV_PACK, EPI_RELU, ActT>(L, fa, blocks, s);
+    case CONV_POOL: return launch_ck_nb<PREC, CONV_POOL, EPI_RELU, ActT>(L, fa, blocks, s);
+    case CONV_CAT: return launch_ck_nb<PREC, CONV_CAT, EPI_RELU, ActT>(L, fa, blocks, s);
+    case CONV_PLAIN:
+        // the head record is fp32 in every precision
+        if (epi == EPI_HEAD_EXP) return launch_ck_nb<PREC, CONV_PLAIN, EPI_HEAD_EXP, float>(L, fa, blocks, s);
+        return launch_ck_nb<PREC, CONV_PLAIN, EPI_HEAD_SOFTPLUS, float>(L, fa, blocks, s);
     default: return false;
     }
-}
-
-template <typename SrcT>
-static bool dispatch_head(const ConvLayer &L, int epi, int prec, const FrameArg &fa, int blocks,
-                          hipStream_t s)
-{
-    if (epi == EPI_HEAD_EXP)
-        return launch_ck_nb<CONV_PLAIN, EPI_HEAD_EXP, SrcT, float>(prec, L, fa, blocks, s);
-    return launch_ck_nb<CONV_PLAIN, EPI_HEAD_SOFTPLUS, SrcT, float>(prec, L, fa, blocks, s);
 }
 
 hipError_t launch_conv(const ConvLayer &L, int mode, int epi, int prec, const FrameArg &fa,
                        int blocks, hipStream_t s)
 {
     if (blocks <= 0) return hipSuccess;
-    bool ok;
-    if (prec == 0)
-        ok = mode == CONV_PLAIN ? dispatch_head<float>(L, epi, prec, fa, blocks, s)
-                                : dispatch_typed<float, float>(L, mode, prec, fa, blocks, s);
-    else
-        ok = mode == CONV_PLAIN ? dispatch_head<unsigned short>(L, epi, prec, fa, blocks, s)
-                                : dispatch_typed<unsigned short, unsigned short>(L, mode, prec, fa, blocks, s);
+    const bool ok = prec == 0 ? dispatch<0>(L, mode, epi, fa, blocks, s)
+                              : dispatch<1>(L, mode, epi, fa, blocks, s);
     if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();
 }

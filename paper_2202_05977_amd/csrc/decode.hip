@@ -6,12 +6,14 @@
 // sum, so every filtered value is a ratio of two box sums:
 //     out_i(p) = sum_{q in Omega_i(p)} W_i(q) c(q) / max(sum_{q in Omega_i(p)} W_i(q), eps)
 // with windows truncated at the image border.  No k x k kernel map is ever
-// formed.  Each workgroup owns a 32 x 16 tile of centres; it stages the
-// (32+2R) x (16+2R) halo of all M weight maps and of the irradiance c once in
-// LDS (R = largest radius), then for each kernel size runs a horizontal pass
-// (row sums of W and W*c, 4 values per position) into LDS and a vertical
-// pass over those, and accumulates softmax(logits)_i * out_i in registers.
-// The last step multiplies by the remodulation factor.
+// formed.  Each workgroup owns a 32 x 16 tile of centres.  It stages the
+// irradiance of the (32+2R) x (16+2R) halo once in LDS (R = largest radius).
+// Then, for each kernel size, it builds a plane of (W_i, W_i c) over the
+// halo (the next size's weights are already being fetched), runs a
+// horizontal pass of row sums into LDS and a vertical pass over those, each
+// thread summing a run of neighbouring outputs in registers, and
+// accumulates softmax(logits)_i * out_i in registers.  The last step
+// multiplies by the remodulation factor.
 //
 // Two input forms share the kernel:
 //   frames   c = r / (a + eps_a) is formed while staging; mod = a + eps_a;
@@ -103,8 +105,122 @@ __device__ __forceinline__ bool decode_locate(const DecodeCfg &dc, const FrameAr
 
 enum DecodeKind { DK_FRAMES = 0, DK_TENSORS = 1, DK_ADJ_A = 2 };
 
-// Dynamic LDS (floats): W planes [M][HY*HX], c planes [3][HY*HX],
-// row sums [4][HY*32].
+__device__ __forceinline__ float4 f4add(float4 a, float4 b)
+{
+    return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+}
+
+// Window sums of K consecutive values for N consecutive window starts:
+//   s[t] = v[t] + ... + v[t+K-1],  t = 0..N-1,
+// with additions only (no running sum with subtraction, so a large value
+// leaving the window cannot cancel the small ones that remain).  For K >= N
+// the part v[N-1..K-1] is common to all N windows and is summed once; each
+// window adds a suffix of the run's head and a prefix of its tail.
+template <int K, int N>
+__device__ __forceinline__ void box_run(const float4 *v, float4 *s)
+{
+    if constexpr (K < N || K <= 3) {
+#pragma unroll
+        for (int t = 0; t < N; ++t) {
+            float4 a = v[t];
+#pragma unroll
+            for (int j = 1; j < K; ++j) a = f4add(a, v[t + j]);
+            s[t] = a;
+        }
+    } else {
+        float4 C = v[N - 1];
+#pragma unroll
+        for (int j = N; j < K; ++j) C = f4add(C, v[j]);
+        float4 L[N], Rt[N];
+        L[N - 1] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if constexpr (N >= 2) L[N - 2] = v[N - 2];
+#pragma unroll
+        for (int t = N - 3; t >= 0; --t) L[t] = f4add(v[t], L[t + 1]);
+        Rt[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if constexpr (N >= 2) Rt[1] = v[K];
+#pragma unroll
+        for (int t = 2; t < N; ++t) Rt[t] = f4add(Rt[t - 1], v[K + t - 1]);
+        s[0] = (N >= 2) ? f4add(L[0], C) : C;
+#pragma unroll
+        for (int t = 1; t < N - 1; ++t) s[t] = f4add(f4add(L[t], C), Rt[t]);
+        if constexpr (N >= 2) s[N - 1] = f4add(C, Rt[N - 1]);
+    }
+}
+
+// Tile geometry: 32 x kDTY centres per workgroup; a thread owns a column
+// tx and a run of kRun = kDTY/8 rows (kRun*ty .. kRun*ty+kRun-1); the
+// horizontal pass gives each thread runs of kHRun columns.
+constexpr int kRun = kDTY / 8;
+constexpr int kHRun = 4;
+constexpr int kMaxPix = 6;   // halo pixels per thread: (32+14)*(16+14) <= 6*256
+
+__device__ __forceinline__ float4 f4scale(float w, float4 c)
+{
+    return make_float4(w, w * c.x, w * c.y, w * c.z);
+}
+
+// Horizontal then vertical window sums of a float4 plane st [HY][HX] for
+// kernel size K: returns in acc[t] the K x K window sums of the 4 components
+// for this thread's kRun centres.  hb holds the row sums [HY][32].
+template <int K>
+__device__ __forceinline__ void window_sums4(int R, int HX, const float4 *st, float4 *hb,
+                                             float4 *acc)
+{
+    constexpr int r = K / 2;
+    const int tid = threadIdx.x;
+    const int nrows = kDTY + 2 * r;
+    constexpr int RPR = 32 / kHRun;
+    for (int it = tid; it < nrows * RPR; it += kThreads) {
+        const int hy = R - r + it / RPR, xr = (it % RPR) * kHRun;
+        const int base = hy * HX + xr + R - r;
+        float4 v[K + kHRun - 1];
+#pragma unroll
+        for (int j = 0; j < K + kHRun - 1; ++j) v[j] = st[base + j];
+        float4 s[kHRun];
+        box_run<K, kHRun>(v, s);
+#pragma unroll
+        for (int t = 0; t < kHRun; ++t) hb[hy * 32 + xr + t] = s[t];
+    }
+    __syncthreads();
+    const int tx = tid & 31, ty = tid >> 5;
+    float4 v[K + kRun - 1];
+#pragma unroll
+    for (int j = 0; j < K + kRun - 1; ++j) v[j] = hb[(kRun * ty + R - r + j) * 32 + tx];
+    box_run<K, kRun>(v, acc);
+    __syncthreads();
+}
+
+#define WSKP_SWITCH_K(k, CALL)      \
+    switch (k) {                    \
+    case 1: CALL(1); break;         \
+    case 3: CALL(3); break;         \
+    case 5: CALL(5); break;         \
+    case 7: CALL(7); break;         \
+    case 9: CALL(9); break;         \
+    case 11: CALL(11); break;       \
+    case 13: CALL(13); break;       \
+    default: CALL(15); break;       \
+    }
+
+// Loads weight map i at this thread's halo pixels (zero outside the image).
+template <int M>
+__device__ __forceinline__ void load_w(const DecodeIO &io, int i, int x0, int y0, int R, int HX,
+                                       int HXY, float *w)
+{
+#pragma unroll
+    for (int k = 0; k < kMaxPix; ++k) {
+        const int p = threadIdx.x + k * kThreads;
+        const int ly = p / HX, lx = p - ly * HX;
+        const int gy = y0 - R + ly, gx = x0 - R + lx;
+        w[k] = 0.f;
+        if (p < HXY && gy >= 0 && gy < io.H && gx >= 0 && gx < io.W)
+            w[k] = io.head[((size_t)gy * io.W + gx) * (2 * M) + i];
+    }
+}
+
+// Dynamic LDS: irradiance plane cq float4 [HXY] (c0, c1, c2, 0), product
+// plane float4 [HXY] (W_i, W_i c) rebuilt for each kernel size, row sums
+// float4 [(kDTY+2R)][32].
 //   DK_FRAMES / DK_TENSORS: forward, writes out.
 //   DK_ADJ_A: first half of the vector-Jacobian product.  Per centre p,
 //     with dF = g * mod, da_i = <dF, out_i>:
@@ -118,55 +234,54 @@ __global__ __launch_bounds__(kThreads) void decode_fwd_kernel(DecodeCfg dc, Fram
 {
     constexpr bool FRAMES = KIND == DK_FRAMES;
     constexpr bool ADJ = KIND == DK_ADJ_A;
-    extern __shared__ float lds[];
+    extern __shared__ float4 lds4[];
     DecodeIO io;
     int x0, y0;
     if (!decode_locate<FRAMES>(dc, fa, dt, io, x0, y0)) return;
 
     const int R = dc.R;
-    const int HX = kDTX + 2 * R, HY = kDTY + 2 * R, HXY = HX * HY;
-    float *Wl = lds;
-    float *cl = Wl + M * HXY;
-    float *hb = cl + 3 * HXY;
-    const int HB = HY * kDTX;
-    const int tid = threadIdx.x;
+    const int HX = 32 + 2 * R, HXY = HX * (kDTY + 2 * R);
+    float4 *cq = lds4;
+    float4 *pr = cq + HXY;
+    float4 *hb = pr + HXY;
     const int H = io.H, W = io.W;
+    const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
 
-    // stage the halo: weights and irradiance, zero outside the image
-    for (int p = tid; p < HXY; p += kThreads) {
-        const int ly = p / HX, lx = p - ly * HX;
-        const int gy = y0 - R + ly, gx = x0 - R + lx;
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-            const size_t pix = (size_t)gy * W + gx;
-            const float *hp = io.head + pix * (2 * M);
+    // irradiance halo: loads of all this thread's pixels first, then LDS
+    {
+        float cv[kMaxPix][3];
 #pragma unroll
-            for (int i = 0; i < M; ++i) Wl[i * HXY + p] = hp[i];
+        for (int k = 0; k < kMaxPix; ++k) {
+            const int p = tid + k * kThreads;
+            const int ly = p / HX, lx = p - ly * HX;
+            const int gy = y0 - R + ly, gx = x0 - R + lx;
+            cv[k][0] = cv[k][1] = cv[k][2] = 0.f;
+            if (p < HXY && gy >= 0 && gy < H && gx >= 0 && gx < W) {
+                const size_t q = ((size_t)gy * W + gx) * 3;
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                float c;
-                if (FRAMES) c = io.r[pix * 3 + ch] / (io.a[pix * 3 + ch] + dc.eps_albedo);
-                else c = io.c[pix * 3 + ch];
-                cl[ch * HXY + p] = c;
+                for (int ch = 0; ch < 3; ++ch) {
+                    if (FRAMES) cv[k][ch] = io.r[q + ch] / (io.a[q + ch] + dc.eps_albedo);
+                    else cv[k][ch] = io.c[q + ch];
+                }
             }
-        } else {
+        }
 #pragma unroll
-            for (int i = 0; i < M; ++i) Wl[i * HXY + p] = 0.f;
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) cl[ch * HXY + p] = 0.f;
+        for (int k = 0; k < kMaxPix; ++k) {
+            const int p = tid + k * kThreads;
+            if (p < HXY) cq[p] = make_float4(cv[k][0], cv[k][1], cv[k][2], 0.f);
         }
     }
+    float wpre[kMaxPix];
+    load_w<M>(io, 0, x0, y0, R, HX, HXY, wpre);
 
-    // each thread owns centres (tx, ty) and (tx, ty + 8)
-    const int tx = tid & 31, ty = tid >> 5;
-    float alpha[2][M], F[2][3];
-    float outv[ADJ ? 2 : 1][ADJ ? M : 1][3];
-    float Sv[ADJ ? 2 : 1][ADJ ? M : 1];
+    // fusion weights of this thread's kRun centres (column tx, rows kRun*ty + o)
+    float alpha[kRun][M], F[kRun][3];
 #pragma unroll
-    for (int o = 0; o < 2; ++o) {
-        const int y = y0 + ty + 8 * o, x = x0 + tx;
-        float lmax = -INFINITY;
+    for (int o = 0; o < kRun; ++o) {
+        const int y = y0 + kRun * ty + o, x = x0 + tx;
         if (y < H && x < W) {
             const float *lp = io.head + ((size_t)y * W + x) * (2 * M) + M;
+            float lmax = -INFINITY;
 #pragma unroll
             for (int i = 0; i < M; ++i) {
                 alpha[o][i] = lp[i];
@@ -187,64 +302,47 @@ __global__ __launch_bounds__(kThreads) void decode_fwd_kernel(DecodeCfg dc, Fram
         }
         F[o][0] = F[o][1] = F[o][2] = 0.f;
     }
+    float outv[ADJ ? kRun : 1][ADJ ? M : 1][3];
+    float Sv[ADJ ? kRun : 1][ADJ ? M : 1];
     __syncthreads();
 
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-        const int r = dc.radius[i];
-        // horizontal pass over the rows this size needs: [R - r, R + 16 + r)
-        const int row0 = R - r, nrows = kDTY + 2 * r;
-        for (int it = tid; it < nrows * kDTX; it += kThreads) {
-            const int hy = row0 + it / kDTX, xx = it % kDTX;
-            const int base = hy * HX + xx + R;
-            float S = 0.f, N0 = 0.f, N1 = 0.f, N2 = 0.f;
-            for (int dx = -r; dx <= r; ++dx) {
-                const float w = Wl[i * HXY + base + dx];
-                S += w;
-                N0 += w * cl[base + dx];
-                N1 += w * cl[HXY + base + dx];
-                N2 += w * cl[2 * HXY + base + dx];
-            }
-            const int q = hy * kDTX + xx;
-            hb[q] = S;
-            hb[HB + q] = N0;
-            hb[2 * HB + q] = N1;
-            hb[3 * HB + q] = N2;
-        }
-        __syncthreads();
+        // product plane of this size, then prefetch the next size's weights
 #pragma unroll
-        for (int o = 0; o < 2; ++o) {
-            const int yl = ty + 8 * o;
-            float S = 0.f, N0 = 0.f, N1 = 0.f, N2 = 0.f;
-            for (int dy = -r; dy <= r; ++dy) {
-                const int q = (yl + R + dy) * kDTX + tx;
-                S += hb[q];
-                N0 += hb[HB + q];
-                N1 += hb[2 * HB + q];
-                N2 += hb[3 * HB + q];
-            }
-            const float inv = 1.f / fmaxf(S, dc.eps_norm);
-            const float o0 = N0 * inv, o1 = N1 * inv, o2 = N2 * inv;
-            if (ADJ) {
-                outv[ADJ ? o : 0][ADJ ? i : 0][0] = o0;
-                outv[ADJ ? o : 0][ADJ ? i : 0][1] = o1;
-                outv[ADJ ? o : 0][ADJ ? i : 0][2] = o2;
-                Sv[ADJ ? o : 0][ADJ ? i : 0] = S;
+        for (int k = 0; k < kMaxPix; ++k) {
+            const int p = tid + k * kThreads;
+            if (p < HXY) pr[p] = f4scale(wpre[k], cq[p]);
+        }
+        if (i + 1 < M) load_w<M>(io, i + 1, x0, y0, R, HX, HXY, wpre);
+        __syncthreads();
+        float4 acc[kRun];
+#define WSKP_WS(KK) window_sums4<KK>(R, HX, pr, hb, acc)
+        WSKP_SWITCH_K(2 * dc.radius[i] + 1, WSKP_WS)
+#undef WSKP_WS
+#pragma unroll
+        for (int o = 0; o < kRun; ++o) {
+            const float inv = 1.f / fmaxf(acc[o].x, dc.eps_norm);
+            const float o0 = acc[o].y * inv, o1 = acc[o].z * inv, o2 = acc[o].w * inv;
+            if constexpr (ADJ) {
+                outv[o][i][0] = o0;
+                outv[o][i][1] = o1;
+                outv[o][i][2] = o2;
+                Sv[o][i] = acc[o].x;
             } else {
                 F[o][0] += alpha[o][i] * o0;
                 F[o][1] += alpha[o][i] * o1;
                 F[o][2] += alpha[o][i] * o2;
             }
         }
-        __syncthreads();
     }
 
 #pragma unroll
-    for (int o = 0; o < 2; ++o) {
-        const int y = y0 + ty + 8 * o, x = x0 + tx;
+    for (int o = 0; o < kRun; ++o) {
+        const int y = y0 + kRun * ty + o, x = x0 + tx;
         if (y >= H || x >= W) continue;
         const size_t pix = (size_t)y * W + x;
-        if (!ADJ) {
+        if constexpr (!ADJ) {
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
                 float m = 1.f;
@@ -260,24 +358,22 @@ __global__ __launch_bounds__(kThreads) void decode_fwd_kernel(DecodeCfg dc, Fram
             float da[M], adot = 0.f;
 #pragma unroll
             for (int i = 0; i < M; ++i) {
-                const int oo = ADJ ? o : 0, ii = ADJ ? i : 0;
-                da[i] = dF[0] * outv[oo][ii][0] + dF[1] * outv[oo][ii][1] + dF[2] * outv[oo][ii][2];
+                da[i] = dF[0] * outv[o][i][0] + dF[1] * outv[o][i][1] + dF[2] * outv[o][i][2];
                 adot += alpha[o][i] * da[i];
             }
             float *gh = io.grad_head + pix * (2 * M);
             const size_t P = (size_t)H * W;
 #pragma unroll
             for (int i = 0; i < M; ++i) {
-                const int oo = ADJ ? o : 0, ii = ADJ ? i : 0;
                 gh[M + i] = alpha[o][i] * (da[i] - adot);
-                const float S = Sv[oo][ii];
+                const float S = Sv[o][i];
                 const float inv = 1.f / fmaxf(S, dc.eps_norm);
                 float4 v;
                 v.x = alpha[o][i] * dF[0] * inv;
                 v.y = alpha[o][i] * dF[1] * inv;
                 v.z = alpha[o][i] * dF[2] * inv;
                 v.w = S > dc.eps_norm
-                          ? -(v.x * outv[oo][ii][0] + v.y * outv[oo][ii][1] + v.z * outv[oo][ii][2])
+                          ? -(v.x * outv[o][i][0] + v.y * outv[o][i][1] + v.z * outv[o][i][2])
                           : 0.f;
                 io.scratch[(size_t)i * P + pix] = v;
             }
@@ -291,86 +387,70 @@ __global__ __launch_bounds__(kThreads) void decode_fwd_kernel(DecodeCfg dc, Fram
 //   dW_i(q)  = sum_ch c_ch(q) box_i(u_i,ch)(q) + box_i(dS_i)(q)  -> grad_head[q][i]
 //   dc_ch(q) = sum_i W_i(q) box_i(u_i,ch)(q)                      -> grad_c[q][ch]
 // One size at a time: stage the halo of (u_i, dS_i) as float4, row sums,
-// column sums.  LDS: [4][HY*HX] staged + [4][HY*32] row sums.
+// column sums.  LDS: float4 [HXY] staged + float4 [(kDTY+2R)][32] row sums.
 template <int M>
 __global__ __launch_bounds__(kThreads) void decode_adj_b_kernel(DecodeCfg dc, DecodeTensors dt,
                                                                  float *grad_c)
 {
-    extern __shared__ float lds[];
+    extern __shared__ float4 lds4[];
     FrameArg fa{};
     DecodeIO io;
     int x0, y0;
     if (!decode_locate<false>(dc, fa, dt, io, x0, y0)) return;
     const int R = dc.R;
-    const int HX = kDTX + 2 * R, HY = kDTY + 2 * R, HXY = HX * HY;
-    float *st = lds;
-    float *hb = st + 4 * HXY;
-    const int HB = HY * kDTX;
+    const int HX = 32 + 2 * R, HXY = HX * (kDTY + 2 * R);
+    float4 *st = lds4;
+    float4 *hb = st + HXY;
     const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
     const int H = io.H, W = io.W;
     const size_t P = (size_t)H * W;
     const int fidx = (int)((io.head - dt.head) / ((size_t)P * 2 * M));
     float *gc = grad_c + (size_t)fidx * P * 3;
 
-    float dcv[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    float dcv[kRun][3];
+#pragma unroll
+    for (int o = 0; o < kRun; ++o) dcv[o][0] = dcv[o][1] = dcv[o][2] = 0.f;
+#pragma unroll
     for (int i = 0; i < M; ++i) {
         const float4 *sp = io.scratch + (size_t)i * P;
-        for (int p = tid; p < HXY; p += kThreads) {
+        float4 v[kMaxPix];
+#pragma unroll
+        for (int k = 0; k < kMaxPix; ++k) {
+            const int p = tid + k * kThreads;
             const int ly = p / HX, lx = p - ly * HX;
             const int gy = y0 - R + ly, gx = x0 - R + lx;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (gy >= 0 && gy < H && gx >= 0 && gx < W) v = sp[(size_t)gy * W + gx];
-            st[p] = v.x;
-            st[HXY + p] = v.y;
-            st[2 * HXY + p] = v.z;
-            st[3 * HXY + p] = v.w;
+            v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (p < HXY && gy >= 0 && gy < H && gx >= 0 && gx < W) v[k] = sp[(size_t)gy * W + gx];
         }
-        __syncthreads();
-        const int r = dc.radius[i];
-        const int row0 = R - r, nrows = kDTY + 2 * r;
-        for (int it = tid; it < nrows * kDTX; it += kThreads) {
-            const int hy = row0 + it / kDTX, xx = it % kDTX;
-            const int base = hy * HX + xx + R;
-            float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-            for (int dx = -r; dx <= r; ++dx) {
-                a0 += st[base + dx];
-                a1 += st[HXY + base + dx];
-                a2 += st[2 * HXY + base + dx];
-                a3 += st[3 * HXY + base + dx];
-            }
-            const int q = hy * kDTX + xx;
-            hb[q] = a0;
-            hb[HB + q] = a1;
-            hb[2 * HB + q] = a2;
-            hb[3 * HB + q] = a3;
-        }
-        __syncthreads();
 #pragma unroll
-        for (int o = 0; o < 2; ++o) {
-            const int yl = ty + 8 * o, y = y0 + yl, x = x0 + tx;
-            float b0 = 0.f, b1 = 0.f, b2 = 0.f, b3 = 0.f;
-            for (int dy = -r; dy <= r; ++dy) {
-                const int q = (yl + R + dy) * kDTX + tx;
-                b0 += hb[q];
-                b1 += hb[HB + q];
-                b2 += hb[2 * HB + q];
-                b3 += hb[3 * HB + q];
-            }
+        for (int k = 0; k < kMaxPix; ++k) {
+            const int p = tid + k * kThreads;
+            if (p < HXY) st[p] = v[k];
+        }
+        __syncthreads();
+        float4 acc[kRun];
+#define WSKP_WS(KK) window_sums4<KK>(R, HX, st, hb, acc)
+        WSKP_SWITCH_K(2 * dc.radius[i] + 1, WSKP_WS)
+#undef WSKP_WS
+#pragma unroll
+        for (int o = 0; o < kRun; ++o) {
+            const int y = y0 + kRun * ty + o, x = x0 + tx;
             if (y < H && x < W) {
                 const size_t pix = (size_t)y * W + x;
                 const float *cp = io.c + pix * 3;
                 const float w = io.head[pix * (2 * M) + i];
-                io.grad_head[pix * (2 * M) + i] = cp[0] * b0 + cp[1] * b1 + cp[2] * b2 + b3;
-                dcv[o][0] += w * b0;
-                dcv[o][1] += w * b1;
-                dcv[o][2] += w * b2;
+                // acc = box sums of (u_0, u_1, u_2, dS)
+                io.grad_head[pix * (2 * M) + i] =
+                    cp[0] * acc[o].x + cp[1] * acc[o].y + cp[2] * acc[o].z + acc[o].w;
+                dcv[o][0] += w * acc[o].x;
+                dcv[o][1] += w * acc[o].y;
+                dcv[o][2] += w * acc[o].z;
             }
         }
-        __syncthreads();
     }
 #pragma unroll
-    for (int o = 0; o < 2; ++o) {
-        const int y = y0 + ty + 8 * o, x = x0 + tx;
+    for (int o = 0; o < kRun; ++o) {
+        const int y = y0 + kRun * ty + o, x = x0 + tx;
         if (y < H && x < W) {
             const size_t pix = (size_t)y * W + x;
 #pragma unroll
@@ -381,14 +461,14 @@ __global__ __launch_bounds__(kThreads) void decode_adj_b_kernel(DecodeCfg dc, De
 
 static size_t decode_lds_bytes(const DecodeCfg &dc)
 {
-    const int HX = kDTX + 2 * dc.R, HY = kDTY + 2 * dc.R;
-    return sizeof(float) * ((size_t)(dc.M + 3) * HX * HY + 4 * (size_t)HY * kDTX);
+    const size_t HX = kDTX + 2 * dc.R, HY = kDTY + 2 * dc.R;
+    return sizeof(float4) * (2 * HX * HY + HY * kDTX);
 }
 
 static size_t adj_b_lds_bytes(const DecodeCfg &dc)
 {
-    const int HX = kDTX + 2 * dc.R, HY = kDTY + 2 * dc.R;
-    return sizeof(float) * (4 * (size_t)HX * HY + 4 * (size_t)HY * kDTX);
+    const size_t HX = kDTX + 2 * dc.R, HY = kDTY + 2 * dc.R;
+    return sizeof(float4) * (HX * HY + HY * kDTX);
 }
 
 template <typename K>
