@@ -55,8 +55,13 @@ def decode_bytes(cfg, H, W):
 
 def time_precision(cfg, blob, dev, H, W, prec, steps, warmup, lat_frames):
     import torch
-    from paper_2202_05977_amd import wskp
-    dn = wskp.Denoiser(cfg, blob, prec)
+    from paper_2202_05977_amd import synth, wskp
+    scales = None
+    if prec == "fp8":
+        # activation scales calibrated on a different frame (seed 999) by the fp32 path
+        calib = {k: torch.from_numpy(v).cuda() for k, v in synth.make_frame(999, H, W).items()}
+        scales = wskp.calibrate_fp8_scales(cfg, blob, calib)
+    dn = wskp.Denoiser(cfg, blob, prec, act_scales=scales)
     out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
     for _ in range(warmup):
@@ -79,6 +84,24 @@ def time_precision(cfg, blob, dev, H, W, prec, steps, warmup, lat_frames):
         e1.record(stream)
         e1.synchronize()
         lat.append(e0.elapsed_time(e1))
+    # throughput with the frame's launches captured once in a HIP graph
+    g = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(stream)
+    with torch.cuda.stream(cap):
+        dn(dev, out)                      # warm the capture stream
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=cap):
+            dn(dev, out)
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - t0) * 1e3 / steps
     # per-kernel durations: events recorded by the library around each launch
     kt = max(1, min(steps, 100))
     wskp.wskp_timing_enable(dn.h, kt)
@@ -96,9 +119,161 @@ def time_precision(cfg, blob, dev, H, W, prec, steps, warmup, lat_frames):
         "fps": 1e3 / ms_per_step,
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
+        "graph_fps": 1e3 / ms_graph,
         "per_kernel_us": per_kernel_us,
         "y": y,
     }
+
+
+def rel_errors(y, yref):
+    return {"rel_l2": float(np.linalg.norm(y - yref) / np.linalg.norm(yref)),
+            "max_rel": float(np.abs(y - yref).max() / np.abs(yref).max()),
+            "max_abs": float(np.abs(y - yref).max())}
+
+
+def mode_sweep(args):
+    """1920x1080 frame: frames/s and error vs the FP64 oracle per precision."""
+    import torch
+    import oracle
+    from paper_2202_05977_amd import synth
+    H, W = 1080, 1920
+    cfg = synth.HD
+    blob = synth.make_weights(cfg, 0)
+    fr = synth.make_frame(1, H, W)
+    dev = {k: torch.from_numpy(v).cuda() for k, v in fr.items()}
+    log("[sweep] FP64 oracle at 1920x1080")
+    yref = oracle.denoise(fr, blob, cfg)
+    out = {}
+    for p in args.precisions.split(","):
+        r = time_precision(cfg, blob, dev, H, W, p, args.steps, args.warmup, min(args.steps, 100))
+        out[p] = {"frames_per_s": r["fps"], "graph_frames_per_s": r["graph_fps"],
+                  "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
+                  "per_kernel_us": r["per_kernel_us"], **rel_errors(r["y"], yref)}
+        log(f"[sweep] {p}: {r['fps']:.1f} frames/s, errors {rel_errors(r['y'], yref)}")
+    print(json.dumps({"mode": "precision_sweep", "workload": "1920x1080 frame, hd net",
+                      "results": out}), flush=True)
+
+
+def mode_train(args):
+    """8 crops of 256x256: decode forward + L1 cotangent + hand-written adjoint."""
+    import torch
+    import oracle
+    from paper_2202_05977_amd import synth, wskp
+    N, H, W = 8, 256, 256
+    cfg = synth.HD
+    blob = synth.make_weights(cfg, 0)
+    fb = synth.make_frame_batch(range(2000, 2000 + N), H, W)
+    # head records from the network itself (fp32), one frame at a time
+    dn = wskp.Denoiser(cfg, blob, "fp32")
+    heads = []
+    for n in range(N):
+        f = {k: torch.from_numpy(fb[k][n]).cuda() for k in ("radiance", "albedo", "normal", "depth")}
+        dn(f)
+        heads.append(dn.intermediate([H], [W], 0, 200).clone())
+    head = torch.stack(heads).contiguous()
+    r = torch.from_numpy(fb["radiance"]).cuda()
+    a = torch.from_numpy(fb["albedo"]).cuda()
+    t = torch.from_numpy(fb["clean"]).cuda()
+    mod = a + cfg.eps_albedo
+    c = r / mod
+    out = torch.empty_like(c)
+    gh = torch.empty_like(head)
+    gc = torch.empty_like(c)
+    ws = torch.empty(wskp.wskp_backward_workspace_size(dn.h, N, H, W), dtype=torch.uint8,
+                     device="cuda")
+    def step():
+        wskp.wskp_decode(dn.h, head, c, mod, out)
+        g = torch.sign(out - t) / out.numel()          # L1 cotangent
+        wskp.wskp_backward(dn.h, head, c, mod, g, gh, gc, ws)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    # kernel-only times with events on the launch stream
+    s = torch.cuda.current_stream()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    g = torch.sign(out - t) / out.numel()
+    fw, bw = [], []
+    for _ in range(20):
+        e[0].record(s)
+        wskp.wskp_decode(dn.h, head, c, mod, out)
+        e[1].record(s)
+        wskp.wskp_backward(dn.h, head, c, mod, g, gh, gc, ws)
+        e[2].record(s)
+        e[2].synchronize()
+        fw.append(e[0].elapsed_time(e[1]))
+        bw.append(e[1].elapsed_time(e[2]))
+    px = N * H * W
+    fwd_us, bwd_us = 1e3 * float(np.median(fw)), 1e3 * float(np.median(bw))
+    # adjoint against the oracle VJP on crop 0 with the same cotangent
+    g0 = g[0].double().cpu().numpy()
+    rh, rc = oracle.decode_vjp(head[0].double().cpu().numpy(), c[0].double().cpu().numpy(),
+                               mod[0].double().cpu().numpy(), cfg.kernel_sizes, g0)
+    err = {"grad_head_rel_l2": float(np.linalg.norm(gh[0].double().cpu().numpy() - rh) /
+                                     np.linalg.norm(rh)),
+           "grad_c_rel_l2": float(np.linalg.norm(gc[0].double().cpu().numpy() - rc) /
+                                  np.linalg.norm(rc))}
+    print(json.dumps({
+        "mode": "train_step", "workload": "8 crops of 256x256, decode+fusion forward, L1, adjoint",
+        "crops_per_s": N * 1e3 / ms, "ms_per_step": ms,
+        "decode_fwd_us": fwd_us, "adjoint_us": bwd_us,
+        "decode_fwd_GBps": px * 76 / (fwd_us * 1e-6) / 1e9,
+        "adjoint_GBps_algorithmic": px * 128 / (bwd_us * 1e-6) / 1e9,
+        "adjoint_vs_fp64_oracle": err}), flush=True)
+    dn.close()
+
+
+def mode_serve(args):
+    """64 streams, Poisson 2000 frames/s: bf16 continuous batching vs the
+    plain fp32 per-frame loop on the same trace."""
+    import torch
+    from paper_2202_05977_amd import serve, synth, wskp
+    cfg = synth.HD
+    blob = synth.make_weights(cfg, 0)
+    sizes, reqs = serve.poisson_trace(64, args.serve_frames, 2000.0, synth.SERVE_RESOLUTIONS,
+                                      seed=7)
+    proto = {}
+    for (H, W) in set(sizes):
+        proto[(H, W)] = {k: torch.from_numpy(v).cuda()
+                         for k, v in synth.make_frame(1000 + H, H, W).items() if k != "clean"}
+    inputs = {s: {k: v.clone() for k, v in proto[sizes[s]].items()} for s in range(64)}
+    budget = 64 << 30
+    res = {}
+    dn = wskp.Denoiser(cfg, blob, "bf16")
+    ex = serve.GpuExecutor(dn, inputs, budget)
+    # warm up every resolution once
+    for (H, W) in proto:
+        tok = ex.launch([serve.Request(-1, sizes.index((H, W)), 0.0, H, W)], 0, 0)
+        ex.wait(tok)
+    st = serve.Server(ex, budget, max_inflight=2, max_batch=64).run(
+        [dataclasses_replace(r) for r in reqs])
+    res["bf16_continuous_batching"] = st.__dict__
+    log(f"[serve] bf16 batching: {st}")
+    n_fifo = min(len(reqs), args.fifo_frames)
+    st = serve.fifo_single(ex, [dataclasses_replace(r) for r in reqs[:n_fifo]])
+    res["bf16_fifo_single"] = {**st.__dict__, "requests": n_fifo}
+    log(f"[serve] bf16 fifo: {st}")
+    del ex
+    dn.close()
+    dn = wskp.Denoiser(cfg, blob, "fp32")
+    ex = serve.GpuExecutor(dn, inputs, 8 << 30)
+    st = serve.fifo_single(ex, [dataclasses_replace(r) for r in reqs[:n_fifo]])
+    res["fp32_fifo_single"] = {**st.__dict__, "requests": n_fifo}
+    log(f"[serve] fp32 fifo: {st}")
+    mean_px = float(np.mean([H * W for (H, W) in sizes]))
+    print(json.dumps({"mode": "serve", "workload": "64 streams, Poisson 2000 frames/s, "
+                      f"{args.serve_frames} frames/stream, resolutions 360p..1440p, 64 GB budget",
+                      "mean_megapixels": mean_px / 1e6, "results": res}), flush=True)
+    dn.close()
+
+
+def dataclasses_replace(r):
+    import dataclasses
+    return dataclasses.replace(r)
 
 
 def omp_threads() -> int:
@@ -121,6 +296,11 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes 5 times (reference "
                          "kernel for scaling HBM traffic counters) and exit")
+    ap.add_argument("--mode", default="headline", choices=["headline", "sweep", "train", "serve"],
+                    help="headline: the 720p JSON line; sweep: 1080p precisions vs oracle; "
+                         "train: decode adjoint on 8x256^2 crops; serve: 64-stream trace")
+    ap.add_argument("--serve-frames", type=int, default=300)
+    ap.add_argument("--fifo-frames", type=int, default=2000)
     ap.add_argument("--height", type=int, default=720)
     ap.add_argument("--width", type=int, default=1280)
     args = ap.parse_args()
@@ -142,6 +322,10 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 5}))
         return
 
+    if args.mode != "headline":
+        {"sweep": mode_sweep, "train": mode_train, "serve": mode_serve}[args.mode](args)
+        return
+
     H, W = args.height, args.width
     cfg = synth.HD
     blob = synth.make_weights(cfg, 0)
@@ -155,7 +339,8 @@ def main():
         res[p] = time_precision(cfg, blob, dev, H, W, p, args.steps, args.warmup,
                                 min(args.steps, 300))
         log(f"[bench] {p}: {res[p]['fps']:.1f} frames/s, {res[p]['ms_per_step']:.3f} ms/frame, "
-            f"p50 {res[p]['p50_ms']:.3f} p99 {res[p]['p99_ms']:.3f} ms")
+            f"p50 {res[p]['p50_ms']:.3f} p99 {res[p]['p99_ms']:.3f} ms, "
+            f"graph replay {res[p]['graph_fps']:.1f} frames/s")
         log(f"[bench] {p} per kernel (us): " +
             ", ".join(f"{k} {v:.1f}" for k, v in res[p]["per_kernel_us"].items()))
 
@@ -226,6 +411,7 @@ def main():
         "conv_mfma": conv_mfma,
         "error_vs_fp64_oracle": errors,
         "precisions": {p: {"frames_per_s": res[p]["fps"], "ms_per_step": res[p]["ms_per_step"],
+                           "graph_frames_per_s": res[p]["graph_fps"],
                            "p50_ms": res[p]["p50_ms"], "p99_ms": res[p]["p99_ms"],
                            "per_kernel_us": res[p]["per_kernel_us"]} for p in precs},
         "cpu_baseline": cpu,

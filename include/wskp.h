@@ -120,9 +120,12 @@ size_t wskp_num_weights(const wskp_config_t *cfg);
 
 /* Creates a handle on HIP device `device`: validates cfg, copies the host
  * weight blob (n_weights floats, owned by the caller, not retained) to the
- * device in the layout the kernels read.  host_act_scales: FP8 activation
- * scales, one per conv in blob order (NULL for other precisions, or to use
- * scales derived from the weights).  Synchronous. */
+ * device in the layout the kernels read.  Synchronous.
+ * host_act_scales: for WSKP_PREC_FP8_E4M3 only (ignored otherwise, may be
+ * NULL), one positive float per conv in blob order: the scale s of that
+ * conv's input activations, which are stored as e4m3(x / s) (values beyond
+ * +-448 s saturate).  Weights are quantised per output channel with
+ * s_w = max|w| / 448.  FP8 needs every level width to be a multiple of 32. */
 wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host_weights, size_t n_weights,
                           const float *host_act_scales, int device, wskp_handle_t *out);
 
@@ -199,6 +202,10 @@ wskp_status_t wskp_timing_enable(wskp_handle_t h, int max_calls);
 wskp_status_t wskp_timing_read(wskp_handle_t h, int max, float *ms_sum, int *n_launches,
                                int *n_calls);
 const char *wskp_launch_name(wskp_handle_t h, int i);
+
+/* Round-to-nearest-even conversion of n floats to OCP e4m3 bytes with
+ * saturation at +-448 (the encoding the FP8 form uses for weights). */
+void wskp_fp8_e4m3_encode(const float *x, uint8_t *out, size_t n);
 
 /* Static text for a status code. */
 const char *wskp_status_string(wskp_status_t s);

@@ -142,6 +142,22 @@ __device__ __forceinline__ unsigned pack2(float a, float b)
     return (unsigned)f32_to_bf16(a) | ((unsigned)f32_to_bf16(b) << 16);
 }
 
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+// Four floats -> four OCP e4m3 bytes (round to nearest even), saturated to
+// the largest finite magnitude 448 first so that no value becomes NaN.
+__device__ __forceinline__ unsigned fp8x4(float a, float b, float c, float d)
+{
+    const float m = 448.f;
+    a = fminf(fmaxf(a, -m), m);
+    b = fminf(fmaxf(b, -m), m);
+    c = fminf(fmaxf(c, -m), m);
+    d = fminf(fmaxf(d, -m), m);
+    int r = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    r = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, r, true);
+    return (unsigned)r;
+}
+
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const u32x4 g_u32x4;
 // 16-byte load through a global-address-space pointer (a global_load
@@ -177,27 +193,32 @@ __device__ __forceinline__ void pack_input(const ConvLayer &L, const FrameDesc &
 // =============================================================================
 template <int PREC, int MODE, int CK, int TH, int NB, typename SrcT>
 struct Stage {
-    static constexpr bool BF = PREC != 0;
+    static constexpr bool BF = PREC == 1;       // bf16 operands
+    static constexpr bool F8 = PREC == 2;       // fp8 (e4m3) operands, bf16 activations in HBM
     static constexpr int TW = kConvTW, HP = TH + 2, WP = TW + 2;
     // input items: a 16-byte run of one pixel's channels (PACK: one pixel)
     static constexpr int G = (MODE == CONV_PACK) ? CK : 16 / (int)sizeof(SrcT);
     static constexpr int NG = CK / G;
     static constexpr int TOT = HP * WP * NG;
     static constexpr int IT = (TOT + kThreads - 1) / kThreads;
-    static constexpr int RW = (MODE == CONV_PACK) ? (BF ? 2 : 3) : 1;   // 16-byte words per item
+    static constexpr int RW = (MODE == CONV_PACK) ? (BF || F8 ? 2 : 3) : 1;  // 16-byte words per item
     // LDS geometry
     static constexpr int PL = ((HP * WP - 16 + 31) / 32) * 32 + 16;     // fp32 plane stride
-    static constexpr int PS = CK + 8;                                    // bf16 pixel stride
+    static constexpr int PS = CK + 8;                                    // bf16 pixel stride (elements)
+    static constexpr int PS8 = CK + 16;                                  // fp8 pixel stride (bytes)
     static constexpr int KE = 9 * CK;
-    static constexpr int NK = BF ? (KE + 31) / 32 : KE / 4;              // MFMAs per chunk
+    static constexpr int NR = KE / 32;                                   // fp8: runs of 32 K values
+    static constexpr int NK = F8 ? (NR + 3) / 4 : (BF ? (KE + 31) / 32 : KE / 4);  // MFMAs per chunk
     static constexpr int BS = NB * 16 + ((NB % 2 == 0) ? 16 : 0);        // fp32 weight row stride
     static constexpr int BSK = NK * 32 + 8;                              // bf16 weight row stride
-    static constexpr int A_BYTES = (BF ? HP * WP * PS * 2 : CK * PL * 4);
-    static constexpr int B_BYTES = (BF ? NB * 16 * BSK * 2 : KE * BS * 4);
+    static constexpr int BSK8 = NK * 128 + 16;                           // fp8 weight row stride (bytes)
+    static constexpr int A_BYTES = F8 ? HP * WP * PS8 : (BF ? HP * WP * PS * 2 : CK * PL * 4);
+    static constexpr int B_BYTES = F8 ? NB * 16 * BSK8 : (BF ? NB * 16 * BSK * 2 : KE * BS * 4);
     // weight items: 16 bytes of the packed chunk
-    static constexpr int WTOT = BF ? NB * 16 * (NK * 32 / 8) : KE * NB * 4;
+    static constexpr int WTOT = F8 ? NB * 16 * NK * 8 : (BF ? NB * 16 * (NK * 32 / 8) : KE * NB * 4);
     static constexpr int WIT = (WTOT + kThreads - 1) / kThreads;
-    static constexpr int WCHUNK = BF ? NK * 32 : KE;   // per-chunk stride factor (x Cout_pad)
+    // per-chunk stride of the packed weights, in elements of the packed type, per output channel
+    static constexpr int WCHUNK = F8 ? NK * 128 : (BF ? NK * 32 : KE);
 
     uint4 in[IT][RW];
     uint4 w[WIT];
@@ -235,7 +256,10 @@ struct Stage {
             const int it = tid + k * kThreads;
             woff[k] = 0;
             if (it < WTOT) {
-                if constexpr (BF) {
+                if constexpr (F8) {
+                    const int co = it / (NK * 8), q = it - co * (NK * 8);
+                    woff[k] = (g * NB * 16 + co) * (NK * 128) + q * 16;
+                } else if constexpr (BF) {
                     constexpr int KV = NK * 32 / 8;
                     const int co = it / KV, q = it - co * KV;
                     woff[k] = (g * NB * 16 + co) * (NK * 32) + q * 8;
@@ -262,7 +286,15 @@ struct Stage {
             if constexpr (MODE == CONV_PACK) {
                 float x[10];
                 pack_input(L, fd, (size_t)off0[k], x);
-                if constexpr (BF) {
+                if constexpr (F8) {
+                    unsigned q[3];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) q[j] = fp8x4(x[4 * j] * L.in_qscale, x[4 * j + 1] * L.in_qscale,
+                                                       j < 2 ? x[4 * j + 2] * L.in_qscale : 0.f,
+                                                       j < 2 ? x[4 * j + 3] * L.in_qscale : 0.f);
+                    in[k][0] = make_uint4(q[0], q[1], q[2], 0);
+                    in[k][1] = make_uint4(0, 0, 0, 0);
+                } else if constexpr (BF) {
                     in[k][0] = make_uint4(pack2(x[0], x[1]), pack2(x[2], x[3]), pack2(x[4], x[5]),
                                           pack2(x[6], x[7]));
                     in[k][1] = make_uint4(pack2(x[8], x[9]), 0, 0, 0);
@@ -284,7 +316,7 @@ struct Stage {
                 const uint4 q1 = gload16(b + L.C0);
                 const uint4 q2 = gload16(b + rs);
                 const uint4 q3 = gload16(b + rs + L.C0);
-                if constexpr (BF) {
+                if constexpr (BF || F8) {
                     const unsigned *a0 = &q0.x, *a1 = &q1.x, *a2 = &q2.x, *a3 = &q3.x;
                     unsigned o[4];
 #pragma unroll
@@ -308,14 +340,15 @@ struct Stage {
             }
         }
         // weight slice of this chunk
-        using WT = typename std::conditional<BF, unsigned short, float>::type;
+        using WT = typename std::conditional<F8, unsigned char,
+                   typename std::conditional<BF, unsigned short, float>::type>::type;
         const WT *wsrc = reinterpret_cast<const WT *>(L.w) + (size_t)cc * WCHUNK * L.Cout_pad;
 #pragma unroll
         for (int k = 0; k < WIT; ++k)
             if (tid + k * kThreads < WTOT) w[k] = gload16(wsrc + woff[k]);
     }
 
-    __device__ __forceinline__ void commit(void *As_, void *Bs_) const
+    __device__ __forceinline__ void commit(void *As_, void *Bs_, float qs) const
     {
         const int tid = threadIdx.x;
 #pragma unroll
@@ -323,7 +356,22 @@ struct Stage {
             const int it = tid + k * kThreads;
             if (it >= TOT) continue;
             const int p = it / NG, cg = it - p * NG;
-            if constexpr (BF) {
+            if constexpr (F8) {
+                unsigned char *As = static_cast<unsigned char *>(As_);
+                if constexpr (MODE == CONV_PACK) {
+                    *reinterpret_cast<uint4 *>(&As[p * PS8]) = in[k][0];
+                    *reinterpret_cast<uint4 *>(&As[p * PS8 + 16]) = in[k][1];
+                } else {
+                    // 8 bf16 channels -> 8 scaled e4m3 bytes
+                    const unsigned *v = &in[k][0].x;
+                    uint2 o;
+                    o.x = fp8x4(bf16_to_f32(v[0] & 0xffff) * qs, bf16_to_f32(v[0] >> 16) * qs,
+                                bf16_to_f32(v[1] & 0xffff) * qs, bf16_to_f32(v[1] >> 16) * qs);
+                    o.y = fp8x4(bf16_to_f32(v[2] & 0xffff) * qs, bf16_to_f32(v[2] >> 16) * qs,
+                                bf16_to_f32(v[3] & 0xffff) * qs, bf16_to_f32(v[3] >> 16) * qs);
+                    *reinterpret_cast<uint2 *>(&As[p * PS8 + cg * 8]) = o;
+                }
+            } else if constexpr (BF) {
                 unsigned short *As = static_cast<unsigned short *>(As_);
 #pragma unroll
                 for (int q = 0; q < RW; ++q)
@@ -345,7 +393,10 @@ struct Stage {
         for (int k = 0; k < WIT; ++k) {
             const int it = tid + k * kThreads;
             if (it >= WTOT) continue;
-            if constexpr (BF) {
+            if constexpr (F8) {
+                const int co = it / (NK * 8), q = it - co * (NK * 8);
+                *reinterpret_cast<uint4 *>(static_cast<unsigned char *>(Bs_) + co * BSK8 + q * 16) = w[k];
+            } else if constexpr (BF) {
                 constexpr int KV = NK * 32 / 8;
                 const int co = it / KV, q = it - co * KV;
                 *reinterpret_cast<uint4 *>(static_cast<unsigned short *>(Bs_) + co * BSK + q * 8) = w[k];
@@ -387,6 +438,43 @@ __device__ __forceinline__ void chunk_mfma(const void *As_, const void *Bs_, f32
                     for (int nb = 0; nb < NB; ++nb)
                         acc[i][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[nb], acc[i][nb], 0, 0, 0);
                 }
+            }
+        }
+    } else if constexpr (PREC == 2) {
+        // v_mfma_f32_16x16x128_f8f6f4: lane (i, q) holds 32 consecutive K
+        // values (one run of 32 channels of one tap); one MFMA = 4 runs.
+        const unsigned char *As = static_cast<const unsigned char *>(As_);
+        const unsigned char *Bs = static_cast<const unsigned char *>(Bs_);
+#pragma unroll
+        for (int s = 0; s < S::NK; ++s) {
+            const int run = 4 * s + lq;
+            const int k0 = run * 32;
+            const int tap = k0 / CK, c0 = k0 - tap * CK;
+            const bool live = run < S::NR;
+            const int dy = live ? tap / 3 : 0, dx = live ? tap % 3 : 0;
+            i32x8 b[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const unsigned char *bp = &Bs[(nb * 16 + lj) * S::BSK8 + s * 128 + lq * 32];
+                const uint4 u0 = *reinterpret_cast<const uint4 *>(bp);
+                const uint4 u1 = *reinterpret_cast<const uint4 *>(bp + 16);
+                b[nb] = i32x8{(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w,
+                              (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
+            }
+#pragma unroll
+            for (int i = 0; i < MB; ++i) {
+                const int blk = wave * MB + i, row = blk >> 1, cb = blk & 1;
+                const int p = (row + dy) * S::WP + cb * 16 + lj + dx;
+                const unsigned char *ap = &As[p * S::PS8 + (live ? c0 : 0)];
+                uint4 u0 = *reinterpret_cast<const uint4 *>(ap);
+                uint4 u1 = *reinterpret_cast<const uint4 *>(ap + 16);
+                if (!live) u0 = u1 = make_uint4(0, 0, 0, 0);
+                const i32x8 a = i32x8{(int)u0.x, (int)u0.y, (int)u0.z, (int)u0.w,
+                                      (int)u1.x, (int)u1.y, (int)u1.z, (int)u1.w};
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[i][nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                        a, b[nb], acc[i][nb], 0, 0, 0, 0, 0, 0);
             }
         }
     } else {
@@ -453,7 +541,7 @@ __global__ __launch_bounds__(kThreads, WSKP_CONV_MIN_WG) void conv3x3_kernel(Con
     st.fetch(L, fd, s0, s1, 0, Wl);
     for (int cc = 0; cc < nchunks; ++cc) {
         if (cc) __syncthreads();
-        st.commit(As, Bs);
+        st.commit(As, Bs, L.in_qscale);
         __syncthreads();
         if (cc + 1 < nchunks) st.fetch(L, fd, s0, s1, cc + 1, Wl);
         chunk_mfma<PREC, MODE, CK, TH, NB, SrcT>(As, Bs, acc);
@@ -470,10 +558,11 @@ __global__ __launch_bounds__(kThreads, WSKP_CONV_MIN_WG) void conv3x3_kernel(Con
         for (int nb = 0; nb < NB; ++nb) {
             const int cl = nb * 16 + lj, co = g * NC + cl;
             const float bias = co < L.Cout ? L.bias[co] : 0.f;
+            const float dq = (PREC == 2 && co < L.Cout) ? L.out_scale[co] : 1.f;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int px = row * kConvTW + cb * 16 + lq * 4 + v;
-                Ot[px * OS + cl] = epilogue<EPI>(acc[i][nb][v] + bias, co, L.M);
+                Ot[px * OS + cl] = epilogue<EPI>(acc[i][nb][v] * dq + bias, co, L.M);
             }
         }
     }
@@ -515,16 +604,30 @@ __global__ __launch_bounds__(kThreads, WSKP_CONV_MIN_WG) void conv3x3_kernel(Con
 // Output rows per conv tile and the minimum number of workgroups per CU the
 // register allocation must allow (build-time tuning knobs).
 #ifndef WSKP_CONV_TH
-#define WSKP_CONV_TH 8
+#define WSKP_CONV_TH 4
 #endif
 constexpr int kTH = WSKP_CONV_TH;
 int conv_tile_rows(int) { return kTH; }
 
 int conv_chunk(int prec, int mode, int Cin, int C0)
 {
+    if (prec == 2) return 32;   // fp8: runs of 32 channels (the network input padded to 32)
     if (mode == CONV_PACK) return prec == 0 ? 12 : 16;
     if (prec != 0 && Cin % 32 == 0 && (mode != CONV_CAT || C0 % 32 == 0)) return 32;
     return 16;
+}
+
+// Wider groups stage and read each input tile fewer times (the A operand is
+// reused across NB blocks); narrower groups give more workgroups.
+#ifndef WSKP_CONV_MAX_NB
+#define WSKP_CONV_MAX_NB 4
+#endif
+int conv_blocks_per_group(int mode, int nblk)
+{
+    if (mode == CONV_PLAIN || mode == CONV_PACK) return nblk % 2 == 0 ? 2 : 1;
+    for (int nb = WSKP_CONV_MAX_NB; nb > 1; --nb)
+        if (nb <= 4 && nblk % nb == 0) return nb;
+    return 1;
 }
 
 int conv_grid(const ConvLayer &L, int n, const int *H, const int *W)
@@ -540,7 +643,8 @@ int conv_grid(const ConvLayer &L, int n, const int *H, const int *W)
 template <int PREC, int MODE, int EPI, int CK, int NB, typename OutT>
 static void launch_one(const ConvLayer &L, const FrameArg &fa, int blocks, hipStream_t s)
 {
-    // fp32 activations travel with the fp32 MFMA form, bf16 with the bf16 form
+    // fp32 activations travel with the fp32 MFMA form; the bf16 and fp8 forms
+    // keep bf16 activations in memory
     using SrcT = typename std::conditional<PREC == 0, float, unsigned short>::type;
     hipLaunchKernelGGL((conv3x3_kernel<PREC, MODE, EPI, kTH, CK, NB, SrcT, OutT>), dim3(blocks),
                        dim3(kThreads), 0, s, L, fa);
@@ -556,13 +660,18 @@ static bool launch_ck_nb(const ConvLayer &L, const FrameArg &fa, int blocks, hip
         launch_one<PREC, MODE, EPI, ck, nb, OutT>(L, fa, blocks, s);       \
         return true;                                                        \
     }
-    if constexpr (MODE == CONV_PACK) {
+    if constexpr (PREC == 2) {
+        WSKP_CASE(32, 1) WSKP_CASE(32, 2)
+        if constexpr (MODE != CONV_PACK && MODE != CONV_PLAIN) { WSKP_CASE(32, 3) WSKP_CASE(32, 4) }
+    } else if constexpr (MODE == CONV_PACK) {
         if constexpr (PREC == 0) { WSKP_CASE(12, 1) WSKP_CASE(12, 2) }
         else { WSKP_CASE(16, 1) WSKP_CASE(16, 2) }
-    } else {
+    } else if constexpr (MODE == CONV_PLAIN) {
         WSKP_CASE(16, 1)
-        WSKP_CASE(16, 2)
-        if constexpr (PREC != 0) { WSKP_CASE(32, 1) WSKP_CASE(32, 2) }
+        if constexpr (PREC != 0) { WSKP_CASE(32, 1) }
+    } else {
+        WSKP_CASE(16, 1) WSKP_CASE(16, 2) WSKP_CASE(16, 3) WSKP_CASE(16, 4)
+        if constexpr (PREC != 0) { WSKP_CASE(32, 1) WSKP_CASE(32, 2) WSKP_CASE(32, 3) WSKP_CASE(32, 4) }
     }
 #undef WSKP_CASE
     return false;
@@ -589,8 +698,9 @@ hipError_t launch_conv(const ConvLayer &L, int mode, int epi, int prec, const Fr
                        int blocks, hipStream_t s)
 {
     if (blocks <= 0) return hipSuccess;
-    const bool ok = prec == 0 ? dispatch<0>(L, mode, epi, fa, blocks, s)
-                              : dispatch<1>(L, mode, epi, fa, blocks, s);
+    const bool ok = prec == 0   ? dispatch<0>(L, mode, epi, fa, blocks, s)
+                    : prec == 1 ? dispatch<1>(L, mode, epi, fa, blocks, s)
+                                : dispatch<2>(L, mode, epi, fa, blocks, s);
     if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();
 }

@@ -159,33 +159,45 @@ __device__ __forceinline__ float4 f4scale(float w, float4 c)
     return make_float4(w, w * c.x, w * c.y, w * c.z);
 }
 
-// Horizontal then vertical window sums of a float4 plane st [HY][HX] for
+// Row stride (in float4) of the halo planes: 8 consecutive rows must fall in
+// distinct 16-byte bank groups (the horizontal pass gives consecutive lanes
+// consecutive rows), i.e. the stride must not be a multiple of 4.
+__device__ __host__ __forceinline__ int halo_stride(int R)
+{
+    const int hx = 32 + 2 * R;
+    return (hx % 4 == 0) ? hx + 2 : hx;
+}
+constexpr int kHB = 33;   // row-sum buffer stride (float4): rows land in distinct bank groups
+
+// Horizontal then vertical window sums of a float4 plane st [HY][HXS] for
 // kernel size K: returns in acc[t] the K x K window sums of the 4 components
-// for this thread's kRun centres.  hb holds the row sums [HY][32].
+// for this thread's kRun centres.  hb holds the row sums [HY][kHB].
+// Horizontal items are numbered row-fastest, so the lanes of a wave read
+// and write different rows at the same columns (no bank conflicts).
 template <int K>
-__device__ __forceinline__ void window_sums4(int R, int HX, const float4 *st, float4 *hb,
+__device__ __forceinline__ void window_sums4(int R, int HXS, const float4 *st, float4 *hb,
                                              float4 *acc)
 {
     constexpr int r = K / 2;
     const int tid = threadIdx.x;
-    const int nrows = kDTY + 2 * r;
+    constexpr int nrows = kDTY + 2 * r;
     constexpr int RPR = 32 / kHRun;
     for (int it = tid; it < nrows * RPR; it += kThreads) {
-        const int hy = R - r + it / RPR, xr = (it % RPR) * kHRun;
-        const int base = hy * HX + xr + R - r;
+        const int hy = R - r + it % nrows, xr = (it / nrows) * kHRun;
+        const int base = hy * HXS + xr + R - r;
         float4 v[K + kHRun - 1];
 #pragma unroll
         for (int j = 0; j < K + kHRun - 1; ++j) v[j] = st[base + j];
         float4 s[kHRun];
         box_run<K, kHRun>(v, s);
 #pragma unroll
-        for (int t = 0; t < kHRun; ++t) hb[hy * 32 + xr + t] = s[t];
+        for (int t = 0; t < kHRun; ++t) hb[hy * kHB + xr + t] = s[t];
     }
     __syncthreads();
     const int tx = tid & 31, ty = tid >> 5;
     float4 v[K + kRun - 1];
 #pragma unroll
-    for (int j = 0; j < K + kRun - 1; ++j) v[j] = hb[(kRun * ty + R - r + j) * 32 + tx];
+    for (int j = 0; j < K + kRun - 1; ++j) v[j] = hb[(kRun * ty + R - r + j) * kHB + tx];
     box_run<K, kRun>(v, acc);
     __syncthreads();
 }
@@ -220,7 +232,7 @@ __device__ __forceinline__ void load_w(const DecodeIO &io, int i, int x0, int y0
 
 // Dynamic LDS: irradiance plane cq float4 [HXY] (c0, c1, c2, 0), product
 // plane float4 [HXY] (W_i, W_i c) rebuilt for each kernel size, row sums
-// float4 [(kDTY+2R)][32].
+// float4 [(kDTY+2R)][kHB].
 //   DK_FRAMES / DK_TENSORS: forward, writes out.
 //   DK_ADJ_A: first half of the vector-Jacobian product.  Per centre p,
 //     with dF = g * mod, da_i = <dF, out_i>:
@@ -240,7 +252,7 @@ __global__ __launch_bounds__(kThreads) void decode_fwd_kernel(DecodeCfg dc, Fram
     if (!decode_locate<FRAMES>(dc, fa, dt, io, x0, y0)) return;
 
     const int R = dc.R;
-    const int HX = 32 + 2 * R, HXY = HX * (kDTY + 2 * R);
+    const int HX = halo_stride(R), HXY = HX * (kDTY + 2 * R);
     float4 *cq = lds4;
     float4 *pr = cq + HXY;
     float4 *hb = pr + HXY;
@@ -387,7 +399,7 @@ __global__ __launch_bounds__(kThreads) void decode_fwd_kernel(DecodeCfg dc, Fram
 //   dW_i(q)  = sum_ch c_ch(q) box_i(u_i,ch)(q) + box_i(dS_i)(q)  -> grad_head[q][i]
 //   dc_ch(q) = sum_i W_i(q) box_i(u_i,ch)(q)                      -> grad_c[q][ch]
 // One size at a time: stage the halo of (u_i, dS_i) as float4, row sums,
-// column sums.  LDS: float4 [HXY] staged + float4 [(kDTY+2R)][32] row sums.
+// column sums.  LDS: float4 [HXY] staged + float4 [(kDTY+2R)][kHB] row sums.
 template <int M>
 __global__ __launch_bounds__(kThreads) void decode_adj_b_kernel(DecodeCfg dc, DecodeTensors dt,
                                                                  float *grad_c)
@@ -398,7 +410,7 @@ __global__ __launch_bounds__(kThreads) void decode_adj_b_kernel(DecodeCfg dc, De
     int x0, y0;
     if (!decode_locate<false>(dc, fa, dt, io, x0, y0)) return;
     const int R = dc.R;
-    const int HX = 32 + 2 * R, HXY = HX * (kDTY + 2 * R);
+    const int HX = halo_stride(R), HXY = HX * (kDTY + 2 * R);
     float4 *st = lds4;
     float4 *hb = st + HXY;
     const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
@@ -461,14 +473,14 @@ __global__ __launch_bounds__(kThreads) void decode_adj_b_kernel(DecodeCfg dc, De
 
 static size_t decode_lds_bytes(const DecodeCfg &dc)
 {
-    const size_t HX = kDTX + 2 * dc.R, HY = kDTY + 2 * dc.R;
-    return sizeof(float4) * (2 * HX * HY + HY * kDTX);
+    const size_t HX = halo_stride(dc.R), HY = kDTY + 2 * dc.R;
+    return sizeof(float4) * (2 * HX * HY + HY * kHB);
 }
 
 static size_t adj_b_lds_bytes(const DecodeCfg &dc)
 {
-    const size_t HX = kDTX + 2 * dc.R, HY = kDTY + 2 * dc.R;
-    return sizeof(float4) * (HX * HY + HY * kDTX);
+    const size_t HX = halo_stride(dc.R), HY = kDTY + 2 * dc.R;
+    return sizeof(float4) * (HX * HY + HY * kHB);
 }
 
 template <typename K>

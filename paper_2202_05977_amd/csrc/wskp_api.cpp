@@ -5,6 +5,7 @@
 #include "wskp.h"
 #include "wskp_internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -38,6 +39,7 @@ struct LayerPlan {
     int epi;
     int Cin;
     size_t w_off, b_off;  // byte offsets into the device weight buffer
+    size_t q_off;         // fp8: per-channel dequantisation factors (0 = none)
 };
 
 // Host round-to-nearest-even to bf16 (the usual bit-level method).
@@ -50,7 +52,50 @@ uint16_t host_bf16(float f)
     return (uint16_t)(u >> 16);
 }
 
+// Host round-to-nearest-even to OCP e4m3 (1 sign, 4 exponent bits with bias
+// 7, 3 mantissa bits; largest finite 448, smallest subnormal 2^-9), with
+// saturation at +-448.  Works on the exact binary value of x.
+uint8_t host_e4m3(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    const uint8_t sign = (uint8_t)((u >> 24) & 0x80);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7f;            // NaN
+    float a = std::fabs(x);
+    if (a >= 448.f) return sign | 0x7e;                           // saturate
+    int e;
+    const float m = std::frexp(a, &e);                            // a = m * 2^e, m in [0.5, 1)
+    if (a == 0.f) return sign;
+    // exponent of the leading bit: E = e - 1; normal range E >= -6
+    int E = e - 1;
+    double q;      // value in units of the last mantissa bit
+    int ulp_exp;
+    if (E < -6) { ulp_exp = -9; }                                 // subnormal spacing 2^-9
+    else { ulp_exp = E - 3; }
+    q = std::ldexp((double)a, -ulp_exp);                          // exact in double
+    double fl = std::floor(q);
+    double rem = q - fl;
+    uint32_t n = (uint32_t)fl;
+    if (rem > 0.5 || (rem == 0.5 && (n & 1u))) ++n;
+    (void)m;
+    // n counts ulps of 2^ulp_exp: encode
+    if (ulp_exp == -9) {
+        // subnormal (n <= 8; n == 8 is the smallest normal 2^-6, encoding 0x08)
+        return sign | (uint8_t)n;
+    }
+    // normal: n in [8, 16]; 16 means the next binade
+    int be = E + 7;
+    if (n >= 16) { n >>= 1; ++be; }
+    if (be > 15 || (be == 15 && (n & 7u) == 7u)) return sign | 0x7e;
+    return sign | (uint8_t)(be << 3) | (uint8_t)(n & 7u);
+}
+
 }  // namespace
+
+extern "C" void wskp_fp8_e4m3_encode(const float *x, uint8_t *out, size_t n)
+{
+    for (size_t i = 0; i < n; ++i) out[i] = host_e4m3(x[i]);
+}
 
 struct wskp_ctx {
     wskp_config_t cfg;
@@ -123,7 +168,11 @@ extern "C" size_t wskp_num_weights(const wskp_config_t *cfg)
 }
 
 // Packs OIHW fp32 weights into the order the kernels read (see conv3x3.hip).
-static void pack_layer(int prec, const LayerPlan &lp, const float *w, std::vector<char> &out)
+// fp8: per output channel, w is divided by s_w[co] = max|w_co| / 448 before
+// rounding; dq[co] receives s_in * s_w[co], the factor that turns the
+// fp8 accumulator back into the layer's pre-bias output.
+static void pack_layer(int prec, const LayerPlan &lp, const float *w, std::vector<char> &out,
+                       float s_in = 1.f, std::vector<float> *dq = nullptr)
 {
     const ConvLayer &L = lp.L;
     const int CK = L.CK, nch = L.Cin_pad / CK, Cin = lp.Cin, Cout = L.Cout;
@@ -131,7 +180,29 @@ static void pack_layer(int prec, const LayerPlan &lp, const float *w, std::vecto
         if (co >= Cout || ci >= Cin) return 0.f;
         return w[((size_t)co * Cin + ci) * 9 + tap];
     };
-    if (prec == WSKP_PREC_FP32) {
+    if (prec == WSKP_PREC_FP8_E4M3) {
+        // [chunk][Cout_pad][NK*128] bytes, K = tap*CK + c, zero padded
+        const int NR = 9 * CK / 32, NK = (NR + 3) / 4, KR = NK * 128;
+        std::vector<float> sw(L.Cout_pad, 1.f);
+        for (int co = 0; co < Cout; ++co) {
+            float mx = 0.f;
+            for (int ci = 0; ci < Cin; ++ci)
+                for (int t = 0; t < 9; ++t) mx = std::max(mx, std::fabs(W(co, ci, t)));
+            sw[co] = mx > 0.f ? mx / 448.f : 1.f;
+        }
+        out.assign((size_t)nch * L.Cout_pad * KR, 0);
+        uint8_t *o = reinterpret_cast<uint8_t *>(out.data());
+        for (int cc = 0; cc < nch; ++cc)
+            for (int co = 0; co < L.Cout_pad; ++co)
+                for (int k = 0; k < 9 * CK; ++k) {
+                    const int tap = k / CK, c = k % CK;
+                    o[((size_t)cc * L.Cout_pad + co) * KR + k] = host_e4m3(W(co, cc * CK + c, tap) / sw[co]);
+                }
+        if (dq) {
+            dq->assign(L.Cout_pad, 0.f);
+            for (int co = 0; co < Cout; ++co) (*dq)[co] = s_in * sw[co];
+        }
+    } else if (prec == WSKP_PREC_FP32) {
         // [chunk][tap][c][Cout_pad]
         out.assign((size_t)nch * 9 * CK * L.Cout_pad * 4, 0);
         float *o = reinterpret_cast<float *>(out.data());
@@ -158,13 +229,17 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
                                      size_t n_weights, const float *host_act_scales, int device,
                                      wskp_handle_t *out)
 {
-    (void)host_act_scales;
     if (!out) return fail(WSKP_E_INVALID_ARG, "out handle pointer is NULL");
     *out = nullptr;
     wskp_status_t st = check_config(cfg);
     if (st != WSKP_OK) return st;
-    if (cfg->precision == WSKP_PREC_FP8_E4M3)
-        return fail(WSKP_E_UNSUPPORTED, "FP8 convolutions are not available in this build");
+    if (cfg->precision == WSKP_PREC_FP8_E4M3) {
+        if (!host_act_scales)
+            return fail(WSKP_E_INVALID_ARG, "FP8 needs one activation scale per conv (host_act_scales)");
+        for (int l = 0; l < cfg->levels; ++l)
+            if (cfg->channels[l] % 32)
+                return fail(WSKP_E_UNSUPPORTED, "FP8 needs every level width to be a multiple of 32");
+    }
     if (!host_weights) return fail(WSKP_E_INVALID_ARG, "weights pointer is NULL");
     if (n_weights != wskp_num_weights(cfg))
         return fail(WSKP_E_INVALID_ARG, "weight count does not match wskp_num_weights(cfg)");
@@ -184,7 +259,7 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
     h->cfg = *cfg;
     h->device = device;
     h->prec = cfg->precision;
-    h->act_bytes = h->prec == WSKP_PREC_FP32 ? 4 : 2;
+    h->act_bytes = h->prec == WSKP_PREC_FP32 ? 4 : 2;   // bf16 activations for bf16 and fp8
 
     // ---- layer plan
     const int L = cfg->levels, M = cfg->num_kernels;
@@ -204,7 +279,7 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
         c.Cin_pad = (Cin + c.CK - 1) / c.CK * c.CK;
         c.Cout = Cout;
         const int nblk = (Cout + 15) / 16;
-        c.NB = (nblk % 2 == 0) ? 2 : 1;
+        c.NB = conv_blocks_per_group(mode, nblk);
         c.groups = nblk / c.NB;
         c.Cout_pad = nblk * 16;
         c.out_kind = okind;
@@ -233,11 +308,25 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
         LayerPlan &lp = h->layers[i];
         const int Cin = dims[i].first, Cout = dims[i].second;
         std::vector<char> pk;
-        pack_layer(h->prec, lp, host_weights + src, pk);
+        std::vector<float> dq;
+        const bool f8 = h->prec == WSKP_PREC_FP8_E4M3;
+        if (f8 && !(host_act_scales[i] > 0.f)) {
+            delete h;
+            return fail(WSKP_E_INVALID_ARG, "FP8 activation scales must be > 0");
+        }
+        const float s_in = f8 ? host_act_scales[i] : 1.f;
+        pack_layer(h->prec, lp, host_weights + src, pk, s_in, f8 ? &dq : nullptr);
+        lp.L.in_qscale = 1.f / s_in;
         src += (size_t)Cout * Cin * 9;
         lp.w_off = align_up(blob.size());
         blob.resize(lp.w_off + pk.size());
         std::memcpy(blob.data() + lp.w_off, pk.data(), pk.size());
+        lp.q_off = 0;
+        if (f8) {
+            lp.q_off = align_up(blob.size());
+            blob.resize(lp.q_off + dq.size() * 4);
+            std::memcpy(blob.data() + lp.q_off, dq.data(), dq.size() * 4);
+        }
         lp.b_off = align_up(blob.size());
         blob.resize(lp.b_off + (size_t)Cout * 4);
         std::memcpy(blob.data() + lp.b_off, host_weights + src, (size_t)Cout * 4);
@@ -255,6 +344,9 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
     for (auto &lp : h->layers) {
         lp.L.w = static_cast<char *>(h->dweights) + lp.w_off;
         lp.L.bias = reinterpret_cast<const float *>(static_cast<char *>(h->dweights) + lp.b_off);
+        lp.L.out_scale = lp.q_off ? reinterpret_cast<const float *>(static_cast<char *>(h->dweights) +
+                                                                    lp.q_off)
+                                  : nullptr;
     }
 
     // ---- decode configuration

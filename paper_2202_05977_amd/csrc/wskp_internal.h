@@ -72,6 +72,8 @@ struct ConvLayer {
     const void *w;     // packed weights
     const float *bias; // [Cout]
     float inv_gamma, dnear, dinv;  // CONV_PACK preprocessing constants
+    float in_qscale;           // fp8: 1 / (input activation scale)
+    const float *out_scale;    // fp8: per output channel, input scale x weight scale
 };
 
 struct DecodeCfg {
@@ -89,6 +91,8 @@ hipError_t launch_conv(const ConvLayer &L, int mode, int epi, int prec, const Fr
                        int blocks, hipStream_t s);
 int conv_grid(const ConvLayer &L, int n, const int *H, const int *W);
 int conv_chunk(int prec, int mode, int Cin, int C0);
+// 16-channel output blocks per workgroup for a layer with nblk blocks.
+int conv_blocks_per_group(int mode, int nblk);
 // Decode + fusion + remodulation over frames of fa (denoise mode: c and mod
 // derive from r, a) -- or over plain tensors (decode mode).
 hipError_t launch_decode_frames(const DecodeCfg &dc, const FrameArg &fa, int blocks, hipStream_t s);

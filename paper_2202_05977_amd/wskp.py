@@ -88,6 +88,8 @@ def lib():
         L.wskp_timing_read.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_float), ip, ip]
         L.wskp_launch_name.argtypes = [vp, i32]
         L.wskp_launch_name.restype = ctypes.c_char_p
+        L.wskp_fp8_e4m3_encode.argtypes = [vp, vp, sz]
+        L.wskp_fp8_e4m3_encode.restype = None
         L.wskp_status_string.argtypes = [i32]
         L.wskp_status_string.restype = ctypes.c_char_p
         L.wskp_last_error.argtypes = []
@@ -245,6 +247,13 @@ def wskp_backward(h, head, c, mod, grad_out, grad_head, grad_c, ws, stream=None)
            "wskp_backward")
 
 
+def wskp_fp8_e4m3_encode(x: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    out = np.empty(x.shape, dtype=np.uint8)
+    lib().wskp_fp8_e4m3_encode(x.ctypes.data, out.ctypes.data, x.size)
+    return out
+
+
 def wskp_timing_enable(h, max_calls: int) -> None:
     _check(lib().wskp_timing_enable(h, max_calls), "wskp_timing_enable")
 
@@ -312,6 +321,30 @@ class Denoiser:
             self.close()
         except Exception:
             pass
+
+
+def calibrate_fp8_scales(cfg: NetConfig, weights: np.ndarray, frame: Dict[str, torch.Tensor],
+                         margin: float = 2.0) -> np.ndarray:
+    """Per-conv input scales for the FP8 form from one pass of the FP32 path.
+
+    Each conv's input activations are stored as e4m3(x / s) with
+    s = margin * amax(x) / 448, amax measured on ``frame`` (the network input
+    lies in [0, 1]; a decoder conv's input is [up(u_{l+1}), e_l], so its
+    amax is the larger of the two).
+    """
+    dn = Denoiser(cfg, weights, "fp32")
+    H, W = frame["radiance"].shape[:2]
+    dn(frame)
+    torch.cuda.synchronize()
+    L = cfg.levels
+    amax_e = [float(dn.intermediate([H], [W], 0, l).abs().max()) for l in range(L)]
+    amax_u = [float(dn.intermediate([H], [W], 0, 100 + l).abs().max()) for l in range(L - 1)]
+    amax_u.append(amax_e[L - 1])
+    amax = [1.0] + [amax_e[l - 1] for l in range(1, L)]
+    amax += [max(amax_u[l + 1], amax_e[l]) for l in range(L - 2, -1, -1)]
+    amax.append(amax_u[0])
+    dn.close()
+    return (np.maximum(np.array(amax), 1e-6) * margin / 448.0).astype(np.float32)
 
 
 class WskpDecode(torch.autograd.Function):

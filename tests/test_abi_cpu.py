@@ -87,3 +87,21 @@ def test_create_without_device_fails_cleanly():
     with pytest.raises(wskp.WskpError) as ei:
         wskp.wskp_create(synth.SMALL, blob)
     assert ei.value.status == -4
+
+
+def test_host_e4m3_encoder_matches_library_cast():
+    """The host e4m3 encoder (FP8 weights) rounds like torch's float8_e4m3fn
+    cast inside the finite range and saturates at +-448 outside it."""
+    wskp = _wskp()
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(0)
+    x = np.concatenate([
+        rng.normal(0, 1, 4000), rng.normal(0, 100, 2000), rng.uniform(-448, 448, 2000),
+        np.ldexp(rng.uniform(1, 2, 1000), rng.integers(-12, -5, 1000)),   # subnormal range
+        np.array([0.0, -0.0, 2.0 ** -9, 2.0 ** -10, 3 * 2.0 ** -11, 448.0, -448.0,
+                  1.0625, 1.1875, 17.0, 19.0, 240.0, 432.0, 440.0, 447.9])]).astype(np.float32)
+    got = wskp.wskp_fp8_e4m3_encode(x)
+    ref = torch.from_numpy(x).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    np.testing.assert_array_equal(got, ref)
+    sat = wskp.wskp_fp8_e4m3_encode(np.array([500.0, -1e9, 449.0], np.float32))
+    np.testing.assert_array_equal(sat, [0x7E, 0xFE, 0x7E])

@@ -106,3 +106,55 @@ def test_shape_errors():
     with pytest.raises(wskp.WskpError) as ei:
         dn(fr)
     assert ei.value.status == -2
+
+
+def test_served_results_equal_single_frames():
+    """Frames pushed through the continuous-batching server (mixed sizes,
+    two streams in flight, shared workspace arena) equal the same frames
+    denoised alone, bitwise."""
+    from paper_2202_05977_amd import serve, wskp
+    cfg = synth.SMALL
+    dn = _denoiser(cfg, "bf16")
+    res = [(64, 64), (128, 96), (32, 160), (72, 104)]
+    sizes, reqs = serve.poisson_trace(8, 6, 4000.0, res, seed=5)
+    inputs = {s: {k: v for k, v in to_dev(synth.make_frame(300 + s, *sizes[s])).items()
+                  if k != "clean"} for s in range(8)}
+    budget = 4 * wskp.wskp_workspace_size(dn.h, [128] * 3, [160] * 3)
+    ex = serve.GpuExecutor(dn, inputs, budget, slots=2, ring=2)
+    st = serve.Server(ex, budget, max_inflight=2, max_batch=5).run(reqs, realtime=False)
+    torch.cuda.synchronize()
+    assert st.errors == 0 and st.frames == len(reqs) and st.max_batch > 1
+    for s in range(8):
+        alone = dn(inputs[s]).clone()
+        torch.cuda.synchronize()
+        for k in range(2):
+            assert torch.equal(ex.output_of(s, k), alone), (s, k)
+
+
+def test_hd_fp8_720p_reported_error():
+    """FP8 (e4m3, per-channel weight scales, calibrated activation scales)
+    convs: the error vs the FP64 oracle is reported; the gate only catches a
+    wrong encoding or layout (those give errors of order 1)."""
+    from paper_2202_05977_amd import wskp
+    cfg = synth.HD
+    blob = synth.make_weights(cfg, 0)
+    scales = wskp.calibrate_fp8_scales(cfg, blob, to_dev(synth.make_frame(999, 720, 1280)))
+    assert scales.shape == (len(synth.conv_shapes(cfg)),) and np.all(scales > 0)
+    fr, y, _ = _oracle("hd", 1, 720, 1280)
+    dn = wskp.Denoiser(cfg, blob, "fp8", act_scales=scales)
+    out = _run(dn, fr)
+    err = rel_l2(out, y)
+    print(f"fp8 720p rel-L2 vs FP64 oracle: {err:.3e}, max-rel {max_rel(out, y):.3e}")
+    assert np.all(np.isfinite(out))
+    assert err <= 0.1
+
+
+def test_fp8_needs_scales_and_32_wide_levels():
+    from paper_2202_05977_amd import wskp
+    with pytest.raises(wskp.WskpError) as ei:
+        wskp.Denoiser(synth.HD, synth.make_weights(synth.HD), "fp8")
+    assert ei.value.status == -1
+    with pytest.raises(wskp.WskpError) as ei:
+        wskp.Denoiser(synth.SMALL, synth.make_weights(synth.SMALL), "fp8",
+                      act_scales=np.ones(6, np.float32))
+    assert ei.value.status == -3
