@@ -276,6 +276,31 @@ def dataclasses_replace(r):
     return dataclasses.replace(r)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_720p.json")
+
+
+def source_sha(rel: str) -> str:
+    import hashlib
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel: str, prec: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counters
+    (FETCH_SIZE and WRITE_SIZE in KiB, scaled by the factors a plain device
+    copy of known size gives), or None if there are none for this kernel or
+    its source has changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    e = t.get("kernels", {}).get(f"{kernel}/{prec}")
+    if not e or source_sha(e["source"]) != e["source_sha256"]:
+        return None
+    return (e["fetch_kib"] * t["fetch_factor"] + e["write_kib"] * t["write_factor"]) * 1024.0
+
+
 def omp_threads() -> int:
     try:
         omp = ctypes.CDLL("libgomp.so.1")
@@ -351,17 +376,18 @@ def main():
     if dom == "decode":
         achieved = decode_bytes(cfg, H, W) / (pk[dom] * 1e-6)
         roof = {"kernel": dom, "bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK, "traffic": None}
+                "unit": "GB/s", "frac": achieved / HBM_PEAK,
+                "traffic": measured_traffic(dom, head)}
     else:
         achieved = flops[dom] / (pk[dom] * 1e-6)
         roof = {"kernel": dom, "bound": "mfma", "achieved": achieved / 1e12,
                 "peak": PEAK[head] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK[head],
-                "traffic": None}
+                "traffic": measured_traffic(dom, head)}
     dbytes = decode_bytes(cfg, H, W)
     dec_gbs = dbytes / (pk["decode"] * 1e-6)
     decode_roof = {"kernel": "decode", "bound": "hbm", "achieved": dec_gbs / 1e9,
                    "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": dec_gbs / HBM_PEAK,
-                   "bytes_per_launch": dbytes, "traffic": None}
+                   "bytes_per_launch": dbytes, "traffic": measured_traffic("decode", head)}
     conv_mfma = {}
     for p in precs:
         tot = sum(flops.values())

@@ -215,10 +215,10 @@ struct Stage {
     static constexpr int A_BYTES = F8 ? HP * WP * PS8 : (BF ? HP * WP * PS * 2 : CK * PL * 4);
     static constexpr int B_BYTES = F8 ? NB * 16 * BSK8 : (BF ? NB * 16 * BSK * 2 : KE * BS * 4);
     // weight items: 16 bytes of the packed chunk
-    static constexpr int WTOT = F8 ? NB * 16 * NK * 8 : (BF ? NB * 16 * (NK * 32 / 8) : KE * NB * 4);
+    static constexpr int WTOT = F8 ? NB * 16 * NK * 8 : (BF ? NB * 16 * (BSK / 8) : KE * NB * 4);
     static constexpr int WIT = (WTOT + kThreads - 1) / kThreads;
     // per-chunk stride of the packed weights, in elements of the packed type, per output channel
-    static constexpr int WCHUNK = F8 ? NK * 128 : (BF ? NK * 32 : KE);
+    static constexpr int WCHUNK = F8 ? NK * 128 : (BF ? BSK : KE);
 
     uint4 in[IT][RW];
     uint4 w[WIT];
@@ -260,9 +260,8 @@ struct Stage {
                     const int co = it / (NK * 8), q = it - co * (NK * 8);
                     woff[k] = (g * NB * 16 + co) * (NK * 128) + q * 16;
                 } else if constexpr (BF) {
-                    constexpr int KV = NK * 32 / 8;
-                    const int co = it / KV, q = it - co * KV;
-                    woff[k] = (g * NB * 16 + co) * (NK * 32) + q * 8;
+                    // the group's padded rows are one contiguous block
+                    woff[k] = g * NB * 16 * BSK + it * 8;
                 } else {
                     const int e = it / (NB * 4), q = it - e * (NB * 4);
                     woff[k] = e * L.Cout_pad + g * NB * 16 + q * 4;
@@ -397,9 +396,7 @@ struct Stage {
                 const int co = it / (NK * 8), q = it - co * (NK * 8);
                 *reinterpret_cast<uint4 *>(static_cast<unsigned char *>(Bs_) + co * BSK8 + q * 16) = w[k];
             } else if constexpr (BF) {
-                constexpr int KV = NK * 32 / 8;
-                const int co = it / KV, q = it - co * KV;
-                *reinterpret_cast<uint4 *>(static_cast<unsigned short *>(Bs_) + co * BSK + q * 8) = w[k];
+                *reinterpret_cast<uint4 *>(static_cast<unsigned short *>(Bs_) + it * 8) = w[k];
             } else {
                 const int e = it / (NB * 4), q = it - e * (NB * 4);
                 *reinterpret_cast<uint4 *>(static_cast<float *>(Bs_) + e * BS + q * 4) = w[k];
@@ -505,6 +502,72 @@ __device__ __forceinline__ void chunk_mfma(const void *As_, const void *Bs_, f32
     }
 }
 
+// Epilogue shared by the conv kernels: bias (and the fp8 dequantisation
+// factor) plus activation into an LDS tile, then coalesced stores of runs of
+// channels per pixel.  smem must hold TH*32*(16*NB+1) floats and be free.
+template <int PREC, int EPI, int TH, int NB, typename OutT>
+__device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDesc &fd, int g, int x0,
+                                              int y0, int Hl, int Wl, f32x4 (*acc)[NB],
+                                              unsigned char *smem)
+{
+    constexpr int MB = TH / 2;
+    constexpr int NC = NB * 16;
+    constexpr int OS = NC + 1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lj = lane & 15, lq = lane >> 4;
+    // phase 1: bias + activation into an LDS tile [TH*32][NC]
+    // (lane holds channel lj of pixels 4*lq + v of each 16-px block)
+    float *Ot = reinterpret_cast<float *>(smem);
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
+        const int blk = wave * MB + i, row = blk >> 1, cb = blk & 1;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int cl = nb * 16 + lj, co = g * NC + cl;
+            const float bias = co < L.Cout ? L.bias[co] : 0.f;
+            const float dq = (PREC == 2 && co < L.Cout) ? L.out_scale[co] : 1.f;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int px = row * kConvTW + cb * 16 + lq * 4 + v;
+                Ot[px * OS + cl] = epilogue<EPI>(acc[i][nb][v] * dq + bias, co, L.M);
+            }
+        }
+    }
+    __syncthreads();
+    // phase 2: coalesced stores of runs of V channels per pixel
+    OutT *dst = conv_dst<OutT>(L, fd);
+    const int ncw = min(NC, L.Cout - g * NC);      // channels this workgroup writes
+    if constexpr (std::is_same<OutT, float>::value) {
+        // fp32 (head record): float2 runs (channel counts are even); the loop
+        // runs over the compile-time maximum so its index math is shifts
+        const int nv = ncw >> 1;
+        constexpr int NV = NC / 2;
+        for (int it = tid; it < TH * kConvTW * NV; it += kThreads) {
+            const int px = it / NV, c2 = (it % NV) * 2;
+            const int y = y0 + px / kConvTW, x = x0 + px % kConvTW;
+            if ((c2 >> 1) < nv && y < Hl && x < Wl) {
+                float2 v = make_float2(Ot[px * OS + c2], Ot[px * OS + c2 + 1]);
+                *reinterpret_cast<float2 *>(dst + ((size_t)y * Wl + x) * L.Cout + g * NC + c2) = v;
+            }
+        }
+    } else {
+        // bf16: runs of 4 channels (8 bytes)
+        const int nv = ncw >> 2;
+        constexpr int NV = NC / 4;
+        for (int it = tid; it < TH * kConvTW * NV; it += kThreads) {
+            const int px = it / NV, c4 = (it % NV) * 4;
+            const int y = y0 + px / kConvTW, x = x0 + px % kConvTW;
+            if ((c4 >> 2) < nv && y < Hl && x < Wl) {
+                const float *o = &Ot[px * OS + c4];
+                uint2 v;
+                v.x = pack2(o[0], o[1]);
+                v.y = pack2(o[2], o[3]);
+                *reinterpret_cast<uint2 *>(dst + ((size_t)y * Wl + x) * L.Cout + g * NC + c4) = v;
+            }
+        }
+    }
+}
+
 template <int PREC, int MODE, int EPI, int TH, int CK, int NB, typename SrcT, typename OutT>
 #ifndef WSKP_CONV_MIN_WG
 #define WSKP_CONV_MIN_WG 1
@@ -547,55 +610,150 @@ __global__ __launch_bounds__(kThreads, WSKP_CONV_MIN_WG) void conv3x3_kernel(Con
         chunk_mfma<PREC, MODE, CK, TH, NB, SrcT>(As, Bs, acc);
     }
 
-    // epilogue, phase 1: bias + activation into an LDS tile [TH*32][NC]
-    // (lane holds channel lj of pixels 4*lq + v of each 16-px block)
     __syncthreads();
-    float *Ot = reinterpret_cast<float *>(smem);
+    conv_epilogue<PREC, EPI, TH, NB, OutT>(L, fd, g, x0, y0, Hl, Wl, acc, smem);
+}
+
+// =============================================================================
+// bf16 decoder and head convs with direct-to-LDS buffer loads
+// =============================================================================
+// Every 16-byte slot of the input halo (8 bf16 channels of one pixel) and of
+// the weight slice goes from memory straight into LDS with
+// buffer_load_dwordx4 ... lds: no registers hold staged data and no commit
+// pass rewrites it.  A wave-level load writes 64 consecutive slots, so the
+// LDS image of the halo is pixel-major with 4 slots per pixel (CK = 32
+// channels); to keep the MFMA fragment reads conflict-free the 4 slots of
+// pixel p hold channel groups in the order g ^ ((p >> 1) & 3), which each
+// lane realises by choosing which group it fetches.  Pixels outside the image
+// get an offset beyond the buffer's range, and the hardware returns zeros:
+// that is the conv's zero padding.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+
+// The descriptor must live in scalar registers: base and size are made
+// visibly wave-uniform (they are: every lane computes the same values).
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, unsigned bytes)
+{
+    const unsigned long long b = reinterpret_cast<unsigned long long>(base);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    void *ub = reinterpret_cast<void *>(((unsigned long long)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(ub, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes),
+                                             0x00020000);
+}
+
+__device__ __forceinline__ void load_lds16(rsrc_t r, unsigned char *lds, unsigned voff)
+{
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void *)lds, 16,
+                                             (int)voff, 0, 0, 0);
+}
+
+constexpr unsigned kOutOfRange = 0x7ffffff0u;
+
+template <int MODE, int EPI, int TH, int NB, typename OutT>
+__global__ __launch_bounds__(kThreads) void conv3x3_bf16_direct(ConvLayer L, FrameArg fa)
+{
+    constexpr int CK = 32, WP = kConvTW + 2, HP = TH + 2, NPIX = HP * WP;
+    constexpr int A_SLOTS = NPIX * 4;
+    constexpr int A_INS = (A_SLOTS + 63) / 64;
+    constexpr int A_PW = (A_INS + 3) / 4;          // load instructions per wave
+    constexpr int NK = 9;                           // one tap (32 channels) per MFMA
+    constexpr int BSK = NK * 32 + 8;                // padded weight row (elements)
+    constexpr int B_SLOTS = NB * 16 * BSK / 8;
+    constexpr int B_INS = (B_SLOTS + 63) / 64;
+    constexpr int B_PW = (B_INS + 3) / 4;
+    constexpr int A_BYTES = A_INS * 1024, B_BYTES = B_INS * 1024;
+    constexpr int MB = TH / 2, NC = NB * 16;
+    constexpr int OUT_BYTES = TH * kConvTW * (NC + 1) * 4;
+    constexpr int LDS_BYTES = (A_BYTES + B_BYTES > OUT_BYTES) ? A_BYTES + B_BYTES : OUT_BYTES;
+    __shared__ __attribute__((aligned(1024))) unsigned char smem[LDS_BYTES];
+    unsigned char *As = smem;
+    unsigned char *Bs = smem + A_BYTES;
+
+    int f, g, x0, y0, Hl, Wl;
+    if (!conv_locate<TH>(L, fa, f, g, x0, y0, Hl, Wl)) return;
+    const FrameDesc &fd = frame_at(fa, f);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lj = lane & 15, lq = lane >> 4;
+
+    const unsigned short *s0 =
+        reinterpret_cast<const unsigned short *>(L.src0_kind ? fd.u[L.src0_idx] : fd.e[L.src0_idx]);
+    const unsigned short *s1 = reinterpret_cast<const unsigned short *>(fd.e[L.src1_idx]);
+    const int H0 = MODE == CONV_CAT ? Hl >> 1 : Hl, W0 = MODE == CONV_CAT ? Wl >> 1 : Wl;
+    const rsrc_t r0 = make_rsrc(s0, (unsigned)((size_t)H0 * W0 * L.C0 * 2));
+    const rsrc_t r1 = make_rsrc(s1, MODE == CONV_CAT ? (unsigned)((size_t)Hl * Wl * L.C1 * 2) : 0u);
+    const int nchunks = L.Cin_pad / CK;
+    const rsrc_t rw = make_rsrc(L.w, (unsigned)((size_t)nchunks * L.Cout_pad * BSK * 2));
+
+    // byte offsets of this wave's A slots in source 0 and source 1 (chunk 0)
+    unsigned oa0[A_PW], oa1[A_PW];
 #pragma unroll
-    for (int i = 0; i < MB; ++i) {
-        const int blk = wave * MB + i, row = blk >> 1, cb = blk & 1;
+    for (int k = 0; k < A_PW; ++k) {
+        const int ins = wave + 4 * k;
+        const int slot = ins * 64 + lane;
+        const int p = slot >> 2, gch = (slot & 3) ^ ((p >> 1) & 3);
+        const int ly = p / WP, lx = p - ly * WP;
+        const int gy = y0 - 1 + ly, gx = x0 - 1 + lx;
+        oa0[k] = oa1[k] = kOutOfRange;
+        if (ins < A_INS && slot < A_SLOTS && gy >= 0 && gy < Hl && gx >= 0 && gx < Wl) {
+            if (MODE == CONV_CAT) {
+                oa0[k] = (unsigned)((((gy >> 1) * W0 + (gx >> 1)) * L.C0 + gch * 8) * 2);
+                oa1[k] = (unsigned)(((gy * Wl + gx) * L.C1 + gch * 8) * 2);
+            } else {
+                oa0[k] = (unsigned)(((gy * Wl + gx) * L.C0 + gch * 8) * 2);
+            }
+        }
+    }
+
+    f32x4 acc[MB][NB];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const int cl = nb * 16 + lj, co = g * NC + cl;
-            const float bias = co < L.Cout ? L.bias[co] : 0.f;
-            const float dq = (PREC == 2 && co < L.Cout) ? L.out_scale[co] : 1.f;
+    for (int i = 0; i < MB; ++i)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int px = row * kConvTW + cb * 16 + lq * 4 + v;
-                Ot[px * OS + cl] = epilogue<EPI>(acc[i][nb][v] * dq + bias, co, L.M);
+        for (int nb = 0; nb < NB; ++nb) acc[i][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int cc = 0; cc < nchunks; ++cc) {
+        if (cc) __syncthreads();     // the previous chunk's fragments have been read
+        const int c0 = cc * CK;
+        const bool up = MODE != CONV_CAT || c0 < L.C0;
+        const unsigned da = (unsigned)((up ? c0 : c0 - L.C0) * 2);
+#pragma unroll
+        for (int k = 0; k < A_PW; ++k) {
+            const int ins = wave + 4 * k;
+            if (ins < A_INS) {
+                if (up) load_lds16(r0, As + ins * 1024, oa0[k] + da);
+                else load_lds16(r1, As + ins * 1024, oa1[k] + da);
+            }
+        }
+        const unsigned wb = (unsigned)((cc * L.Cout_pad + g * NC) * BSK * 2);
+#pragma unroll
+        for (int k = 0; k < B_PW; ++k) {
+            const int ins = wave + 4 * k;
+            if (ins < B_INS) load_lds16(rw, Bs + ins * 1024, wb + (unsigned)((ins * 64 + lane) * 16));
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < NK; ++s) {
+            const int dy = s / 3, dx = s % 3;
+            bf16x8 b[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+                b[nb] = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const u16x8 *>(Bs + ((nb * 16 + lj) * BSK + s * 32 + lq * 8) * 2));
+#pragma unroll
+            for (int i = 0; i < MB; ++i) {
+                const int blk = wave * MB + i, row = blk >> 1, cb = blk & 1;
+                const int p = (row + dy) * WP + cb * 16 + lj + dx;
+                const int slot = p * 4 + (lq ^ ((p >> 1) & 3));
+                const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(As + slot * 16));
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[i][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[i][nb], 0, 0, 0);
             }
         }
     }
     __syncthreads();
-    // phase 2: coalesced stores of runs of V channels per pixel
-    OutT *dst = conv_dst<OutT>(L, fd);
-    const int ncw = min(NC, L.Cout - g * NC);      // channels this workgroup writes
-    if constexpr (std::is_same<OutT, float>::value) {
-        // fp32 (head record): float2 runs (channel counts are even)
-        const int nv = ncw >> 1;
-        for (int it = tid; it < TH * kConvTW * nv; it += kThreads) {
-            const int px = it / nv, c2 = (it - px * nv) * 2;
-            const int y = y0 + px / kConvTW, x = x0 + px % kConvTW;
-            if (y < Hl && x < Wl) {
-                float2 v = make_float2(Ot[px * OS + c2], Ot[px * OS + c2 + 1]);
-                *reinterpret_cast<float2 *>(dst + ((size_t)y * Wl + x) * L.Cout + g * NC + c2) = v;
-            }
-        }
-    } else {
-        // bf16: runs of 4 channels (8 bytes)
-        const int nv = ncw >> 2;
-        for (int it = tid; it < TH * kConvTW * nv; it += kThreads) {
-            const int px = it / nv, c4 = (it - px * nv) * 4;
-            const int y = y0 + px / kConvTW, x = x0 + px % kConvTW;
-            if (y < Hl && x < Wl) {
-                const float *o = &Ot[px * OS + c4];
-                uint2 v;
-                v.x = pack2(o[0], o[1]);
-                v.y = pack2(o[2], o[3]);
-                *reinterpret_cast<uint2 *>(dst + ((size_t)y * Wl + x) * L.Cout + g * NC + c4) = v;
-            }
-        }
-    }
+    conv_epilogue<1, EPI, TH, NB, OutT>(L, fd, g, x0, y0, Hl, Wl, acc, smem);
 }
 
 // =============================================================================
@@ -640,9 +798,18 @@ int conv_grid(const ConvLayer &L, int n, const int *H, const int *W)
     return (int)total;
 }
 
+#ifndef WSKP_CONV_DIRECT
+#define WSKP_CONV_DIRECT 1
+#endif
+
 template <int PREC, int MODE, int EPI, int CK, int NB, typename OutT>
 static void launch_one(const ConvLayer &L, const FrameArg &fa, int blocks, hipStream_t s)
 {
+    if constexpr (WSKP_CONV_DIRECT && PREC == 1 && CK == 32 && (MODE == CONV_CAT || MODE == CONV_PLAIN)) {
+        hipLaunchKernelGGL((conv3x3_bf16_direct<MODE, EPI, kTH, NB, OutT>), dim3(blocks),
+                           dim3(kThreads), 0, s, L, fa);
+        return;
+    }
     // fp32 activations travel with the fp32 MFMA form; the bf16 and fp8 forms
     // keep bf16 activations in memory
     using SrcT = typename std::conditional<PREC == 0, float, unsigned short>::type;

@@ -214,20 +214,28 @@ __device__ __forceinline__ void window_sums4(int R, int HXS, const float4 *st, f
     default: CALL(15); break;       \
     }
 
-// Loads weight map i at this thread's halo pixels (zero outside the image).
-template <int M>
-__device__ __forceinline__ void load_w(const DecodeIO &io, int i, int x0, int y0, int R, int HX,
-                                       int HXY, float *w)
+// Global pixel index of each of this thread's halo slots (-1 outside the
+// image or past the halo), computed once per workgroup: the halo width is a
+// runtime value, so the division is paid here only.
+__device__ __forceinline__ void halo_pixels(int x0, int y0, int R, int HX, int HXY, int H, int W,
+                                            int *gp)
 {
 #pragma unroll
     for (int k = 0; k < kMaxPix; ++k) {
         const int p = threadIdx.x + k * kThreads;
         const int ly = p / HX, lx = p - ly * HX;
         const int gy = y0 - R + ly, gx = x0 - R + lx;
-        w[k] = 0.f;
-        if (p < HXY && gy >= 0 && gy < io.H && gx >= 0 && gx < io.W)
-            w[k] = io.head[((size_t)gy * io.W + gx) * (2 * M) + i];
+        gp[k] = (p < HXY && gy >= 0 && gy < H && gx >= 0 && gx < W) ? gy * W + gx : -1;
     }
+}
+
+// Loads weight map i at this thread's halo pixels (zero outside the image).
+template <int M>
+__device__ __forceinline__ void load_w(const DecodeIO &io, int i, const int *gp, float *w)
+{
+#pragma unroll
+    for (int k = 0; k < kMaxPix; ++k)
+        w[k] = gp[k] >= 0 ? io.head[(size_t)gp[k] * (2 * M) + i] : 0.f;
 }
 
 // Dynamic LDS: irradiance plane cq float4 [HXY] (c0, c1, c2, 0), product
@@ -259,17 +267,16 @@ __global__ __launch_bounds__(kThreads) void decode_fwd_kernel(DecodeCfg dc, Fram
     const int H = io.H, W = io.W;
     const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
 
+    int gp[kMaxPix];
+    halo_pixels(x0, y0, R, HX, HXY, H, W, gp);
     // irradiance halo: loads of all this thread's pixels first, then LDS
     {
         float cv[kMaxPix][3];
 #pragma unroll
         for (int k = 0; k < kMaxPix; ++k) {
-            const int p = tid + k * kThreads;
-            const int ly = p / HX, lx = p - ly * HX;
-            const int gy = y0 - R + ly, gx = x0 - R + lx;
             cv[k][0] = cv[k][1] = cv[k][2] = 0.f;
-            if (p < HXY && gy >= 0 && gy < H && gx >= 0 && gx < W) {
-                const size_t q = ((size_t)gy * W + gx) * 3;
+            if (gp[k] >= 0) {
+                const size_t q = (size_t)gp[k] * 3;
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) {
                     if (FRAMES) cv[k][ch] = io.r[q + ch] / (io.a[q + ch] + dc.eps_albedo);
@@ -284,7 +291,7 @@ __global__ __launch_bounds__(kThreads) void decode_fwd_kernel(DecodeCfg dc, Fram
         }
     }
     float wpre[kMaxPix];
-    load_w<M>(io, 0, x0, y0, R, HX, HXY, wpre);
+    load_w<M>(io, 0, gp, wpre);
 
     // fusion weights of this thread's kRun centres (column tx, rows kRun*ty + o)
     float alpha[kRun][M], F[kRun][3];
@@ -326,7 +333,7 @@ __global__ __launch_bounds__(kThreads) void decode_fwd_kernel(DecodeCfg dc, Fram
             const int p = tid + k * kThreads;
             if (p < HXY) pr[p] = f4scale(wpre[k], cq[p]);
         }
-        if (i + 1 < M) load_w<M>(io, i + 1, x0, y0, R, HX, HXY, wpre);
+        if (i + 1 < M) load_w<M>(io, i + 1, gp, wpre);
         __syncthreads();
         float4 acc[kRun];
 #define WSKP_WS(KK) window_sums4<KK>(R, HX, pr, hb, acc)
@@ -419,6 +426,8 @@ __global__ __launch_bounds__(kThreads) void decode_adj_b_kernel(DecodeCfg dc, De
     const int fidx = (int)((io.head - dt.head) / ((size_t)P * 2 * M));
     float *gc = grad_c + (size_t)fidx * P * 3;
 
+    int gp[kMaxPix];
+    halo_pixels(x0, y0, R, HX, HXY, H, W, gp);
     float dcv[kRun][3];
 #pragma unroll
     for (int o = 0; o < kRun; ++o) dcv[o][0] = dcv[o][1] = dcv[o][2] = 0.f;
@@ -427,13 +436,8 @@ __global__ __launch_bounds__(kThreads) void decode_adj_b_kernel(DecodeCfg dc, De
         const float4 *sp = io.scratch + (size_t)i * P;
         float4 v[kMaxPix];
 #pragma unroll
-        for (int k = 0; k < kMaxPix; ++k) {
-            const int p = tid + k * kThreads;
-            const int ly = p / HX, lx = p - ly * HX;
-            const int gy = y0 - R + ly, gx = x0 - R + lx;
-            v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (p < HXY && gy >= 0 && gy < H && gx >= 0 && gx < W) v[k] = sp[(size_t)gy * W + gx];
-        }
+        for (int k = 0; k < kMaxPix; ++k)
+            v[k] = gp[k] >= 0 ? sp[gp[k]] : make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
         for (int k = 0; k < kMaxPix; ++k) {
             const int p = tid + k * kThreads;

@@ -212,8 +212,10 @@ static void pack_layer(int prec, const LayerPlan &lp, const float *w, std::vecto
                     for (int co = 0; co < L.Cout_pad; ++co)
                         o[(((size_t)cc * 9 + tap) * CK + c) * L.Cout_pad + co] = W(co, cc * CK + c, tap);
     } else {
-        // [chunk][Cout_pad][NK*32], K = tap*CK + c, zero padded
-        const int NK = (9 * CK + 31) / 32, KR = NK * 32;
+        // [chunk][Cout_pad][NK*32 + 8], K = tap*CK + c, zero padded; the 8
+        // extra elements per row make the row stride in LDS bank-friendly and
+        // let the kernels copy a group's rows as one contiguous block
+        const int NK = (9 * CK + 31) / 32, KR = NK * 32 + 8;
         out.assign((size_t)nch * L.Cout_pad * KR * 2, 0);
         uint16_t *o = reinterpret_cast<uint16_t *>(out.data());
         for (int cc = 0; cc < nch; ++cc)
