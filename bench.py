@@ -253,6 +253,12 @@ def mode_serve(args):
         [dataclasses_replace(r) for r in reqs])
     res["bf16_continuous_batching"] = st.__dict__
     log(f"[serve] bf16 batching: {st}")
+    # capacity: the whole trace queued at once, frames per wall-clock second
+    st = serve.Server(ex, budget, max_inflight=2, max_batch=64).run(
+        [dataclasses_replace(r) for r in reqs], realtime=False)
+    res["bf16_batching_capacity_fps"] = st.frames / st.wall_s
+    log(f"[serve] bf16 batching capacity: {st.frames / st.wall_s:.1f} frames/s "
+        f"(mean batch {st.mean_batch:.1f})")
     n_fifo = min(len(reqs), args.fifo_frames)
     st = serve.fifo_single(ex, [dataclasses_replace(r) for r in reqs[:n_fifo]])
     res["bf16_fifo_single"] = {**st.__dict__, "requests": n_fifo}

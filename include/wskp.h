@@ -143,7 +143,9 @@ wskp_status_t wskp_workspace_size(wskp_handle_t h, int n, const int *H, const in
  * device workspace of ws_bytes >= wskp_workspace_size(h, 1, &H, &W);
  * its content is scratch (the intermediate feature maps and the
  * [H,W,2M] head record: weights W_i, then logits).  H and W must be
- * multiples of 2^(levels-1). */
+ * multiples of 2^(levels-1), at most 16384, and every level's feature map
+ * (H>>l) x (W>>l) x channels[l] must stay below 2^29 values (the kernels
+ * use 32-bit byte offsets); otherwise WSKP_E_SHAPE. */
 wskp_status_t wskp_denoise(wskp_handle_t h, void *stream, int H, int W, const float *radiance,
                            const float *albedo, const float *normal, const float *depth,
                            float *out, void *ws, size_t ws_bytes);

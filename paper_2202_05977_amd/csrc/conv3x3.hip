@@ -1,8 +1,10 @@
 // 3x3 convolutions of the prediction network (Sec. 4.1, Eq. 2) as implicit
 // GEMMs on the gfx950 matrix cores.
 //
-// GEMM view of one layer: rows = output pixels, columns = output channels,
-// reduction K = 9 taps x C_in.  A workgroup (4 wave64s) owns a tile of
+// GEMM view of one layer: output pixels x output channels, reduction K =
+// 9 taps x C_in (the MFMAs take the weights as their first operand, so each
+// lane ends with 4 consecutive channels of one pixel, which the epilogue
+// stores directly).  A workgroup (4 wave64s) owns a tile of
 // TH x 32 output pixels and 16*NB output channels.  The reduction runs over
 // chunks of CK input channels: the (TH+2) x 34 input halo of the chunk and
 // the matching 9*CK x 16*NB weight slice are staged in LDS, then every wave
@@ -39,14 +41,16 @@ __device__ __forceinline__ float bf16_to_f32(unsigned short h)
     return __uint_as_float(((unsigned int)h) << 16);
 }
 
-// Round to nearest, ties to even (the standard bit-level method); NaN stays NaN.
-__device__ __forceinline__ unsigned short f32_to_bf16(float f)
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// fp32 -> bf16 with round-to-nearest-even: one v_cvt_pk_bf16_f32 for a pair
+__device__ __forceinline__ unsigned cvt_pk_bf16(float a, float b)
 {
-    unsigned int u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
+    return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2{a, b}), bf16x2));
 }
+
+__device__ __forceinline__ unsigned short f32_to_bf16(float f) { return (unsigned short)cvt_pk_bf16(f, 0.f); }
 
 template <typename T> struct Elem;
 template <> struct Elem<float> {
@@ -79,22 +83,20 @@ __device__ __forceinline__ bool conv_locate(const ConvLayer &L, const FrameArg &
     const int nbk = gridDim.x;
     int t = xcd_logical_id(blockIdx.x, nbk);
     if (fa.reverse) t = nbk - 1 - t;
-    for (f = 0; f < fa.n; ++f) {
-        const FrameDesc &fd = frame_at(fa, f);
-        Hl = fd.H >> L.level;
-        Wl = fd.W >> L.level;
-        const int txn = (Wl + kConvTW - 1) / kConvTW, tyn = (Hl + TH - 1) / TH;
-        const int cnt = txn * tyn * L.groups;
-        if (t < cnt) {
-            g = t % L.groups;
-            t /= L.groups;
-            x0 = (t % txn) * kConvTW;
-            y0 = (t / txn) * TH;
-            return true;
-        }
-        t -= cnt;
-    }
-    return false;
+    const int lev = L.level, groups = L.groups;
+    f = batch_frame(fa, t, [=](int H, int W) {
+        return (((W >> lev) + kConvTW - 1) / kConvTW) * (((H >> lev) + TH - 1) / TH) * groups;
+    });
+    if (f < 0) return false;
+    const FrameDesc &fd = frame_at(fa, f);
+    Hl = fd.H >> lev;
+    Wl = fd.W >> lev;
+    const int txn = (Wl + kConvTW - 1) / kConvTW;
+    g = t % groups;
+    t /= groups;
+    x0 = (t % txn) * kConvTW;
+    y0 = (t / txn) * TH;
+    return true;
 }
 
 // ---- fast transcendental helpers -------------------------------------------
@@ -139,7 +141,7 @@ __device__ __forceinline__ OutT *conv_dst(const ConvLayer &L, const FrameDesc &f
 
 __device__ __forceinline__ unsigned pack2(float a, float b)
 {
-    return (unsigned)f32_to_bf16(a) | ((unsigned)f32_to_bf16(b) << 16);
+    return cvt_pk_bf16(a, b);
 }
 
 typedef int i32x8 __attribute__((ext_vector_type(8)));
@@ -433,7 +435,7 @@ __device__ __forceinline__ void chunk_mfma(const void *As_, const void *Bs_, f32
                     const float a = As[(c4 * 4 + lq) * S::PL + (row + dy) * S::WP + cb * 16 + lj + dx];
 #pragma unroll
                     for (int nb = 0; nb < NB; ++nb)
-                        acc[i][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[nb], acc[i][nb], 0, 0, 0);
+                        acc[i][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(b[nb], a, acc[i][nb], 0, 0, 0);
                 }
             }
         }
@@ -471,7 +473,7 @@ __device__ __forceinline__ void chunk_mfma(const void *As_, const void *Bs_, f32
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
                     acc[i][nb] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-                        a, b[nb], acc[i][nb], 0, 0, 0, 0, 0, 0);
+                        b[nb], a, acc[i][nb], 0, 0, 0, 0, 0, 0);
             }
         }
     } else {
@@ -496,73 +498,56 @@ __device__ __forceinline__ void chunk_mfma(const void *As_, const void *Bs_, f32
                 const bf16x8 a = __builtin_bit_cast(bf16x8, q);
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
-                    acc[i][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[i][nb], 0, 0, 0);
+                    acc[i][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(b[nb], a, acc[i][nb], 0, 0, 0);
             }
         }
     }
 }
 
-// Epilogue shared by the conv kernels: bias (and the fp8 dequantisation
-// factor) plus activation into an LDS tile, then coalesced stores of runs of
-// channels per pixel.  smem must hold TH*32*(16*NB+1) floats and be free.
+// Epilogue shared by the conv kernels.  The MFMAs take the weights as their
+// first operand, so in output block (i, nb) lane (j, q) holds pixel j of the
+// block and the 4 consecutive output channels nb*16 + 4q .. 4q+3.  Bias (and
+// the fp8 dequantisation factor) and the activation are applied in
+// registers, and each lane writes its 4 channels with one 8-byte store
+// (bf16) or two (fp32); the 4 lanes of a pixel cover 16 contiguous channels.
 template <int PREC, int EPI, int TH, int NB, typename OutT>
 __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDesc &fd, int g, int x0,
-                                              int y0, int Hl, int Wl, f32x4 (*acc)[NB],
-                                              unsigned char *smem)
+                                              int y0, int Hl, int Wl, f32x4 (*acc)[NB])
 {
     constexpr int MB = TH / 2;
     constexpr int NC = NB * 16;
-    constexpr int OS = NC + 1;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lj = lane & 15, lq = lane >> 4;
-    // phase 1: bias + activation into an LDS tile [TH*32][NC]
-    // (lane holds channel lj of pixels 4*lq + v of each 16-px block)
-    float *Ot = reinterpret_cast<float *>(smem);
+    OutT *dst = conv_dst<OutT>(L, fd);
+    float bias[NB][4], dq[NB][4];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int co = g * NC + nb * 16 + 4 * lq + v;
+            bias[nb][v] = co < L.Cout ? L.bias[co] : 0.f;
+            dq[nb][v] = (PREC == 2 && co < L.Cout) ? L.out_scale[co] : 1.f;
+        }
 #pragma unroll
     for (int i = 0; i < MB; ++i) {
         const int blk = wave * MB + i, row = blk >> 1, cb = blk & 1;
+        const int y = y0 + row, x = x0 + cb * 16 + lj;
+        if (y >= Hl || x >= Wl) continue;
+        OutT *pp = dst + ((size_t)y * Wl + x) * L.Cout;
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            const int cl = nb * 16 + lj, co = g * NC + cl;
-            const float bias = co < L.Cout ? L.bias[co] : 0.f;
-            const float dq = (PREC == 2 && co < L.Cout) ? L.out_scale[co] : 1.f;
+            const int co = g * NC + nb * 16 + 4 * lq;
+            if (co >= L.Cout) continue;
+            float v[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int px = row * kConvTW + cb * 16 + lq * 4 + v;
-                Ot[px * OS + cl] = epilogue<EPI>(acc[i][nb][v] * dq + bias, co, L.M);
-            }
-        }
-    }
-    __syncthreads();
-    // phase 2: coalesced stores of runs of V channels per pixel
-    OutT *dst = conv_dst<OutT>(L, fd);
-    const int ncw = min(NC, L.Cout - g * NC);      // channels this workgroup writes
-    if constexpr (std::is_same<OutT, float>::value) {
-        // fp32 (head record): float2 runs (channel counts are even); the loop
-        // runs over the compile-time maximum so its index math is shifts
-        const int nv = ncw >> 1;
-        constexpr int NV = NC / 2;
-        for (int it = tid; it < TH * kConvTW * NV; it += kThreads) {
-            const int px = it / NV, c2 = (it % NV) * 2;
-            const int y = y0 + px / kConvTW, x = x0 + px % kConvTW;
-            if ((c2 >> 1) < nv && y < Hl && x < Wl) {
-                float2 v = make_float2(Ot[px * OS + c2], Ot[px * OS + c2 + 1]);
-                *reinterpret_cast<float2 *>(dst + ((size_t)y * Wl + x) * L.Cout + g * NC + c2) = v;
-            }
-        }
-    } else {
-        // bf16: runs of 4 channels (8 bytes)
-        const int nv = ncw >> 2;
-        constexpr int NV = NC / 4;
-        for (int it = tid; it < TH * kConvTW * NV; it += kThreads) {
-            const int px = it / NV, c4 = (it % NV) * 4;
-            const int y = y0 + px / kConvTW, x = x0 + px % kConvTW;
-            if ((c4 >> 2) < nv && y < Hl && x < Wl) {
-                const float *o = &Ot[px * OS + c4];
-                uint2 v;
-                v.x = pack2(o[0], o[1]);
-                v.y = pack2(o[2], o[3]);
-                *reinterpret_cast<uint2 *>(dst + ((size_t)y * Wl + x) * L.Cout + g * NC + c4) = v;
+            for (int k = 0; k < 4; ++k) v[k] = epilogue<EPI>(acc[i][nb][k] * dq[nb][k] + bias[nb][k], co + k, L.M);
+            if constexpr (std::is_same<OutT, float>::value) {
+                // head record: Cout = 2M is even, so channel pairs are whole
+                *reinterpret_cast<float2 *>(pp + co) = make_float2(v[0], v[1]);
+                if (co + 2 < L.Cout) *reinterpret_cast<float2 *>(pp + co + 2) = make_float2(v[2], v[3]);
+            } else {
+                // activations: Cout is a multiple of 16
+                *reinterpret_cast<uint2 *>(pp + co) = make_uint2(pack2(v[0], v[1]), pack2(v[2], v[3]));
             }
         }
     }
@@ -576,10 +561,7 @@ __global__ __launch_bounds__(kThreads, WSKP_CONV_MIN_WG) void conv3x3_kernel(Con
 {
     using S = Stage<PREC, MODE, CK, TH, NB, SrcT>;
     constexpr int MB = TH / 2;
-    constexpr int NC = NB * 16;                 // output channels of this workgroup
-    constexpr int OS = NC + 1;                  // LDS row stride of the output tile (floats)
-    constexpr int OUT_BYTES = TH * kConvTW * OS * 4;
-    constexpr int LDS_BYTES = (S::A_BYTES + S::B_BYTES > OUT_BYTES) ? S::A_BYTES + S::B_BYTES : OUT_BYTES;
+    constexpr int LDS_BYTES = S::A_BYTES + S::B_BYTES;
     __shared__ __attribute__((aligned(16))) unsigned char smem[LDS_BYTES];
     void *As = smem;
     void *Bs = smem + S::A_BYTES;
@@ -589,9 +571,6 @@ __global__ __launch_bounds__(kThreads, WSKP_CONV_MIN_WG) void conv3x3_kernel(Con
     const FrameDesc &fd = frame_at(fa, f);
     const SrcT *s0 = reinterpret_cast<const SrcT *>(L.src0_kind ? fd.u[L.src0_idx] : fd.e[L.src0_idx]);
     const SrcT *s1 = reinterpret_cast<const SrcT *>(fd.e[L.src1_idx]);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int lj = lane & 15, lq = lane >> 4;
-
     f32x4 acc[MB][NB];
 #pragma unroll
     for (int i = 0; i < MB; ++i)
@@ -610,8 +589,7 @@ __global__ __launch_bounds__(kThreads, WSKP_CONV_MIN_WG) void conv3x3_kernel(Con
         chunk_mfma<PREC, MODE, CK, TH, NB, SrcT>(As, Bs, acc);
     }
 
-    __syncthreads();
-    conv_epilogue<PREC, EPI, TH, NB, OutT>(L, fd, g, x0, y0, Hl, Wl, acc, smem);
+    conv_epilogue<PREC, EPI, TH, NB, OutT>(L, fd, g, x0, y0, Hl, Wl, acc);
 }
 
 // =============================================================================
@@ -622,9 +600,12 @@ __global__ __launch_bounds__(kThreads, WSKP_CONV_MIN_WG) void conv3x3_kernel(Con
 // buffer_load_dwordx4 ... lds: no registers hold staged data and no commit
 // pass rewrites it.  A wave-level load writes 64 consecutive slots, so the
 // LDS image of the halo is pixel-major with 4 slots per pixel (CK = 32
-// channels); to keep the MFMA fragment reads conflict-free the 4 slots of
-// pixel p hold channel groups in the order g ^ ((p >> 1) & 3), which each
-// lane realises by choosing which group it fetches.  Pixels outside the image
+// channels).  A 16-byte LDS read serves 8 lanes per cycle from 32 banks, so
+// the 8 pixels a fragment read takes in one cycle must land in 8 distinct
+// 16-byte bank groups of a 128-byte line: the 4 slots of pixel p hold channel
+// groups in the order g ^ ((p >> 1) & 3), which with the pixel's position
+// in the line (p & 1) enumerates all 8 groups for any 8 consecutive pixels.
+// Each lane realises the order by choosing which group it fetches.  Pixels outside the image
 // get an offset beyond the buffer's range, and the hardware returns zeros:
 // that is the conv's zero padding.
 typedef __amdgpu_buffer_rsrc_t rsrc_t;
@@ -649,25 +630,57 @@ __device__ __forceinline__ void load_lds16(rsrc_t r, unsigned char *lds, unsigne
 
 constexpr unsigned kOutOfRange = 0x7ffffff0u;
 
-template <int MODE, int EPI, int TH, int NB, typename OutT>
+// Workgroup barrier without the memory fence of __syncthreads(): the fence
+// would wait for every load in flight, including the direct-to-LDS loads of
+// the next chunk.  The loop makes the data it needs visible explicitly
+// (wait_vmem / wait_lds before the barrier); the empty asm statements keep
+// the compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// lgkmcnt(0): this wave's LDS reads have completed.
+__device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt((15) | (3 << 14) | (7 << 4) | (0 << 8)); }
+
+// vmcnt(N) with lgkmcnt(0): waits until at most N vector-memory loads of
+// this wave are outstanding (loads complete in order); N = 0 waits for the
+// direct-to-LDS loads of the stage.
+template <int N>
+__device__ __forceinline__ void wait_vmem()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt is a 6-bit field");
+    __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (0 << 8));
+}
+
+// Each wave computes HW = TH/4 output rows of the tile (both 16-pixel column
+// blocks, all NB output blocks).  For one column offset dx it reads the A
+// fragments of its HW+2 input rows once and uses each for up to three
+// vertical taps dy (input row r+dy feeds output row r), so a chunk costs
+// 6 (HW+2) A fragment reads instead of 18 HW: the LDS bytes per MFMA, which
+// bound this loop, fall with HW.
+template <int MODE, int EPI, int TH, int NB, bool DB, typename OutT>
 __global__ __launch_bounds__(kThreads) void conv3x3_bf16_direct(ConvLayer L, FrameArg fa)
 {
     constexpr int CK = 32, WP = kConvTW + 2, HP = TH + 2, NPIX = HP * WP;
     constexpr int A_SLOTS = NPIX * 4;
-    constexpr int A_INS = (A_SLOTS + 63) / 64;
-    constexpr int A_PW = (A_INS + 3) / 4;          // load instructions per wave
-    constexpr int NK = 9;                           // one tap (32 channels) per MFMA
-    constexpr int BSK = NK * 32 + 8;                // padded weight row (elements)
+    // with DB every wave issues the same number of loads per chunk (the
+    // instruction counts are padded to whole rounds of the 4 waves)
+    constexpr int A_INS0 = (A_SLOTS + 63) / 64;
+    constexpr int A_PW = (A_INS0 + 3) / 4;                // load instructions per wave
+    constexpr int A_INS = DB ? 4 * A_PW : A_INS0;
+    constexpr int NK = 9;                                  // one tap (32 channels) per MFMA
+    constexpr int BSK = NK * 32 + 8;                       // padded weight row (elements)
     constexpr int B_SLOTS = NB * 16 * BSK / 8;
-    constexpr int B_INS = (B_SLOTS + 63) / 64;
-    constexpr int B_PW = (B_INS + 3) / 4;
-    constexpr int A_BYTES = A_INS * 1024, B_BYTES = B_INS * 1024;
-    constexpr int MB = TH / 2, NC = NB * 16;
-    constexpr int OUT_BYTES = TH * kConvTW * (NC + 1) * 4;
-    constexpr int LDS_BYTES = (A_BYTES + B_BYTES > OUT_BYTES) ? A_BYTES + B_BYTES : OUT_BYTES;
-    __shared__ __attribute__((aligned(1024))) unsigned char smem[LDS_BYTES];
-    unsigned char *As = smem;
-    unsigned char *Bs = smem + A_BYTES;
+    constexpr int B_INS0 = (B_SLOTS + 63) / 64;
+    constexpr int B_PW = (B_INS0 + 3) / 4;
+    constexpr int B_INS = DB ? 4 * B_PW : B_INS0;
+    constexpr int A_BYTES = A_INS * 1024, B_BYTES = B_INS * 1024, STAGE = A_BYTES + B_BYTES;
+    constexpr int MB = TH / 2, NC = NB * 16, HW = TH / 4;
+    static_assert(TH % 4 == 0, "each wave owns TH/4 whole rows");
+    __shared__ __attribute__((aligned(1024))) unsigned char smem[DB ? 2 * STAGE : STAGE];
 
     int f, g, x0, y0, Hl, Wl;
     if (!conv_locate<TH>(L, fa, f, g, x0, y0, Hl, Wl)) return;
@@ -685,7 +698,11 @@ __global__ __launch_bounds__(kThreads) void conv3x3_bf16_direct(ConvLayer L, Fra
     const int nchunks = L.Cin_pad / CK;
     const rsrc_t rw = make_rsrc(L.w, (unsigned)((size_t)nchunks * L.Cout_pad * BSK * 2));
 
-    // byte offsets of this wave's A slots in source 0 and source 1 (chunk 0)
+    // byte offsets of this wave's A slots in source 0 and source 1 (chunk 0).
+    // Row and pixel pitches are below 2^24, so the products are 24-bit
+    // multiplies (full rate, unlike 32-bit ones).
+    const unsigned cp0 = (unsigned)L.C0 * 2u, rp0 = (unsigned)W0 * cp0;
+    const unsigned cp1 = (unsigned)L.C1 * 2u, rp1 = (unsigned)Wl * cp1;
     unsigned oa0[A_PW], oa1[A_PW];
 #pragma unroll
     for (int k = 0; k < A_PW; ++k) {
@@ -695,15 +712,36 @@ __global__ __launch_bounds__(kThreads) void conv3x3_bf16_direct(ConvLayer L, Fra
         const int ly = p / WP, lx = p - ly * WP;
         const int gy = y0 - 1 + ly, gx = x0 - 1 + lx;
         oa0[k] = oa1[k] = kOutOfRange;
-        if (ins < A_INS && slot < A_SLOTS && gy >= 0 && gy < Hl && gx >= 0 && gx < Wl) {
+        if (slot < A_SLOTS && gy >= 0 && gy < Hl && gx >= 0 && gx < Wl) {
             if (MODE == CONV_CAT) {
-                oa0[k] = (unsigned)((((gy >> 1) * W0 + (gx >> 1)) * L.C0 + gch * 8) * 2);
-                oa1[k] = (unsigned)(((gy * Wl + gx) * L.C1 + gch * 8) * 2);
+                oa0[k] = __umul24((unsigned)gy >> 1, rp0) + __umul24((unsigned)gx >> 1, cp0) + gch * 16;
+                oa1[k] = __umul24((unsigned)gy, rp1) + __umul24((unsigned)gx, cp1) + gch * 16;
             } else {
-                oa0[k] = (unsigned)(((gy * Wl + gx) * L.C0 + gch * 8) * 2);
+                oa0[k] = __umul24((unsigned)gy, rp0) + __umul24((unsigned)gx, cp0) + gch * 16;
             }
         }
     }
+
+    // issues chunk cc's halo and weight slices into the stage at `buf`
+    auto issue = [&](int cc, unsigned char *buf) {
+        const int c0 = cc * CK;
+        const bool up = MODE != CONV_CAT || c0 < L.C0;
+        const unsigned da = (unsigned)((up ? c0 : c0 - L.C0) * 2);
+#pragma unroll
+        for (int k = 0; k < A_PW; ++k) {
+            const int ins = wave + 4 * k;
+            if (!DB && ins >= A_INS) break;
+            if (up) load_lds16(r0, buf + ins * 1024, oa0[k] + da);
+            else load_lds16(r1, buf + ins * 1024, oa1[k] + da);
+        }
+        const unsigned wb = (unsigned)((cc * L.Cout_pad + g * NC) * BSK * 2);
+#pragma unroll
+        for (int k = 0; k < B_PW; ++k) {
+            const int ins = wave + 4 * k;
+            if (!DB && ins >= B_INS) break;
+            load_lds16(rw, buf + A_BYTES + ins * 1024, wb + (unsigned)((ins * 64 + lane) * 16));
+        }
+    };
 
     f32x4 acc[MB][NB];
 #pragma unroll
@@ -711,61 +749,98 @@ __global__ __launch_bounds__(kThreads) void conv3x3_bf16_direct(ConvLayer L, Fra
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[i][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int cc = 0; cc < nchunks; ++cc) {
-        if (cc) __syncthreads();     // the previous chunk's fragments have been read
-        const int c0 = cc * CK;
-        const bool up = MODE != CONV_CAT || c0 < L.C0;
-        const unsigned da = (unsigned)((up ? c0 : c0 - L.C0) * 2);
+    // MFMAs of one chunk from the stage at As (halo) / As + A_BYTES (weights)
+    auto compute = [&](const unsigned char *As) {
+        const unsigned char *Bs = As + A_BYTES;
 #pragma unroll
-        for (int k = 0; k < A_PW; ++k) {
-            const int ins = wave + 4 * k;
-            if (ins < A_INS) {
-                if (up) load_lds16(r0, As + ins * 1024, oa0[k] + da);
-                else load_lds16(r1, As + ins * 1024, oa1[k] + da);
-            }
-        }
-        const unsigned wb = (unsigned)((cc * L.Cout_pad + g * NC) * BSK * 2);
+        for (int dx = 0; dx < 3; ++dx) {
+            bf16x8 a[HW + 2][2];
 #pragma unroll
-        for (int k = 0; k < B_PW; ++k) {
-            const int ins = wave + 4 * k;
-            if (ins < B_INS) load_lds16(rw, Bs + ins * 1024, wb + (unsigned)((ins * 64 + lane) * 16));
-        }
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
+            for (int rr = 0; rr < HW + 2; ++rr)
 #pragma unroll
-        for (int s = 0; s < NK; ++s) {
-            const int dy = s / 3, dx = s % 3;
-            bf16x8 b[NB];
+                for (int cb = 0; cb < 2; ++cb) {
+                    const int p = (wave * HW + rr) * WP + cb * 16 + lj + dx;
+                    const int slot = p * 4 + (lq ^ ((p >> 1) & 3));
+                    a[rr][cb] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(As + slot * 16));
+                }
 #pragma unroll
-            for (int nb = 0; nb < NB; ++nb)
-                b[nb] = __builtin_bit_cast(
-                    bf16x8, *reinterpret_cast<const u16x8 *>(Bs + ((nb * 16 + lj) * BSK + s * 32 + lq * 8) * 2));
-#pragma unroll
-            for (int i = 0; i < MB; ++i) {
-                const int blk = wave * MB + i, row = blk >> 1, cb = blk & 1;
-                const int p = (row + dy) * WP + cb * 16 + lj + dx;
-                const int slot = p * 4 + (lq ^ ((p >> 1) & 3));
-                const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(As + slot * 16));
+            for (int dy = 0; dy < 3; ++dy) {
+                const int s = dy * 3 + dx;
+                bf16x8 b[NB];
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
-                    acc[i][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[nb], acc[i][nb], 0, 0, 0);
+                    b[nb] = __builtin_bit_cast(
+                        bf16x8, *reinterpret_cast<const u16x8 *>(Bs + ((nb * 16 + lj) * BSK + s * 32 + lq * 8) * 2));
+#pragma unroll
+                for (int r = 0; r < HW; ++r)
+#pragma unroll
+                    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                        for (int nb = 0; nb < NB; ++nb)
+                            acc[2 * r + cb][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                b[nb], a[r + dy][cb], acc[2 * r + cb][nb], 0, 0, 0);
             }
         }
+    };
+
+    issue(0, smem);
+    if constexpr (DB) {
+        // chunk cc+1 streams into the other stage while chunk cc is computed;
+        // vmcnt(A_PW + B_PW) leaves only the newer chunk's loads in flight
+        for (int cc = 0; cc < nchunks; ++cc) {
+            const unsigned char *cur = smem + (cc & 1) * STAGE;
+            if (cc + 1 < nchunks) {
+                issue(cc + 1, smem + ((cc + 1) & 1) * STAGE);
+                wait_vmem<A_PW + B_PW>();
+            } else {
+                wait_vmem<0>();
+            }
+            lds_barrier();
+            compute(cur);
+            wait_lds();
+            lds_barrier();   // the stage has been read before it is refilled
+        }
+    } else {
+        for (int cc = 0; cc < nchunks; ++cc) {
+            wait_vmem<0>();
+            lds_barrier();
+            compute(smem);
+            wait_lds();
+            lds_barrier();   // the stage has been read before it is refilled
+            if (cc + 1 < nchunks) issue(cc + 1, smem);
+        }
     }
-    __syncthreads();
-    conv_epilogue<1, EPI, TH, NB, OutT>(L, fd, g, x0, y0, Hl, Wl, acc, smem);
+    conv_epilogue<1, EPI, TH, NB, OutT>(L, fd, g, x0, y0, Hl, Wl, acc);
 }
 
 // =============================================================================
 // dispatch
 // =============================================================================
-// Output rows per conv tile and the minimum number of workgroups per CU the
-// register allocation must allow (build-time tuning knobs).
+// Output rows per conv tile (build-time tuning knobs): kTH for the kernels
+// that stage through registers, kTHD (a multiple of 4) for the direct-load
+// bf16 kernel.
 #ifndef WSKP_CONV_TH
 #define WSKP_CONV_TH 4
 #endif
+#ifndef WSKP_DIRECT_TH
+#define WSKP_DIRECT_TH 8
+#endif
+#ifndef WSKP_CONV_DIRECT
+#define WSKP_CONV_DIRECT 1
+#endif
 constexpr int kTH = WSKP_CONV_TH;
-int conv_tile_rows(int) { return kTH; }
+constexpr int kTHD = WSKP_DIRECT_TH;
+#ifndef WSKP_DIRECT_DB
+#define WSKP_DIRECT_DB 0
+#endif
+constexpr bool kDirectDB = WSKP_DIRECT_DB != 0;
+
+static bool uses_direct(int prec, int mode, int CK)
+{
+    return WSKP_CONV_DIRECT && prec == 1 && CK == 32 && (mode == CONV_CAT || mode == CONV_PLAIN);
+}
+
+int conv_tile_rows(int prec, int mode, int CK) { return uses_direct(prec, mode, CK) ? kTHD : kTH; }
 
 int conv_chunk(int prec, int mode, int Cin, int C0)
 {
@@ -793,20 +868,16 @@ int conv_grid(const ConvLayer &L, int n, const int *H, const int *W)
     long total = 0;
     for (int f = 0; f < n; ++f) {
         const int Hl = H[f] >> L.level, Wl = W[f] >> L.level;
-        total += (long)((Wl + kConvTW - 1) / kConvTW) * ((Hl + kTH - 1) / kTH) * L.groups;
+        total += (long)((Wl + kConvTW - 1) / kConvTW) * ((Hl + L.th - 1) / L.th) * L.groups;
     }
     return (int)total;
 }
-
-#ifndef WSKP_CONV_DIRECT
-#define WSKP_CONV_DIRECT 1
-#endif
 
 template <int PREC, int MODE, int EPI, int CK, int NB, typename OutT>
 static void launch_one(const ConvLayer &L, const FrameArg &fa, int blocks, hipStream_t s)
 {
     if constexpr (WSKP_CONV_DIRECT && PREC == 1 && CK == 32 && (MODE == CONV_CAT || MODE == CONV_PLAIN)) {
-        hipLaunchKernelGGL((conv3x3_bf16_direct<MODE, EPI, kTH, NB, OutT>), dim3(blocks),
+        hipLaunchKernelGGL((conv3x3_bf16_direct<MODE, EPI, kTHD, NB, kDirectDB, OutT>), dim3(blocks),
                            dim3(kThreads), 0, s, L, fa);
         return;
     }

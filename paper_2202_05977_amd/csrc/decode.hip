@@ -55,52 +55,45 @@ __device__ __forceinline__ bool decode_locate(const DecodeCfg &dc, const FrameAr
     const int nbk = gridDim.x;
     int t = xcd_logical_id(blockIdx.x, nbk);
     if (FRAMES && fa.reverse) t = nbk - 1 - t;
-    const int n = FRAMES ? fa.n : dt.N;
     const int twoM = 2 * dc.M;
-    for (int f = 0; f < n; ++f) {
-        int H, W;
-        if (FRAMES) {
-            const FrameDesc &fd = frame_at(fa, f);
-            H = fd.H;
-            W = fd.W;
-        } else {
-            H = dt.H;
-            W = dt.W;
-        }
-        const int txn = (W + kDTX - 1) / kDTX, tyn = (H + kDTY - 1) / kDTY;
-        const int cnt = txn * tyn;
-        if (t < cnt) {
-            x0 = (t % txn) * kDTX;
-            y0 = (t / txn) * kDTY;
-            io.H = H;
-            io.W = W;
-            if (FRAMES) {
-                const FrameDesc &fd = frame_at(fa, f);
-                io.head = fd.head;
-                io.r = fd.r;
-                io.a = fd.a;
-                io.c = nullptr;
-                io.mod = nullptr;
-                io.out = fd.out;
-                io.g = nullptr;
-                io.grad_head = nullptr;
-                io.scratch = nullptr;
-            } else {
-                const size_t P = (size_t)H * W;
-                io.head = dt.head + (size_t)f * P * twoM;
-                io.r = io.a = nullptr;
-                io.c = dt.c + (size_t)f * P * 3;
-                io.mod = dt.mod ? dt.mod + (size_t)f * P * 3 : nullptr;
-                io.out = dt.out ? dt.out + (size_t)f * P * 3 : nullptr;
-                io.g = dt.g ? dt.g + (size_t)f * P * 3 : nullptr;
-                io.grad_head = dt.grad_head ? dt.grad_head + (size_t)f * P * twoM : nullptr;
-                io.scratch = dt.scratch ? dt.scratch + (size_t)f * P * dc.M : nullptr;
-            }
-            return true;
-        }
-        t -= cnt;
+    auto tiles = [](int H, int W) { return ((W + kDTX - 1) / kDTX) * ((H + kDTY - 1) / kDTY); };
+    if constexpr (FRAMES) {
+        const int f = batch_frame(fa, t, tiles);
+        if (f < 0) return false;
+        const FrameDesc &fd = frame_at(fa, f);
+        io.H = fd.H;
+        io.W = fd.W;
+        io.head = fd.head;
+        io.r = fd.r;
+        io.a = fd.a;
+        io.c = nullptr;
+        io.mod = nullptr;
+        io.out = fd.out;
+        io.g = nullptr;
+        io.grad_head = nullptr;
+        io.scratch = nullptr;
+    } else {
+        // equal-size frames: the frame index is a division
+        const int cnt = tiles(dt.H, dt.W);
+        const int f = t / cnt;
+        if (f >= dt.N) return false;
+        t -= f * cnt;
+        const size_t P = (size_t)dt.H * dt.W;
+        io.H = dt.H;
+        io.W = dt.W;
+        io.head = dt.head + (size_t)f * P * twoM;
+        io.r = io.a = nullptr;
+        io.c = dt.c + (size_t)f * P * 3;
+        io.mod = dt.mod ? dt.mod + (size_t)f * P * 3 : nullptr;
+        io.out = dt.out ? dt.out + (size_t)f * P * 3 : nullptr;
+        io.g = dt.g ? dt.g + (size_t)f * P * 3 : nullptr;
+        io.grad_head = dt.grad_head ? dt.grad_head + (size_t)f * P * twoM : nullptr;
+        io.scratch = dt.scratch ? dt.scratch + (size_t)f * P * dc.M : nullptr;
     }
-    return false;
+    const int txn = (io.W + kDTX - 1) / kDTX;
+    x0 = (t % txn) * kDTX;
+    y0 = (t / txn) * kDTY;
+    return true;
 }
 
 enum DecodeKind { DK_FRAMES = 0, DK_TENSORS = 1, DK_ADJ_A = 2 };
@@ -159,14 +152,11 @@ __device__ __forceinline__ float4 f4scale(float w, float4 c)
     return make_float4(w, w * c.x, w * c.y, w * c.z);
 }
 
-// Row stride (in float4) of the halo planes: 8 consecutive rows must fall in
-// distinct 16-byte bank groups (the horizontal pass gives consecutive lanes
-// consecutive rows), i.e. the stride must not be a multiple of 4.
-__device__ __host__ __forceinline__ int halo_stride(int R)
-{
-    const int hx = 32 + 2 * R;
-    return (hx % 4 == 0) ? hx + 2 : hx;
-}
+// Row stride (in float4) of the halo planes.  A 16-byte LDS read serves 8
+// lanes per cycle from 32 banks and the horizontal pass gives consecutive
+// lanes consecutive rows, so 8 consecutive rows must fall in distinct
+// 16-byte bank groups: an odd stride does that.
+__device__ __host__ __forceinline__ int halo_stride(int R) { return 32 + 2 * R + 1; }
 constexpr int kHB = 33;   // row-sum buffer stride (float4): rows land in distinct bank groups
 
 // Horizontal then vertical window sums of a float4 plane st [HY][HXS] for

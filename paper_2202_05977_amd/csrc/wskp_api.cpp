@@ -283,6 +283,7 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
         const int nblk = (Cout + 15) / 16;
         c.NB = conv_blocks_per_group(mode, nblk);
         c.groups = nblk / c.NB;
+        c.th = conv_tile_rows(h->prec, mode, c.CK);
         c.Cout_pad = nblk * 16;
         c.out_kind = okind;
         c.out_idx = oidx;
@@ -406,7 +407,14 @@ static wskp_status_t check_frame_size(const wskp_ctx *h, int H, int W)
     if (H < 1 || W < 1) return fail(WSKP_E_SHAPE, "H and W must be >= 1");
     if (H % a || W % a)
         return fail(WSKP_E_SHAPE, "H and W must be multiples of 2^(levels-1) = " + std::to_string(a));
-    if ((long)H * W > (1L << 28)) return fail(WSKP_E_SHAPE, "frame too large");
+    if ((long)H * W > (1L << 28) || H > 16384 || W > 16384)
+        return fail(WSKP_E_SHAPE, "frame too large (H, W <= 16384)");
+    // the conv kernels address activation maps with 32-bit byte offsets
+    for (int l = 0; l < h->cfg.levels; ++l) {
+        const long bytes = (long)(H >> l) * (W >> l) * h->cfg.channels[l] * 4;
+        if (bytes >= (1L << 31) - (1L << 16))
+            return fail(WSKP_E_SHAPE, "frame too large: an activation map would exceed 2 GiB");
+    }
     return WSKP_OK;
 }
 

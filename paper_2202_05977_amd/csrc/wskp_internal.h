@@ -37,6 +37,39 @@ __device__ __forceinline__ const FrameDesc &frame_at(const FrameArg &fa, int f)
     return fa.table ? fa.table[f] : fa.one;
 }
 
+// Finds the frame of a batch that holds logical tile t, given the tile
+// count of a frame of size H x W, and rewrites t as the tile index inside
+// that frame.  Each lane reads one frame's size, a wave-wide inclusive scan
+// turns the counts into cumulative ends, and a ballot counts the frames
+// that end at or before t: one round of loads per 64 frames instead of one
+// dependent load per frame.  Returns -1 past the batch's last tile.  Every
+// lane of the wave calls it with the same t; the results are wave-uniform.
+template <typename Count>
+__device__ __forceinline__ int batch_frame(const FrameArg &fa, int &t, Count count)
+{
+    if (!fa.table) return t < count(fa.one.H, fa.one.W) ? 0 : -1;
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    for (int f0 = 0; f0 < fa.n; f0 += 64) {
+        const int f = f0 + lane;
+        int c = f < fa.n ? count(fa.table[f].H, fa.table[f].W) : 0;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(c, d, 64);
+            if (lane >= d) c += v;
+        }
+        const int end = base + c;
+        const int k = __popcll(__ballot(f < fa.n && end <= t));
+        const int valid = fa.n - f0 < 64 ? fa.n - f0 : 64;
+        if (k < valid) {
+            t = __builtin_amdgcn_readfirstlane(t - (k > 0 ? __shfl(end, k - 1, 64) : base));
+            return __builtin_amdgcn_readfirstlane(f0 + k);
+        }
+        base = __shfl(end, 63, 64);
+    }
+    return -1;
+}
+
 // Spread consecutive logical tile ids over one XCD.  The hardware deals
 // workgroups round-robin to the 8 XCDs (block b runs on XCD b % 8); this
 // bijection gives each XCD a contiguous run of logical ids so that tiles
@@ -69,6 +102,7 @@ struct ConvLayer {
     int M;             // head: channels 0..M-1 get the weight activation
     int CK;            // input channels per reduction chunk (weights packed to match)
     int NB;            // 16-channel output blocks per workgroup
+    int th;            // output rows per tile of the kernel that runs this layer
     const void *w;     // packed weights
     const float *bias; // [Cout]
     float inv_gamma, dnear, dinv;  // CONV_PACK preprocessing constants
@@ -107,6 +141,6 @@ size_t decode_backward_scratch_bytes(const DecodeCfg &dc, int N, int H, int W);
 
 // Tile geometry of the conv kernels (host and device agree on these).
 constexpr int kConvTW = 32;  // output columns per tile (two 16-pixel MFMA blocks)
-int conv_tile_rows(int prec);
+int conv_tile_rows(int prec, int mode, int CK);
 
 }  // namespace wskp

@@ -82,10 +82,19 @@ class Arena:
 
 
 class Executor:
-    """Interface: launch(batch, slot, ws_offset) -> token; done(token) -> bool."""
+    """Interface: launch(batch, slot, ws_offset) -> token; done(token) -> bool.
+
+    ``request_bytes(r)`` is the workspace of ``r`` alone; a batch needs at
+    most the sum of its requests' values (``workspace_bytes(batch)``), so the
+    scheduler can account memory per request without re-sizing whole
+    batches.
+    """
 
     def workspace_bytes(self, reqs: List[Request]) -> int:
         raise NotImplementedError
+
+    def request_bytes(self, r: Request) -> int:
+        return self.workspace_bytes([r])
 
     def launch(self, reqs: List[Request], slot: int, ws_offset: int = 0):
         raise NotImplementedError
@@ -138,10 +147,16 @@ class Server:
         now = lambda: self.clock() - t0
         while nxt < len(reqs) or pending or inflight:
             t = now()
-            # arrivals up to now (offline: everything)
+            # arrivals up to now (offline: everything); a request larger than
+            # the whole budget can never run and is rejected on arrival
             while nxt < len(reqs) and (not realtime or reqs[nxt].t_arrival <= t):
-                pending.append(reqs[nxt])
+                r = reqs[nxt]
                 nxt += 1
+                if self.ex.request_bytes(r) > self.budget:
+                    r.error = "budget"
+                    r.t_start = r.t_done = now()
+                else:
+                    pending.append(r)
             # completions free their slot and their memory
             still = []
             for tok, b, off in inflight:
@@ -153,20 +168,23 @@ class Server:
                 else:
                     still.append((tok, b, off))
             inflight = still
-            # admission: oldest first, while a slot is free and memory fits
+            # admission: oldest first, while a slot is free and memory fits;
+            # a request that does not fit lets younger, smaller ones pass
             if pending and len(inflight) < self.max_inflight:
-                batch, rest = [], []
-                for r in pending:
-                    if self.ex.workspace_bytes([r]) > self.budget:
-                        r.error = "budget"
-                        r.t_start = r.t_done = now()
-                    elif len(batch) < self.max_batch and \
-                            self.ex.workspace_bytes(batch + [r]) <= self.budget - arena.used:
+                free = self.budget - arena.used
+                batch, rest, need = [], [], 0
+                for i, r in enumerate(pending):
+                    if len(batch) == self.max_batch:
+                        rest.extend(pending[i:])
+                        break
+                    rb = self.ex.request_bytes(r)
+                    if need + rb <= free:
                         batch.append(r)
+                        need += rb
                     else:
                         rest.append(r)
                 pending = rest
-                off = arena.alloc(self.ex.workspace_bytes(batch)) if batch else None
+                off = arena.alloc(need) if batch else None
                 if batch and off is None:       # fragmented: retry after a completion
                     pending = batch + pending
                     batch = []
@@ -249,9 +267,16 @@ class GpuExecutor(Executor):
         self.count = {s: 0 for s in stream_inputs}
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+        self._one: Dict[Tuple[int, int], int] = {}
 
     def workspace_bytes(self, reqs: List[Request]) -> int:
         return self.wskp.wskp_workspace_size(self.dn.h, [r.H for r in reqs], [r.W for r in reqs])
+
+    def request_bytes(self, r: Request) -> int:
+        key = (r.H, r.W)
+        if key not in self._one:
+            self._one[key] = self.workspace_bytes([r])
+        return self._one[key]
 
     def output_of(self, stream: int, k: int):
         ring = self.outputs[stream]

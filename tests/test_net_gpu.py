@@ -99,6 +99,26 @@ def test_batch_mixed_sizes_equals_single_frames():
             assert torch.equal(f["out"], s)
 
 
+def test_batch_of_more_than_64_frames():
+    """Frame lookup in batches that span several 64-frame groups: 130 small
+    frames of five sizes, each equal to the frame denoised alone."""
+    cfg = synth.SMALL
+    dn = _denoiser(cfg, "bf16")
+    sizes = [(4, 4), (8, 12), (16, 8), (12, 36), (28, 20)]
+    protos = [to_dev(synth.make_frame(40 + i, H, W)) for i, (H, W) in enumerate(sizes)]
+    singles = [dn(f).clone() for f in protos]
+    order = [(7 * i + i // 11) % len(sizes) for i in range(130)]
+    frames = []
+    for j in order:
+        f = {k: v for k, v in protos[j].items() if k != "clean"}
+        f["out"] = torch.full_like(f["radiance"], float("nan"))
+        frames.append(f)
+    dn.batch(frames)
+    torch.cuda.synchronize()
+    for j, f in zip(order, frames):
+        assert torch.equal(f["out"], singles[j]), j
+
+
 def test_shape_errors():
     from paper_2202_05977_amd import wskp
     dn = _denoiser(synth.HD, "fp32")
