@@ -6,13 +6,14 @@
 // sum, so every filtered value is a ratio of two box sums:
 //     out_i(p) = sum_{q in Omega_i(p)} W_i(q) c(q) / max(sum_{q in Omega_i(p)} W_i(q), eps)
 // with windows truncated at the image border.  No k x k kernel map is ever
-// formed.  Each workgroup owns a 32 x 16 tile of centres.  It stages the
-// irradiance of the (32+2R) x (16+2R) halo once in LDS (R = largest radius).
-// Then, for each kernel size, it builds a plane of (W_i, W_i c) over the
-// halo (the next size's weights are already being fetched), runs a
-// horizontal pass of row sums into LDS and a vertical pass over those, each
-// thread summing a run of neighbouring outputs in registers, and
-// accumulates softmax(logits)_i * out_i in registers.  The last step
+// formed.  Each workgroup owns a 32 x kDTY tile of centres.  Every thread
+// keeps the irradiance of its share of the (32+2R) x (kDTY+2R) halo (R =
+// largest radius) in registers and fetches each weight map one size ahead.
+// For each kernel size, each thread writes the plane (W_i, W_i c) of its
+// halo pixels to LDS, a horizontal pass
+// forms row sums into LDS and a vertical pass sums those, each thread
+// summing a run of neighbouring outputs in registers, and softmax(logits)_i
+// * out_i accumulates in registers: two barriers per size.  The last step
 // multiplies by the remodulation factor.
 //
 // Two input forms share the kernel:
@@ -23,7 +24,11 @@
 
 namespace wskp {
 
-constexpr int kDTX = 32, kDTY = 16;
+#ifndef WSKP_DECODE_TY
+#define WSKP_DECODE_TY 16
+#endif
+constexpr int kDTX = 32, kDTY = WSKP_DECODE_TY;
+static_assert(kDTY % 8 == 0, "8 row groups of kDTY/8 rows");
 
 struct DecodeIO {
     int H, W;
@@ -109,30 +114,32 @@ __device__ __forceinline__ float4 f4add(float4 a, float4 b)
 // leaving the window cannot cancel the small ones that remain).  For K >= N
 // the part v[N-1..K-1] is common to all N windows and is summed once; each
 // window adds a suffix of the run's head and a prefix of its tail.
-template <int K, int N>
-__device__ __forceinline__ void box_run(const float4 *v, float4 *s)
+template <int K, int N, typename LD>
+__device__ __forceinline__ void box_run(LD v, float4 *s)
 {
+    // v(j) reads value j where it is needed, so that only the running
+    // partial sums stay live (not all K + N - 1 inputs)
     if constexpr (K < N || K <= 3) {
 #pragma unroll
         for (int t = 0; t < N; ++t) {
-            float4 a = v[t];
+            float4 a = v(t);
 #pragma unroll
-            for (int j = 1; j < K; ++j) a = f4add(a, v[t + j]);
+            for (int j = 1; j < K; ++j) a = f4add(a, v(t + j));
             s[t] = a;
         }
     } else {
-        float4 C = v[N - 1];
+        float4 C = v(N - 1);
 #pragma unroll
-        for (int j = N; j < K; ++j) C = f4add(C, v[j]);
+        for (int j = N; j < K; ++j) C = f4add(C, v(j));
         float4 L[N], Rt[N];
         L[N - 1] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if constexpr (N >= 2) L[N - 2] = v[N - 2];
+        if constexpr (N >= 2) L[N - 2] = v(N - 2);
 #pragma unroll
-        for (int t = N - 3; t >= 0; --t) L[t] = f4add(v[t], L[t + 1]);
+        for (int t = N - 3; t >= 0; --t) L[t] = f4add(v(t), L[t + 1]);
         Rt[0] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if constexpr (N >= 2) Rt[1] = v[K];
+        if constexpr (N >= 2) Rt[1] = v(K);
 #pragma unroll
-        for (int t = 2; t < N; ++t) Rt[t] = f4add(Rt[t - 1], v[K + t - 1]);
+        for (int t = 2; t < N; ++t) Rt[t] = f4add(Rt[t - 1], v(K + t - 1));
         s[0] = (N >= 2) ? f4add(L[0], C) : C;
 #pragma unroll
         for (int t = 1; t < N - 1; ++t) s[t] = f4add(f4add(L[t], C), Rt[t]);
@@ -145,12 +152,11 @@ __device__ __forceinline__ void box_run(const float4 *v, float4 *s)
 // horizontal pass gives each thread runs of kHRun columns.
 constexpr int kRun = kDTY / 8;
 constexpr int kHRun = 4;
-constexpr int kMaxPix = 6;   // halo pixels per thread: (32+14)*(16+14) <= 6*256
-
-__device__ __forceinline__ float4 f4scale(float w, float4 c)
-{
-    return make_float4(w, w * c.x, w * c.y, w * c.z);
-}
+// Halo pixels per thread for a largest radius of at most RM.  The kernels
+// are instantiated for RM = 5 (kernel sizes up to 11) and RM = 7 (up to 15):
+// the smaller bound needs fewer registers.
+template <int RM>
+constexpr int max_pix() { return ((32 + 2 * RM + 1) * (kDTY + 2 * RM) + kThreads - 1) / kThreads; }
 
 // Row stride (in float4) of the halo planes.  A 16-byte LDS read serves 8
 // lanes per cycle from 32 banks and the horizontal pass gives consecutive
@@ -175,43 +181,40 @@ __device__ __forceinline__ void window_sums4(int R, int HXS, const float4 *st, f
     for (int it = tid; it < nrows * RPR; it += kThreads) {
         const int hy = R - r + it % nrows, xr = (it / nrows) * kHRun;
         const int base = hy * HXS + xr + R - r;
-        float4 v[K + kHRun - 1];
-#pragma unroll
-        for (int j = 0; j < K + kHRun - 1; ++j) v[j] = st[base + j];
         float4 s[kHRun];
-        box_run<K, kHRun>(v, s);
+        box_run<K, kHRun>([&](int j) { return st[base + j]; }, s);
 #pragma unroll
         for (int t = 0; t < kHRun; ++t) hb[hy * kHB + xr + t] = s[t];
     }
     __syncthreads();
     const int tx = tid & 31, ty = tid >> 5;
-    float4 v[K + kRun - 1];
-#pragma unroll
-    for (int j = 0; j < K + kRun - 1; ++j) v[j] = hb[(kRun * ty + R - r + j) * kHB + tx];
-    box_run<K, kRun>(v, acc);
-    __syncthreads();
+    const int vb = (kRun * ty + R - r) * kHB + tx;
+    box_run<K, kRun>([&](int j) { return hb[vb + j * kHB]; }, acc);
+    // no barrier here: the next writer of hb runs after the caller's next
+    // barrier, and the horizontal reads of st ended at the barrier above
 }
 
-#define WSKP_SWITCH_K(k, CALL)      \
-    switch (k) {                    \
-    case 1: CALL(1); break;         \
-    case 3: CALL(3); break;         \
-    case 5: CALL(5); break;         \
-    case 7: CALL(7); break;         \
-    case 9: CALL(9); break;         \
-    case 11: CALL(11); break;       \
-    case 13: CALL(13); break;       \
-    default: CALL(15); break;       \
+#define WSKP_SWITCH_K(RM, k, CALL)                       \
+    switch (k) {                                         \
+    case 1: CALL(1); break;                              \
+    case 3: CALL(3); break;                              \
+    case 5: CALL(5); break;                              \
+    case 7: CALL(7); break;                              \
+    case 9: CALL(9); break;                              \
+    case 11: CALL(11); break;                            \
+    case 13: if constexpr (RM >= 6) { CALL(13); } break; \
+    default: if constexpr (RM >= 7) { CALL(15); } break; \
     }
 
 // Global pixel index of each of this thread's halo slots (-1 outside the
 // image or past the halo), computed once per workgroup: the halo width is a
 // runtime value, so the division is paid here only.
+template <int RM>
 __device__ __forceinline__ void halo_pixels(int x0, int y0, int R, int HX, int HXY, int H, int W,
                                             int *gp)
 {
 #pragma unroll
-    for (int k = 0; k < kMaxPix; ++k) {
+    for (int k = 0; k < max_pix<RM>(); ++k) {
         const int p = threadIdx.x + k * kThreads;
         const int ly = p / HX, lx = p - ly * HX;
         const int gy = y0 - R + ly, gx = x0 - R + lx;
@@ -220,17 +223,16 @@ __device__ __forceinline__ void halo_pixels(int x0, int y0, int R, int HX, int H
 }
 
 // Loads weight map i at this thread's halo pixels (zero outside the image).
-template <int M>
+template <int M, int RM>
 __device__ __forceinline__ void load_w(const DecodeIO &io, int i, const int *gp, float *w)
 {
 #pragma unroll
-    for (int k = 0; k < kMaxPix; ++k)
+    for (int k = 0; k < max_pix<RM>(); ++k)
         w[k] = gp[k] >= 0 ? io.head[(size_t)gp[k] * (2 * M) + i] : 0.f;
 }
 
-// Dynamic LDS: irradiance plane cq float4 [HXY] (c0, c1, c2, 0), product
-// plane float4 [HXY] (W_i, W_i c) rebuilt for each kernel size, row sums
-// float4 [(kDTY+2R)][kHB].
+// Dynamic LDS: product plane float4 [HXY] (W_i, W_i c) rebuilt for each
+// kernel size, row sums float4 [(kDTY+2R)][kHB].
 //   DK_FRAMES / DK_TENSORS: forward, writes out.
 //   DK_ADJ_A: first half of the vector-Jacobian product.  Per centre p,
 //     with dF = g * mod, da_i = <dF, out_i>:
@@ -238,7 +240,7 @@ __device__ __forceinline__ void load_w(const DecodeIO &io, int i, const int *gp,
 //       u_i,ch(p)  = alpha_i dF_ch / max(S_i, eps)
 //       dS_i(p)    = -[S_i > eps] sum_ch u_i,ch(p) out_i,ch(p)
 //     (u_i, dS_i) go to scratch; decode_adj_b_kernel box-sums them.
-template <int M, int KIND>
+template <int M, int KIND, int RM>
 __global__ __launch_bounds__(kThreads) void decode_fwd_kernel(DecodeCfg dc, FrameArg fa,
                                                                DecodeTensors dt)
 {
@@ -251,37 +253,31 @@ __global__ __launch_bounds__(kThreads) void decode_fwd_kernel(DecodeCfg dc, Fram
 
     const int R = dc.R;
     const int HX = halo_stride(R), HXY = HX * (kDTY + 2 * R);
-    float4 *cq = lds4;
-    float4 *pr = cq + HXY;
+    float4 *pr = lds4;
     float4 *hb = pr + HXY;
     const int H = io.H, W = io.W;
     const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
 
+    constexpr int kMaxPix = max_pix<RM>();
     int gp[kMaxPix];
-    halo_pixels(x0, y0, R, HX, HXY, H, W, gp);
-    // irradiance halo: loads of all this thread's pixels first, then LDS
-    {
-        float cv[kMaxPix][3];
+    halo_pixels<RM>(x0, y0, R, HX, HXY, H, W, gp);
+    // irradiance of this thread's halo pixels, kept in registers; c = r /
+    // (a + eps_a) uses the hardware reciprocal.  The weight map of each size
+    // is fetched one size ahead.
+    float cv[kMaxPix][3], wv[kMaxPix];
 #pragma unroll
-        for (int k = 0; k < kMaxPix; ++k) {
-            cv[k][0] = cv[k][1] = cv[k][2] = 0.f;
-            if (gp[k] >= 0) {
-                const size_t q = (size_t)gp[k] * 3;
+    for (int k = 0; k < kMaxPix; ++k) {
+        cv[k][0] = cv[k][1] = cv[k][2] = 0.f;
+        if (gp[k] >= 0) {
+            const size_t q = (size_t)gp[k] * 3;
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch) {
-                    if (FRAMES) cv[k][ch] = io.r[q + ch] / (io.a[q + ch] + dc.eps_albedo);
-                    else cv[k][ch] = io.c[q + ch];
-                }
+            for (int ch = 0; ch < 3; ++ch) {
+                if (FRAMES) cv[k][ch] = io.r[q + ch] * __builtin_amdgcn_rcpf(io.a[q + ch] + dc.eps_albedo);
+                else cv[k][ch] = io.c[q + ch];
             }
         }
-#pragma unroll
-        for (int k = 0; k < kMaxPix; ++k) {
-            const int p = tid + k * kThreads;
-            if (p < HXY) cq[p] = make_float4(cv[k][0], cv[k][1], cv[k][2], 0.f);
-        }
     }
-    float wpre[kMaxPix];
-    load_w<M>(io, 0, gp, wpre);
+    load_w<M, RM>(io, 0, gp, wv);
 
     // fusion weights of this thread's kRun centres (column tx, rows kRun*ty + o)
     float alpha[kRun][M], F[kRun][3];
@@ -313,21 +309,21 @@ __global__ __launch_bounds__(kThreads) void decode_fwd_kernel(DecodeCfg dc, Fram
     }
     float outv[ADJ ? kRun : 1][ADJ ? M : 1][3];
     float Sv[ADJ ? kRun : 1][ADJ ? M : 1];
-    __syncthreads();
 
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-        // product plane of this size, then prefetch the next size's weights
+        // product plane of this size from this thread's registers, then
+        // fetch the next size's weights
 #pragma unroll
         for (int k = 0; k < kMaxPix; ++k) {
             const int p = tid + k * kThreads;
-            if (p < HXY) pr[p] = f4scale(wpre[k], cq[p]);
+            if (p < HXY) pr[p] = make_float4(wv[k], wv[k] * cv[k][0], wv[k] * cv[k][1], wv[k] * cv[k][2]);
         }
-        if (i + 1 < M) load_w<M>(io, i + 1, gp, wpre);
+        if (i + 1 < M) load_w<M, RM>(io, i + 1, gp, wv);
         __syncthreads();
         float4 acc[kRun];
 #define WSKP_WS(KK) window_sums4<KK>(R, HX, pr, hb, acc)
-        WSKP_SWITCH_K(2 * dc.radius[i] + 1, WSKP_WS)
+        WSKP_SWITCH_K(RM, 2 * dc.radius[i] + 1, WSKP_WS)
 #undef WSKP_WS
 #pragma unroll
         for (int o = 0; o < kRun; ++o) {
@@ -397,7 +393,7 @@ __global__ __launch_bounds__(kThreads) void decode_fwd_kernel(DecodeCfg dc, Fram
 //   dc_ch(q) = sum_i W_i(q) box_i(u_i,ch)(q)                      -> grad_c[q][ch]
 // One size at a time: stage the halo of (u_i, dS_i) as float4, row sums,
 // column sums.  LDS: float4 [HXY] staged + float4 [(kDTY+2R)][kHB] row sums.
-template <int M>
+template <int M, int RM>
 __global__ __launch_bounds__(kThreads) void decode_adj_b_kernel(DecodeCfg dc, DecodeTensors dt,
                                                                  float *grad_c)
 {
@@ -416,8 +412,9 @@ __global__ __launch_bounds__(kThreads) void decode_adj_b_kernel(DecodeCfg dc, De
     const int fidx = (int)((io.head - dt.head) / ((size_t)P * 2 * M));
     float *gc = grad_c + (size_t)fidx * P * 3;
 
+    constexpr int kMaxPix = max_pix<RM>();
     int gp[kMaxPix];
-    halo_pixels(x0, y0, R, HX, HXY, H, W, gp);
+    halo_pixels<RM>(x0, y0, R, HX, HXY, H, W, gp);
     float dcv[kRun][3];
 #pragma unroll
     for (int o = 0; o < kRun; ++o) dcv[o][0] = dcv[o][1] = dcv[o][2] = 0.f;
@@ -436,7 +433,7 @@ __global__ __launch_bounds__(kThreads) void decode_adj_b_kernel(DecodeCfg dc, De
         __syncthreads();
         float4 acc[kRun];
 #define WSKP_WS(KK) window_sums4<KK>(R, HX, st, hb, acc)
-        WSKP_SWITCH_K(2 * dc.radius[i] + 1, WSKP_WS)
+        WSKP_SWITCH_K(RM, 2 * dc.radius[i] + 1, WSKP_WS)
 #undef WSKP_WS
 #pragma unroll
         for (int o = 0; o < kRun; ++o) {
@@ -468,7 +465,7 @@ __global__ __launch_bounds__(kThreads) void decode_adj_b_kernel(DecodeCfg dc, De
 static size_t decode_lds_bytes(const DecodeCfg &dc)
 {
     const size_t HX = halo_stride(dc.R), HY = kDTY + 2 * dc.R;
-    return sizeof(float4) * (2 * HX * HY + HY * kHB);
+    return sizeof(float4) * (HX * HY + HY * kHB);
 }
 
 static size_t adj_b_lds_bytes(const DecodeCfg &dc)
@@ -491,12 +488,20 @@ static hipError_t launch_decode(const DecodeCfg &dc, const FrameArg &fa, const D
 {
     if (blocks <= 0) return hipSuccess;
     const size_t lds = decode_lds_bytes(dc);
+    // the largest radius selects the register-lean instantiation when it can
+    const bool r5 = dc.R <= 5;
     switch (dc.M) {
-#define WSKP_M(m)                                                                                 \
-    case m:                                                                                       \
-        allow_lds(decode_fwd_kernel<m, KIND>, lds);                                               \
-        hipLaunchKernelGGL((decode_fwd_kernel<m, KIND>), dim3(blocks), dim3(kThreads), lds, s, dc, \
-                           fa, dt);                                                               \
+#define WSKP_M(m)                                                                                  \
+    case m:                                                                                        \
+        if (r5) {                                                                                  \
+            allow_lds(decode_fwd_kernel<m, KIND, 5>, lds);                                         \
+            hipLaunchKernelGGL((decode_fwd_kernel<m, KIND, 5>), dim3(blocks), dim3(kThreads), lds, \
+                               s, dc, fa, dt);                                                     \
+        } else {                                                                                   \
+            allow_lds(decode_fwd_kernel<m, KIND, 7>, lds);                                         \
+            hipLaunchKernelGGL((decode_fwd_kernel<m, KIND, 7>), dim3(blocks), dim3(kThreads), lds, \
+                               s, dc, fa, dt);                                                     \
+        }                                                                                          \
         break;
         WSKP_M(1) WSKP_M(2) WSKP_M(3) WSKP_M(4) WSKP_M(5) WSKP_M(6) WSKP_M(7) WSKP_M(8)
 #undef WSKP_M
@@ -544,12 +549,19 @@ hipError_t launch_decode_backward(const DecodeCfg &dc, int N, int H, int W, cons
     hipError_t e = launch_decode<DK_ADJ_A>(dc, fa, dt, blocks, s);
     if (e != hipSuccess) return e;
     const size_t lds = adj_b_lds_bytes(dc);
+    const bool r5 = dc.R <= 5;
     switch (dc.M) {
 #define WSKP_M(m)                                                                                 \
     case m:                                                                                       \
-        allow_lds(decode_adj_b_kernel<m>, lds);                                                   \
-        hipLaunchKernelGGL((decode_adj_b_kernel<m>), dim3(blocks), dim3(kThreads), lds, s, dc, dt, \
-                           grad_c);                                                               \
+        if (r5) {                                                                                 \
+            allow_lds(decode_adj_b_kernel<m, 5>, lds);                                            \
+            hipLaunchKernelGGL((decode_adj_b_kernel<m, 5>), dim3(blocks), dim3(kThreads), lds, s, \
+                               dc, dt, grad_c);                                                   \
+        } else {                                                                                  \
+            allow_lds(decode_adj_b_kernel<m, 7>, lds);                                            \
+            hipLaunchKernelGGL((decode_adj_b_kernel<m, 7>), dim3(blocks), dim3(kThreads), lds, s, \
+                               dc, dt, grad_c);                                                   \
+        }                                                                                         \
         break;
         WSKP_M(1) WSKP_M(2) WSKP_M(3) WSKP_M(4) WSKP_M(5) WSKP_M(6) WSKP_M(7) WSKP_M(8)
 #undef WSKP_M
