@@ -141,8 +141,8 @@ wskp_status_t wskp_workspace_size(wskp_handle_t h, int n, const int *H, const in
  * normal and depth in, denoised radiance out).  Inputs as wskp_frame_t;
  * `out` [H,W,3] receives albedo * fused filtered irradiance.  `ws` is a
  * device workspace of ws_bytes >= wskp_workspace_size(h, 1, &H, &W);
- * its content is scratch (the intermediate feature maps and the
- * [H,W,2M] head record: weights W_i, then logits).  H and W must be
+ * its content is scratch (the intermediate feature maps and the head
+ * record, planar [2M][H][W]: weight maps W_i, then logits).  H and W must be
  * multiples of 2^(levels-1), at most 16384, and every level's feature map
  * (H>>l) x (W>>l) x channels[l] must stay below 2^29 values (the kernels
  * use 32-bit byte offsets); otherwise WSKP_E_SHAPE. */
@@ -185,9 +185,12 @@ wskp_status_t wskp_backward_workspace_size(wskp_handle_t h, int N, int H, int W,
 
 /* Location of an intermediate tensor of frame `frame` inside the workspace
  * of the last-planned batch layout for frames of sizes H[i] x W[i]: which =
- * 0..L-1 for encoder output e_l, 100 + l for decoder output u_l, 200 for
- * the head record.  Returns byte offset, shape and element size (4 = fp32,
- * 2 = bf16).  For debugging and layer-by-layer checks. */
+ * 0..L-1 for encoder output e_l, 100 + l for decoder output u_l (shape
+ * th x tw x tc = H_l x W_l x C_l), 200 for the head record (planar: th x
+ * tw x tc = 2M x H x W), and (bf16 handles whose encoders pass on 2x2
+ * means) 300 + l for the pooled copy of e_l, l < L-1.  Returns byte offset,
+ * shape and element size (4 = fp32, 2 = bf16).  For debugging and
+ * layer-by-layer checks. */
 wskp_status_t wskp_workspace_tensor(wskp_handle_t h, int n, const int *H, const int *W, int frame,
                                     int which, size_t *offset, int *th, int *tw, int *tc,
                                     int *elem_bytes);

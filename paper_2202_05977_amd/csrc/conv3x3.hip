@@ -132,6 +132,11 @@ __device__ __forceinline__ float epilogue(float v, int co, int M)
     return v;
 }
 
+__device__ __forceinline__ const void *conv_src0(const ConvLayer &L, const FrameDesc &fd)
+{
+    return L.src0_kind == 0 ? fd.e[L.src0_idx] : (L.src0_kind == 1 ? fd.u[L.src0_idx] : fd.p[L.src0_idx]);
+}
+
 template <typename OutT>
 __device__ __forceinline__ OutT *conv_dst(const ConvLayer &L, const FrameDesc &fd)
 {
@@ -508,17 +513,27 @@ __device__ __forceinline__ void chunk_mfma(const void *As_, const void *Bs_, f32
 // first operand, so in output block (i, nb) lane (j, q) holds pixel j of the
 // block and the 4 consecutive output channels nb*16 + 4q .. 4q+3.  Bias (and
 // the fp8 dequantisation factor) and the activation are applied in
-// registers, and each lane writes its 4 channels with one 8-byte store
-// (bf16) or two (fp32); the 4 lanes of a pixel cover 16 contiguous channels.
+// registers.  Activations (bf16 or fp32 NHWC): each lane writes its 4
+// channels with one 8- or 16-byte store; the 4 lanes of a pixel cover 16
+// contiguous channels.  The head record (fp32) is planar [2M][H][W], the
+// layout the decode reads one map at a time.
+//
+// With L.pool_idx >= 0 (bf16 activations, a wave owning whole row pairs:
+// TH >= 8) the epilogue also writes the 2x2 means of the stored (rounded)
+// values to the next level, summed in the order (2y,2x), (2y,2x+1),
+// (2y+1,2x), (2y+1,2x+1): the column partner is the neighbouring lane, the
+// row partner is block i+2 of the same lane.
 template <int PREC, int EPI, int TH, int NB, typename OutT>
 __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDesc &fd, int g, int x0,
                                               int y0, int Hl, int Wl, f32x4 (*acc)[NB])
 {
     constexpr int MB = TH / 2;
     constexpr int NC = NB * 16;
+    constexpr bool CAN_POOL = !std::is_same<OutT, float>::value && EPI == EPI_RELU && MB >= 4;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lj = lane & 15, lq = lane >> 4;
     OutT *dst = conv_dst<OutT>(L, fd);
+    const bool pool = CAN_POOL && L.pool_idx >= 0;
     float bias[NB][4], dq[NB][4];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
@@ -528,26 +543,58 @@ __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDes
             bias[nb][v] = co < L.Cout ? L.bias[co] : 0.f;
             dq[nb][v] = (PREC == 2 && co < L.Cout) ? L.out_scale[co] : 1.f;
         }
+    float pe[CAN_POOL ? 2 : 1][CAN_POOL ? NB : 1][4];   // even-row partial sums
 #pragma unroll
     for (int i = 0; i < MB; ++i) {
         const int blk = wave * MB + i, row = blk >> 1, cb = blk & 1;
         const int y = y0 + row, x = x0 + cb * 16 + lj;
-        if (y >= Hl || x >= Wl) continue;
+        const bool in = y < Hl && x < Wl;
         OutT *pp = dst + ((size_t)y * Wl + x) * L.Cout;
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const int co = g * NC + nb * 16 + 4 * lq;
-            if (co >= L.Cout) continue;
+            const bool cin = co < L.Cout;
             float v[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) v[k] = epilogue<EPI>(acc[i][nb][k] * dq[nb][k] + bias[nb][k], co + k, L.M);
-            if constexpr (std::is_same<OutT, float>::value) {
-                // head record: Cout = 2M is even, so channel pairs are whole
-                *reinterpret_cast<float2 *>(pp + co) = make_float2(v[0], v[1]);
-                if (co + 2 < L.Cout) *reinterpret_cast<float2 *>(pp + co + 2) = make_float2(v[2], v[3]);
+            if constexpr (EPI != EPI_RELU) {
+                // head record, planar [2M][H][W]: the 16 lanes of a channel
+                // write 16 consecutive pixels of its plane
+                if (in) {
+                    OutT *q = dst + (size_t)y * Wl + x;
+                    const size_t P = (size_t)Hl * Wl;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (co + k < L.Cout) q[(size_t)(co + k) * P] = v[k];
+                }
+            } else if constexpr (std::is_same<OutT, float>::value) {
+                // fp32 activations: Cout is a multiple of 16
+                if (in && cin) *reinterpret_cast<float4 *>(pp + co) = make_float4(v[0], v[1], v[2], v[3]);
             } else {
                 // activations: Cout is a multiple of 16
-                *reinterpret_cast<uint2 *>(pp + co) = make_uint2(pack2(v[0], v[1]), pack2(v[2], v[3]));
+                const uint2 q = make_uint2(pack2(v[0], v[1]), pack2(v[2], v[3]));
+                if (in && cin) *reinterpret_cast<uint2 *>(pp + co) = q;
+                if constexpr (CAN_POOL) {
+                    if (pool) {
+                        const float r[4] = {__uint_as_float(q.x << 16), __uint_as_float(q.x & 0xffff0000u),
+                                            __uint_as_float(q.y << 16), __uint_as_float(q.y & 0xffff0000u)};
+                        const bool odd_row = (i >> 1) & 1;
+                        if (!odd_row) {
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) pe[cb][nb][k] = r[k] + __shfl_xor(r[k], 1, 64);
+                        } else {
+                            float m[4];
+#pragma unroll
+                            for (int k = 0; k < 4; ++k) m[k] = 0.25f * ((pe[cb][nb][k] + r[k]) + __shfl_xor(r[k], 1, 64));
+                            const int Y = y >> 1, X = x >> 1;
+                            if ((lj & 1) == 0 && Y < (Hl >> 1) && X < (Wl >> 1) && cin) {
+                                OutT *pd = reinterpret_cast<OutT *>(fd.p[L.pool_idx]) +
+                                           ((size_t)Y * (Wl >> 1) + X) * L.Cout + co;
+                                *reinterpret_cast<uint2 *>(pd) = make_uint2(pack2(m[0], m[1]), pack2(m[2], m[3]));
+                            }
+                        }
+                    }
+                }
             }
         }
     }
@@ -569,7 +616,7 @@ __global__ __launch_bounds__(kThreads, WSKP_CONV_MIN_WG) void conv3x3_kernel(Con
     int f, g, x0, y0, Hl, Wl;
     if (!conv_locate<TH>(L, fa, f, g, x0, y0, Hl, Wl)) return;
     const FrameDesc &fd = frame_at(fa, f);
-    const SrcT *s0 = reinterpret_cast<const SrcT *>(L.src0_kind ? fd.u[L.src0_idx] : fd.e[L.src0_idx]);
+    const SrcT *s0 = reinterpret_cast<const SrcT *>(conv_src0(L, fd));
     const SrcT *s1 = reinterpret_cast<const SrcT *>(fd.e[L.src1_idx]);
     f32x4 acc[MB][NB];
 #pragma unroll
@@ -690,7 +737,7 @@ __global__ __launch_bounds__(kThreads) void conv3x3_bf16_direct(ConvLayer L, Fra
     const int lj = lane & 15, lq = lane >> 4;
 
     const unsigned short *s0 =
-        reinterpret_cast<const unsigned short *>(L.src0_kind ? fd.u[L.src0_idx] : fd.e[L.src0_idx]);
+        reinterpret_cast<const unsigned short *>(conv_src0(L, fd));
     const unsigned short *s1 = reinterpret_cast<const unsigned short *>(fd.e[L.src1_idx]);
     const int H0 = MODE == CONV_CAT ? Hl >> 1 : Hl, W0 = MODE == CONV_CAT ? Wl >> 1 : Wl;
     const rsrc_t r0 = make_rsrc(s0, (unsigned)((size_t)H0 * W0 * L.C0 * 2));
@@ -829,6 +876,11 @@ __global__ __launch_bounds__(kThreads) void conv3x3_bf16_direct(ConvLayer L, Fra
 #define WSKP_CONV_DIRECT 1
 #endif
 constexpr int kTH = WSKP_CONV_TH;
+// the network-input layer (one reduction chunk) gets its own knob
+#ifndef WSKP_PACK_TH
+#define WSKP_PACK_TH 8
+#endif
+constexpr int kTHP = WSKP_PACK_TH;
 constexpr int kTHD = WSKP_DIRECT_TH;
 #ifndef WSKP_DIRECT_DB
 #define WSKP_DIRECT_DB 0
@@ -840,7 +892,10 @@ static bool uses_direct(int prec, int mode, int CK)
     return WSKP_CONV_DIRECT && prec == 1 && CK == 32 && (mode == CONV_CAT || mode == CONV_PLAIN);
 }
 
-int conv_tile_rows(int prec, int mode, int CK) { return uses_direct(prec, mode, CK) ? kTHD : kTH; }
+int conv_tile_rows(int prec, int mode, int CK)
+{
+    return uses_direct(prec, mode, CK) ? kTHD : (mode == CONV_PACK ? kTHP : kTH);
+}
 
 int conv_chunk(int prec, int mode, int Cin, int C0)
 {
@@ -857,7 +912,7 @@ int conv_chunk(int prec, int mode, int Cin, int C0)
 #endif
 int conv_blocks_per_group(int mode, int nblk)
 {
-    if (mode == CONV_PLAIN || mode == CONV_PACK) return nblk % 2 == 0 ? 2 : 1;
+    if (mode == CONV_PACK) return nblk % 2 == 0 ? 2 : 1;
     for (int nb = WSKP_CONV_MAX_NB; nb > 1; --nb)
         if (nb <= 4 && nblk % nb == 0) return nb;
     return 1;
@@ -884,7 +939,8 @@ static void launch_one(const ConvLayer &L, const FrameArg &fa, int blocks, hipSt
     // fp32 activations travel with the fp32 MFMA form; the bf16 and fp8 forms
     // keep bf16 activations in memory
     using SrcT = typename std::conditional<PREC == 0, float, unsigned short>::type;
-    hipLaunchKernelGGL((conv3x3_kernel<PREC, MODE, EPI, kTH, CK, NB, SrcT, OutT>), dim3(blocks),
+    constexpr int TH = MODE == CONV_PACK ? kTHP : kTH;
+    hipLaunchKernelGGL((conv3x3_kernel<PREC, MODE, EPI, TH, CK, NB, SrcT, OutT>), dim3(blocks),
                        dim3(kThreads), 0, s, L, fa);
 }
 
@@ -907,6 +963,7 @@ static bool launch_ck_nb(const ConvLayer &L, const FrameArg &fa, int blocks, hip
     } else if constexpr (MODE == CONV_PLAIN) {
         WSKP_CASE(16, 1)
         if constexpr (PREC != 0) { WSKP_CASE(32, 1) }
+        if constexpr (PREC == 1 && EPI == EPI_RELU) { WSKP_CASE(32, 2) WSKP_CASE(32, 3) WSKP_CASE(32, 4) }
     } else {
         WSKP_CASE(16, 1) WSKP_CASE(16, 2) WSKP_CASE(16, 3) WSKP_CASE(16, 4)
         if constexpr (PREC != 0) { WSKP_CASE(32, 1) WSKP_CASE(32, 2) WSKP_CASE(32, 3) WSKP_CASE(32, 4) }
@@ -925,7 +982,8 @@ static bool dispatch(const ConvLayer &L, int mode, int epi, const FrameArg &fa, 
     case CONV_POOL: return launch_ck_nb<PREC, CONV_POOL, EPI_RELU, ActT>(L, fa, blocks, s);
     case CONV_CAT: return launch_ck_nb<PREC, CONV_CAT, EPI_RELU, ActT>(L, fa, blocks, s);
     case CONV_PLAIN:
-        // the head record is fp32 in every precision
+        // encoders on pooled maps (bf16); the head record is fp32 in every precision
+        if (epi == EPI_RELU) return launch_ck_nb<PREC, CONV_PLAIN, EPI_RELU, ActT>(L, fa, blocks, s);
         if (epi == EPI_HEAD_EXP) return launch_ck_nb<PREC, CONV_PLAIN, EPI_HEAD_EXP, float>(L, fa, blocks, s);
         return launch_ck_nb<PREC, CONV_PLAIN, EPI_HEAD_SOFTPLUS, float>(L, fa, blocks, s);
     default: return false;

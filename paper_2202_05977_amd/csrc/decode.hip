@@ -29,10 +29,16 @@ namespace wskp {
 #endif
 constexpr int kDTX = 32, kDTY = WSKP_DECODE_TY;
 static_assert(kDTY % 8 == 0, "8 row groups of kDTY/8 rows");
+// minimum resident workgroups per CU the forward kernel's registers must
+// allow (a build-time tuning knob)
+#ifndef WSKP_DECODE_MIN_WG
+#define WSKP_DECODE_MIN_WG 1
+#endif
 
 struct DecodeIO {
     int H, W;
-    const float *head;  // [H,W,2M]
+    const float *head;  // map j of pixel q at head[q * hs_pix + j * hs_map]
+    size_t hs_pix, hs_map;
     const float *r, *a; // frames form
     const float *c;     // tensors form
     const float *mod;   // tensors form, may be null
@@ -68,7 +74,9 @@ __device__ __forceinline__ bool decode_locate(const DecodeCfg &dc, const FrameAr
         const FrameDesc &fd = frame_at(fa, f);
         io.H = fd.H;
         io.W = fd.W;
-        io.head = fd.head;
+        io.head = fd.head;              // planar [2M][H][W] (written by the head conv)
+        io.hs_pix = 1;
+        io.hs_map = (size_t)fd.H * fd.W;
         io.r = fd.r;
         io.a = fd.a;
         io.c = nullptr;
@@ -86,7 +94,9 @@ __device__ __forceinline__ bool decode_locate(const DecodeCfg &dc, const FrameAr
         const size_t P = (size_t)dt.H * dt.W;
         io.H = dt.H;
         io.W = dt.W;
-        io.head = dt.head + (size_t)f * P * twoM;
+        io.head = dt.head + (size_t)f * P * twoM;   // interleaved [H][W][2M]
+        io.hs_pix = twoM;
+        io.hs_map = 1;
         io.r = io.a = nullptr;
         io.c = dt.c + (size_t)f * P * 3;
         io.mod = dt.mod ? dt.mod + (size_t)f * P * 3 : nullptr;
@@ -228,7 +238,7 @@ __device__ __forceinline__ void load_w(const DecodeIO &io, int i, const int *gp,
 {
 #pragma unroll
     for (int k = 0; k < max_pix<RM>(); ++k)
-        w[k] = gp[k] >= 0 ? io.head[(size_t)gp[k] * (2 * M) + i] : 0.f;
+        w[k] = gp[k] >= 0 ? io.head[(size_t)gp[k] * io.hs_pix + i * io.hs_map] : 0.f;
 }
 
 // Dynamic LDS: product plane float4 [HXY] (W_i, W_i c) rebuilt for each
@@ -241,7 +251,7 @@ __device__ __forceinline__ void load_w(const DecodeIO &io, int i, const int *gp,
 //       dS_i(p)    = -[S_i > eps] sum_ch u_i,ch(p) out_i,ch(p)
 //     (u_i, dS_i) go to scratch; decode_adj_b_kernel box-sums them.
 template <int M, int KIND, int RM>
-__global__ __launch_bounds__(kThreads) void decode_fwd_kernel(DecodeCfg dc, FrameArg fa,
+__global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kernel(DecodeCfg dc, FrameArg fa,
                                                                DecodeTensors dt)
 {
     constexpr bool FRAMES = KIND == DK_FRAMES;
@@ -279,39 +289,43 @@ __global__ __launch_bounds__(kThreads) void decode_fwd_kernel(DecodeCfg dc, Fram
     }
     load_w<M, RM>(io, 0, gp, wv);
 
-    // fusion weights of this thread's kRun centres (column tx, rows kRun*ty + o)
-    float alpha[kRun][M], F[kRun][3];
+    // Fusion (Eq. 5) of this thread's kRun centres (column tx, rows
+    // kRun*ty + o).  Forward: softmax numerators exp(l_i - max_j l_j) weight
+    // the filtered values as they are produced and the sum of the
+    // numerators divides once at the end; no per-size state is kept, so the
+    // size loop need not be unrolled.  Adjoint: the normalised alpha_i are
+    // kept for the gradient.
+    const float *lp[kRun];
+    float lmax[kRun], esum[kRun], F[kRun][3];
+    float alpha[ADJ ? kRun : 1][ADJ ? M : 1];
 #pragma unroll
     for (int o = 0; o < kRun; ++o) {
         const int y = y0 + kRun * ty + o, x = x0 + tx;
-        if (y < H && x < W) {
-            const float *lp = io.head + ((size_t)y * W + x) * (2 * M) + M;
-            float lmax = -INFINITY;
+        const bool in = y < H && x < W;
+        lp[o] = io.head + ((size_t)(in ? y : 0) * W + (in ? x : 0)) * io.hs_pix + M * io.hs_map;
+        float m = -INFINITY;
+#pragma unroll
+        for (int i = 0; i < M; ++i) m = fmaxf(m, lp[o][i * io.hs_map]);
+        lmax[o] = m;
+        esum[o] = 0.f;
+        F[o][0] = F[o][1] = F[o][2] = 0.f;
+        if constexpr (ADJ) {
+            float sum = 0.f;
 #pragma unroll
             for (int i = 0; i < M; ++i) {
-                alpha[o][i] = lp[i];
-                lmax = fmaxf(lmax, alpha[o][i]);
+                alpha[o][i] = expf(lp[o][i * io.hs_map] - m);
+                sum += alpha[o][i];
             }
-            float s = 0.f;
-#pragma unroll
-            for (int i = 0; i < M; ++i) {
-                alpha[o][i] = expf(alpha[o][i] - lmax);
-                s += alpha[o][i];
-            }
-            const float inv = 1.f / s;
+            const float inv = 1.f / sum;
 #pragma unroll
             for (int i = 0; i < M; ++i) alpha[o][i] *= inv;
-        } else {
-#pragma unroll
-            for (int i = 0; i < M; ++i) alpha[o][i] = 0.f;
         }
-        F[o][0] = F[o][1] = F[o][2] = 0.f;
     }
     float outv[ADJ ? kRun : 1][ADJ ? M : 1][3];
     float Sv[ADJ ? kRun : 1][ADJ ? M : 1];
 
-#pragma unroll
-    for (int i = 0; i < M; ++i) {
+    // one kernel size: product plane, window sums, normalisation, fusion
+    auto size_step = [&](int i) {
         // product plane of this size from this thread's registers, then
         // fetch the next size's weights
 #pragma unroll
@@ -327,7 +341,7 @@ __global__ __launch_bounds__(kThreads) void decode_fwd_kernel(DecodeCfg dc, Fram
 #undef WSKP_WS
 #pragma unroll
         for (int o = 0; o < kRun; ++o) {
-            const float inv = 1.f / fmaxf(acc[o].x, dc.eps_norm);
+            const float inv = __builtin_amdgcn_rcpf(fmaxf(acc[o].x, dc.eps_norm));
             const float o0 = acc[o].y * inv, o1 = acc[o].z * inv, o2 = acc[o].w * inv;
             if constexpr (ADJ) {
                 outv[o][i][0] = o0;
@@ -335,10 +349,26 @@ __global__ __launch_bounds__(kThreads) void decode_fwd_kernel(DecodeCfg dc, Fram
                 outv[o][i][2] = o2;
                 Sv[o][i] = acc[o].x;
             } else {
-                F[o][0] += alpha[o][i] * o0;
-                F[o][1] += alpha[o][i] * o1;
-                F[o][2] += alpha[o][i] * o2;
+                const float e = expf(lp[o][i * io.hs_map] - lmax[o]);
+                esum[o] += e;
+                F[o][0] += e * o0;
+                F[o][1] += e * o1;
+                F[o][2] += e * o2;
             }
+        }
+    };
+    if constexpr (ADJ) {
+#pragma unroll
+        for (int i = 0; i < M; ++i) size_step(i);
+    } else {
+#pragma unroll 1
+        for (int i = 0; i < M; ++i) size_step(i);
+#pragma unroll
+        for (int o = 0; o < kRun; ++o) {
+            const float inv = 1.f / esum[o];
+            F[o][0] *= inv;
+            F[o][1] *= inv;
+            F[o][2] *= inv;
         }
     }
 

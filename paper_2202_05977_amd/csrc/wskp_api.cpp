@@ -102,6 +102,7 @@ struct wskp_ctx {
     int device = 0;
     int prec = 0;
     int act_bytes = 4;
+    bool pooled = false;   // encoder epilogues write 2x2 means p_l; enc_{l+1} reads them plainly
     std::vector<LayerPlan> layers;
     void *dweights = nullptr;
     DecodeCfg dc{};
@@ -268,7 +269,7 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
     std::vector<std::pair<int, int>> dims;
     conv_dims(cfg, dims);
     auto add = [&](int mode, int level, int s0kind, int s0, int s1, int C0, int C1, int Cin, int Cout,
-                   int okind, int oidx) {
+                   int okind, int oidx, int pool_idx) {
         LayerPlan lp{};
         ConvLayer &c = lp.L;
         c.level = level;
@@ -284,6 +285,7 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
         c.NB = conv_blocks_per_group(mode, nblk);
         c.groups = nblk / c.NB;
         c.th = conv_tile_rows(h->prec, mode, c.CK);
+        c.pool_idx = pool_idx;
         c.Cout_pad = nblk * 16;
         c.out_kind = okind;
         c.out_idx = oidx;
@@ -298,11 +300,25 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
         h->layers.push_back(lp);
     };
     const int *ch = cfg->channels;
-    add(CONV_PACK, 0, 0, 0, 0, 10, 0, 10, ch[0], 0, 0);
-    for (int l = 1; l < L; ++l) add(CONV_POOL, l, 0, l - 1, 0, ch[l - 1], 0, ch[l - 1], ch[l], 0, l);
+    // bf16: each encoder epilogue (a workgroup owning whole row pairs) also
+    // writes the 2x2 means of its output, and the next encoder reads those
+    // with the direct-load kernel (32-channel chunks)
+    h->pooled = h->prec == WSKP_PREC_BF16 && L > 1 && conv_tile_rows(h->prec, CONV_PACK, 16) >= 8 &&
+                conv_tile_rows(h->prec, CONV_PLAIN, 32) >= 8;
+    for (int l = 0; l + 1 < L && h->pooled; ++l)
+        if (ch[l] % 32) h->pooled = false;
+    if (h->pooled) {
+        add(CONV_PACK, 0, 0, 0, 0, 10, 0, 10, ch[0], 0, 0, 0);
+        for (int l = 1; l < L; ++l)
+            add(CONV_PLAIN, l, 2, l - 1, 0, ch[l - 1], 0, ch[l - 1], ch[l], 0, l, l + 1 < L ? l : -1);
+    } else {
+        add(CONV_PACK, 0, 0, 0, 0, 10, 0, 10, ch[0], 0, 0, -1);
+        for (int l = 1; l < L; ++l)
+            add(CONV_POOL, l, 0, l - 1, 0, ch[l - 1], 0, ch[l - 1], ch[l], 0, l, -1);
+    }
     for (int l = L - 2; l >= 0; --l)
-        add(CONV_CAT, l, 1, l + 1, l, ch[l + 1], ch[l], ch[l + 1] + ch[l], ch[l], 1, l);
-    add(CONV_PLAIN, 0, 1, 0, 0, ch[0], 0, ch[0], 2 * M, 2, 0);
+        add(CONV_CAT, l, 1, l + 1, l, ch[l + 1], ch[l], ch[l + 1] + ch[l], ch[l], 1, l, -1);
+    add(CONV_PLAIN, 0, 1, 0, 0, ch[0], 0, ch[0], 2 * M, 2, 0, -1);
 
     // ---- pack weights into one device buffer
     std::vector<char> blob;
@@ -380,9 +396,9 @@ extern "C" wskp_status_t wskp_destroy(wskp_handle_t h)
 
 // ---------------------------------------------------------------------------
 // Workspace: [frame table][frame 0][frame 1]...; per frame e_0..e_{L-1},
-// u_0..u_{L-2}, head, each 256-byte aligned.
+// u_0..u_{L-2}, (pooled plan) p_0..p_{L-2}, head, each 256-byte aligned.
 static size_t frame_bytes(const wskp_ctx *h, int H, int W, size_t *off_e, size_t *off_u,
-                          size_t *off_head)
+                          size_t *off_head, size_t *off_p = nullptr)
 {
     const int L = h->cfg.levels;
     size_t o = 0;
@@ -393,6 +409,10 @@ static size_t frame_bytes(const wskp_ctx *h, int H, int W, size_t *off_e, size_t
     for (int l = 0; l < L - 1; ++l) {
         if (off_u) off_u[l] = o;
         o += align_up((size_t)(H >> l) * (W >> l) * h->cfg.channels[l] * h->act_bytes);
+    }
+    for (int l = 0; l < L - 1 && h->pooled; ++l) {
+        if (off_p) off_p[l] = o;
+        o += align_up((size_t)(H >> (l + 1)) * (W >> (l + 1)) * h->cfg.channels[l] * h->act_bytes);
     }
     if (off_head) *off_head = o;
     o += align_up((size_t)H * W * 2 * h->cfg.num_kernels * 4);
@@ -442,8 +462,8 @@ extern "C" wskp_status_t wskp_workspace_tensor(wskp_handle_t h, int n, const int
     const int L = h->cfg.levels;
     size_t base = table_bytes(n);
     for (int i = 0; i < frame; ++i) base += frame_bytes(h, H[i], W[i], nullptr, nullptr, nullptr);
-    size_t oe[kMaxLevels], ou[kMaxLevels], oh;
-    frame_bytes(h, H[frame], W[frame], oe, ou, &oh);
+    size_t oe[kMaxLevels], ou[kMaxLevels], op[kMaxLevels], oh;
+    frame_bytes(h, H[frame], W[frame], oe, ou, &oh, op);
     int l, c, eb = h->act_bytes;
     size_t o;
     if (which >= 0 && which < L) {
@@ -453,7 +473,15 @@ extern "C" wskp_status_t wskp_workspace_tensor(wskp_handle_t h, int n, const int
         o = (l == L - 1) ? oe[l] : ou[l];
         c = h->cfg.channels[l];
     } else if (which == 200) {
-        l = 0; o = oh; c = 2 * h->cfg.num_kernels; eb = 4;
+        // planar [2M][H][W]
+        *offset = base + oh;
+        if (th) *th = 2 * h->cfg.num_kernels;
+        if (tw) *tw = H[frame];
+        if (tc) *tc = W[frame];
+        if (elem_bytes) *elem_bytes = 4;
+        return WSKP_OK;
+    } else if (h->pooled && which >= 300 && which < 300 + L - 1) {
+        o = op[which - 300]; c = h->cfg.channels[which - 300]; l = which - 300 + 1;
     } else {
         return fail(WSKP_E_INVALID_ARG, "unknown tensor id");
     }
@@ -467,8 +495,8 @@ extern "C" wskp_status_t wskp_workspace_tensor(wskp_handle_t h, int n, const int
 
 static void fill_frame(const wskp_ctx *h, FrameDesc &fd, char *fbase, const wskp_frame_t &f)
 {
-    size_t oe[kMaxLevels], ou[kMaxLevels], oh;
-    frame_bytes(h, f.H, f.W, oe, ou, &oh);
+    size_t oe[kMaxLevels], ou[kMaxLevels], op[kMaxLevels], oh;
+    frame_bytes(h, f.H, f.W, oe, ou, &oh, op);
     const int L = h->cfg.levels;
     std::memset(&fd, 0, sizeof(fd));
     fd.H = f.H;
@@ -481,6 +509,7 @@ static void fill_frame(const wskp_ctx *h, FrameDesc &fd, char *fbase, const wskp
     for (int l = 0; l < L; ++l) fd.e[l] = fbase + oe[l];
     for (int l = 0; l < L - 1; ++l) fd.u[l] = fbase + ou[l];
     fd.u[L - 1] = fd.e[L - 1];
+    for (int l = 0; l < L - 1 && h->pooled; ++l) fd.p[l] = fbase + op[l];
     fd.head = reinterpret_cast<float *>(fbase + oh);
 }
 

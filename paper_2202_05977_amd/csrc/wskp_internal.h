@@ -20,6 +20,7 @@ struct FrameDesc {
     float *out;                  // [H,W,3]
     void *e[kMaxLevels];         // encoder outputs e_l  [H>>l, W>>l, C_l]
     void *u[kMaxLevels];         // decoder outputs u_l  [H>>l, W>>l, C_l]; u[L-1] == e[L-1]
+    void *p[kMaxLevels];         // bf16 form: 2x2 means of e_l [H>>(l+1), W>>(l+1), C_l]
     float *head;                 // [H,W,2M]: weights W_i then logits
 };
 
@@ -89,7 +90,7 @@ enum ActType { ACT_F32 = 0, ACT_BF16 = 1 };
 // One 3x3 conv layer as the kernels see it.
 struct ConvLayer {
     int level;         // output resolution level (H >> level, W >> level)
-    int src0_kind;     // 0: e[src0_idx], 1: u[src0_idx]
+    int src0_kind;     // 0: e[src0_idx], 1: u[src0_idx], 2: p[src0_idx]
     int src0_idx;
     int src1_idx;      // CAT: skip e[src1_idx]
     int C0, C1;        // channels of source 0 / source 1 (CAT: up, skip)
@@ -103,6 +104,7 @@ struct ConvLayer {
     int CK;            // input channels per reduction chunk (weights packed to match)
     int NB;            // 16-channel output blocks per workgroup
     int th;            // output rows per tile of the kernel that runs this layer
+    int pool_idx;      // >= 0: the epilogue also writes the 2x2 means of the output to p[pool_idx]
     const void *w;     // packed weights
     const float *bias; // [Cout]
     float inv_gamma, dnear, dinv;  // CONV_PACK preprocessing constants

@@ -303,12 +303,15 @@ class Denoiser:
         wskp_denoise_batch(self.h, frames, ws, flags, stream)
 
     def intermediate(self, Hs, Ws, frame: int, which: int) -> torch.Tensor:
-        """View of an intermediate map in the current workspace (debugging)."""
+        """View of an intermediate map in the current workspace (debugging),
+        as [H_l, W_l, C]; the planar head record (which = 200) is returned as
+        a permuted [H, W, 2M] view."""
         off, (th, tw, tc), eb = wskp_workspace_tensor(self.h, Hs, Ws, frame, which)
         ws = self._ws
         raw = ws[off:off + th * tw * tc * eb]
         if eb == 4:
-            return raw.view(torch.float32).view(th, tw, tc)
+            t = raw.view(torch.float32).view(th, tw, tc)
+            return t.permute(1, 2, 0) if which == 200 else t
         return raw.view(torch.bfloat16).view(th, tw, tc)
 
     def close(self):

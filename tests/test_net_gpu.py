@@ -73,6 +73,32 @@ def test_hd_bf16_720p_end_to_end():
     assert err <= TOL_BF16
 
 
+def test_hd_bf16_layers_and_pooled_copies():
+    """bf16 HD net layer by layer against the FP64 oracle (bf16 tolerance),
+    and the pooled copies p_l that the encoder epilogues pass on: each is
+    exactly the 2x2 mean of the stored e_l (summed in fp32 in the order
+    (2y,2x), (2y,2x+1), (2y+1,2x), (2y+1,2x+1), rounded to bf16)."""
+    H, W = 64, 96
+    cfg = synth.HD
+    L = cfg.levels
+    fr, y, it = _oracle("hd", 2, H, W)
+    layers = oracle.unet_layers(it["X"], synth.make_weights(cfg, 0), cfg)
+    dn = _denoiser(cfg, "bf16")
+    out = _run(dn, fr)
+    for l in range(L):
+        g = dn.intermediate([H], [W], 0, l).float().cpu().numpy()
+        assert rel_l2(g, layers[f"e{l}"]) <= TOL_BF16, f"e{l}"
+    for l in range(L - 1):
+        g = dn.intermediate([H], [W], 0, 100 + l).float().cpu().numpy()
+        assert rel_l2(g, layers[f"u{l}"]) <= TOL_BF16, f"u{l}"
+    assert rel_l2(out, y) <= TOL_BF16
+    for l in range(L - 1):
+        e = dn.intermediate([H], [W], 0, l).float()
+        p = dn.intermediate([H], [W], 0, 300 + l)
+        m = (((e[0::2, 0::2] + e[0::2, 1::2]) + e[1::2, 0::2]) + e[1::2, 1::2]) * 0.25
+        assert torch.equal(p, m.to(torch.bfloat16)), f"p{l}"
+
+
 def test_small_bf16_ragged():
     fr, y, _ = _oracle("small", 1, 72, 104)
     out = _run(_denoiser(synth.SMALL, "bf16"), fr)
