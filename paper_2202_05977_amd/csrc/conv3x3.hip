@@ -183,12 +183,12 @@ __device__ __forceinline__ void pack_input(const ConvLayer &L, const FrameDesc &
 {
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-        const float r = fminf(fmaxf(fd.r[pix * 3 + ch], 0.f), 1.f);
+        const float r = fminf(fmaxf(gload(fd.r + pix * 3 + ch), 0.f), 1.f);
         x[ch] = fast_exp2(fast_log2(r) * L.inv_gamma);
-        x[3 + ch] = fd.a[pix * 3 + ch];
-        x[6 + ch] = (fd.n[pix * 3 + ch] + 1.f) * 0.5f;
+        x[3 + ch] = gload(fd.a + pix * 3 + ch);
+        x[6 + ch] = (gload(fd.n + pix * 3 + ch) + 1.f) * 0.5f;
     }
-    x[9] = fminf(fmaxf((fd.d[pix] - L.dnear) * L.dinv, 0.f), 1.f);
+    x[9] = fminf(fmaxf((gload(fd.d + pix) - L.dnear) * L.dinv, 0.f), 1.f);
 }
 
 // =============================================================================
@@ -534,14 +534,15 @@ __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDes
     const int lj = lane & 15, lq = lane >> 4;
     OutT *dst = conv_dst<OutT>(L, fd);
     const bool pool = CAN_POOL && L.pool_idx >= 0;
+    OutT *pdst = pool ? reinterpret_cast<OutT *>(fd.p[L.pool_idx]) : nullptr;
     float bias[NB][4], dq[NB][4];
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int co = g * NC + nb * 16 + 4 * lq + v;
-            bias[nb][v] = co < L.Cout ? L.bias[co] : 0.f;
-            dq[nb][v] = (PREC == 2 && co < L.Cout) ? L.out_scale[co] : 1.f;
+            bias[nb][v] = co < L.Cout ? gload(L.bias + co) : 0.f;
+            dq[nb][v] = (PREC == 2 && co < L.Cout) ? gload(L.out_scale + co) : 1.f;
         }
     float pe[CAN_POOL ? 2 : 1][CAN_POOL ? NB : 1][4];   // even-row partial sums
 #pragma unroll
@@ -565,15 +566,15 @@ __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDes
                     const size_t P = (size_t)Hl * Wl;
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
-                        if (co + k < L.Cout) q[(size_t)(co + k) * P] = v[k];
+                        if (co + k < L.Cout) gstore(q + (size_t)(co + k) * P, v[k]);
                 }
             } else if constexpr (std::is_same<OutT, float>::value) {
                 // fp32 activations: Cout is a multiple of 16
-                if (in && cin) *reinterpret_cast<float4 *>(pp + co) = make_float4(v[0], v[1], v[2], v[3]);
+                if (in && cin) gstore(reinterpret_cast<gf32x4 *>(pp + co), gf32x4{v[0], v[1], v[2], v[3]});
             } else {
                 // activations: Cout is a multiple of 16
                 const uint2 q = make_uint2(pack2(v[0], v[1]), pack2(v[2], v[3]));
-                if (in && cin) *reinterpret_cast<uint2 *>(pp + co) = q;
+                if (in && cin) gstore(reinterpret_cast<gu32x2 *>(pp + co), gu32x2{q.x, q.y});
                 if constexpr (CAN_POOL) {
                     if (pool) {
                         const float r[4] = {__uint_as_float(q.x << 16), __uint_as_float(q.x & 0xffff0000u),
@@ -588,9 +589,8 @@ __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDes
                             for (int k = 0; k < 4; ++k) m[k] = 0.25f * ((pe[cb][nb][k] + r[k]) + __shfl_xor(r[k], 1, 64));
                             const int Y = y >> 1, X = x >> 1;
                             if ((lj & 1) == 0 && Y < (Hl >> 1) && X < (Wl >> 1) && cin) {
-                                OutT *pd = reinterpret_cast<OutT *>(fd.p[L.pool_idx]) +
-                                           ((size_t)Y * (Wl >> 1) + X) * L.Cout + co;
-                                *reinterpret_cast<uint2 *>(pd) = make_uint2(pack2(m[0], m[1]), pack2(m[2], m[3]));
+                                OutT *pd = pdst + ((size_t)Y * (Wl >> 1) + X) * L.Cout + co;
+                                gstore(reinterpret_cast<gu32x2 *>(pd), gu32x2{pack2(m[0], m[1]), pack2(m[2], m[3])});
                             }
                         }
                     }

@@ -238,7 +238,7 @@ __device__ __forceinline__ void load_w(const DecodeIO &io, int i, const int *gp,
 {
 #pragma unroll
     for (int k = 0; k < max_pix<RM>(); ++k)
-        w[k] = gp[k] >= 0 ? io.head[(size_t)gp[k] * io.hs_pix + i * io.hs_map] : 0.f;
+        w[k] = gp[k] >= 0 ? gload(io.head + (size_t)gp[k] * io.hs_pix + i * io.hs_map) : 0.f;
 }
 
 // Dynamic LDS: product plane float4 [HXY] (W_i, W_i c) rebuilt for each
@@ -282,8 +282,8 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
             const size_t q = (size_t)gp[k] * 3;
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
-                if (FRAMES) cv[k][ch] = io.r[q + ch] * __builtin_amdgcn_rcpf(io.a[q + ch] + dc.eps_albedo);
-                else cv[k][ch] = io.c[q + ch];
+                if (FRAMES) cv[k][ch] = gload(io.r + q + ch) * __builtin_amdgcn_rcpf(gload(io.a + q + ch) + dc.eps_albedo);
+                else cv[k][ch] = gload(io.c + q + ch);
             }
         }
     }
@@ -305,7 +305,7 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
         lp[o] = io.head + ((size_t)(in ? y : 0) * W + (in ? x : 0)) * io.hs_pix + M * io.hs_map;
         float m = -INFINITY;
 #pragma unroll
-        for (int i = 0; i < M; ++i) m = fmaxf(m, lp[o][i * io.hs_map]);
+        for (int i = 0; i < M; ++i) m = fmaxf(m, gload(lp[o] + i * io.hs_map));
         lmax[o] = m;
         esum[o] = 0.f;
         F[o][0] = F[o][1] = F[o][2] = 0.f;
@@ -313,7 +313,7 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
             float sum = 0.f;
 #pragma unroll
             for (int i = 0; i < M; ++i) {
-                alpha[o][i] = expf(lp[o][i * io.hs_map] - m);
+                alpha[o][i] = expf(gload(lp[o] + i * io.hs_map) - m);
                 sum += alpha[o][i];
             }
             const float inv = 1.f / sum;
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
                 outv[o][i][2] = o2;
                 Sv[o][i] = acc[o].x;
             } else {
-                const float e = expf(lp[o][i * io.hs_map] - lmax[o]);
+                const float e = expf(gload(lp[o] + i * io.hs_map) - lmax[o]);
                 esum[o] += e;
                 F[o][0] += e * o0;
                 F[o][1] += e * o1;
@@ -381,15 +381,15 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
                 float m = 1.f;
-                if (FRAMES) m = io.a[pix * 3 + ch] + dc.eps_albedo;
-                else if (io.mod) m = io.mod[pix * 3 + ch];
-                io.out[pix * 3 + ch] = m * F[o][ch];
+                if (FRAMES) m = gload(io.a + pix * 3 + ch) + dc.eps_albedo;
+                else if (io.mod) m = gload(io.mod + pix * 3 + ch);
+                gstore(io.out + pix * 3 + ch, m * F[o][ch]);
             }
         } else {
             float dF[3];
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch)
-                dF[ch] = io.g[pix * 3 + ch] * (io.mod ? io.mod[pix * 3 + ch] : 1.f);
+                dF[ch] = gload(io.g + pix * 3 + ch) * (io.mod ? gload(io.mod + pix * 3 + ch) : 1.f);
             float da[M], adot = 0.f;
 #pragma unroll
             for (int i = 0; i < M; ++i) {
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
             const size_t P = (size_t)H * W;
 #pragma unroll
             for (int i = 0; i < M; ++i) {
-                gh[M + i] = alpha[o][i] * (da[i] - adot);
+                gstore(gh + M + i, alpha[o][i] * (da[i] - adot));
                 const float S = Sv[o][i];
                 const float inv = 1.f / fmaxf(S, dc.eps_norm);
                 float4 v;
@@ -410,7 +410,7 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
                 v.w = S > dc.eps_norm
                           ? -(v.x * outv[o][i][0] + v.y * outv[o][i][1] + v.z * outv[o][i][2])
                           : 0.f;
-                io.scratch[(size_t)i * P + pix] = v;
+                gstore(reinterpret_cast<gf32x4 *>(io.scratch + (size_t)i * P + pix), gf32x4{v.x, v.y, v.z, v.w});
             }
         }
     }
@@ -454,7 +454,12 @@ __global__ __launch_bounds__(kThreads) void decode_adj_b_kernel(DecodeCfg dc, De
         float4 v[kMaxPix];
 #pragma unroll
         for (int k = 0; k < kMaxPix; ++k)
-            v[k] = gp[k] >= 0 ? sp[gp[k]] : make_float4(0.f, 0.f, 0.f, 0.f);
+            if (gp[k] >= 0) {
+                const gf32x4 q = gload(reinterpret_cast<const gf32x4 *>(sp + gp[k]));
+                v[k] = make_float4(q.x, q.y, q.z, q.w);
+            } else {
+                v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
 #pragma unroll
         for (int k = 0; k < kMaxPix; ++k) {
             const int p = tid + k * kThreads;
@@ -471,10 +476,10 @@ __global__ __launch_bounds__(kThreads) void decode_adj_b_kernel(DecodeCfg dc, De
             if (y < H && x < W) {
                 const size_t pix = (size_t)y * W + x;
                 const float *cp = io.c + pix * 3;
-                const float w = io.head[pix * (2 * M) + i];
+                const float w = gload(io.head + pix * (2 * M) + i);
                 // acc = box sums of (u_0, u_1, u_2, dS)
-                io.grad_head[pix * (2 * M) + i] =
-                    cp[0] * acc[o].x + cp[1] * acc[o].y + cp[2] * acc[o].z + acc[o].w;
+                gstore(io.grad_head + pix * (2 * M) + i,
+                       gload(cp) * acc[o].x + gload(cp + 1) * acc[o].y + gload(cp + 2) * acc[o].z + acc[o].w);
                 dcv[o][0] += w * acc[o].x;
                 dcv[o][1] += w * acc[o].y;
                 dcv[o][2] += w * acc[o].z;
@@ -487,7 +492,7 @@ __global__ __launch_bounds__(kThreads) void decode_adj_b_kernel(DecodeCfg dc, De
         if (y < H && x < W) {
             const size_t pix = (size_t)y * W + x;
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) gc[pix * 3 + ch] = dcv[o][ch];
+            for (int ch = 0; ch < 3; ++ch) gstore(gc + pix * 3 + ch, dcv[o][ch]);
         }
     }
 }

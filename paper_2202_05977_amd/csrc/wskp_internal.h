@@ -24,6 +24,23 @@ struct FrameDesc {
     float *head;                 // [H,W,2M]: weights W_i then logits
 };
 
+// Global-memory access through address-space-1 pointers.  Pointers that
+// reach a kernel inside a structure are generic, and generic (flat)
+// accesses also count against the LDS wait counter: every wait for an LDS
+// read would then also wait for the global loads still in flight.
+template <typename T>
+__device__ __forceinline__ T gload(const T *p)
+{
+    return *(const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ void gstore(T *p, T v)
+{
+    *(__attribute__((address_space(1))) T *)p = v;
+}
+typedef float gf32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int gu32x2 __attribute__((ext_vector_type(2)));
+
 // A batch of frames for one launch: either one frame passed by value or a
 // device-resident table of n frames.
 struct FrameArg {
@@ -53,7 +70,7 @@ __device__ __forceinline__ int batch_frame(const FrameArg &fa, int &t, Count cou
     int base = 0;
     for (int f0 = 0; f0 < fa.n; f0 += 64) {
         const int f = f0 + lane;
-        int c = f < fa.n ? count(fa.table[f].H, fa.table[f].W) : 0;
+        int c = f < fa.n ? count(gload(&fa.table[f].H), gload(&fa.table[f].W)) : 0;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
             const int v = __shfl_up(c, d, 64);
