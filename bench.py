@@ -249,12 +249,12 @@ def mode_serve(args):
     for (H, W) in proto:
         tok = ex.launch([serve.Request(-1, sizes.index((H, W)), 0.0, H, W)], 0, 0)
         ex.wait(tok)
-    st = serve.Server(ex, budget, max_inflight=2, max_batch=64).run(
+    st = serve.Server(ex, budget, max_inflight=2, max_batch=args.max_batch).run(
         [dataclasses_replace(r) for r in reqs])
     res["bf16_continuous_batching"] = st.__dict__
     log(f"[serve] bf16 batching: {st}")
     # capacity: the whole trace queued at once, frames per wall-clock second
-    st = serve.Server(ex, budget, max_inflight=2, max_batch=64).run(
+    st = serve.Server(ex, budget, max_inflight=2, max_batch=args.max_batch).run(
         [dataclasses_replace(r) for r in reqs], realtime=False)
     res["bf16_batching_capacity_fps"] = st.frames / st.wall_s
     log(f"[serve] bf16 batching capacity: {st.frames / st.wall_s:.1f} frames/s "
@@ -332,6 +332,8 @@ def main():
                          "train: decode adjoint on 8x256^2 crops; serve: 64-stream trace")
     ap.add_argument("--serve-frames", type=int, default=300)
     ap.add_argument("--fifo-frames", type=int, default=2000)
+    ap.add_argument("--max-batch", type=int, default=64,
+                    help="serve: most frames one batch may hold")
     ap.add_argument("--height", type=int, default=720)
     ap.add_argument("--width", type=int, default=1280)
     args = ap.parse_args()

@@ -892,9 +892,18 @@ static bool uses_direct(int prec, int mode, int CK)
     return WSKP_CONV_DIRECT && prec == 1 && CK == 32 && (mode == CONV_CAT || mode == CONV_PLAIN);
 }
 
-int conv_tile_rows(int prec, int mode, int CK)
+// Tile rows per layer: the input layer uses kTHP; the direct-load kernel uses
+// kTHD, or 4 rows on the coarsest levels (>= WSKP_COARSE_LEVEL), which have
+// few pixels, so that they still spread over all CUs, unless the layer passes
+// on 2x2 means (that needs whole row pairs per wave, 8 rows).
+#ifndef WSKP_COARSE_LEVEL
+#define WSKP_COARSE_LEVEL 3
+#endif
+int conv_tile_rows(int prec, int mode, int CK, int level, bool pool)
 {
-    return uses_direct(prec, mode, CK) ? kTHD : (mode == CONV_PACK ? kTHP : kTH);
+    if (mode == CONV_PACK) return kTHP;
+    if (!uses_direct(prec, mode, CK)) return kTH;
+    return (level >= WSKP_COARSE_LEVEL && !pool) ? 4 : kTHD;
 }
 
 int conv_chunk(int prec, int mode, int Cin, int C0)
@@ -905,14 +914,16 @@ int conv_chunk(int prec, int mode, int Cin, int C0)
     return 16;
 }
 
-// Wider groups stage and read each input tile fewer times (the A operand is
-// reused across NB blocks); narrower groups give more workgroups.
 #ifndef WSKP_CONV_MAX_NB
 #define WSKP_CONV_MAX_NB 4
 #endif
-int conv_blocks_per_group(int mode, int nblk)
+// Wider groups stage and read each input tile fewer times (the A operand is
+// reused across NB blocks); narrower groups give more workgroups, which the
+// direct-load kernel needs on the coarsest levels.
+int conv_blocks_per_group(int prec, int mode, int CK, int nblk, int level)
 {
     if (mode == CONV_PACK) return nblk % 2 == 0 ? 2 : 1;
+    if (uses_direct(prec, mode, CK) && level >= WSKP_COARSE_LEVEL) return 1;
     for (int nb = WSKP_CONV_MAX_NB; nb > 1; --nb)
         if (nb <= 4 && nblk % nb == 0) return nb;
     return 1;
@@ -932,8 +943,12 @@ template <int PREC, int MODE, int EPI, int CK, int NB, typename OutT>
 static void launch_one(const ConvLayer &L, const FrameArg &fa, int blocks, hipStream_t s)
 {
     if constexpr (WSKP_CONV_DIRECT && PREC == 1 && CK == 32 && (MODE == CONV_CAT || MODE == CONV_PLAIN)) {
-        hipLaunchKernelGGL((conv3x3_bf16_direct<MODE, EPI, kTHD, NB, kDirectDB, OutT>), dim3(blocks),
-                           dim3(kThreads), 0, s, L, fa);
+        if (L.th == 4)
+            hipLaunchKernelGGL((conv3x3_bf16_direct<MODE, EPI, 4, NB, kDirectDB, OutT>), dim3(blocks),
+                               dim3(kThreads), 0, s, L, fa);
+        else
+            hipLaunchKernelGGL((conv3x3_bf16_direct<MODE, EPI, kTHD, NB, kDirectDB, OutT>), dim3(blocks),
+                               dim3(kThreads), 0, s, L, fa);
         return;
     }
     // fp32 activations travel with the fp32 MFMA form; the bf16 and fp8 forms

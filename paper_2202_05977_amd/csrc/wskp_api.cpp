@@ -282,9 +282,9 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
         c.Cin_pad = (Cin + c.CK - 1) / c.CK * c.CK;
         c.Cout = Cout;
         const int nblk = (Cout + 15) / 16;
-        c.NB = conv_blocks_per_group(mode, nblk);
+        c.NB = conv_blocks_per_group(h->prec, mode, c.CK, nblk, level);
         c.groups = nblk / c.NB;
-        c.th = conv_tile_rows(h->prec, mode, c.CK);
+        c.th = conv_tile_rows(h->prec, mode, c.CK, level, pool_idx >= 0);
         c.pool_idx = pool_idx;
         c.Cout_pad = nblk * 16;
         c.out_kind = okind;
@@ -303,8 +303,8 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
     // bf16: each encoder epilogue (a workgroup owning whole row pairs) also
     // writes the 2x2 means of its output, and the next encoder reads those
     // with the direct-load kernel (32-channel chunks)
-    h->pooled = h->prec == WSKP_PREC_BF16 && L > 1 && conv_tile_rows(h->prec, CONV_PACK, 16) >= 8 &&
-                conv_tile_rows(h->prec, CONV_PLAIN, 32) >= 8;
+    h->pooled = h->prec == WSKP_PREC_BF16 && L > 1 && conv_tile_rows(h->prec, CONV_PACK, 16, 0, true) >= 8 &&
+                conv_tile_rows(h->prec, CONV_PLAIN, 32, 1, true) >= 8;
     for (int l = 0; l + 1 < L && h->pooled; ++l)
         if (ch[l] % 32) h->pooled = false;
     if (h->pooled) {

@@ -145,7 +145,7 @@ hipError_t launch_conv(const ConvLayer &L, int mode, int epi, int prec, const Fr
 int conv_grid(const ConvLayer &L, int n, const int *H, const int *W);
 int conv_chunk(int prec, int mode, int Cin, int C0);
 // 16-channel output blocks per workgroup for a layer with nblk blocks.
-int conv_blocks_per_group(int mode, int nblk);
+int conv_blocks_per_group(int prec, int mode, int CK, int nblk, int level);
 // Decode + fusion + remodulation over frames of fa (denoise mode: c and mod
 // derive from r, a) -- or over plain tensors (decode mode).
 hipError_t launch_decode_frames(const DecodeCfg &dc, const FrameArg &fa, int blocks, hipStream_t s);
@@ -160,6 +160,6 @@ size_t decode_backward_scratch_bytes(const DecodeCfg &dc, int N, int H, int W);
 
 // Tile geometry of the conv kernels (host and device agree on these).
 constexpr int kConvTW = 32;  // output columns per tile (two 16-pixel MFMA blocks)
-int conv_tile_rows(int prec, int mode, int CK);
+int conv_tile_rows(int prec, int mode, int CK, int level, bool pool);
 
 }  // namespace wskp
