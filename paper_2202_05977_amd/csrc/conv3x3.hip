@@ -177,18 +177,28 @@ __device__ __forceinline__ uint4 gload16(const void *p)
 
 // Network input of Sec. 5.1 at one pixel: [T(r) 3, a 3, (n+1)/2 3, depth 1],
 // T(x) = clamp(x,0,1)^(1/gamma) = 2^(log2(x)/gamma), depth scaled to [0,1]
-// and clamped.
-__device__ __forceinline__ void pack_input(const ConvLayer &L, const FrameDesc &fd, size_t pix,
-                                           float x[10])
+// and clamped.  pack_load only loads the raw values (so that the loads of
+// every item are in flight before any result is used); pack_transform maps
+// them in place.
+__device__ __forceinline__ void pack_load(const FrameDesc &fd, size_t pix, float x[10])
 {
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-        const float r = fminf(fmaxf(gload(fd.r + pix * 3 + ch), 0.f), 1.f);
-        x[ch] = fast_exp2(fast_log2(r) * L.inv_gamma);
+        x[ch] = gload(fd.r + pix * 3 + ch);
         x[3 + ch] = gload(fd.a + pix * 3 + ch);
-        x[6 + ch] = (gload(fd.n + pix * 3 + ch) + 1.f) * 0.5f;
+        x[6 + ch] = gload(fd.n + pix * 3 + ch);
     }
-    x[9] = fminf(fmaxf((gload(fd.d + pix) - L.dnear) * L.dinv, 0.f), 1.f);
+    x[9] = gload(fd.d + pix);
+}
+
+__device__ __forceinline__ void pack_transform(const ConvLayer &L, float x[10])
+{
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        x[ch] = fast_exp2(fast_log2(fminf(fmaxf(x[ch], 0.f), 1.f)) * L.inv_gamma);
+        x[6 + ch] = (x[6 + ch] + 1.f) * 0.5f;
+    }
+    x[9] = fminf(fmaxf((x[9] - L.dnear) * L.dinv, 0.f), 1.f);
 }
 
 // =============================================================================
@@ -284,14 +294,21 @@ struct Stage {
         const int c0 = cc * CK;
         // decoder input: the whole chunk comes from one source (CK divides C0)
         const bool from_up = (MODE != CONV_CAT) || c0 < L.C0;
+        // network input: the raw values of every item (items outside the
+        // image read pixel 0 and are zeroed below) are loaded first
+        float raw[MODE == CONV_PACK ? IT : 1][10];
+        if constexpr (MODE == CONV_PACK) {
+#pragma unroll
+            for (int k = 0; k < IT; ++k) pack_load(fd, (size_t)off0[k], raw[k]);
+        }
 #pragma unroll
         for (int k = 0; k < IT; ++k) {
 #pragma unroll
             for (int q = 0; q < RW; ++q) in[k][q] = make_uint4(0, 0, 0, 0);
             if (!((live >> k) & 1u)) continue;
             if constexpr (MODE == CONV_PACK) {
-                float x[10];
-                pack_input(L, fd, (size_t)off0[k], x);
+                float *x = raw[k];
+                pack_transform(L, x);
                 if constexpr (F8) {
                     unsigned q[3];
 #pragma unroll
@@ -604,7 +621,7 @@ template <int PREC, int MODE, int EPI, int TH, int CK, int NB, typename SrcT, ty
 #ifndef WSKP_CONV_MIN_WG
 #define WSKP_CONV_MIN_WG 1
 #endif
-__global__ __launch_bounds__(kThreads, WSKP_CONV_MIN_WG) void conv3x3_kernel(ConvLayer L, FrameArg fa)
+__global__ __launch_bounds__(kThreads, (MODE == CONV_PACK && PREC == 1) ? 4 : WSKP_CONV_MIN_WG) void conv3x3_kernel(ConvLayer L, FrameArg fa)
 {
     using S = Stage<PREC, MODE, CK, TH, NB, SrcT>;
     constexpr int MB = TH / 2;

@@ -32,7 +32,7 @@ static_assert(kDTY % 8 == 0, "8 row groups of kDTY/8 rows");
 // minimum resident workgroups per CU the forward kernel's registers must
 // allow (a build-time tuning knob)
 #ifndef WSKP_DECODE_MIN_WG
-#define WSKP_DECODE_MIN_WG 1
+#define WSKP_DECODE_MIN_WG 4
 #endif
 
 struct DecodeIO {
@@ -232,13 +232,14 @@ __device__ __forceinline__ void halo_pixels(int x0, int y0, int R, int HX, int H
     }
 }
 
-// Loads weight map i at this thread's halo pixels (zero outside the image).
+// Loads weight map i at this thread's halo pixels, unconditionally (pixels
+// outside the image read pixel 0; the caller masks them with gp < 0).
 template <int M, int RM>
 __device__ __forceinline__ void load_w(const DecodeIO &io, int i, const int *gp, float *w)
 {
 #pragma unroll
     for (int k = 0; k < max_pix<RM>(); ++k)
-        w[k] = gp[k] >= 0 ? gload(io.head + (size_t)gp[k] * io.hs_pix + i * io.hs_map) : 0.f;
+        w[k] = gload(io.head + (size_t)(gp[k] >= 0 ? gp[k] : 0) * io.hs_pix + i * io.hs_map);
 }
 
 // Dynamic LDS: product plane float4 [HXY] (W_i, W_i c) rebuilt for each
@@ -274,20 +275,28 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
     // irradiance of this thread's halo pixels, kept in registers; c = r /
     // (a + eps_a) uses the hardware reciprocal.  The weight map of each size
     // is fetched one size ahead.
-    float cv[kMaxPix][3], wv[kMaxPix];
+    // All loads are unconditional (pixels outside the image or the halo read
+    // pixel 0 and are masked afterwards), so that every request is in flight
+    // before the first result is used.
+    float cv[kMaxPix][3], av[FRAMES ? kMaxPix : 1][3], wv[kMaxPix];
 #pragma unroll
     for (int k = 0; k < kMaxPix; ++k) {
-        cv[k][0] = cv[k][1] = cv[k][2] = 0.f;
-        if (gp[k] >= 0) {
-            const size_t q = (size_t)gp[k] * 3;
+        const size_t q = (size_t)(gp[k] >= 0 ? gp[k] : 0) * 3;
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                if (FRAMES) cv[k][ch] = gload(io.r + q + ch) * __builtin_amdgcn_rcpf(gload(io.a + q + ch) + dc.eps_albedo);
-                else cv[k][ch] = gload(io.c + q + ch);
-            }
+        for (int ch = 0; ch < 3; ++ch) {
+            cv[k][ch] = gload((FRAMES ? io.r : io.c) + q + ch);
+            if constexpr (FRAMES) av[k][ch] = gload(io.a + q + ch);
         }
     }
     load_w<M, RM>(io, 0, gp, wv);
+#pragma unroll
+    for (int k = 0; k < kMaxPix; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float c = cv[k][ch];
+            if constexpr (FRAMES) c *= __builtin_amdgcn_rcpf(av[FRAMES ? k : 0][ch] + dc.eps_albedo);
+            cv[k][ch] = gp[k] >= 0 ? c : 0.f;
+        }
 
     // Fusion (Eq. 5) of this thread's kRun centres (column tx, rows
     // kRun*ty + o).  Forward: softmax numerators exp(l_i - max_j l_j) weight
@@ -331,7 +340,8 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
 #pragma unroll
         for (int k = 0; k < kMaxPix; ++k) {
             const int p = tid + k * kThreads;
-            if (p < HXY) pr[p] = make_float4(wv[k], wv[k] * cv[k][0], wv[k] * cv[k][1], wv[k] * cv[k][2]);
+            const float w = gp[k] >= 0 ? wv[k] : 0.f;
+            if (p < HXY) pr[p] = make_float4(w, w * cv[k][0], w * cv[k][1], w * cv[k][2]);
         }
         if (i + 1 < M) load_w<M, RM>(io, i + 1, gp, wv);
         __syncthreads();
@@ -453,13 +463,10 @@ __global__ __launch_bounds__(kThreads) void decode_adj_b_kernel(DecodeCfg dc, De
         const float4 *sp = io.scratch + (size_t)i * P;
         float4 v[kMaxPix];
 #pragma unroll
-        for (int k = 0; k < kMaxPix; ++k)
-            if (gp[k] >= 0) {
-                const gf32x4 q = gload(reinterpret_cast<const gf32x4 *>(sp + gp[k]));
-                v[k] = make_float4(q.x, q.y, q.z, q.w);
-            } else {
-                v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-            }
+        for (int k = 0; k < kMaxPix; ++k) {
+            const gf32x4 q = gload(reinterpret_cast<const gf32x4 *>(sp + (gp[k] >= 0 ? gp[k] : 0)));
+            v[k] = gp[k] >= 0 ? make_float4(q.x, q.y, q.z, q.w) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
 #pragma unroll
         for (int k = 0; k < kMaxPix; ++k) {
             const int p = tid + k * kThreads;
