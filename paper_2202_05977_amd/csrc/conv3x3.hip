@@ -694,21 +694,6 @@ __device__ __forceinline__ void load_lds16(rsrc_t r, unsigned char *lds, unsigne
 
 constexpr unsigned kOutOfRange = 0x7ffffff0u;
 
-// Workgroup barrier without the memory fence of __syncthreads(): the fence
-// would wait for every load in flight, including the direct-to-LDS loads of
-// the next chunk.  The loop makes the data it needs visible explicitly
-// (wait_vmem / wait_lds before the barrier); the empty asm statements keep
-// the compiler from moving memory accesses across it.
-__device__ __forceinline__ void lds_barrier()
-{
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-}
-
-// lgkmcnt(0): this wave's LDS reads have completed.
-__device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt((15) | (3 << 14) | (7 << 4) | (0 << 8)); }
-
 // vmcnt(N) with lgkmcnt(0): waits until at most N vector-memory loads of
 // this wave are outstanding (loads complete in order); N = 0 waits for the
 // direct-to-LDS loads of the stage.

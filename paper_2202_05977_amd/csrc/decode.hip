@@ -58,13 +58,13 @@ struct DecodeTensors {
     float4 *scratch;    // [N,M,H,W] x (u_0, u_1, u_2, dS)
 };
 
+// Tile u of nbk (u in launch order) -> frame, tile origin and I/O pointers.
 template <bool FRAMES>
-__device__ __forceinline__ bool decode_locate(const DecodeCfg &dc, const FrameArg &fa,
-                                              const DecodeTensors &dt, DecodeIO &io, int &x0,
-                                              int &y0)
+__device__ __forceinline__ bool decode_locate_at(const DecodeCfg &dc, const FrameArg &fa,
+                                                 const DecodeTensors &dt, int u, int nbk,
+                                                 DecodeIO &io, int &x0, int &y0)
 {
-    const int nbk = gridDim.x;
-    int t = xcd_logical_id(blockIdx.x, nbk);
+    int t = xcd_logical_id(u, nbk);
     if (FRAMES && fa.reverse) t = nbk - 1 - t;
     const int twoM = 2 * dc.M;
     auto tiles = [](int H, int W) { return ((W + kDTX - 1) / kDTX) * ((H + kDTY - 1) / kDTY); };
@@ -109,6 +109,14 @@ __device__ __forceinline__ bool decode_locate(const DecodeCfg &dc, const FrameAr
     x0 = (t % txn) * kDTX;
     y0 = (t / txn) * kDTY;
     return true;
+}
+
+template <bool FRAMES>
+__device__ __forceinline__ bool decode_locate(const DecodeCfg &dc, const FrameArg &fa,
+                                              const DecodeTensors &dt, DecodeIO &io, int &x0,
+                                              int &y0)
+{
+    return decode_locate_at<FRAMES>(dc, fa, dt, blockIdx.x, gridDim.x, io, x0, y0);
 }
 
 enum DecodeKind { DK_FRAMES = 0, DK_TENSORS = 1, DK_ADJ_A = 2 };
@@ -196,7 +204,7 @@ __device__ __forceinline__ void window_sums4(int R, int HXS, const float4 *st, f
 #pragma unroll
         for (int t = 0; t < kHRun; ++t) hb[hy * kHB + xr + t] = s[t];
     }
-    __syncthreads();
+    lds_sync();
     const int tx = tid & 31, ty = tid >> 5;
     const int vb = (kRun * ty + R - r) * kHB + tx;
     box_run<K, kRun>([&](int j) { return hb[vb + j * kHB]; }, acc);
@@ -344,7 +352,7 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
             if (p < HXY) pr[p] = make_float4(w, w * cv[k][0], w * cv[k][1], w * cv[k][2]);
         }
         if (i + 1 < M) load_w<M, RM>(io, i + 1, gp, wv);
-        __syncthreads();
+        lds_sync();
         float4 acc[kRun];
 #define WSKP_WS(KK) window_sums4<KK>(R, HX, pr, hb, acc)
         WSKP_SWITCH_K(RM, 2 * dc.radius[i] + 1, WSKP_WS)
@@ -426,6 +434,150 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
     }
 }
 
+// Forward decode, persistent and software-pipelined.  Each workgroup walks
+// the tiles u = blockIdx.x, blockIdx.x + gridDim.x, ...  Every input of a
+// tile (irradiance inputs and all M weight maps over the halo, logits and
+// albedo of the centres) is loaded into registers one tile ahead: while tile
+// u is filtered, its successor's requests are in flight, so that memory
+// traffic and the LDS/VALU work of the box sums overlap within a workgroup
+// instead of alternating across the whole device.  The arithmetic is that of
+// decode_fwd_kernel.
+template <int M, int KIND, int RM>
+__global__ __launch_bounds__(kThreads, 2) void decode_stream_kernel(DecodeCfg dc, FrameArg fa,
+                                                                     DecodeTensors dt, int ntiles)
+{
+    constexpr bool FRAMES = KIND == DK_FRAMES;
+    constexpr int kMaxPix = max_pix<RM>();
+    extern __shared__ float4 lds4[];
+    const int R = dc.R;
+    const int HX = halo_stride(R), HXY = HX * (kDTY + 2 * R);
+    float4 *pr = lds4;
+    float4 *hb = pr + HXY;
+    const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+
+    // one tile's inputs, as loaded (pixels outside the image or the halo
+    // read pixel 0; gp < 0 marks them)
+    struct Raw {
+        int gp[kMaxPix];
+        float x[kMaxPix][3];                       // r (frames) or c (tensors)
+        float a[FRAMES ? kMaxPix : 1][3];
+        float w[M][kMaxPix];
+        float lg[kRun][M];                         // centre logits
+        float m[kRun][3];                          // centre remodulation factor (a or mod)
+    };
+    auto fetch = [&](const DecodeIO &io, int x0, int y0, Raw &rw) {
+        halo_pixels<RM>(x0, y0, R, HX, HXY, io.H, io.W, rw.gp);
+#pragma unroll
+        for (int k = 0; k < kMaxPix; ++k) {
+            const size_t q = (size_t)(rw.gp[k] >= 0 ? rw.gp[k] : 0);
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                rw.x[k][ch] = gload((FRAMES ? io.r : io.c) + q * 3 + ch);
+                if constexpr (FRAMES) rw.a[k][ch] = gload(io.a + q * 3 + ch);
+            }
+#pragma unroll
+            for (int i = 0; i < M; ++i) rw.w[i][k] = gload(io.head + q * io.hs_pix + i * io.hs_map);
+        }
+#pragma unroll
+        for (int o = 0; o < kRun; ++o) {
+            const int y = y0 + kRun * ty + o, x = x0 + tx;
+            const bool in = y < io.H && x < io.W;
+            const size_t pix = in ? (size_t)y * io.W + x : 0;
+#pragma unroll
+            for (int i = 0; i < M; ++i) rw.lg[o][i] = gload(io.head + pix * io.hs_pix + (M + i) * io.hs_map);
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                if constexpr (FRAMES) rw.m[o][ch] = gload(io.a + pix * 3 + ch) + dc.eps_albedo;
+                else rw.m[o][ch] = io.mod ? gload(io.mod + pix * 3 + ch) : 1.f;
+            }
+        }
+    };
+
+    int u = blockIdx.x;
+    if (u >= ntiles) return;
+    DecodeIO io;
+    int x0, y0;
+    decode_locate_at<FRAMES>(dc, fa, dt, u, ntiles, io, x0, y0);
+    Raw cur;
+    fetch(io, x0, y0, cur);
+    for (;;) {
+        // this tile's masked irradiance and weights
+        float cv[kMaxPix][3], wv[M][kMaxPix];
+#pragma unroll
+        for (int k = 0; k < kMaxPix; ++k) {
+            const bool live = cur.gp[k] >= 0;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                float c = cur.x[k][ch];
+                if constexpr (FRAMES) c *= __builtin_amdgcn_rcpf(cur.a[k][ch] + dc.eps_albedo);
+                cv[k][ch] = live ? c : 0.f;
+            }
+#pragma unroll
+            for (int i = 0; i < M; ++i) wv[i][k] = live ? cur.w[i][k] : 0.f;
+        }
+        float lmax[kRun], esum[kRun], F[kRun][3], mo[kRun][3], lg[kRun][M];
+#pragma unroll
+        for (int o = 0; o < kRun; ++o) {
+            float m = -INFINITY;
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                lg[o][i] = cur.lg[o][i];
+                m = fmaxf(m, lg[o][i]);
+            }
+            lmax[o] = m;
+            esum[o] = 0.f;
+            F[o][0] = F[o][1] = F[o][2] = 0.f;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) mo[o][ch] = cur.m[o][ch];
+        }
+        const DecodeIO iot = io;
+        const int xt = x0, yt = y0;
+
+        // the next tile's requests go out before this tile is filtered
+        const int un = u + gridDim.x;
+        const bool more = un < ntiles;
+        if (more) {
+            decode_locate_at<FRAMES>(dc, fa, dt, un, ntiles, io, x0, y0);
+            fetch(io, x0, y0, cur);
+        }
+
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+#pragma unroll
+            for (int k = 0; k < kMaxPix; ++k) {
+                const int p = tid + k * kThreads;
+                if (p < HXY)
+                    pr[p] = make_float4(wv[i][k], wv[i][k] * cv[k][0], wv[i][k] * cv[k][1], wv[i][k] * cv[k][2]);
+            }
+            lds_sync();
+            float4 acc[kRun];
+#define WSKP_WS(KK) window_sums4<KK>(R, HX, pr, hb, acc)
+            WSKP_SWITCH_K(RM, 2 * dc.radius[i] + 1, WSKP_WS)
+#undef WSKP_WS
+#pragma unroll
+            for (int o = 0; o < kRun; ++o) {
+                const float inv = __builtin_amdgcn_rcpf(fmaxf(acc[o].x, dc.eps_norm));
+                const float e = expf(lg[o][i] - lmax[o]);
+                esum[o] += e;
+                F[o][0] += e * (acc[o].y * inv);
+                F[o][1] += e * (acc[o].z * inv);
+                F[o][2] += e * (acc[o].w * inv);
+            }
+        }
+#pragma unroll
+        for (int o = 0; o < kRun; ++o) {
+            const int y = yt + kRun * ty + o, x = xt + tx;
+            if (y >= iot.H || x >= iot.W) continue;
+            const size_t pix = (size_t)y * iot.W + x;
+            const float inv = 1.f / esum[o];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) gstore(iot.out + pix * 3 + ch, mo[o][ch] * (F[o][ch] * inv));
+        }
+        if (!more) break;
+        u = un;
+    }
+}
+
 // Second half of the vector-Jacobian product.  Windows are symmetric and
 // truncated the same way at the border (p in Omega(q) <=> q in Omega(p)), so
 // the adjoint of a box sum is the same box sum:
@@ -472,7 +624,7 @@ __global__ __launch_bounds__(kThreads) void decode_adj_b_kernel(DecodeCfg dc, De
             const int p = tid + k * kThreads;
             if (p < HXY) st[p] = v[k];
         }
-        __syncthreads();
+        lds_sync();
         float4 acc[kRun];
 #define WSKP_WS(KK) window_sums4<KK>(R, HX, st, hb, acc)
         WSKP_SWITCH_K(RM, 2 * dc.radius[i] + 1, WSKP_WS)
@@ -560,10 +712,49 @@ int decode_grid(int n, const int *H, const int *W)
     return (int)total;
 }
 
+// The persistent form is used where it measured faster: the tensor form
+// (wskp_decode, several equal frames).  For frames it holds the radiance and
+// albedo of the next tile as well and runs at lower occupancy than the
+// one-tile-per-workgroup kernel, which is then faster (build-time knob).
+#ifndef WSKP_DECODE_STREAM_FRAMES
+#define WSKP_DECODE_STREAM_FRAMES 0
+#endif
+
+// Forward decode over `tiles` tiles with the persistent kernel: at most
+// dc.grid_cap workgroups, each walking its share of the tiles.
+template <int KIND>
+static hipError_t launch_stream(const DecodeCfg &dc, const FrameArg &fa, const DecodeTensors &dt,
+                                int tiles, hipStream_t s)
+{
+    if (tiles <= 0) return hipSuccess;
+    if (KIND == DK_FRAMES && !WSKP_DECODE_STREAM_FRAMES) return launch_decode<KIND>(dc, fa, dt, tiles, s);
+    const size_t lds = decode_lds_bytes(dc);
+    const int grid = tiles < dc.grid_cap ? tiles : dc.grid_cap;
+    const bool r5 = dc.R <= 5;
+    switch (dc.M) {
+#define WSKP_M(m)                                                                                 \
+    case m:                                                                                       \
+        if (r5) {                                                                                 \
+            allow_lds(decode_stream_kernel<m, KIND, 5>, lds);                                     \
+            hipLaunchKernelGGL((decode_stream_kernel<m, KIND, 5>), dim3(grid), dim3(kThreads), lds, \
+                               s, dc, fa, dt, tiles);                                             \
+        } else {                                                                                  \
+            allow_lds(decode_stream_kernel<m, KIND, 7>, lds);                                     \
+            hipLaunchKernelGGL((decode_stream_kernel<m, KIND, 7>), dim3(grid), dim3(kThreads), lds, \
+                               s, dc, fa, dt, tiles);                                             \
+        }                                                                                         \
+        break;
+        WSKP_M(1) WSKP_M(2) WSKP_M(3) WSKP_M(4) WSKP_M(5) WSKP_M(6) WSKP_M(7) WSKP_M(8)
+#undef WSKP_M
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_decode_frames(const DecodeCfg &dc, const FrameArg &fa, int blocks, hipStream_t s)
 {
     DecodeTensors dt{};
-    return launch_decode<DK_FRAMES>(dc, fa, dt, blocks, s);
+    return launch_stream<DK_FRAMES>(dc, fa, dt, blocks, s);
 }
 
 hipError_t launch_decode_tensors(const DecodeCfg &dc, int N, int H, int W, const float *head,
@@ -572,7 +763,7 @@ hipError_t launch_decode_tensors(const DecodeCfg &dc, int N, int H, int W, const
     FrameArg fa{};
     DecodeTensors dt{N, H, W, head, c, mod, out, nullptr, nullptr, nullptr};
     const int blocks = N * ((W + kDTX - 1) / kDTX) * ((H + kDTY - 1) / kDTY);
-    return launch_decode<DK_TENSORS>(dc, fa, dt, blocks, s);
+    return launch_stream<DK_TENSORS>(dc, fa, dt, blocks, s);
 }
 
 size_t decode_backward_scratch_bytes(const DecodeCfg &dc, int N, int H, int W)

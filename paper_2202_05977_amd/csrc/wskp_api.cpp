@@ -377,6 +377,10 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
     }
     h->dc.eps_norm = cfg->eps_norm;
     h->dc.eps_albedo = cfg->eps_albedo;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1)
+        cus = 256;
+    h->dc.grid_cap = 2 * cus;
     *out = h;
     return WSKP_OK;
 }

@@ -41,6 +41,30 @@ __device__ __forceinline__ void gstore(T *p, T v)
 typedef float gf32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int gu32x2 __attribute__((ext_vector_type(2)));
 
+// Workgroup barrier without the memory fence of __syncthreads(): the fence
+// waits for every global load in flight (prefetches included).  Callers make
+// the data they need visible explicitly (wait_lds / a vmcnt wait before the
+// barrier); the empty asm statements keep the compiler from moving memory
+// accesses across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
+// lgkmcnt(0): this wave's LDS reads and writes have completed.
+__device__ __forceinline__ void wait_lds() { __builtin_amdgcn_s_waitcnt((15) | (3 << 14) | (7 << 4) | (0 << 8)); }
+
+// Barrier for LDS producer/consumer phases: this wave's LDS accesses are
+// complete, then every wave of the workgroup has arrived.  Global loads
+// stay in flight.
+__device__ __forceinline__ void lds_sync()
+{
+    wait_lds();
+    lds_barrier();
+}
+
 // A batch of frames for one launch: either one frame passed by value or a
 // device-resident table of n frames.
 struct FrameArg {
@@ -135,6 +159,7 @@ struct DecodeCfg {
     int radius[kMaxKernels];  // (k_i - 1)/2
     float eps_norm;
     float eps_albedo;
+    int grid_cap;             // workgroups of the persistent forward decode (resident capacity)
 };
 
 // ---- launchers (defined in the .hip files) --------------------------------
