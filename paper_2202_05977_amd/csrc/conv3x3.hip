@@ -710,26 +710,22 @@ __device__ __forceinline__ void wait_vmem()
 // vertical taps dy (input row r+dy feeds output row r), so a chunk costs
 // 6 (HW+2) A fragment reads instead of 18 HW: the LDS bytes per MFMA, which
 // bound this loop, fall with HW.
-template <int MODE, int EPI, int TH, int NB, bool DB, typename OutT>
+template <int MODE, int EPI, int TH, int NB, typename OutT>
 __global__ __launch_bounds__(kThreads) void conv3x3_bf16_direct(ConvLayer L, FrameArg fa)
 {
     constexpr int CK = 32, WP = kConvTW + 2, HP = TH + 2, NPIX = HP * WP;
     constexpr int A_SLOTS = NPIX * 4;
-    // with DB every wave issues the same number of loads per chunk (the
-    // instruction counts are padded to whole rounds of the 4 waves)
-    constexpr int A_INS0 = (A_SLOTS + 63) / 64;
-    constexpr int A_PW = (A_INS0 + 3) / 4;                // load instructions per wave
-    constexpr int A_INS = DB ? 4 * A_PW : A_INS0;
+    constexpr int A_INS = (A_SLOTS + 63) / 64;
+    constexpr int A_PW = (A_INS + 3) / 4;                 // load instructions per wave
     constexpr int NK = 9;                                  // one tap (32 channels) per MFMA
     constexpr int BSK = NK * 32 + 8;                       // padded weight row (elements)
     constexpr int B_SLOTS = NB * 16 * BSK / 8;
-    constexpr int B_INS0 = (B_SLOTS + 63) / 64;
-    constexpr int B_PW = (B_INS0 + 3) / 4;
-    constexpr int B_INS = DB ? 4 * B_PW : B_INS0;
+    constexpr int B_INS = (B_SLOTS + 63) / 64;
+    constexpr int B_PW = (B_INS + 3) / 4;
     constexpr int A_BYTES = A_INS * 1024, B_BYTES = B_INS * 1024, STAGE = A_BYTES + B_BYTES;
     constexpr int MB = TH / 2, NC = NB * 16, HW = TH / 4;
     static_assert(TH % 4 == 0, "each wave owns TH/4 whole rows");
-    __shared__ __attribute__((aligned(1024))) unsigned char smem[DB ? 2 * STAGE : STAGE];
+    __shared__ __attribute__((aligned(1024))) unsigned char smem[STAGE];
 
     int f, g, x0, y0, Hl, Wl;
     if (!conv_locate<TH>(L, fa, f, g, x0, y0, Hl, Wl)) return;
@@ -779,7 +775,7 @@ __global__ __launch_bounds__(kThreads) void conv3x3_bf16_direct(ConvLayer L, Fra
 #pragma unroll
         for (int k = 0; k < A_PW; ++k) {
             const int ins = wave + 4 * k;
-            if (!DB && ins >= A_INS) break;
+            if (ins >= A_INS) break;
             if (up) load_lds16(r0, buf + ins * 1024, oa0[k] + da);
             else load_lds16(r1, buf + ins * 1024, oa1[k] + da);
         }
@@ -787,7 +783,7 @@ __global__ __launch_bounds__(kThreads) void conv3x3_bf16_direct(ConvLayer L, Fra
 #pragma unroll
         for (int k = 0; k < B_PW; ++k) {
             const int ins = wave + 4 * k;
-            if (!DB && ins >= B_INS) break;
+            if (ins >= B_INS) break;
             load_lds16(rw, buf + A_BYTES + ins * 1024, wb + (unsigned)((ins * 64 + lane) * 16));
         }
     };
@@ -833,31 +829,13 @@ __global__ __launch_bounds__(kThreads) void conv3x3_bf16_direct(ConvLayer L, Fra
     };
 
     issue(0, smem);
-    if constexpr (DB) {
-        // chunk cc+1 streams into the other stage while chunk cc is computed;
-        // vmcnt(A_PW + B_PW) leaves only the newer chunk's loads in flight
-        for (int cc = 0; cc < nchunks; ++cc) {
-            const unsigned char *cur = smem + (cc & 1) * STAGE;
-            if (cc + 1 < nchunks) {
-                issue(cc + 1, smem + ((cc + 1) & 1) * STAGE);
-                wait_vmem<A_PW + B_PW>();
-            } else {
-                wait_vmem<0>();
-            }
-            lds_barrier();
-            compute(cur);
-            wait_lds();
-            lds_barrier();   // the stage has been read before it is refilled
-        }
-    } else {
-        for (int cc = 0; cc < nchunks; ++cc) {
-            wait_vmem<0>();
-            lds_barrier();
-            compute(smem);
-            wait_lds();
-            lds_barrier();   // the stage has been read before it is refilled
-            if (cc + 1 < nchunks) issue(cc + 1, smem);
-        }
+    for (int cc = 0; cc < nchunks; ++cc) {
+        wait_vmem<0>();
+        lds_barrier();
+        compute(smem);
+        wait_lds();
+        lds_barrier();   // the stage has been read before it is refilled
+        if (cc + 1 < nchunks) issue(cc + 1, smem);
     }
     conv_epilogue<1, EPI, TH, NB, OutT>(L, fd, g, x0, y0, Hl, Wl, acc);
 }
@@ -884,10 +862,6 @@ constexpr int kTH = WSKP_CONV_TH;
 #endif
 constexpr int kTHP = WSKP_PACK_TH;
 constexpr int kTHD = WSKP_DIRECT_TH;
-#ifndef WSKP_DIRECT_DB
-#define WSKP_DIRECT_DB 0
-#endif
-constexpr bool kDirectDB = WSKP_DIRECT_DB != 0;
 
 static bool uses_direct(int prec, int mode, int CK)
 {
@@ -946,10 +920,10 @@ static void launch_one(const ConvLayer &L, const FrameArg &fa, int blocks, hipSt
 {
     if constexpr (WSKP_CONV_DIRECT && PREC == 1 && CK == 32 && (MODE == CONV_CAT || MODE == CONV_PLAIN)) {
         if (L.th == 4)
-            hipLaunchKernelGGL((conv3x3_bf16_direct<MODE, EPI, 4, NB, kDirectDB, OutT>), dim3(blocks),
+            hipLaunchKernelGGL((conv3x3_bf16_direct<MODE, EPI, 4, NB, OutT>), dim3(blocks),
                                dim3(kThreads), 0, s, L, fa);
         else
-            hipLaunchKernelGGL((conv3x3_bf16_direct<MODE, EPI, kTHD, NB, kDirectDB, OutT>), dim3(blocks),
+            hipLaunchKernelGGL((conv3x3_bf16_direct<MODE, EPI, kTHD, NB, OutT>), dim3(blocks),
                                dim3(kThreads), 0, s, L, fa);
         return;
     }
