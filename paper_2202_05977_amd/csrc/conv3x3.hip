@@ -540,6 +540,13 @@ __device__ __forceinline__ void chunk_mfma(const void *As_, const void *Bs_, f32
 // values to the next level, summed in the order (2y,2x), (2y,2x+1),
 // (2y+1,2x), (2y+1,2x+1): the column partner is the neighbouring lane, the
 // row partner is block i+2 of the same lane.
+// Value held by the neighbouring lane (lane ^ 1), through a DPP quad
+// permutation [1, 0, 3, 2] (a VALU move, no LDS round trip).
+__device__ __forceinline__ float lane_xor1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
 template <int PREC, int EPI, int TH, int NB, typename OutT>
 __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDesc &fd, int g, int x0,
                                               int y0, int Hl, int Wl, f32x4 (*acc)[NB])
@@ -599,11 +606,11 @@ __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDes
                         const bool odd_row = (i >> 1) & 1;
                         if (!odd_row) {
 #pragma unroll
-                            for (int k = 0; k < 4; ++k) pe[cb][nb][k] = r[k] + __shfl_xor(r[k], 1, 64);
+                            for (int k = 0; k < 4; ++k) pe[cb][nb][k] = r[k] + lane_xor1(r[k]);
                         } else {
                             float m[4];
 #pragma unroll
-                            for (int k = 0; k < 4; ++k) m[k] = 0.25f * ((pe[cb][nb][k] + r[k]) + __shfl_xor(r[k], 1, 64));
+                            for (int k = 0; k < 4; ++k) m[k] = 0.25f * ((pe[cb][nb][k] + r[k]) + lane_xor1(r[k]));
                             const int Y = y >> 1, X = x >> 1;
                             if ((lj & 1) == 0 && Y < (Hl >> 1) && X < (Wl >> 1) && cin) {
                                 OutT *pd = pdst + ((size_t)Y * (Wl >> 1) + X) * L.Cout + co;
@@ -710,19 +717,26 @@ __device__ __forceinline__ void wait_vmem()
 // vertical taps dy (input row r+dy feeds output row r), so a chunk costs
 // 6 (HW+2) A fragment reads instead of 18 HW: the LDS bytes per MFMA, which
 // bound this loop, fall with HW.
+// Workgroups per CU that the stage's LDS admits at TH = 8 (40, 49 and 59 KiB
+// for 2, 3 and 4 output blocks); the register budget is capped to match.
+constexpr int direct_min_wg(int NB) { return NB <= 2 ? 4 : (NB == 3 ? 3 : 2); }
+
 template <int MODE, int EPI, int TH, int NB, typename OutT>
-__global__ __launch_bounds__(kThreads) void conv3x3_bf16_direct(ConvLayer L, FrameArg fa)
+__global__ __launch_bounds__(kThreads, direct_min_wg(NB)) void conv3x3_bf16_direct(ConvLayer L, FrameArg fa)
 {
     constexpr int CK = 32, WP = kConvTW + 2, HP = TH + 2, NPIX = HP * WP;
     constexpr int A_SLOTS = NPIX * 4;
-    constexpr int A_INS = (A_SLOTS + 63) / 64;
-    constexpr int A_PW = (A_INS + 3) / 4;                 // load instructions per wave
     constexpr int NK = 9;                                  // one tap (32 channels) per MFMA
     constexpr int BSK = NK * 32 + 8;                       // padded weight row (elements)
     constexpr int B_SLOTS = NB * 16 * BSK / 8;
-    constexpr int B_INS = (B_SLOTS + 63) / 64;
-    constexpr int B_PW = (B_INS + 3) / 4;
-    constexpr int A_BYTES = A_INS * 1024, B_BYTES = B_INS * 1024, STAGE = A_BYTES + B_BYTES;
+    // The stage is one array of 16-byte slots, halo first, weights right
+    // after it; load instruction j fills slots [64j, 64j + 64).  The
+    // instruction that straddles the boundary is issued twice, once per
+    // source, each with only its own lanes active.
+    constexpr int SLOTS = A_SLOTS + B_SLOTS;
+    constexpr int INS = (SLOTS + 63) / 64;
+    constexpr int PW = (INS + 3) / 4;                      // load instructions per wave
+    constexpr int A_BYTES = A_SLOTS * 16, STAGE = INS * 1024;
     constexpr int MB = TH / 2, NC = NB * 16, HW = TH / 4;
     static_assert(TH % 4 == 0, "each wave owns TH/4 whole rows");
     __shared__ __attribute__((aligned(1024))) unsigned char smem[STAGE];
@@ -748,9 +762,9 @@ __global__ __launch_bounds__(kThreads) void conv3x3_bf16_direct(ConvLayer L, Fra
     // multiplies (full rate, unlike 32-bit ones).
     const unsigned cp0 = (unsigned)L.C0 * 2u, rp0 = (unsigned)W0 * cp0;
     const unsigned cp1 = (unsigned)L.C1 * 2u, rp1 = (unsigned)Wl * cp1;
-    unsigned oa0[A_PW], oa1[A_PW];
+    unsigned oa0[PW], oa1[PW];
 #pragma unroll
-    for (int k = 0; k < A_PW; ++k) {
+    for (int k = 0; k < PW; ++k) {
         const int ins = wave + 4 * k;
         const int slot = ins * 64 + lane;
         const int p = slot >> 2, gch = (slot & 3) ^ ((p >> 1) & 3);
@@ -772,19 +786,19 @@ __global__ __launch_bounds__(kThreads) void conv3x3_bf16_direct(ConvLayer L, Fra
         const int c0 = cc * CK;
         const bool up = MODE != CONV_CAT || c0 < L.C0;
         const unsigned da = (unsigned)((up ? c0 : c0 - L.C0) * 2);
-#pragma unroll
-        for (int k = 0; k < A_PW; ++k) {
-            const int ins = wave + 4 * k;
-            if (ins >= A_INS) break;
-            if (up) load_lds16(r0, buf + ins * 1024, oa0[k] + da);
-            else load_lds16(r1, buf + ins * 1024, oa1[k] + da);
-        }
         const unsigned wb = (unsigned)((cc * L.Cout_pad + g * NC) * BSK * 2);
 #pragma unroll
-        for (int k = 0; k < B_PW; ++k) {
+        for (int k = 0; k < PW; ++k) {
             const int ins = wave + 4 * k;
-            if (ins >= B_INS) break;
-            load_lds16(rw, buf + A_BYTES + ins * 1024, wb + (unsigned)((ins * 64 + lane) * 16));
+            if (ins >= INS) break;
+            const int slot = ins * 64 + lane;
+            unsigned char *dst = buf + ins * 1024;
+            if (ins * 64 < A_SLOTS && slot < A_SLOTS) {
+                if (up) load_lds16(r0, dst, oa0[k] + da);
+                else load_lds16(r1, dst, oa1[k] + da);
+            }
+            if (ins * 64 + 64 > A_SLOTS && slot >= A_SLOTS && slot < SLOTS)
+                load_lds16(rw, dst, wb + (unsigned)((slot - A_SLOTS) * 16));
         }
     };
 
