@@ -8,7 +8,9 @@ fusion + remodulation.  A step is one whole frame through wskp_denoise
 (input pack, encoder, decoder, head, decode), inputs resident in HBM.
 
 Prints ONE JSON line on stdout.  `value` is frames/s of the BF16-conv path
-(the FP32 path is reported beside it), `roofline` is for the kernel that
+with consecutive frames in flight on --streams HIP streams (frames/s on one
+stream, latency of single frames and the FP32 path are reported beside it),
+`roofline` is for the kernel that
 takes the most time per frame, `decode_roofline` for the decode kernel,
 `cpu_baseline` is the FP64 CPU oracle on the same frame.
 """
@@ -53,7 +55,7 @@ def decode_bytes(cfg, H, W):
     return float(H * W * (2 * cfg.M * 4 + 12 + 12 + 12))
 
 
-def time_precision(cfg, blob, dev, H, W, prec, steps, warmup, lat_frames):
+def time_precision(cfg, blob, dev, H, W, prec, steps, warmup, lat_frames, nstreams=3):
     import torch
     from paper_2202_05977_amd import synth, wskp
     scales = None
@@ -67,13 +69,35 @@ def time_precision(cfg, blob, dev, H, W, prec, steps, warmup, lat_frames):
     for _ in range(warmup):
         dn(dev, out)
     torch.cuda.synchronize()
-    # throughput: frames queued back to back on one stream
+    # throughput, one stream: frames queued back to back
     t0 = time.perf_counter()
     for _ in range(steps):
         dn(dev, out)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_per_step = (t1 - t0) * 1e3 / steps
+    ms_single = (time.perf_counter() - t0) * 1e3 / steps
+    # throughput, several streams (the headline): consecutive frames go to
+    # the streams in turn, each stream with its own workspace and output, so
+    # that one frame's kernels fill the CUs another frame's ramp-down and
+    # ramp-up leave idle
+    extra = [wskp.Denoiser(cfg, blob, prec, act_scales=scales) for _ in range(nstreams - 1)]
+    lanes = [(dn, out)] + [(d, torch.empty_like(out)) for d in extra]
+    streams = [torch.cuda.Stream() for _ in range(nstreams)]
+    for s_ in streams:
+        s_.wait_stream(stream)
+
+    def pipelined(n):
+        for k in range(n):
+            d_, o_ = lanes[k % nstreams]
+            d_(dev, o_, stream=streams[k % nstreams])
+
+    pipelined(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pipelined(steps)
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / steps
+    for d in extra:
+        d.close()
     # latency: one frame at a time, HIP events on the launch stream
     lat = []
     for _ in range(lat_frames):
@@ -117,6 +141,9 @@ def time_precision(cfg, blob, dev, H, W, prec, steps, warmup, lat_frames):
     return {
         "ms_per_step": ms_per_step,
         "fps": 1e3 / ms_per_step,
+        "streams": nstreams,
+        "single_stream_ms_per_step": ms_single,
+        "single_stream_fps": 1e3 / ms_single,
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "graph_fps": 1e3 / ms_graph,
@@ -145,7 +172,8 @@ def mode_sweep(args):
     yref = oracle.denoise(fr, blob, cfg)
     out = {}
     for p in args.precisions.split(","):
-        r = time_precision(cfg, blob, dev, H, W, p, args.steps, args.warmup, min(args.steps, 100))
+        r = time_precision(cfg, blob, dev, H, W, p, args.steps, args.warmup, min(args.steps, 100),
+                           args.streams)
         out[p] = {"frames_per_s": r["fps"], "graph_frames_per_s": r["graph_fps"],
                   "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
                   "per_kernel_us": r["per_kernel_us"], **rel_errors(r["y"], yref)}
@@ -244,17 +272,17 @@ def mode_serve(args):
     budget = 64 << 30
     res = {}
     dn = wskp.Denoiser(cfg, blob, "bf16")
-    ex = serve.GpuExecutor(dn, inputs, budget)
+    ex = serve.GpuExecutor(dn, inputs, budget, slots=args.inflight)
     # warm up every resolution once
     for (H, W) in proto:
         tok = ex.launch([serve.Request(-1, sizes.index((H, W)), 0.0, H, W)], 0, 0)
         ex.wait(tok)
-    st = serve.Server(ex, budget, max_inflight=2, max_batch=args.max_batch).run(
+    st = serve.Server(ex, budget, max_inflight=args.inflight, max_batch=args.max_batch).run(
         [dataclasses_replace(r) for r in reqs])
     res["bf16_continuous_batching"] = st.__dict__
     log(f"[serve] bf16 batching: {st}")
     # capacity: the whole trace queued at once, frames per wall-clock second
-    st = serve.Server(ex, budget, max_inflight=2, max_batch=args.max_batch).run(
+    st = serve.Server(ex, budget, max_inflight=args.inflight, max_batch=args.max_batch).run(
         [dataclasses_replace(r) for r in reqs], realtime=False)
     res["bf16_batching_capacity_fps"] = st.frames / st.wall_s
     log(f"[serve] bf16 batching capacity: {st.frames / st.wall_s:.1f} frames/s "
@@ -273,7 +301,8 @@ def mode_serve(args):
     mean_px = float(np.mean([H * W for (H, W) in sizes]))
     print(json.dumps({"mode": "serve", "workload": "64 streams, Poisson 2000 frames/s, "
                       f"{args.serve_frames} frames/stream, resolutions 360p..1440p, 64 GB budget",
-                      "mean_megapixels": mean_px / 1e6, "results": res}), flush=True)
+                      "mean_megapixels": mean_px / 1e6, "batches_in_flight": args.inflight,
+                      "max_batch": args.max_batch, "results": res}), flush=True)
     dn.close()
 
 
@@ -334,6 +363,10 @@ def main():
     ap.add_argument("--fifo-frames", type=int, default=2000)
     ap.add_argument("--max-batch", type=int, default=64,
                     help="serve: most frames one batch may hold")
+    ap.add_argument("--streams", type=int, default=3,
+                    help="headline throughput: frames in flight on this many HIP streams")
+    ap.add_argument("--inflight", type=int, default=3,
+                    help="serve: batches in flight at once, one HIP stream each")
     ap.add_argument("--height", type=int, default=720)
     ap.add_argument("--width", type=int, default=1280)
     args = ap.parse_args()
@@ -370,10 +403,11 @@ def main():
     for p in precs:
         log(f"[bench] timing {p} at {W}x{H}: warmup {args.warmup}, steps {args.steps}")
         res[p] = time_precision(cfg, blob, dev, H, W, p, args.steps, args.warmup,
-                                min(args.steps, 300))
+                                min(args.steps, 300), args.streams)
         log(f"[bench] {p}: {res[p]['fps']:.1f} frames/s, {res[p]['ms_per_step']:.3f} ms/frame, "
             f"p50 {res[p]['p50_ms']:.3f} p99 {res[p]['p99_ms']:.3f} ms, "
-            f"graph replay {res[p]['graph_fps']:.1f} frames/s")
+            f"one stream {res[p]['single_stream_fps']:.1f} frames/s, "
+            f"graph replay (one stream) {res[p]['graph_fps']:.1f} frames/s")
         log(f"[bench] {p} per kernel (us): " +
             ", ".join(f"{k} {v:.1f}" for k, v in res[p]["per_kernel_us"].items()))
 
@@ -437,7 +471,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{W}x{H} frame, 4-level U-Net 32/64/96/128, "
                                f"M=5 kernels k=3..11, convs {head}, decode fp32",
-                   "height": H, "width": W, "conv_precision": head},
+                   "height": H, "width": W, "conv_precision": head,
+                   "streams": args.streams},
+        "single_stream": {"frames_per_s": res[head]["single_stream_fps"],
+                          "ms_per_step": res[head]["single_stream_ms_per_step"]},
         "latency_ms": {"p50": res[head]["p50_ms"], "p99": res[head]["p99_ms"]},
         "per_kernel_us": res[head]["per_kernel_us"],
         "roofline": roof,
@@ -446,6 +483,7 @@ def main():
         "error_vs_fp64_oracle": errors,
         "precisions": {p: {"frames_per_s": res[p]["fps"], "ms_per_step": res[p]["ms_per_step"],
                            "graph_frames_per_s": res[p]["graph_fps"],
+                           "single_stream_frames_per_s": res[p]["single_stream_fps"],
                            "p50_ms": res[p]["p50_ms"], "p99_ms": res[p]["p99_ms"],
                            "per_kernel_us": res[p]["per_kernel_us"]} for p in precs},
         "cpu_baseline": cpu,

@@ -248,20 +248,22 @@ class GpuExecutor(Executor):
     """Runs batches through libwskp on ``slots`` HIP streams.
 
     Every stream of the trace owns resident device buffers: its input frame
-    and an output ring of ``ring`` frames (consecutive frames of a stream
-    that are in flight together write different slots).  One workspace of
+    and an output ring of ``ring`` frames (default slots + 1, so that
+    consecutive frames of a stream in flight together, one per batch, write
+    different slots).  One workspace of
     ``ws_bytes`` (the admission budget) is shared by the in-flight batches;
     the server hands each batch a disjoint range of it.
     """
 
     def __init__(self, denoiser, stream_inputs: Dict[int, Dict[str, "object"]], ws_bytes: int,
-                 slots: int = 2, ring: int = 2):
+                 slots: int = 2, ring: Optional[int] = None):
         import torch
         from . import wskp
         self.torch = torch
         self.wskp = wskp
         self.dn = denoiser
         self.inputs = stream_inputs
+        ring = slots + 1 if ring is None else ring
         self.outputs = {s: [torch.empty_like(f["radiance"]) for _ in range(ring)]
                         for s, f in stream_inputs.items()}
         self.count = {s: 0 for s in stream_inputs}
