@@ -343,6 +343,13 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
 
     // one kernel size: product plane, window sums, normalisation, fusion
     auto size_step = [&](int i) {
+        // this size's logits of the thread's centres, requested first so
+        // that the window sums hide their latency
+        float lgv[ADJ ? 1 : kRun];
+        if constexpr (!ADJ) {
+#pragma unroll
+            for (int o = 0; o < kRun; ++o) lgv[o] = gload(lp[o] + i * io.hs_map);
+        }
         // product plane of this size from this thread's registers, then
         // fetch the next size's weights
 #pragma unroll
@@ -367,7 +374,7 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
                 outv[o][i][2] = o2;
                 Sv[o][i] = acc[o].x;
             } else {
-                const float e = expf(gload(lp[o] + i * io.hs_map) - lmax[o]);
+                const float e = expf(lgv[o] - lmax[o]);
                 esum[o] += e;
                 F[o][0] += e * o0;
                 F[o][1] += e * o1;
