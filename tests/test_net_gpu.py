@@ -105,6 +105,36 @@ def test_small_bf16_ragged():
     assert rel_l2(out, y) <= TOL_BF16
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_graph_replay_matches_eager(prec):
+    """One frame's launches captured once in a HIP graph: every replay, with
+    eager work (other frames through the same workspace, fills) and
+    synchronisations between the replays, equals the eager result bitwise."""
+    cfg = synth.HD
+    dn = _denoiser(cfg, prec)
+    H, W = 96, 160
+    f = to_dev(synth.make_frame(3, H, W))
+    eager = dn(f).clone()
+    out = torch.full_like(eager, float("nan"))
+    dn.workspace([H], [W])                      # no allocation inside the capture
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        dn(f, out, stream=s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        dn(f, out, stream=s)
+    other = to_dev(synth.make_frame(4, H, W))
+    for k in range(4):
+        out.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), f"replay {k}"
+        dn(other)
+        torch.cuda.synchronize()
+
+
 def test_batch_mixed_sizes_equals_single_frames():
     """Each frame alone == in a mixed-resolution batch == with tiles walked in
     reverse (bitwise)."""
