@@ -281,6 +281,17 @@ def mode_serve(args):
         [dataclasses_replace(r) for r in reqs])
     res["bf16_continuous_batching"] = st.__dict__
     log(f"[serve] bf16 batching: {st}")
+    # the same server, every batch a graph replay (one graph per stream and
+    # capacity bucket, captured on first use).  The first pass over the trace
+    # captures the buckets it meets (each capture stalls the loop); the
+    # second pass is the steady state of a long-running server
+    exg = serve.GpuExecutor(dn, inputs, budget, slots=args.inflight, graph=True)
+    for k in range(2):
+        st = serve.Server(exg, budget, max_inflight=args.inflight, max_batch=args.max_batch).run(
+            [dataclasses_replace(r) for r in reqs])
+        res["bf16_continuous_batching_graph" + ("_first_pass" if k == 0 else "")] = st.__dict__
+        log(f"[serve] bf16 batching, graph replay, pass {k + 1}: {st}")
+    del exg
     # capacity: the whole trace queued at once, frames per wall-clock second
     st = serve.Server(ex, budget, max_inflight=args.inflight, max_batch=args.max_batch).run(
         [dataclasses_replace(r) for r in reqs], realtime=False)

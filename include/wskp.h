@@ -151,12 +151,24 @@ wskp_status_t wskp_denoise(wskp_handle_t h, void *stream, int H, int W, const fl
                            float *out, void *ws, size_t ws_bytes);
 
 #define WSKP_BATCH_REVERSE_TILES 1u /* walk tiles in reverse order (result must not change) */
+#define WSKP_BATCH_GRAPH 2u         /* replay one HIP graph per stream and capacity bucket */
 
 /* Denoises n independent frames of possibly different sizes with one
  * launch per network layer.  `frames` is a HOST array of n descriptors
  * (read during the call only).  Each frame's result is the same as that of
  * wskp_denoise on it alone: no arithmetic crosses frames.  Workspace from
- * wskp_workspace_size(h, n, H, W). */
+ * wskp_workspace_size(h, n, H, W).
+ * WSKP_BATCH_GRAPH: the launches run as one HIP graph per (stream, flags,
+ * capacity bucket).  A bucket is the batch's workgroup count of every
+ * launch rounded up to a power of two; the first batch of a bucket captures
+ * the graph (and allocates its device frame table, header plus 1024
+ * descriptors, owned by the handle until wskp_destroy); every batch then
+ * uploads its frame count and descriptors to that table on `stream` and
+ * replays the graph, whose workgroups beyond the batch's tiles exit at once.
+ * Results are identical to the direct launches.  Up to 256 graphs per
+ * handle; beyond that, batches of new buckets are launched directly.  Calls
+ * on the same stream are ordered; the caller must not capture this call
+ * into a graph of its own. */
 wskp_status_t wskp_denoise_batch(wskp_handle_t h, void *stream, int n, const wskp_frame_t *frames,
                                  uint32_t flags, void *ws, size_t ws_bytes);
 

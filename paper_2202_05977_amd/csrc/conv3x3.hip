@@ -15,16 +15,20 @@
 //               (normal+1)/2 and clamped scaled depth, from the raw buffers
 //   CONV_POOL   2x2 mean of the finer level (encoder down path)
 //   CONV_CAT    [nearest x2 upsample of the coarser level, skip] (decoder)
-//   CONV_PLAIN  the map itself (head)
+//   CONV_PLAIN  the map itself (the head; in the bf16 plan also the encoders
+//               >= 1, whose input is the 2x2-mean copy the previous encoder's
+//               epilogue wrote)
 // The epilogue adds the bias and applies ReLU, or for the head the weight
 // activation (softplus or exp) on channels 0..M-1 and nothing on the logits.
 //
-// Two arithmetic forms:
+// Three arithmetic forms:
 //   fp32: v_mfma_f32_16x16x4f32; LDS holds channel planes so that the 16
 //         pixels x 4 channels of an A fragment are bank-conflict free.
 //   bf16: v_mfma_f32_16x16x32_bf16; LDS holds pixels with 8-channel runs so
 //         that each lane reads its A fragment with one 16-byte load.
-//   Both accumulate in fp32.
+//   fp8:  v_mfma_f32_16x16x128_f8f6f4 on e4m3 operands (bf16 activations in
+//         memory, quantised with the layer's input scale while staging).
+//   All accumulate in fp32.
 #include "wskp_internal.h"
 
 #include <type_traits>
@@ -80,13 +84,14 @@ template <int TH>
 __device__ __forceinline__ bool conv_locate(const ConvLayer &L, const FrameArg &fa, int &f, int &g,
                                             int &x0, int &y0, int &Hl, int &Wl)
 {
-    const int nbk = gridDim.x;
-    int t = xcd_logical_id(blockIdx.x, nbk);
-    if (fa.reverse) t = nbk - 1 - t;
     const int lev = L.level, groups = L.groups;
-    f = batch_frame(fa, t, [=](int H, int W) {
+    auto tiles = [=](int H, int W) {
         return (((W >> lev) + kConvTW - 1) / kConvTW) * (((H >> lev) + TH - 1) / TH) * groups;
-    });
+    };
+    int n;
+    int t = batch_tile_id(fa, blockIdx.x, gridDim.x, n, tiles);
+    if (t < 0) return false;
+    f = batch_frame(fa, n, t, tiles);
     if (f < 0) return false;
     const FrameDesc &fd = frame_at(fa, f);
     Hl = fd.H >> lev;

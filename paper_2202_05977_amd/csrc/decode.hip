@@ -64,12 +64,14 @@ __device__ __forceinline__ bool decode_locate_at(const DecodeCfg &dc, const Fram
                                                  const DecodeTensors &dt, int u, int nbk,
                                                  DecodeIO &io, int &x0, int &y0)
 {
-    int t = xcd_logical_id(u, nbk);
-    if (FRAMES && fa.reverse) t = nbk - 1 - t;
     const int twoM = 2 * dc.M;
     auto tiles = [](int H, int W) { return ((W + kDTX - 1) / kDTX) * ((H + kDTY - 1) / kDTY); };
+    int t = xcd_logical_id(u, nbk);
     if constexpr (FRAMES) {
-        const int f = batch_frame(fa, t, tiles);
+        int n;
+        t = batch_tile_id(fa, u, nbk, n, tiles);
+        if (t < 0) return false;
+        const int f = batch_frame(fa, n, t, tiles);
         if (f < 0) return false;
         const FrameDesc &fd = frame_at(fa, f);
         io.H = fd.H;
@@ -734,7 +736,10 @@ static hipError_t launch_stream(const DecodeCfg &dc, const FrameArg &fa, const D
                                 int tiles, hipStream_t s)
 {
     if (tiles <= 0) return hipSuccess;
-    if (KIND == DK_FRAMES && !WSKP_DECODE_STREAM_FRAMES) return launch_decode<KIND>(dc, fa, dt, tiles, s);
+    // capacity launches (frame count in device memory) use the one-tile-per-
+    // workgroup kernel, whose workgroups beyond the batch exit
+    if (KIND == DK_FRAMES && (!WSKP_DECODE_STREAM_FRAMES || fa.dev_n))
+        return launch_decode<KIND>(dc, fa, dt, tiles, s);
     const size_t lds = decode_lds_bytes(dc);
     const int grid = tiles < dc.grid_cap ? tiles : dc.grid_cap;
     const bool r5 = dc.R <= 5;

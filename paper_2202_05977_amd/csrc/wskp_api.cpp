@@ -106,11 +106,23 @@ struct wskp_ctx {
     std::vector<LayerPlan> layers;
     void *dweights = nullptr;
     DecodeCfg dc{};
-    // pinned host staging for batch frame tables
+    // pinned host staging for batch frame tables: per slot a header (the
+    // frame count) and up to kMaxBatch descriptors
     std::mutex mu;
-    FrameDesc *ring = nullptr;
+    char *ring = nullptr;
     std::vector<hipEvent_t> ring_ev;
     int ring_next = 0;
+    // graph replay of batches (WSKP_BATCH_GRAPH): one executable graph per
+    // (stream, capacity bucket), each reading its own device frame table
+    struct BatchGraph {
+        hipStream_t s;
+        bool reverse;
+        std::vector<int> caps;   // workgroups of each launch
+        hipGraphExec_t exec;
+        char *tab;               // device: header + descriptors
+    };
+    std::vector<BatchGraph> graphs;
+    hipStream_t cap_stream = nullptr;
     // launch timing (diagnostics): events recorded around every launch
     std::vector<hipEvent_t> tev;
     int t_max_calls = 0, t_calls = 0;
@@ -118,6 +130,9 @@ struct wskp_ctx {
 
 static constexpr int kRingSlots = 8;
 static constexpr int kMaxBatch = 1024;
+static constexpr size_t kTableHeader = 256;   // frame count, padded
+static constexpr size_t kSlotBytes = kTableHeader + sizeof(FrameDesc) * kMaxBatch;
+static constexpr size_t kMaxGraphs = 256;
 
 // ---------------------------------------------------------------------------
 static wskp_status_t check_config(const wskp_config_t *c)
@@ -392,6 +407,11 @@ extern "C" wskp_status_t wskp_destroy(wskp_handle_t h)
     (void)hipDeviceSynchronize();
     for (auto ev : h->ring_ev) (void)hipEventDestroy(ev);
     for (auto ev : h->tev) (void)hipEventDestroy(ev);
+    for (auto &g : h->graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipFree(g.tab);
+    }
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->ring) (void)hipHostFree(h->ring);
     if (h->dweights) (void)hipFree(h->dweights);
     delete h;
@@ -627,6 +647,56 @@ extern "C" wskp_status_t wskp_denoise(wskp_handle_t h, void *stream, int H, int 
     return run_frames(h, fa, 1, &H, &W, static_cast<hipStream_t>(stream));
 }
 
+static int next_pow2(int v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// Captures the network and the decode for capacity c.caps into an
+// executable graph whose launches read the frame count and the descriptors
+// from the device buffer c.tab (header, then descriptors), on the handle's
+// own capture stream.
+static wskp_status_t capture_batch_graph(wskp_ctx *h, wskp_ctx::BatchGraph &c)
+{
+    hipError_t e;
+    if (!h->cap_stream && (e = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "hipStreamCreate");
+    if ((e = hipMalloc(reinterpret_cast<void **>(&c.tab), kSlotBytes)) != hipSuccess)
+        return hip_fail(e, "hipMalloc(graph frame table)", WSKP_E_OOM);
+    FrameArg fa{};
+    fa.table = reinterpret_cast<const FrameDesc *>(c.tab + kTableHeader);
+    fa.n = 0;
+    fa.reverse = c.reverse ? 1 : 0;
+    fa.dev_n = reinterpret_cast<const int *>(c.tab);
+    hipStream_t cs = h->cap_stream;
+    if ((e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed)) != hipSuccess) {
+        (void)hipFree(c.tab);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    hipError_t le = hipSuccess;
+    for (size_t i = 0; i < h->layers.size() && le == hipSuccess; ++i) {
+        const LayerPlan &lp = h->layers[i];
+        le = launch_conv(lp.L, lp.mode, lp.epi, h->prec, fa, c.caps[i], cs);
+    }
+    if (le == hipSuccess) le = launch_decode_frames(h->dc, fa, c.caps.back(), cs);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipFree(c.tab);
+        return hip_fail(le != hipSuccess ? le : e, "graph capture", WSKP_E_LAUNCH);
+    }
+    e = hipGraphInstantiate(&c.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        (void)hipFree(c.tab);
+        return hip_fail(e, "hipGraphInstantiate", WSKP_E_LAUNCH);
+    }
+    return WSKP_OK;
+}
+
 extern "C" wskp_status_t wskp_denoise_batch(wskp_handle_t h, void *stream, int n,
                                             const wskp_frame_t *frames, uint32_t flags, void *ws,
                                             size_t ws_bytes)
@@ -654,9 +724,8 @@ extern "C" wskp_status_t wskp_denoise_batch(wskp_handle_t h, void *stream, int n
     std::lock_guard<std::mutex> lock(h->mu);
     hipError_t e;
     if (!h->ring) {
-        if ((e = hipHostMalloc(reinterpret_cast<void **>(&h->ring),
-                               sizeof(FrameDesc) * kMaxBatch * kRingSlots, hipHostMallocDefault)) !=
-            hipSuccess)
+        if ((e = hipHostMalloc(reinterpret_cast<void **>(&h->ring), kSlotBytes * kRingSlots,
+                               hipHostMallocDefault)) != hipSuccess)
             return hip_fail(e, "hipHostMalloc(frame table ring)", WSKP_E_OOM);
         h->ring_ev.resize(kRingSlots);
         for (auto &ev : h->ring_ev)
@@ -664,15 +733,43 @@ extern "C" wskp_status_t wskp_denoise_batch(wskp_handle_t h, void *stream, int n
                 return hip_fail(e, "hipEventCreate");
         for (auto &ev : h->ring_ev) (void)hipEventRecord(ev, s);
     }
+    const bool reverse = (flags & WSKP_BATCH_REVERSE_TILES) != 0;
+    // graph replay: the executable graph of this stream and capacity bucket
+    // (launch grids rounded up to powers of two), captured on first use
+    wskp_ctx::BatchGraph *g = nullptr;
+    if (flags & WSKP_BATCH_GRAPH) {
+        std::vector<int> caps;
+        for (const LayerPlan &lp : h->layers) caps.push_back(next_pow2(conv_grid(lp.L, n, Hs.data(), Ws.data())));
+        caps.push_back(next_pow2(decode_grid(n, Hs.data(), Ws.data())));
+        for (auto &c : h->graphs)
+            if (c.s == s && c.reverse == reverse && c.caps == caps) g = &c;
+        if (!g && h->graphs.size() < kMaxGraphs) {
+            wskp_ctx::BatchGraph c{s, reverse, caps, nullptr, nullptr};
+            if ((st = capture_batch_graph(h, c)) != WSKP_OK) return st;
+            h->graphs.push_back(c);
+            g = &h->graphs.back();
+        }
+        // (a full cache falls back to direct launches)
+    }
     const int slot = h->ring_next;
     h->ring_next = (h->ring_next + 1) % kRingSlots;
     // the slot's previous copy must have left host memory before it is rewritten
     if ((e = hipEventSynchronize(h->ring_ev[slot])) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-    FrameDesc *tab = h->ring + (size_t)slot * kMaxBatch;
+    char *sbase = h->ring + kSlotBytes * slot;
+    FrameDesc *tab = reinterpret_cast<FrameDesc *>(sbase + kTableHeader);
+    *reinterpret_cast<int *>(sbase) = n;
     char *base = static_cast<char *>(ws) + table_bytes(n);
     for (int i = 0; i < n; ++i) {
         fill_frame(h, tab[i], base, frames[i]);
         base += frame_bytes(h, Hs[i], Ws[i], nullptr, nullptr, nullptr);
+    }
+    if (g) {
+        if ((e = hipMemcpyAsync(g->tab, sbase, kTableHeader + sizeof(FrameDesc) * n, hipMemcpyHostToDevice,
+                                s)) != hipSuccess)
+            return hip_fail(e, "hipMemcpyAsync(frame table)");
+        if ((e = hipEventRecord(h->ring_ev[slot], s)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+        if ((e = hipGraphLaunch(g->exec, s)) != hipSuccess) return hip_fail(e, "hipGraphLaunch", WSKP_E_LAUNCH);
+        return WSKP_OK;
     }
     if ((e = hipMemcpyAsync(ws, tab, sizeof(FrameDesc) * n, hipMemcpyHostToDevice, s)) != hipSuccess)
         return hip_fail(e, "hipMemcpyAsync(frame table)");
@@ -680,7 +777,8 @@ extern "C" wskp_status_t wskp_denoise_batch(wskp_handle_t h, void *stream, int n
     FrameArg fa{};
     fa.table = static_cast<const FrameDesc *>(ws);
     fa.n = n;
-    fa.reverse = (flags & WSKP_BATCH_REVERSE_TILES) ? 1 : 0;
+    fa.reverse = reverse ? 1 : 0;
+    fa.dev_n = nullptr;
     return run_frames(h, fa, n, Hs.data(), Ws.data(), s);
 }
 

@@ -71,45 +71,16 @@ struct FrameArg {
     const FrameDesc *table;  // device pointer, or nullptr to use `one`
     int n;
     int reverse;             // walk tiles in reverse order
+    // capacity launch (graph replay): when non-null, the frame count is read
+    // from this device word and the grid is an upper bound on the batch's
+    // tiles; workgroups beyond them exit
+    const int *dev_n;
     FrameDesc one;
 };
 
 __device__ __forceinline__ const FrameDesc &frame_at(const FrameArg &fa, int f)
 {
     return fa.table ? fa.table[f] : fa.one;
-}
-
-// Finds the frame of a batch that holds logical tile t, given the tile
-// count of a frame of size H x W, and rewrites t as the tile index inside
-// that frame.  Each lane reads one frame's size, a wave-wide inclusive scan
-// turns the counts into cumulative ends, and a ballot counts the frames
-// that end at or before t: one round of loads per 64 frames instead of one
-// dependent load per frame.  Returns -1 past the batch's last tile.  Every
-// lane of the wave calls it with the same t; the results are wave-uniform.
-template <typename Count>
-__device__ __forceinline__ int batch_frame(const FrameArg &fa, int &t, Count count)
-{
-    if (!fa.table) return t < count(fa.one.H, fa.one.W) ? 0 : -1;
-    const int lane = threadIdx.x & 63;
-    int base = 0;
-    for (int f0 = 0; f0 < fa.n; f0 += 64) {
-        const int f = f0 + lane;
-        int c = f < fa.n ? count(gload(&fa.table[f].H), gload(&fa.table[f].W)) : 0;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int v = __shfl_up(c, d, 64);
-            if (lane >= d) c += v;
-        }
-        const int end = base + c;
-        const int k = __popcll(__ballot(f < fa.n && end <= t));
-        const int valid = fa.n - f0 < 64 ? fa.n - f0 : 64;
-        if (k < valid) {
-            t = __builtin_amdgcn_readfirstlane(t - (k > 0 ? __shfl(end, k - 1, 64) : base));
-            return __builtin_amdgcn_readfirstlane(f0 + k);
-        }
-        base = __shfl(end, 63, 64);
-    }
-    return -1;
 }
 
 // Spread consecutive logical tile ids over one XCD.  The hardware deals
@@ -123,6 +94,76 @@ __device__ __forceinline__ int xcd_logical_id(int b, int nb)
     const int q = nb >> 3, rmd = nb & 7;
     return x * q + (x < rmd ? x : rmd) + i;
 }
+
+// Finds the frame of a batch that holds logical tile t, given the tile
+// count of a frame of size H x W, and rewrites t as the tile index inside
+// that frame.  Each lane reads one frame's size, a wave-wide inclusive scan
+// turns the counts into cumulative ends, and a ballot counts the frames
+// that end at or before t: one round of loads per 64 frames instead of one
+// dependent load per frame.  Returns -1 past the batch's last tile.  Every
+// lane of the wave calls it with the same t; the results are wave-uniform.
+template <typename Count>
+__device__ __forceinline__ int batch_frame(const FrameArg &fa, int n, int &t, Count count)
+{
+    if (!fa.table) return t < count(fa.one.H, fa.one.W) ? 0 : -1;
+    const int lane = threadIdx.x & 63;
+    int base = 0;
+    for (int f0 = 0; f0 < n; f0 += 64) {
+        const int f = f0 + lane;
+        int c = f < n ? count(gload(&fa.table[f].H), gload(&fa.table[f].W)) : 0;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(c, d, 64);
+            if (lane >= d) c += v;
+        }
+        const int end = base + c;
+        const int k = __popcll(__ballot(f < n && end <= t));
+        const int valid = n - f0 < 64 ? n - f0 : 64;
+        if (k < valid) {
+            t = __builtin_amdgcn_readfirstlane(t - (k > 0 ? __shfl(end, k - 1, 64) : base));
+            return __builtin_amdgcn_readfirstlane(f0 + k);
+        }
+        base = __shfl(end, 63, 64);
+    }
+    return -1;
+}
+
+// Total tiles of a batch (capacity launches): a wave-wide sum of the
+// frames' tile counts, one round of loads per 64 frames.
+template <typename Count>
+__device__ __forceinline__ int batch_tiles(const FrameArg &fa, int n, Count count)
+{
+    if (!fa.table) return count(fa.one.H, fa.one.W);
+    const int lane = threadIdx.x & 63;
+    int total = 0;
+    for (int f0 = 0; f0 < n; f0 += 64) {
+        const int f = f0 + lane;
+        int c = f < n ? count(gload(&fa.table[f].H), gload(&fa.table[f].W)) : 0;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
+        total += c;
+    }
+    return __builtin_amdgcn_readfirstlane(total);
+}
+
+// Logical tile of workgroup b of a launch of nb workgroups: the batch's
+// frame count n and its tile count nt (capacity launches read both from
+// device memory; nt < nb there, and workgroups b >= nt get -1), then the
+// XCD-aware spread of the ids and the optional reversal.
+template <typename Count>
+__device__ __forceinline__ int batch_tile_id(const FrameArg &fa, int b, int nb, int &n, Count count)
+{
+    n = fa.n;
+    if (fa.dev_n) {
+        n = __builtin_amdgcn_readfirstlane(gload(fa.dev_n));
+        nb = batch_tiles(fa, n, count);
+        if (b >= nb) return -1;
+    }
+    int t = xcd_logical_id(b, nb);
+    if (fa.reverse) t = nb - 1 - t;
+    return t;
+}
+
 
 enum ConvMode { CONV_PACK = 0, CONV_POOL = 1, CONV_CAT = 2, CONV_PLAIN = 3 };
 enum ConvEpi { EPI_RELU = 0, EPI_HEAD_SOFTPLUS = 1, EPI_HEAD_EXP = 2 };

@@ -245,7 +245,9 @@ def fifo_single(executor: Executor, requests: List[Request], realtime: bool = Tr
 
 
 class GpuExecutor(Executor):
-    """Runs batches through libwskp on ``slots`` HIP streams.
+    """Runs batches through libwskp on ``slots`` HIP streams (with
+    ``graph``, each batch replays the graph of its stream and capacity
+    bucket).
 
     Every stream of the trace owns resident device buffers: its input frame
     and an output ring of ``ring`` frames (default slots + 1, so that
@@ -256,7 +258,7 @@ class GpuExecutor(Executor):
     """
 
     def __init__(self, denoiser, stream_inputs: Dict[int, Dict[str, "object"]], ws_bytes: int,
-                 slots: int = 2, ring: Optional[int] = None):
+                 slots: int = 2, ring: Optional[int] = None, graph: bool = False):
         import torch
         from . import wskp
         self.torch = torch
@@ -264,6 +266,8 @@ class GpuExecutor(Executor):
         self.dn = denoiser
         self.inputs = stream_inputs
         ring = slots + 1 if ring is None else ring
+        # graph replay: one HIP graph per stream and capacity bucket
+        self.flags = wskp.BATCH_GRAPH if graph else 0
         self.outputs = {s: [torch.empty_like(f["radiance"]) for _ in range(ring)]
                         for s, f in stream_inputs.items()}
         self.count = {s: 0 for s in stream_inputs}
@@ -293,7 +297,8 @@ class GpuExecutor(Executor):
             self.count[r.stream] += 1
             frames.append(f)
         need = self.workspace_bytes(reqs)
-        self.wskp.wskp_denoise_batch(self.dn.h, frames, self.ws[ws_offset:ws_offset + need], 0, s)
+        self.wskp.wskp_denoise_batch(self.dn.h, frames, self.ws[ws_offset:ws_offset + need],
+                                     self.flags, s)
         ev = self.torch.cuda.Event()
         ev.record(s)
         return ev

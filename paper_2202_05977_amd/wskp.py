@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libwskp.so")
 PREC = {"fp32": 0, "bf16": 1, "fp8": 2}
 ACT = {"softplus": 0, "exp": 1}
 BATCH_REVERSE_TILES = 1
+BATCH_GRAPH = 2
 
 _lib = None
 

@@ -155,6 +155,36 @@ def test_batch_mixed_sizes_equals_single_frames():
             assert torch.equal(f["out"], s)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_batch_graph_replay_equals_single_frames(prec):
+    """Batches run as graph replays: batches of different compositions that
+    fall in the same capacity bucket replay one graph (the workgroups beyond
+    each batch's tiles exit), on two streams, with eager work in between;
+    every frame equals the frame denoised alone, bitwise."""
+    from paper_2202_05977_amd import wskp
+    cfg = synth.SMALL
+    dn = _denoiser(cfg, prec)
+    sizes = [(64, 64), (128, 96), (32, 160), (72, 104), (16, 16), (128, 160)]
+    frames = [to_dev(synth.make_frame(40 + i, H, W)) for i, (H, W) in enumerate(sizes)]
+    singles = [dn(f).clone() for f in frames]
+    batches = [[0, 1, 2, 3], [3, 2, 1, 0], [0, 1, 2], [5], [4, 5, 0], [0, 1, 2, 3], [4]]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    wss = [torch.empty(wskp.wskp_workspace_size(dn.h, [H for H, _ in sizes], [W for _, W in sizes]),
+                       dtype=torch.uint8, device="cuda") for _ in streams]
+    for rep in range(2):
+        for j, b in enumerate(batches):
+            k = j % 2
+            fb = [dict(frames[i]) for i in b]
+            for f in fb:
+                f["out"] = torch.full_like(f["radiance"], float("nan"))
+            torch.cuda.synchronize()
+            wskp.wskp_denoise_batch(dn.h, fb, wss[k], wskp.BATCH_GRAPH, streams[k])
+            torch.cuda.synchronize()
+            for i, f in zip(b, fb):
+                assert torch.equal(f["out"], singles[i]), (rep, j, i)
+            dn(frames[(j + 1) % len(frames)])          # eager work between replays
+
+
 def test_batch_of_more_than_64_frames():
     """Frame lookup in batches that span several 64-frame groups: 130 small
     frames of five sizes, each equal to the frame denoised alone."""
@@ -184,10 +214,11 @@ def test_shape_errors():
     assert ei.value.status == -2
 
 
-def test_served_results_equal_single_frames():
+@pytest.mark.parametrize("graph", [False, True])
+def test_served_results_equal_single_frames(graph):
     """Frames pushed through the continuous-batching server (mixed sizes,
-    two streams in flight, shared workspace arena) equal the same frames
-    denoised alone, bitwise."""
+    two streams in flight, shared workspace arena; direct launches or graph
+    replay) equal the same frames denoised alone, bitwise."""
     from paper_2202_05977_amd import serve, wskp
     cfg = synth.SMALL
     dn = _denoiser(cfg, "bf16")
@@ -196,7 +227,7 @@ def test_served_results_equal_single_frames():
     inputs = {s: {k: v for k, v in to_dev(synth.make_frame(300 + s, *sizes[s])).items()
                   if k != "clean"} for s in range(8)}
     budget = 4 * wskp.wskp_workspace_size(dn.h, [128] * 3, [160] * 3)
-    ex = serve.GpuExecutor(dn, inputs, budget, slots=2, ring=2)
+    ex = serve.GpuExecutor(dn, inputs, budget, slots=2, ring=2, graph=graph)
     st = serve.Server(ex, budget, max_inflight=2, max_batch=5).run(reqs, realtime=False)
     torch.cuda.synchronize()
     assert st.errors == 0 and st.frames == len(reqs) and st.max_batch > 1
