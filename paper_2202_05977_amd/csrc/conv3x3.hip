@@ -116,7 +116,9 @@ __device__ __forceinline__ float log1p_small(float t)
 {
     const float u = 1.f + t;
     if (u == 1.f) return t;
-    return fast_log2(u) * 0.69314718055994531f * (t / (u - 1.f));
+    // t / (u - 1) is 1 up to the rounding of u: the hardware reciprocal
+    // (1 ulp) instead of an IEEE division
+    return fast_log2(u) * 0.69314718055994531f * (t * __builtin_amdgcn_rcpf(u - 1.f));
 }
 
 // softplus(x) = max(x, 0) + log(1 + e^{-|x|})
@@ -574,6 +576,11 @@ __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDes
             dq[nb][v] = (PREC == 2 && co < L.Cout) ? gload(L.out_scale + co) : 1.f;
         }
     float pe[CAN_POOL ? 2 : 1][CAN_POOL ? NB : 1][4];   // even-row partial sums
+    // head record: element offset of this lane's first channel plane, per block
+    const size_t P = (size_t)Hl * Wl;
+    size_t plane0[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) plane0[nb] = (size_t)(g * NC + nb * 16 + 4 * lq) * P;
 #pragma unroll
     for (int i = 0; i < MB; ++i) {
         const int blk = wave * MB + i, row = blk >> 1, cb = blk & 1;
@@ -591,11 +598,10 @@ __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDes
                 // head record, planar [2M][H][W]: the 16 lanes of a channel
                 // write 16 consecutive pixels of its plane
                 if (in) {
-                    OutT *q = dst + (size_t)y * Wl + x;
-                    const size_t P = (size_t)Hl * Wl;
+                    OutT *q = dst + plane0[nb] + (unsigned)(y * Wl + x);
 #pragma unroll
                     for (int k = 0; k < 4; ++k)
-                        if (co + k < L.Cout) gstore(q + (size_t)(co + k) * P, v[k]);
+                        if (co + k < L.Cout) gstore(q + k * P, v[k]);
                 }
             } else if constexpr (std::is_same<OutT, float>::value) {
                 // fp32 activations: Cout is a multiple of 16
@@ -684,19 +690,6 @@ __global__ __launch_bounds__(kThreads, (MODE == CONV_PACK && PREC == 1) ? 4 : WS
 // Each lane realises the order by choosing which group it fetches.  Pixels outside the image
 // get an offset beyond the buffer's range, and the hardware returns zeros:
 // that is the conv's zero padding.
-typedef __amdgpu_buffer_rsrc_t rsrc_t;
-
-// The descriptor must live in scalar registers: base and size are made
-// visibly wave-uniform (they are: every lane computes the same values).
-__device__ __forceinline__ rsrc_t make_rsrc(const void *base, unsigned bytes)
-{
-    const unsigned long long b = reinterpret_cast<unsigned long long>(base);
-    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
-    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
-    void *ub = reinterpret_cast<void *>(((unsigned long long)hi << 32) | lo);
-    return __builtin_amdgcn_make_buffer_rsrc(ub, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes),
-                                             0x00020000);
-}
 
 __device__ __forceinline__ void load_lds16(rsrc_t r, unsigned char *lds, unsigned voff)
 {

@@ -227,19 +227,46 @@ __device__ __forceinline__ void window_sums4(int R, int HXS, const float4 *st, f
     }
 
 // Global pixel index of each of this thread's halo slots (-1 outside the
-// image or past the halo), computed once per workgroup: the halo width is a
-// runtime value, so the division is paid here only.
+// image or past the halo), computed once per workgroup.  The halo width HX
+// is a runtime value: one division gives the first slot's row and column,
+// and each further slot (kThreads later) steps them by the wave-uniform
+// quotient and remainder of kThreads / HX (the remainder is below HX, so
+// the column wraps at most once).
 template <int RM>
 __device__ __forceinline__ void halo_pixels(int x0, int y0, int R, int HX, int HXY, int H, int W,
                                             int *gp)
 {
+    const int sy = kThreads / HX, sx = kThreads - sy * HX;
+    int ly = threadIdx.x / HX, lx = threadIdx.x - ly * HX;
 #pragma unroll
     for (int k = 0; k < max_pix<RM>(); ++k) {
         const int p = threadIdx.x + k * kThreads;
-        const int ly = p / HX, lx = p - ly * HX;
         const int gy = y0 - R + ly, gx = x0 - R + lx;
         gp[k] = (p < HXY && gy >= 0 && gy < H && gx >= 0 && gx < W) ? gy * W + gx : -1;
+        lx += sx;
+        ly += sy;
+        if (lx >= HX) {
+            lx -= HX;
+            ++ly;
+        }
     }
+}
+
+// Frames form: byte offset of a slot that holds no image pixel, beyond
+// every buffer the decode reads (frames hold at most 2^28 pixels, so the
+// largest, radiance and albedo, stay below 3.3e9 bytes); such loads read 0.
+constexpr unsigned kNoPixel = 0xfffffff0u;
+
+// Frames form: weight map i (a plane of the head record) at this thread's
+// halo slots, from byte offsets o1 (4 * pixel, or kNoPixel: reads 0).
+template <int RM>
+__device__ __forceinline__ void load_w_frames(const DecodeIO &io, int i, const unsigned *o1, float *w)
+{
+    const unsigned P = (unsigned)(io.H * io.W);
+    const rsrc_t rs = make_rsrc(io.head + (size_t)i * P, P * 4u);
+#pragma unroll
+    for (int k = 0; k < max_pix<RM>(); ++k)
+        w[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, o1[k], 0, 0));
 }
 
 // Loads weight map i at this thread's halo pixels, unconditionally (pixels
@@ -288,24 +315,44 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
     // All loads are unconditional (pixels outside the image or the halo read
     // pixel 0 and are masked afterwards), so that every request is in flight
     // before the first result is used.
+    // The frames form uses buffer loads from precomputed byte offsets: a
+    // slot outside the image gets kNoPixel and reads zeros (c = 0 * rcp(eps_a)
+    // = 0, W = 0), so nothing needs masking afterwards.
     float cv[kMaxPix][3], av[FRAMES ? kMaxPix : 1][3], wv[kMaxPix];
+    unsigned o1[FRAMES ? kMaxPix : 1];
+    if constexpr (FRAMES) {
+        const unsigned P = (unsigned)(H * W);
+        const rsrc_t rr = make_rsrc(io.r, P * 12u), ra = make_rsrc(io.a, P * 12u);
 #pragma unroll
-    for (int k = 0; k < kMaxPix; ++k) {
-        const size_t q = (size_t)(gp[k] >= 0 ? gp[k] : 0) * 3;
+        for (int k = 0; k < kMaxPix; ++k) {
+            const unsigned o3 = gp[k] >= 0 ? (unsigned)gp[k] * 12u : kNoPixel;
+            o1[k] = gp[k] >= 0 ? (unsigned)gp[k] * 4u : kNoPixel;
+            const auto r3 = __builtin_amdgcn_raw_buffer_load_b96(rr, o3, 0, 0);
+            const auto a3 = __builtin_amdgcn_raw_buffer_load_b96(ra, o3, 0, 0);
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            cv[k][ch] = gload((FRAMES ? io.r : io.c) + q + ch);
-            if constexpr (FRAMES) av[k][ch] = gload(io.a + q + ch);
+            for (int ch = 0; ch < 3; ++ch) {
+                cv[k][ch] = __uint_as_float(r3[ch]);
+                av[k][ch] = __uint_as_float(a3[ch]);
+            }
         }
+        load_w_frames<RM>(io, 0, o1, wv);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kMaxPix; ++k) {
+            const size_t q = (size_t)(gp[k] >= 0 ? gp[k] : 0) * 3;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) cv[k][ch] = gload(io.c + q + ch);
+        }
+        load_w<M, RM>(io, 0, gp, wv);
     }
-    load_w<M, RM>(io, 0, gp, wv);
 #pragma unroll
     for (int k = 0; k < kMaxPix; ++k)
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
-            float c = cv[k][ch];
-            if constexpr (FRAMES) c *= __builtin_amdgcn_rcpf(av[FRAMES ? k : 0][ch] + dc.eps_albedo);
-            cv[k][ch] = gp[k] >= 0 ? c : 0.f;
+            if constexpr (FRAMES)
+                cv[k][ch] *= __builtin_amdgcn_rcpf(av[FRAMES ? k : 0][ch] + dc.eps_albedo);
+            else
+                cv[k][ch] = gp[k] >= 0 ? cv[k][ch] : 0.f;
         }
 
     // Fusion (Eq. 5) of this thread's kRun centres (column tx, rows
@@ -357,10 +404,13 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
 #pragma unroll
         for (int k = 0; k < kMaxPix; ++k) {
             const int p = tid + k * kThreads;
-            const float w = gp[k] >= 0 ? wv[k] : 0.f;
+            const float w = (FRAMES || gp[k] >= 0) ? wv[k] : 0.f;
             if (p < HXY) pr[p] = make_float4(w, w * cv[k][0], w * cv[k][1], w * cv[k][2]);
         }
-        if (i + 1 < M) load_w<M, RM>(io, i + 1, gp, wv);
+        if (i + 1 < M) {
+            if constexpr (FRAMES) load_w_frames<RM>(io, i + 1, o1, wv);
+            else load_w<M, RM>(io, i + 1, gp, wv);
+        }
         lds_sync();
         float4 acc[kRun];
 #define WSKP_WS(KK) window_sums4<KK>(R, HX, pr, hb, acc)

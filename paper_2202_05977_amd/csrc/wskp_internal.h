@@ -83,6 +83,21 @@ __device__ __forceinline__ const FrameDesc &frame_at(const FrameArg &fa, int f)
     return fa.table ? fa.table[f] : fa.one;
 }
 
+// Raw buffer resource over `bytes` bytes at `base`.  Loads through it
+// whose offset lies beyond `bytes` return zeros.  The descriptor must live
+// in scalar registers: base and size are made visibly wave-uniform (the
+// callers pass wave-uniform values).
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, unsigned bytes)
+{
+    const unsigned long long b = reinterpret_cast<unsigned long long>(base);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    void *ub = reinterpret_cast<void *>(((unsigned long long)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(ub, (short)0, (int)__builtin_amdgcn_readfirstlane(bytes),
+                                             0x00020000);
+}
+
 // Spread consecutive logical tile ids over one XCD.  The hardware deals
 // workgroups round-robin to the 8 XCDs (block b runs on XCD b % 8); this
 // bijection gives each XCD a contiguous run of logical ids so that tiles
