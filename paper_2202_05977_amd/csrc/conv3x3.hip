@@ -89,7 +89,7 @@ __device__ __forceinline__ bool conv_locate(const ConvLayer &L, const FrameArg &
         return (((W >> lev) + kConvTW - 1) / kConvTW) * (((H >> lev) + TH - 1) / TH) * groups;
     };
     int n;
-    int t = batch_tile_id(fa, blockIdx.x, gridDim.x, n, tiles);
+    int t = batch_tile_id(fa, blockIdx.x, gridDim.x, n);
     if (t < 0) return false;
     f = batch_frame(fa, n, t, tiles);
     if (f < 0) return false;

@@ -69,7 +69,7 @@ __device__ __forceinline__ bool decode_locate_at(const DecodeCfg &dc, const Fram
     int t = xcd_logical_id(u, nbk);
     if constexpr (FRAMES) {
         int n;
-        t = batch_tile_id(fa, u, nbk, n, tiles);
+        t = batch_tile_id(fa, u, nbk, n);
         if (t < 0) return false;
         const int f = batch_frame(fa, n, t, tiles);
         if (f < 0) return false;

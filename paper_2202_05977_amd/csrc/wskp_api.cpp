@@ -130,9 +130,10 @@ struct wskp_ctx {
 
 static constexpr int kRingSlots = 8;
 static constexpr int kMaxBatch = 1024;
-static constexpr size_t kTableHeader = 256;   // frame count, padded
+static constexpr size_t kTableHeader = 256;   // frame count, tile count of each launch; padded
 static constexpr size_t kSlotBytes = kTableHeader + sizeof(FrameDesc) * kMaxBatch;
 static constexpr size_t kMaxGraphs = 256;
+static_assert(kTableHeader >= sizeof(int) * (2 + 2 * WSKP_MAX_LEVELS), "header holds n and every launch's tiles");
 
 // ---------------------------------------------------------------------------
 static wskp_status_t check_config(const wskp_config_t *c)
@@ -678,8 +679,10 @@ static wskp_status_t capture_batch_graph(wskp_ctx *h, wskp_ctx::BatchGraph &c)
     hipError_t le = hipSuccess;
     for (size_t i = 0; i < h->layers.size() && le == hipSuccess; ++i) {
         const LayerPlan &lp = h->layers[i];
+        fa.launch = (int)i;
         le = launch_conv(lp.L, lp.mode, lp.epi, h->prec, fa, c.caps[i], cs);
     }
+    fa.launch = (int)h->layers.size();
     if (le == hipSuccess) le = launch_decode_frames(h->dc, fa, c.caps.back(), cs);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cs, &graph);
@@ -737,10 +740,12 @@ extern "C" wskp_status_t wskp_denoise_batch(wskp_handle_t h, void *stream, int n
     // graph replay: the executable graph of this stream and capacity bucket
     // (launch grids rounded up to powers of two), captured on first use
     wskp_ctx::BatchGraph *g = nullptr;
+    std::vector<int> tiles;
     if (flags & WSKP_BATCH_GRAPH) {
         std::vector<int> caps;
-        for (const LayerPlan &lp : h->layers) caps.push_back(next_pow2(conv_grid(lp.L, n, Hs.data(), Ws.data())));
-        caps.push_back(next_pow2(decode_grid(n, Hs.data(), Ws.data())));
+        for (const LayerPlan &lp : h->layers) tiles.push_back(conv_grid(lp.L, n, Hs.data(), Ws.data()));
+        tiles.push_back(decode_grid(n, Hs.data(), Ws.data()));
+        for (int t : tiles) caps.push_back(next_pow2(t));
         for (auto &c : h->graphs)
             if (c.s == s && c.reverse == reverse && c.caps == caps) g = &c;
         if (!g && h->graphs.size() < kMaxGraphs) {
@@ -757,7 +762,9 @@ extern "C" wskp_status_t wskp_denoise_batch(wskp_handle_t h, void *stream, int n
     if ((e = hipEventSynchronize(h->ring_ev[slot])) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
     char *sbase = h->ring + kSlotBytes * slot;
     FrameDesc *tab = reinterpret_cast<FrameDesc *>(sbase + kTableHeader);
-    *reinterpret_cast<int *>(sbase) = n;
+    int *hdr = reinterpret_cast<int *>(sbase);
+    hdr[0] = n;
+    for (size_t i = 0; i < tiles.size(); ++i) hdr[1 + i] = tiles[i];
     char *base = static_cast<char *>(ws) + table_bytes(n);
     for (int i = 0; i < n; ++i) {
         fill_frame(h, tab[i], base, frames[i]);

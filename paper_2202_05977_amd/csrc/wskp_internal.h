@@ -71,10 +71,12 @@ struct FrameArg {
     const FrameDesc *table;  // device pointer, or nullptr to use `one`
     int n;
     int reverse;             // walk tiles in reverse order
-    // capacity launch (graph replay): when non-null, the frame count is read
-    // from this device word and the grid is an upper bound on the batch's
-    // tiles; workgroups beyond them exit
+    // capacity launch (graph replay): when non-null, dev_n[0] is the frame
+    // count and dev_n[1 + launch] this launch's tile count, both in device
+    // memory, and the grid is an upper bound on those tiles; workgroups
+    // beyond them exit
     const int *dev_n;
+    int launch;
     FrameDesc one;
 };
 
@@ -143,35 +145,19 @@ __device__ __forceinline__ int batch_frame(const FrameArg &fa, int n, int &t, Co
     return -1;
 }
 
-// Total tiles of a batch (capacity launches): a wave-wide sum of the
-// frames' tile counts, one round of loads per 64 frames.
-template <typename Count>
-__device__ __forceinline__ int batch_tiles(const FrameArg &fa, int n, Count count)
-{
-    if (!fa.table) return count(fa.one.H, fa.one.W);
-    const int lane = threadIdx.x & 63;
-    int total = 0;
-    for (int f0 = 0; f0 < n; f0 += 64) {
-        const int f = f0 + lane;
-        int c = f < n ? count(gload(&fa.table[f].H), gload(&fa.table[f].W)) : 0;
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) c += __shfl_xor(c, d, 64);
-        total += c;
-    }
-    return __builtin_amdgcn_readfirstlane(total);
-}
-
-// Logical tile of workgroup b of a launch of nb workgroups: the batch's
-// frame count n and its tile count nt (capacity launches read both from
-// device memory; nt < nb there, and workgroups b >= nt get -1), then the
-// XCD-aware spread of the ids and the optional reversal.
-template <typename Count>
-__device__ __forceinline__ int batch_tile_id(const FrameArg &fa, int b, int nb, int &n, Count count)
+// Logical tile of workgroup b of a launch of nb workgroups, and the batch's
+// frame count n.  Capacity launches read n and the launch's tile count from
+// device memory (one load round: the two words share a cache line); there
+// the tile count is below nb, and workgroups beyond it get -1.  Then the
+// XCD-aware spread of the ids over the real tile count and the optional
+// reversal.
+__device__ __forceinline__ int batch_tile_id(const FrameArg &fa, int b, int nb, int &n)
 {
     n = fa.n;
     if (fa.dev_n) {
-        n = __builtin_amdgcn_readfirstlane(gload(fa.dev_n));
-        nb = batch_tiles(fa, n, count);
+        const int dn = gload(fa.dev_n), dt = gload(fa.dev_n + 1 + fa.launch);
+        n = __builtin_amdgcn_readfirstlane(dn);
+        nb = __builtin_amdgcn_readfirstlane(dt);
         if (b >= nb) return -1;
     }
     int t = xcd_logical_id(b, nb);
