@@ -35,6 +35,16 @@ def test_header_declares_the_entry_points():
         assert n in names
 
 
+def test_binding_constants_match_the_header():
+    """The flag and enum values the binding passes are the header's."""
+    wskp = _wskp()
+    text = open(HEADER).read()
+    defs = dict(re.findall(r"#define\s+(WSKP_BATCH_[A-Z_]+)\s+(\d+)u", text))
+    assert int(defs["WSKP_BATCH_REVERSE_TILES"]) == wskp.BATCH_REVERSE_TILES
+    assert int(defs["WSKP_BATCH_GRAPH"]) == wskp.BATCH_GRAPH
+    assert wskp.BATCH_REVERSE_TILES & wskp.BATCH_GRAPH == 0
+
+
 def test_library_exports_every_declared_symbol():
     wskp = _wskp()
     lib = wskp.lib()
