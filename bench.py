@@ -152,6 +152,63 @@ def time_precision(cfg, blob, dev, H, W, prec, steps, warmup, lat_frames, nstrea
     }
 
 
+def decode_cold_warm(cfg, blob, H, W, reps=20):
+    """The decode alone (tensor form, wskp_decode) on one H x W frame, timed
+    with HIP events: warm (launched back to back, inputs left in the caches by
+    the previous launch) and cold (a 1 GiB buffer written between launches
+    evicts the L2s and the 256 MB last-level cache first)."""
+    import torch
+    from paper_2202_05977_amd import wskp
+    g = torch.Generator().manual_seed(5)
+    M = len(cfg.kernel_sizes)
+    head = torch.randn(1, H, W, 2 * M, generator=g).cuda()
+    head[..., :M] = torch.nn.functional.softplus(head[..., :M])
+    c = torch.rand(1, H, W, 3, generator=g).cuda()
+    mod = torch.rand(1, H, W, 3, generator=g).cuda() + 0.1
+    out = torch.empty_like(c)
+    dn = wskp.Denoiser(cfg, blob, "fp32")
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    s = torch.cuda.current_stream()
+
+    def timed(cold):
+        ts = []
+        for _ in range(reps):
+            if cold:
+                flush.fill_(1)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            wskp.wskp_decode(dn.h, head, c, mod, out)
+            e1.record(s)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e3)
+        return float(np.median(ts))
+
+    timed(False)
+    warm, cold = timed(False), timed(True)
+    dn.close()
+    b = H * W * (8 * M + 36)        # head 2M floats + c + mod read, out written
+    return {"workload": f"{W}x{H}, M={M}, tensor form", "bytes": b,
+            "warm_us": warm, "cold_us": cold,
+            "warm_GBps": b / warm / 1e3, "cold_GBps": b / cold / 1e3}
+
+
+def gpu_clocks():
+    """Shader and memory clock levels the driver reports (the current level
+    is marked with *), where the sysfs files are readable."""
+    import glob
+    out = {}
+    for dev in sorted(glob.glob("/sys/class/drm/card*/device")):
+        for k in ("pp_dpm_sclk", "pp_dpm_mclk"):
+            try:
+                with open(os.path.join(dev, k)) as f:
+                    cur = [l.strip() for l in f if l.strip().endswith("*")]
+                if cur:
+                    out.setdefault(os.path.basename(os.path.dirname(dev)), {})[k] = cur[0]
+            except OSError:
+                pass
+    return out or None
+
+
 def rel_errors(y, yref):
     return {"rel_l2": float(np.linalg.norm(y - yref) / np.linalg.norm(yref)),
             "max_rel": float(np.abs(y - yref).max() / np.abs(yref).max()),
@@ -438,6 +495,9 @@ def main():
                 "traffic": measured_traffic(dom, head)}
     dbytes = decode_bytes(cfg, H, W)
     dec_gbs = dbytes / (pk["decode"] * 1e-6)
+    dcw = decode_cold_warm(cfg, blob, H, W)
+    log(f"[bench] decode alone (tensor form): warm {dcw['warm_us']:.1f} us = {dcw['warm_GBps']:.0f} GB/s, "
+        f"cold {dcw['cold_us']:.1f} us = {dcw['cold_GBps']:.0f} GB/s")
     decode_roof = {"kernel": "decode", "bound": "hbm", "achieved": dec_gbs / 1e9,
                    "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": dec_gbs / HBM_PEAK,
                    "bytes_per_launch": dbytes, "traffic": measured_traffic("decode", head)}
@@ -490,6 +550,8 @@ def main():
         "per_kernel_us": res[head]["per_kernel_us"],
         "roofline": roof,
         "decode_roofline": decode_roof,
+        "decode_tensor_form": dcw,
+        "clocks": gpu_clocks(),
         "conv_mfma": conv_mfma,
         "error_vs_fp64_oracle": errors,
         "precisions": {p: {"frames_per_s": res[p]["fps"], "ms_per_step": res[p]["ms_per_step"],

@@ -73,6 +73,23 @@ def test_hd_bf16_720p_end_to_end():
     assert err <= TOL_BF16
 
 
+@pytest.mark.parametrize("shape", [(8, 16384), (16384, 8), (8, 8)])
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_extreme_frame_shapes(shape, prec):
+    """The largest accepted width or height (16384) and the smallest frame the
+    hd net accepts (8 x 8: its coarsest level is one pixel), end to end
+    against the FP64 oracle."""
+    H, W = shape
+    fr, y, _ = _oracle("hd", 7, H, W)
+    out = _run(_denoiser(synth.HD, prec), fr)
+    assert np.all(np.isfinite(out))
+    if prec == "fp32":
+        assert rel_l2(out, y) <= TOL_FP32
+        assert max_rel(out, y) <= TOL_FP32
+    else:
+        assert rel_l2(out, y) <= TOL_BF16
+
+
 def test_hd_bf16_layers_and_pooled_copies():
     """bf16 HD net layer by layer against the FP64 oracle (bf16 tolerance),
     and the pooled copies p_l that the encoder epilogues pass on: each is
