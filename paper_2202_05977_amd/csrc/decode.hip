@@ -16,10 +16,13 @@
 // * out_i accumulates in registers: two barriers per size.  The last step
 // multiplies by the remodulation factor.
 //
-// Two input forms share the kernel:
+// Two input forms:
 //   frames   c = r / (a + eps_a) is formed while staging; mod = a + eps_a;
 //            head, r, a and out come from the frame descriptors
+//            (decode_fwd_kernel, one tile per workgroup)
 //   tensors  head, c, mod (optional) and out are plain [N,H,W,*] tensors
+//            (decode_stream_kernel, persistent; decode_fwd_kernel for the
+//            first half of the adjoint)
 #include "wskp_internal.h"
 
 namespace wskp {
@@ -362,6 +365,13 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
     // size loop need not be unrolled.  Adjoint: the normalised alpha_i are
     // kept for the gradient.
     const float *lp[kRun];
+    unsigned lo[FRAMES ? kRun : 1];   // frames: byte offset of the centre in a plane
+    // frames: logit i of this thread's centres, from plane M + i by buffer load
+    auto logit_frames = [&](int i, int o) {
+        const unsigned P = (unsigned)(H * W);
+        const rsrc_t rs = make_rsrc(io.head + (size_t)(M + i) * P, P * 4u);
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, lo[FRAMES ? o : 0], 0, 0));
+    };
     float lmax[kRun], esum[kRun], F[kRun][3];
     float alpha[ADJ ? kRun : 1][ADJ ? M : 1];
 #pragma unroll
@@ -369,9 +379,10 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
         const int y = y0 + kRun * ty + o, x = x0 + tx;
         const bool in = y < H && x < W;
         lp[o] = io.head + ((size_t)(in ? y : 0) * W + (in ? x : 0)) * io.hs_pix + M * io.hs_map;
+        if constexpr (FRAMES) lo[o] = in ? (unsigned)(y * W + x) * 4u : 0u;
         float m = -INFINITY;
 #pragma unroll
-        for (int i = 0; i < M; ++i) m = fmaxf(m, gload(lp[o] + i * io.hs_map));
+        for (int i = 0; i < M; ++i) m = fmaxf(m, FRAMES ? logit_frames(i, o) : gload(lp[o] + i * io.hs_map));
         lmax[o] = m;
         esum[o] = 0.f;
         F[o][0] = F[o][1] = F[o][2] = 0.f;
@@ -397,7 +408,7 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
         float lgv[ADJ ? 1 : kRun];
         if constexpr (!ADJ) {
 #pragma unroll
-            for (int o = 0; o < kRun; ++o) lgv[o] = gload(lp[o] + i * io.hs_map);
+            for (int o = 0; o < kRun; ++o) lgv[o] = FRAMES ? logit_frames(i, o) : gload(lp[o] + i * io.hs_map);
         }
         // product plane of this size from this thread's registers, then
         // fetch the next size's weights
@@ -493,19 +504,20 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
     }
 }
 
-// Forward decode, persistent and software-pipelined.  Each workgroup walks
-// the tiles u = blockIdx.x, blockIdx.x + gridDim.x, ...  Every input of a
-// tile (irradiance inputs and all M weight maps over the halo, logits and
-// albedo of the centres) is loaded into registers one tile ahead: while tile
-// u is filtered, its successor's requests are in flight, so that memory
-// traffic and the LDS/VALU work of the box sums overlap within a workgroup
-// instead of alternating across the whole device.  The arithmetic is that of
+// Forward decode of the tensor form (stacks of equal frames), persistent
+// and software-pipelined.  Each workgroup walks the tiles u = blockIdx.x,
+// blockIdx.x + gridDim.x, ...  Every input of a tile (irradiance and all M
+// weight maps over the halo, logits and remodulation factor of the centres)
+// is loaded into registers one tile ahead: while tile u is filtered, its
+// successor's requests are in flight, so that memory traffic and the
+// LDS/VALU work of the box sums overlap within a workgroup instead of
+// alternating across the whole device.  The arithmetic is that of
 // decode_fwd_kernel.
-template <int M, int KIND, int RM>
-__global__ __launch_bounds__(kThreads, 2) void decode_stream_kernel(DecodeCfg dc, FrameArg fa,
-                                                                     DecodeTensors dt, int ntiles)
+template <int M, int RM>
+__global__ __launch_bounds__(kThreads, 2) void decode_stream_kernel(DecodeCfg dc, DecodeTensors dt,
+                                                                     int ntiles)
 {
-    constexpr bool FRAMES = KIND == DK_FRAMES;
+    const FrameArg fa{};
     constexpr int kMaxPix = max_pix<RM>();
     extern __shared__ float4 lds4[];
     const int R = dc.R;
@@ -518,11 +530,10 @@ __global__ __launch_bounds__(kThreads, 2) void decode_stream_kernel(DecodeCfg dc
     // read pixel 0; gp < 0 marks them)
     struct Raw {
         int gp[kMaxPix];
-        float x[kMaxPix][3];                       // r (frames) or c (tensors)
-        float a[FRAMES ? kMaxPix : 1][3];
+        float x[kMaxPix][3];                       // c
         float w[M][kMaxPix];
         float lg[kRun][M];                         // centre logits
-        float m[kRun][3];                          // centre remodulation factor (a or mod)
+        float m[kRun][3];                          // centre remodulation factor
     };
     auto fetch = [&](const DecodeIO &io, int x0, int y0, Raw &rw) {
         halo_pixels<RM>(x0, y0, R, HX, HXY, io.H, io.W, rw.gp);
@@ -530,10 +541,7 @@ __global__ __launch_bounds__(kThreads, 2) void decode_stream_kernel(DecodeCfg dc
         for (int k = 0; k < kMaxPix; ++k) {
             const size_t q = (size_t)(rw.gp[k] >= 0 ? rw.gp[k] : 0);
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                rw.x[k][ch] = gload((FRAMES ? io.r : io.c) + q * 3 + ch);
-                if constexpr (FRAMES) rw.a[k][ch] = gload(io.a + q * 3 + ch);
-            }
+            for (int ch = 0; ch < 3; ++ch) rw.x[k][ch] = gload(io.c + q * 3 + ch);
 #pragma unroll
             for (int i = 0; i < M; ++i) rw.w[i][k] = gload(io.head + q * io.hs_pix + i * io.hs_map);
         }
@@ -545,10 +553,7 @@ __global__ __launch_bounds__(kThreads, 2) void decode_stream_kernel(DecodeCfg dc
 #pragma unroll
             for (int i = 0; i < M; ++i) rw.lg[o][i] = gload(io.head + pix * io.hs_pix + (M + i) * io.hs_map);
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                if constexpr (FRAMES) rw.m[o][ch] = gload(io.a + pix * 3 + ch) + dc.eps_albedo;
-                else rw.m[o][ch] = io.mod ? gload(io.mod + pix * 3 + ch) : 1.f;
-            }
+            for (int ch = 0; ch < 3; ++ch) rw.m[o][ch] = io.mod ? gload(io.mod + pix * 3 + ch) : 1.f;
         }
     };
 
@@ -556,7 +561,7 @@ __global__ __launch_bounds__(kThreads, 2) void decode_stream_kernel(DecodeCfg dc
     if (u >= ntiles) return;
     DecodeIO io;
     int x0, y0;
-    decode_locate_at<FRAMES>(dc, fa, dt, u, ntiles, io, x0, y0);
+    decode_locate_at<false>(dc, fa, dt, u, ntiles, io, x0, y0);
     Raw cur;
     fetch(io, x0, y0, cur);
     for (;;) {
@@ -566,11 +571,7 @@ __global__ __launch_bounds__(kThreads, 2) void decode_stream_kernel(DecodeCfg dc
         for (int k = 0; k < kMaxPix; ++k) {
             const bool live = cur.gp[k] >= 0;
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                float c = cur.x[k][ch];
-                if constexpr (FRAMES) c *= __builtin_amdgcn_rcpf(cur.a[k][ch] + dc.eps_albedo);
-                cv[k][ch] = live ? c : 0.f;
-            }
+            for (int ch = 0; ch < 3; ++ch) cv[k][ch] = live ? cur.x[k][ch] : 0.f;
 #pragma unroll
             for (int i = 0; i < M; ++i) wv[i][k] = live ? cur.w[i][k] : 0.f;
         }
@@ -596,7 +597,7 @@ __global__ __launch_bounds__(kThreads, 2) void decode_stream_kernel(DecodeCfg dc
         const int un = u + gridDim.x;
         const bool more = un < ntiles;
         if (more) {
-            decode_locate_at<FRAMES>(dc, fa, dt, un, ntiles, io, x0, y0);
+            decode_locate_at<false>(dc, fa, dt, un, ntiles, io, x0, y0);
             fetch(io, x0, y0, cur);
         }
 
@@ -771,25 +772,14 @@ int decode_grid(int n, const int *H, const int *W)
     return (int)total;
 }
 
-// The persistent form is used where it measured faster: the tensor form
-// (wskp_decode, several equal frames).  For frames it holds the radiance and
-// albedo of the next tile as well and runs at lower occupancy than the
-// one-tile-per-workgroup kernel, which is then faster (build-time knob).
-#ifndef WSKP_DECODE_STREAM_FRAMES
-#define WSKP_DECODE_STREAM_FRAMES 0
-#endif
-
-// Forward decode over `tiles` tiles with the persistent kernel: at most
-// dc.grid_cap workgroups, each walking its share of the tiles.
-template <int KIND>
-static hipError_t launch_stream(const DecodeCfg &dc, const FrameArg &fa, const DecodeTensors &dt,
-                                int tiles, hipStream_t s)
+// Forward decode of the tensor form over `tiles` tiles with the persistent
+// kernel: at most dc.grid_cap workgroups, each walking its share of the tiles.
+// (The frames form uses the one-tile-per-workgroup kernel, which measured
+// faster there: the persistent one would hold the next tile's radiance and
+// albedo as well, at lower occupancy.)
+static hipError_t launch_stream(const DecodeCfg &dc, const DecodeTensors &dt, int tiles, hipStream_t s)
 {
     if (tiles <= 0) return hipSuccess;
-    // capacity launches (frame count in device memory) use the one-tile-per-
-    // workgroup kernel, whose workgroups beyond the batch exit
-    if (KIND == DK_FRAMES && (!WSKP_DECODE_STREAM_FRAMES || fa.dev_n))
-        return launch_decode<KIND>(dc, fa, dt, tiles, s);
     const size_t lds = decode_lds_bytes(dc);
     const int grid = tiles < dc.grid_cap ? tiles : dc.grid_cap;
     const bool r5 = dc.R <= 5;
@@ -797,13 +787,13 @@ static hipError_t launch_stream(const DecodeCfg &dc, const FrameArg &fa, const D
 #define WSKP_M(m)                                                                                 \
     case m:                                                                                       \
         if (r5) {                                                                                 \
-            allow_lds(decode_stream_kernel<m, KIND, 5>, lds);                                     \
-            hipLaunchKernelGGL((decode_stream_kernel<m, KIND, 5>), dim3(grid), dim3(kThreads), lds, \
-                               s, dc, fa, dt, tiles);                                             \
+            allow_lds(decode_stream_kernel<m, 5>, lds);                                           \
+            hipLaunchKernelGGL((decode_stream_kernel<m, 5>), dim3(grid), dim3(kThreads), lds, s,  \
+                               dc, dt, tiles);                                                    \
         } else {                                                                                  \
-            allow_lds(decode_stream_kernel<m, KIND, 7>, lds);                                     \
-            hipLaunchKernelGGL((decode_stream_kernel<m, KIND, 7>), dim3(grid), dim3(kThreads), lds, \
-                               s, dc, fa, dt, tiles);                                             \
+            allow_lds(decode_stream_kernel<m, 7>, lds);                                           \
+            hipLaunchKernelGGL((decode_stream_kernel<m, 7>), dim3(grid), dim3(kThreads), lds, s,  \
+                               dc, dt, tiles);                                                    \
         }                                                                                         \
         break;
         WSKP_M(1) WSKP_M(2) WSKP_M(3) WSKP_M(4) WSKP_M(5) WSKP_M(6) WSKP_M(7) WSKP_M(8)
@@ -816,16 +806,15 @@ static hipError_t launch_stream(const DecodeCfg &dc, const FrameArg &fa, const D
 hipError_t launch_decode_frames(const DecodeCfg &dc, const FrameArg &fa, int blocks, hipStream_t s)
 {
     DecodeTensors dt{};
-    return launch_stream<DK_FRAMES>(dc, fa, dt, blocks, s);
+    return launch_decode<DK_FRAMES>(dc, fa, dt, blocks, s);
 }
 
 hipError_t launch_decode_tensors(const DecodeCfg &dc, int N, int H, int W, const float *head,
                                  const float *c, const float *mod, float *out, hipStream_t s)
 {
-    FrameArg fa{};
     DecodeTensors dt{N, H, W, head, c, mod, out, nullptr, nullptr, nullptr};
     const int blocks = N * ((W + kDTX - 1) / kDTX) * ((H + kDTY - 1) / kDTY);
-    return launch_stream<DK_TENSORS>(dc, fa, dt, blocks, s);
+    return launch_stream(dc, dt, blocks, s);
 }
 
 size_t decode_backward_scratch_bytes(const DecodeCfg &dc, int N, int H, int W)
