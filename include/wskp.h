@@ -18,8 +18,12 @@
  *    stay valid until the work queued on `stream` has completed.  The
  *    library never frees or retains caller memory.
  *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
- *    All work is queued asynchronously on it; no call synchronises the
- *    device except wskp_create / wskp_destroy.
+ *    All work is queued asynchronously on it.  wskp_create, wskp_destroy and
+ *    wskp_timing_enable synchronise the device; wskp_denoise_batch may wait
+ *    for the host-to-device copy of its own frame table from 8 calls earlier
+ *    (its pinned staging ring), and with WSKP_BATCH_GRAPH the first batch of
+ *    a new capacity bucket allocates and captures a graph; no other call
+ *    waits for the device.
  *  - Calls validate their arguments synchronously and return a status; no
  *    exception crosses the ABI.  A failed call queues no work.  Faults that
  *    happen later on the device surface at the caller's next
