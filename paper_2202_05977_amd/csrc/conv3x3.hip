@@ -756,26 +756,34 @@ __global__ __launch_bounds__(kThreads, direct_min_wg(NB)) void conv3x3_bf16_dire
     const rsrc_t rw = make_rsrc(L.w, (unsigned)((size_t)nchunks * L.Cout_pad * BSK * 2));
 
     // byte offsets of this wave's A slots in source 0 and source 1 (chunk 0).
-    // Row and pixel pitches are below 2^24, so the products are 24-bit
-    // multiplies (full rate, unlike 32-bit ones).
+    // The lane's k-th slot is slot0 + 256 k: halo pixel p0 + 64 k with the
+    // same channel group (adding 64 leaves bits 1-2 of the pixel index
+    // unchanged), so its row and column step by the quotient and remainder
+    // of 64 / WP.  Row and pixel pitches are below 2^24, so the products are
+    // 24-bit multiplies (full rate, unlike 32-bit ones).
     const unsigned cp0 = (unsigned)L.C0 * 2u, rp0 = (unsigned)W0 * cp0;
     const unsigned cp1 = (unsigned)L.C1 * 2u, rp1 = (unsigned)Wl * cp1;
+    const int slot0 = wave * 64 + lane, p0 = slot0 >> 2;
+    const unsigned goff = (unsigned)(((slot0 & 3) ^ ((p0 >> 1) & 3)) * 16);
+    constexpr int SY = 64 / WP, SX = 64 - SY * WP;
+    int ly = p0 / WP, lx = p0 - ly * WP;
     unsigned oa0[PW], oa1[PW];
 #pragma unroll
     for (int k = 0; k < PW; ++k) {
-        const int ins = wave + 4 * k;
-        const int slot = ins * 64 + lane;
-        const int p = slot >> 2, gch = (slot & 3) ^ ((p >> 1) & 3);
-        const int ly = p / WP, lx = p - ly * WP;
         const int gy = y0 - 1 + ly, gx = x0 - 1 + lx;
-        oa0[k] = oa1[k] = kOutOfRange;
-        if (slot < A_SLOTS && gy >= 0 && gy < Hl && gx >= 0 && gx < Wl) {
-            if (MODE == CONV_CAT) {
-                oa0[k] = __umul24((unsigned)gy >> 1, rp0) + __umul24((unsigned)gx >> 1, cp0) + gch * 16;
-                oa1[k] = __umul24((unsigned)gy, rp1) + __umul24((unsigned)gx, cp1) + gch * 16;
-            } else {
-                oa0[k] = __umul24((unsigned)gy, rp0) + __umul24((unsigned)gx, cp0) + gch * 16;
-            }
+        const bool in = p0 + 64 * k < NPIX && (unsigned)gy < (unsigned)Hl && (unsigned)gx < (unsigned)Wl;
+        if (MODE == CONV_CAT) {
+            oa0[k] = in ? __umul24((unsigned)gy >> 1, rp0) + __umul24((unsigned)gx >> 1, cp0) + goff : kOutOfRange;
+            oa1[k] = in ? __umul24((unsigned)gy, rp1) + __umul24((unsigned)gx, cp1) + goff : kOutOfRange;
+        } else {
+            oa0[k] = in ? __umul24((unsigned)gy, rp0) + __umul24((unsigned)gx, cp0) + goff : kOutOfRange;
+            oa1[k] = kOutOfRange;
+        }
+        lx += SX;
+        ly += SY;
+        if (lx >= WP) {
+            lx -= WP;
+            ++ly;
         }
     }
 
