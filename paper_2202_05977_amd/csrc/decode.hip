@@ -126,6 +126,15 @@ __device__ __forceinline__ bool decode_locate(const DecodeCfg &dc, const FrameAr
 
 enum DecodeKind { DK_FRAMES = 0, DK_TENSORS = 1, DK_ADJ_A = 2 };
 
+// e^x for the softmax numerators (x = l_i - max_j l_j <= 0): the hardware
+// 2^x of x log2(e) instead of the library expf.  Relative error about
+// 1 ulp + |x| * 6e-8 (the rounding of x log2(e)); the numerators with a
+// large |x| are the small ones, whose errors hardly move the blend.
+__device__ __forceinline__ float exp_softmax(float x)
+{
+    return __builtin_amdgcn_exp2f(x * 1.4426950408889634f);
+}
+
 __device__ __forceinline__ float4 f4add(float4 a, float4 b)
 {
     return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
@@ -437,7 +446,7 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
                 outv[o][i][2] = o2;
                 Sv[o][i] = acc[o].x;
             } else {
-                const float e = expf(lgv[o] - lmax[o]);
+                const float e = exp_softmax(lgv[o] - lmax[o]);
                 esum[o] += e;
                 F[o][0] += e * o0;
                 F[o][1] += e * o1;
@@ -617,7 +626,7 @@ __global__ __launch_bounds__(kThreads, 2) void decode_stream_kernel(DecodeCfg dc
 #pragma unroll
             for (int o = 0; o < kRun; ++o) {
                 const float inv = __builtin_amdgcn_rcpf(fmaxf(acc[o].x, dc.eps_norm));
-                const float e = expf(lg[o][i] - lmax[o]);
+                const float e = exp_softmax(lg[o][i] - lmax[o]);
                 esum[o] += e;
                 F[o][0] += e * (acc[o].y * inv);
                 F[o][1] += e * (acc[o].z * inv);
