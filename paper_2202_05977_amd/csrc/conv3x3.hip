@@ -913,14 +913,20 @@ int conv_chunk(int prec, int mode, int Cin, int C0)
 #ifndef WSKP_CONV_MAX_NB
 #define WSKP_CONV_MAX_NB 4
 #endif
+#ifndef WSKP_DIRECT_MAX_NB
+#define WSKP_DIRECT_MAX_NB 2
+#endif
 // Wider groups stage and read each input tile fewer times (the A operand is
-// reused across NB blocks); narrower groups give more workgroups, which the
-// direct-load kernel needs on the coarsest levels.
+// reused across NB blocks); narrower groups give more workgroups and a
+// smaller stage, so more of them fit a CU.  The direct-load kernel measured
+// fastest with at most two blocks (stage <= 40 KiB, four workgroups per CU)
+// and one block on the coarsest levels.
 int conv_blocks_per_group(int prec, int mode, int CK, int nblk, int level)
 {
     if (mode == CONV_PACK) return nblk % 2 == 0 ? 2 : 1;
-    if (uses_direct(prec, mode, CK) && level >= WSKP_COARSE_LEVEL) return 1;
-    for (int nb = WSKP_CONV_MAX_NB; nb > 1; --nb)
+    const bool direct = uses_direct(prec, mode, CK);
+    if (direct && level >= WSKP_COARSE_LEVEL) return 1;
+    for (int nb = direct ? WSKP_DIRECT_MAX_NB : WSKP_CONV_MAX_NB; nb > 1; --nb)
         if (nb <= 4 && nblk % nb == 0) return nb;
     return 1;
 }
