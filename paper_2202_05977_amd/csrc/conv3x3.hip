@@ -561,6 +561,8 @@ __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDes
     constexpr int MB = TH / 2;
     constexpr int NC = NB * 16;
     constexpr bool CAN_POOL = !std::is_same<OutT, float>::value && EPI == EPI_RELU && MB >= 4;
+    // bf16 activations of an even number of blocks: stored in pairs
+    constexpr bool PAIR = !std::is_same<OutT, float>::value && EPI == EPI_RELU && NB % 2 == 0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lj = lane & 15, lq = lane >> 4;
     OutT *dst = conv_dst<OutT>(L, fd);
@@ -587,6 +589,7 @@ __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDes
         const int y = y0 + row, x = x0 + cb * 16 + lj;
         const bool in = y < Hl && x < Wl;
         OutT *pp = dst + ((size_t)y * Wl + x) * L.Cout;
+        uint2 qs[NB];   // packed bf16 of each block (paired stores)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const int co = g * NC + nb * 16 + 4 * lq;
@@ -609,7 +612,10 @@ __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDes
             } else {
                 // activations: Cout is a multiple of 16
                 const uint2 q = make_uint2(pack2(v[0], v[1]), pack2(v[2], v[3]));
-                if (in && cin) gstore(reinterpret_cast<gu32x2 *>(pp + co), gu32x2{q.x, q.y});
+                qs[nb] = q;
+                if constexpr (!PAIR) {
+                    if (in && cin) gstore(reinterpret_cast<gu32x2 *>(pp + co), gu32x2{q.x, q.y});
+                }
                 if constexpr (CAN_POOL) {
                     if (pool) {
                         const float r[4] = {__uint_as_float(q.x << 16), __uint_as_float(q.x & 0xffff0000u),
@@ -630,6 +636,22 @@ __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDes
                         }
                     }
                 }
+            }
+        }
+        if constexpr (PAIR) {
+            // Blocks nb and nb+1 together: lane row q holds channels 4q..4q+3
+            // of each.  v_permlane16_swap exchanges the odd rows of the first
+            // operand with the even rows of the second, after which even rows
+            // hold 8 consecutive channels of block nb (from rows q, q+1) and
+            // odd rows 8 of block nb+1 (rows q-1, q): one 16-byte store per
+            // lane, and the 4 lanes of a pixel cover its 32 channels.
+#pragma unroll
+            for (int nb = 0; nb < NB; nb += 2) {
+                const auto s0 = __builtin_amdgcn_permlane16_swap(qs[nb].x, qs[nb + 1].x, false, false);
+                const auto s1 = __builtin_amdgcn_permlane16_swap(qs[nb].y, qs[nb + 1].y, false, false);
+                const int c = g * NC + ((lq & 1) ? (nb + 1) * 16 + 4 * (lq - 1) : nb * 16 + 4 * lq);
+                if (in && c < L.Cout)
+                    gstore(reinterpret_cast<gu32x4 *>(pp + c), gu32x4{s0[0], s1[0], s0[1], s1[1]});
             }
         }
     }

@@ -40,6 +40,7 @@ __device__ __forceinline__ void gstore(T *p, T v)
 }
 typedef float gf32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int gu32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int gu32x4 __attribute__((ext_vector_type(4)));
 
 // Workgroup barrier without the memory fence of __syncthreads(): the fence
 // waits for every global load in flight (prefetches included).  Callers make
