@@ -590,6 +590,7 @@ __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDes
         const bool in = y < Hl && x < Wl;
         OutT *pp = dst + ((size_t)y * Wl + x) * L.Cout;
         uint2 qs[NB];   // packed bf16 of each block (paired stores)
+        uint2 pm[NB];   // packed 2x2 means of each block (odd rows, paired stores)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const int co = g * NC + nb * 16 + 4 * lq;
@@ -628,10 +629,13 @@ __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDes
                             float m[4];
 #pragma unroll
                             for (int k = 0; k < 4; ++k) m[k] = 0.25f * ((pe[cb][nb][k] + r[k]) + lane_xor1(r[k]));
-                            const int Y = y >> 1, X = x >> 1;
-                            if ((lj & 1) == 0 && Y < (Hl >> 1) && X < (Wl >> 1) && cin) {
-                                OutT *pd = pdst + ((size_t)Y * (Wl >> 1) + X) * L.Cout + co;
-                                gstore(reinterpret_cast<gu32x2 *>(pd), gu32x2{pack2(m[0], m[1]), pack2(m[2], m[3])});
+                            pm[nb] = make_uint2(pack2(m[0], m[1]), pack2(m[2], m[3]));
+                            if constexpr (!PAIR) {
+                                const int Y = y >> 1, X = x >> 1;
+                                if ((lj & 1) == 0 && Y < (Hl >> 1) && X < (Wl >> 1) && cin) {
+                                    OutT *pd = pdst + ((size_t)Y * (Wl >> 1) + X) * L.Cout + co;
+                                    gstore(reinterpret_cast<gu32x2 *>(pd), gu32x2{pm[nb].x, pm[nb].y});
+                                }
                             }
                         }
                     }
@@ -652,6 +656,18 @@ __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDes
                 const int c = g * NC + ((lq & 1) ? (nb + 1) * 16 + 4 * (lq - 1) : nb * 16 + 4 * lq);
                 if (in && c < L.Cout)
                     gstore(reinterpret_cast<gu32x4 *>(pp + c), gu32x4{s0[0], s1[0], s0[1], s1[1]});
+                if constexpr (CAN_POOL) {
+                    // the 2x2 means of a row pair, the same way (even lanes)
+                    if (pool && ((i >> 1) & 1)) {
+                        const auto t0 = __builtin_amdgcn_permlane16_swap(pm[nb].x, pm[nb + 1].x, false, false);
+                        const auto t1 = __builtin_amdgcn_permlane16_swap(pm[nb].y, pm[nb + 1].y, false, false);
+                        const int Y = y >> 1, X = x >> 1;
+                        if ((lj & 1) == 0 && Y < (Hl >> 1) && X < (Wl >> 1) && c < L.Cout) {
+                            OutT *pd = pdst + ((size_t)Y * (Wl >> 1) + X) * L.Cout + c;
+                            gstore(reinterpret_cast<gu32x4 *>(pd), gu32x4{t0[0], t1[0], t0[1], t1[1]});
+                        }
+                    }
+                }
             }
         }
     }
