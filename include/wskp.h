@@ -48,7 +48,7 @@ typedef enum {
     WSKP_OK = 0,
     WSKP_E_INVALID_ARG = -1, /* NULL pointer, bad config value, weight count mismatch */
     WSKP_E_SHAPE = -2,       /* H or W < 1, or not a multiple of 2^(levels-1) for the net */
-    WSKP_E_UNSUPPORTED = -3, /* valid request this build does not implement */
+    WSKP_E_UNSUPPORTED = -3, /* valid request the library does not implement */
     WSKP_E_DEVICE = -4,      /* no usable gfx950 device, or a HIP runtime error */
     WSKP_E_OOM = -5,         /* device or pinned-host allocation failed */
     WSKP_E_BUDGET = -6,      /* workspace too small for the request */
