@@ -412,6 +412,69 @@ def omp_threads() -> int:
         return os.cpu_count() or 1
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_stages(oracle, fr, blob, cfg):
+    """The oracle's per-frame path in two timed parts: (y, seconds of
+    preprocess + U-Net + head activation, seconds of decode + fusion +
+    remodulation, the decode's inputs).  The same composition as
+    oracle.denoise."""
+    t0 = time.perf_counter()
+    X, c, mod = oracle.preprocess(fr["radiance"], fr["albedo"], fr["normal"], fr["depth"],
+                                  cfg.gamma, cfg.depth_near, cfg.depth_far, cfg.eps_albedo)
+    h = oracle.unet(X, blob, cfg.levels, cfg.channels, 2 * len(cfg.kernel_sizes))
+    head = oracle.activate(h, len(cfg.kernel_sizes), cfg.weight_act)
+    t1 = time.perf_counter()
+    y = oracle.decode(head, c, mod, cfg.kernel_sizes, cfg.eps_norm)
+    t2 = time.perf_counter()
+    return y, t1 - t0, t2 - t1, (head, c, mod)
+
+
+def cpu_baseline(fr, blob, cfg, H: int, W: int):
+    """The FP64 oracle timed on the host: the whole frame on all OpenMP
+    threads (the reported value), split into net and decode, plus a
+    one-thread figure (the decode on the whole frame, the net on a crop of
+    about 1/16 of its pixels, scaled by pixel count).  Returns (cpu_baseline
+    object, oracle output)."""
+    import oracle
+    threads = omp_threads()
+    log(f"[bench] FP64 oracle on the same {W}x{H} frame ({threads} threads)")
+    yref, t_net, t_dec, dec_in = oracle_stages(oracle, fr, blob, cfg)
+    dt = t_net + t_dec
+    a = 2 ** (cfg.levels - 1)          # the net needs sides that are multiples of this
+    ch = max(a, (H // 4) // a * a)
+    cw = max(a, (W // 4) // a * a)
+    crop = {k: np.ascontiguousarray(v[:ch, :cw]) for k, v in fr.items()}
+    oracle.set_threads(1)
+    try:
+        _, t1_net, _, _ = oracle_stages(oracle, crop, blob, cfg)
+        t1_dec = time.perf_counter()
+        oracle.decode(*dec_in, cfg.kernel_sizes, cfg.eps_norm)
+        t1_dec = time.perf_counter() - t1_dec
+    finally:
+        oracle.set_threads(threads)
+    t1_net *= (H * W) / (ch * cw)
+    log(f"[bench] oracle: net {t_net:.2f} s + decode {t_dec:.2f} s on {threads} threads; "
+        f"one thread: net {t1_net:.1f} s (from a {cw}x{ch} crop), decode {t1_dec:.2f} s")
+    cpu = {"value": 1.0 / dt, "unit": "frames/s", "cores": threads, "kind": "oracle",
+           "sample": f"one full {W}x{H} frame of the same workload (FP64 U-Net + decode), {dt:.1f} s",
+           "net_s": t_net, "decode_s": t_dec,
+           "one_thread": {"net_s": t1_net, "decode_s": t1_dec,
+                          "sample": f"net timed on a {cw}x{ch} crop of the frame and scaled by pixel "
+                                    f"count; decode on the whole frame"},
+           "cpu_model": cpu_model(), "cpus_visible": len(os.sched_getaffinity(0))}
+    return cpu, yref
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -510,15 +573,7 @@ def main():
     cpu = None
     errors = {}
     if not args.no_cpu_baseline:
-        import oracle
-        threads = omp_threads()
-        log(f"[bench] FP64 oracle on the same {W}x{H} frame ({threads} threads)")
-        t0 = time.perf_counter()
-        yref = oracle.denoise(fr, blob, cfg)
-        dt = time.perf_counter() - t0
-        cpu = {"value": 1.0 / dt, "unit": "frames/s", "cores": threads, "kind": "oracle",
-               "sample": f"one full {W}x{H} frame of the same workload (FP64 U-Net + decode), "
-                         f"{dt:.1f} s"}
+        cpu, yref = cpu_baseline(fr, blob, cfg, H, W)
         for p in precs:
             y = res[p]["y"]
             errors[p] = {
