@@ -96,6 +96,10 @@ def time_precision(cfg, blob, dev, H, W, prec, steps, warmup, lat_frames, nstrea
     pipelined(steps)
     torch.cuda.synchronize()
     ms_per_step = (time.perf_counter() - t0) * 1e3 / steps
+    # every stream's last frame is bitwise the one-stream result of the frame
+    ref = dn(dev, torch.empty_like(out))
+    torch.cuda.synchronize()
+    streams_equal = all(bool(torch.equal(o_, ref)) for _, o_ in lanes)
     for d in extra:
         d.close()
     # latency: one frame at a time, HIP events on the launch stream
@@ -147,6 +151,7 @@ def time_precision(cfg, blob, dev, H, W, prec, steps, warmup, lat_frames, nstrea
         "p50_ms": float(np.percentile(lat, 50)),
         "p99_ms": float(np.percentile(lat, 99)),
         "graph_fps": 1e3 / ms_graph,
+        "streams_equal_single": streams_equal,
         "per_kernel_us": per_kernel_us,
         "y": y,
     }
@@ -538,7 +543,8 @@ def main():
         log(f"[bench] {p}: {res[p]['fps']:.1f} frames/s, {res[p]['ms_per_step']:.3f} ms/frame, "
             f"p50 {res[p]['p50_ms']:.3f} p99 {res[p]['p99_ms']:.3f} ms, "
             f"one stream {res[p]['single_stream_fps']:.1f} frames/s, "
-            f"graph replay (one stream) {res[p]['graph_fps']:.1f} frames/s")
+            f"graph replay (one stream) {res[p]['graph_fps']:.1f} frames/s, "
+            f"{args.streams}-stream outputs == one-stream: {res[p]['streams_equal_single']}")
         log(f"[bench] {p} per kernel (us): " +
             ", ".join(f"{k} {v:.1f}" for k, v in res[p]["per_kernel_us"].items()))
 
@@ -601,6 +607,7 @@ def main():
                    "streams": args.streams},
         "single_stream": {"frames_per_s": res[head]["single_stream_fps"],
                           "ms_per_step": res[head]["single_stream_ms_per_step"]},
+        "streams_bitwise_equal_single_stream": res[head]["streams_equal_single"],
         "latency_ms": {"p50": res[head]["p50_ms"], "p99": res[head]["p99_ms"]},
         "per_kernel_us": res[head]["per_kernel_us"],
         "roofline": roof,

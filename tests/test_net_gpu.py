@@ -123,6 +123,35 @@ def test_small_bf16_ragged():
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_three_stream_pipeline_matches_single_stream(prec):
+    """The launch configuration of the throughput figure: 720p frames dealt
+    in turn to three streams, each stream with its own handle, workspace and
+    outputs, so that kernels of different frames run concurrently.  Two
+    different frames alternate; every result is bitwise the one-stream
+    result of its frame."""
+    frames = [to_dev(synth.make_frame(seed, 720, 1280)) for seed in (1, 2)]
+    dns = [_denoiser(synth.HD, prec) for _ in range(3)]
+    refs = [dns[0](f).clone() for f in frames]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    for s_ in streams:
+        s_.wait_stream(torch.cuda.current_stream())
+    outs = []
+    for k in range(9):
+        o = torch.empty((720, 1280, 3), dtype=torch.float32, device="cuda")
+        o.fill_(float("nan"))
+        streams[k % 3].wait_stream(torch.cuda.current_stream())
+        dns[k % 3](frames[k % 2], o, stream=streams[k % 3])
+        outs.append(o)
+    torch.cuda.synchronize()
+    for k, o in enumerate(outs):
+        assert torch.equal(o, refs[k % 2]), f"frame {k} on stream {k % 3} differs"
+    assert not torch.equal(refs[0], refs[1])
+    for d in dns:
+        d.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_graph_replay_matches_eager(prec):
     """One frame's launches captured once in a HIP graph: every replay, with
     eager work (other frames through the same workspace, fills) and
