@@ -302,6 +302,34 @@ def test_hd_fp8_720p_reported_error():
     assert err <= 0.1
 
 
+def test_hd_1080p_every_precision_against_oracle():
+    """The 1920x1080 frame in each precision against one FP64 oracle run:
+    fp32 to the FP32 gate (relative L2 and relative max norm), bf16 to the
+    BF16 gate, fp8 reported with the encoding gate of the 720p test."""
+    from paper_2202_05977_amd import wskp
+    cfg = synth.HD
+    blob = synth.make_weights(cfg, 0)
+    fr, y, _ = _oracle("hd", 1, 1080, 1920)
+    out = _run(wskp.Denoiser(cfg, blob, "fp32"), fr)
+    assert rel_l2(out, y) <= TOL_FP32 and max_rel(out, y) <= TOL_FP32
+    out = _run(wskp.Denoiser(cfg, blob, "bf16"), fr)
+    assert rel_l2(out, y) <= TOL_BF16
+    scales = wskp.calibrate_fp8_scales(cfg, blob, to_dev(synth.make_frame(999, 1080, 1920)))
+    out = _run(wskp.Denoiser(cfg, blob, "fp8", act_scales=scales), fr)
+    err = rel_l2(out, y)
+    print(f"fp8 1080p rel-L2 vs FP64 oracle: {err:.3e}, max-rel {max_rel(out, y):.3e}")
+    assert np.all(np.isfinite(out)) and err <= 0.1
+
+
+def test_hd_1440p_bf16_against_oracle():
+    """The largest resolution of the serving mix (2560x1440), in the serving
+    precision, against the FP64 oracle."""
+    fr, y, _ = _oracle("hd", 1, 1440, 2560)
+    out = _run(_denoiser(synth.HD, "bf16"), fr)
+    assert np.all(np.isfinite(out))
+    assert rel_l2(out, y) <= TOL_BF16
+
+
 def test_fp8_needs_scales_and_32_wide_levels():
     from paper_2202_05977_amd import wskp
     with pytest.raises(wskp.WskpError) as ei:
