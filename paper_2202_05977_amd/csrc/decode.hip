@@ -409,6 +409,7 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
     }
     float outv[ADJ ? kRun : 1][ADJ ? M : 1][3];
     float Sv[ADJ ? kRun : 1][ADJ ? M : 1];
+    float mv[ADJ ? 1 : kRun][3];   // forward: remodulation factor of the centres
 
     // one kernel size: product plane, window sums, normalisation, fusion
     auto size_step = [&](int i) {
@@ -459,7 +460,25 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
         for (int i = 0; i < M; ++i) size_step(i);
     } else {
 #pragma unroll 1
-        for (int i = 0; i < M; ++i) size_step(i);
+        for (int i = 0; i < M - 1; ++i) size_step(i);
+        // the centres' remodulation factors are requested before the last
+        // size's window sums, which hide their latency (centres outside the
+        // image read pixel 0 and are not stored)
+#pragma unroll
+        for (int o = 0; o < kRun; ++o) {
+            if constexpr (FRAMES) {
+                const unsigned P = (unsigned)(H * W);
+                const auto a3 = __builtin_amdgcn_raw_buffer_load_b96(make_rsrc(io.a, P * 12u), lo[o] * 3u, 0, 0);
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) mv[o][ch] = __uint_as_float(a3[ch]) + dc.eps_albedo;
+            } else {
+                const int y = y0 + kRun * ty + o, x = x0 + tx;
+                const size_t pix = (y < H && x < W) ? (size_t)y * W + x : 0;
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) mv[o][ch] = io.mod ? gload(io.mod + pix * 3 + ch) : 1.f;
+            }
+        }
+        size_step(M - 1);
 #pragma unroll
         for (int o = 0; o < kRun; ++o) {
             const float inv = 1.f / esum[o];
@@ -476,12 +495,7 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
         const size_t pix = (size_t)y * W + x;
         if constexpr (!ADJ) {
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                float m = 1.f;
-                if (FRAMES) m = gload(io.a + pix * 3 + ch) + dc.eps_albedo;
-                else if (io.mod) m = gload(io.mod + pix * 3 + ch);
-                gstore(io.out + pix * 3 + ch, m * F[o][ch]);
-            }
+            for (int ch = 0; ch < 3; ++ch) gstore(io.out + pix * 3 + ch, mv[o][ch] * F[o][ch]);
         } else {
             float dF[3];
 #pragma unroll
