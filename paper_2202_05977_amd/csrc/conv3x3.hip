@@ -554,9 +554,29 @@ __device__ __forceinline__ float lane_xor1(float v)
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
 }
 
+// Per-lane output-channel constants of the epilogue: the bias and, for fp8,
+// the dequantisation factor of this lane's 4 channels in each block.
+template <int PREC, int NB>
+struct EpiConsts {
+    float bias[NB][4], dq[NB][4];
+    __device__ __forceinline__ void load(const ConvLayer &L, int g)
+    {
+        const int lq = (threadIdx.x & 63) >> 4;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int co = g * NB * 16 + nb * 16 + 4 * lq + v;
+                bias[nb][v] = co < L.Cout ? gload(L.bias + co) : 0.f;
+                dq[nb][v] = (PREC == 2 && co < L.Cout) ? gload(L.out_scale + co) : 1.f;
+            }
+    }
+};
+
 template <int PREC, int EPI, int TH, int NB, typename OutT>
 __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDesc &fd, int g, int x0,
-                                              int y0, int Hl, int Wl, f32x4 (*acc)[NB])
+                                              int y0, int Hl, int Wl, f32x4 (*acc)[NB],
+                                              const EpiConsts<PREC, NB> &ec)
 {
     constexpr int MB = TH / 2;
     constexpr int NC = NB * 16;
@@ -568,15 +588,8 @@ __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDes
     OutT *dst = conv_dst<OutT>(L, fd);
     const bool pool = CAN_POOL && L.pool_idx >= 0;
     OutT *pdst = pool ? reinterpret_cast<OutT *>(fd.p[L.pool_idx]) : nullptr;
-    float bias[NB][4], dq[NB][4];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int co = g * NC + nb * 16 + 4 * lq + v;
-            bias[nb][v] = co < L.Cout ? gload(L.bias + co) : 0.f;
-            dq[nb][v] = (PREC == 2 && co < L.Cout) ? gload(L.out_scale + co) : 1.f;
-        }
+    const auto &bias = ec.bias;
+    const auto &dq = ec.dq;
     float pe[CAN_POOL ? 2 : 1][CAN_POOL ? NB : 1][4];   // even-row partial sums
     // head record: element offset of this lane's first channel plane, per block
     const size_t P = (size_t)Hl * Wl;
@@ -701,15 +714,28 @@ __global__ __launch_bounds__(kThreads, (MODE == CONV_PACK && PREC == 1) ? 4 : WS
     st.init(L, g, x0, y0, Hl, Wl);
     const int nchunks = L.Cin_pad / CK;
     st.fetch(L, fd, s0, s1, 0, Wl);
-    for (int cc = 0; cc < nchunks; ++cc) {
-        if (cc) __syncthreads();
+    EpiConsts<PREC, NB> ec;
+    if constexpr (MODE == CONV_PACK) {
+        // the network input is one chunk: the epilogue's constants are
+        // requested once the staged values are in LDS (their registers are
+        // free again) and the MFMAs hide their latency; the barrier waits for
+        // LDS only, not for these loads
         st.commit(As, Bs, L.in_qscale);
-        __syncthreads();
-        if (cc + 1 < nchunks) st.fetch(L, fd, s0, s1, cc + 1, Wl);
+        ec.load(L, g);
+        lds_sync();
         chunk_mfma<PREC, MODE, CK, TH, NB, SrcT>(As, Bs, acc);
+    } else {
+        for (int cc = 0; cc < nchunks; ++cc) {
+            if (cc) __syncthreads();
+            st.commit(As, Bs, L.in_qscale);
+            __syncthreads();
+            if (cc + 1 < nchunks) st.fetch(L, fd, s0, s1, cc + 1, Wl);
+            chunk_mfma<PREC, MODE, CK, TH, NB, SrcT>(As, Bs, acc);
+        }
+        ec.load(L, g);
     }
 
-    conv_epilogue<PREC, EPI, TH, NB, OutT>(L, fd, g, x0, y0, Hl, Wl, acc);
+    conv_epilogue<PREC, EPI, TH, NB, OutT>(L, fd, g, x0, y0, Hl, Wl, acc, ec);
 }
 
 // =============================================================================
@@ -895,7 +921,9 @@ __global__ __launch_bounds__(kThreads, direct_min_wg(NB)) void conv3x3_bf16_dire
         lds_barrier();   // the stage has been read before it is refilled
         if (cc + 1 < nchunks) issue(cc + 1, smem);
     }
-    conv_epilogue<1, EPI, TH, NB, OutT>(L, fd, g, x0, y0, Hl, Wl, acc);
+    EpiConsts<1, NB> ec;
+    ec.load(L, g);
+    conv_epilogue<1, EPI, TH, NB, OutT>(L, fd, g, x0, y0, Hl, Wl, acc, ec);
 }
 
 // =============================================================================
