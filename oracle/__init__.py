@@ -6,6 +6,10 @@ shares no code with the HIP path: the arithmetic lives in
 ``wskp_oracle.c`` (plain loops in double precision); this module only
 marshals NumPy arrays into it.
 
+Every step is pinned by the tests against something other than itself; the
+end-to-end output of ``denoise`` is parity unpinned against the paper (it
+prints no numeric example and no trained weights exist).
+
 Functions take and return NumPy arrays in NHWC layout without a batch axis
 unless stated.  Inputs may be float32; everything is widened to float64.
 """

@@ -13,6 +13,13 @@
  * float32 (the same arrays the GPU path reads) and are widened to double;
  * all arithmetic is double.
  *
+ * Pins: every step below is checked by the tests against something other
+ * than itself (closed forms, brute force, library routines, invariants,
+ * finite differences).  End-to-end values of the whole path (preprocess,
+ * U-Net, activation and decode composed) are parity unpinned against the
+ * paper, which prints no numeric example and whose trained weights do not
+ * exist here.
+ *
  * Layouts: images are NHWC without the batch axis, i.e. element (y, x, ch)
  * of an H x W x C image sits at ((y * W) + x) * C + ch.  Conv weights are
  * OIHW: w[co][ci][ky][kx], followed in the blob by b[co].
