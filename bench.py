@@ -385,6 +385,9 @@ def dataclasses_replace(r):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_720p.json")
+TRAFFIC_NOTE = ("not measured in this run: HBM bytes per launch from the committed rocprofv3 "
+                "FETCH_SIZE/WRITE_SIZE counters in profiles/traffic_720p.json, scaled by a plain "
+                "device copy; null when the kernel's source changed since they were taken")
 
 
 def source_sha(rel: str) -> str:
@@ -503,6 +506,9 @@ def main():
                     help="headline throughput: frames in flight on this many HIP streams")
     ap.add_argument("--inflight", type=int, default=3,
                     help="serve: batches in flight at once, one HIP stream each")
+    ap.add_argument("--latency-frames", type=int, default=300,
+                    help="single frames timed one at a time for p50/p99 (outside the timed "
+                         "throughput region, independent of --steps)")
     ap.add_argument("--height", type=int, default=720)
     ap.add_argument("--width", type=int, default=1280)
     args = ap.parse_args()
@@ -539,7 +545,7 @@ def main():
     for p in precs:
         log(f"[bench] timing {p} at {W}x{H}: warmup {args.warmup}, steps {args.steps}")
         res[p] = time_precision(cfg, blob, dev, H, W, p, args.steps, args.warmup,
-                                min(args.steps, 300), args.streams)
+                                args.latency_frames, args.streams)
         log(f"[bench] {p}: {res[p]['fps']:.1f} frames/s, {res[p]['ms_per_step']:.3f} ms/frame, "
             f"p50 {res[p]['p50_ms']:.3f} p99 {res[p]['p99_ms']:.3f} ms, "
             f"one stream {res[p]['single_stream_fps']:.1f} frames/s, "
@@ -556,12 +562,12 @@ def main():
         achieved = decode_bytes(cfg, H, W) / (pk[dom] * 1e-6)
         roof = {"kernel": dom, "bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK,
-                "traffic": measured_traffic(dom, head)}
+                "traffic": measured_traffic(dom, head), "traffic_source": TRAFFIC_NOTE}
     else:
         achieved = flops[dom] / (pk[dom] * 1e-6)
         roof = {"kernel": dom, "bound": "mfma", "achieved": achieved / 1e12,
                 "peak": PEAK[head] / 1e12, "unit": "TFLOP/s", "frac": achieved / PEAK[head],
-                "traffic": measured_traffic(dom, head)}
+                "traffic": measured_traffic(dom, head), "traffic_source": TRAFFIC_NOTE}
     dbytes = decode_bytes(cfg, H, W)
     dec_gbs = dbytes / (pk["decode"] * 1e-6)
     dcw = decode_cold_warm(cfg, blob, H, W)
@@ -569,7 +575,8 @@ def main():
         f"cold {dcw['cold_us']:.1f} us = {dcw['cold_GBps']:.0f} GB/s")
     decode_roof = {"kernel": "decode", "bound": "hbm", "achieved": dec_gbs / 1e9,
                    "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": dec_gbs / HBM_PEAK,
-                   "bytes_per_launch": dbytes, "traffic": measured_traffic("decode", head)}
+                   "bytes_per_launch": dbytes, "traffic": measured_traffic("decode", head),
+                   "traffic_source": TRAFFIC_NOTE}
     conv_mfma = {}
     for p in precs:
         tot = sum(flops.values())
@@ -608,7 +615,8 @@ def main():
         "single_stream": {"frames_per_s": res[head]["single_stream_fps"],
                           "ms_per_step": res[head]["single_stream_ms_per_step"]},
         "streams_bitwise_equal_single_stream": res[head]["streams_equal_single"],
-        "latency_ms": {"p50": res[head]["p50_ms"], "p99": res[head]["p99_ms"]},
+        "latency_ms": {"p50": res[head]["p50_ms"], "p99": res[head]["p99_ms"],
+                       "samples": args.latency_frames},
         "per_kernel_us": res[head]["per_kernel_us"],
         "roofline": roof,
         "decode_roofline": decode_roof,

@@ -28,6 +28,7 @@ class Request:
     t_arrival: float
     H: int
     W: int
+    seq: int = 0                 # index of the frame within its stream
     t_start: float = float("nan")
     t_done: float = float("nan")
     error: Optional[str] = None
@@ -45,9 +46,9 @@ def poisson_trace(n_streams: int, frames_per_stream: int, rate_total: float,
     for s in range(n_streams):
         t = np.cumsum(rng.exponential(1.0 / per, size=frames_per_stream))
         for k in range(frames_per_stream):
-            reqs.append((float(t[k]), s))
+            reqs.append((float(t[k]), s, k))
     reqs.sort()
-    out = [Request(i, s, t, *sizes[s]) for i, (t, s) in enumerate(reqs)]
+    out = [Request(i, s, t, *sizes[s], seq=k) for i, (t, s, k) in enumerate(reqs)]
     return sizes, out
 
 
@@ -88,7 +89,12 @@ class Executor:
     most the sum of its requests' values (``workspace_bytes(batch)``), so the
     scheduler can account memory per request without re-sizing whole
     batches.
+
+    ``per_stream_cap``: at most this many frames of one stream may be in
+    flight at once (None: no limit), e.g. the size of a stream's output ring.
     """
+
+    per_stream_cap: Optional[int] = None
 
     def workspace_bytes(self, reqs: List[Request]) -> int:
         raise NotImplementedError
@@ -125,6 +131,9 @@ class Server:
 
     budget_bytes bounds the workspace of all in-flight batches together; a
     single request larger than the budget is rejected (error "budget").
+    Frames of one stream start in arrival order, and no more than the
+    executor's ``per_stream_cap`` of them are in flight together; a stream
+    at its cap waits while other streams' requests pass.
     """
 
     def __init__(self, executor: Executor, budget_bytes: int, max_inflight: int = 2,
@@ -143,6 +152,9 @@ class Server:
         nxt = 0
         slot = 0
         batches = []
+        cap = self.ex.per_stream_cap
+        live: Dict[int, int] = {}            # frames in flight per stream
+        self.max_stream_inflight = 0
         t0 = self.clock()
         now = lambda: self.clock() - t0
         while nxt < len(reqs) or pending or inflight:
@@ -164,6 +176,7 @@ class Server:
                     td = now()
                     for r in b:
                         r.t_done = td
+                        live[r.stream] -= 1
                     arena.free(off)
                 else:
                     still.append((tok, b, off))
@@ -173,20 +186,29 @@ class Server:
             if pending and len(inflight) < self.max_inflight:
                 free = self.budget - arena.used
                 batch, rest, need = [], [], 0
+                taken: Dict[int, int] = {}       # frames of each stream in this batch
+                blocked = set()                  # streams whose next frame waits
                 for i, r in enumerate(pending):
                     if len(batch) == self.max_batch:
                         rest.extend(pending[i:])
                         break
+                    n_s = live.get(r.stream, 0) + taken.get(r.stream, 0)
+                    if r.stream in blocked or (cap is not None and n_s >= cap):
+                        blocked.add(r.stream)    # keeps the stream's frames in order
+                        rest.append(r)
+                        continue
                     rb = self.ex.request_bytes(r)
                     if need + rb <= free:
                         batch.append(r)
+                        taken[r.stream] = taken.get(r.stream, 0) + 1
                         need += rb
                     else:
+                        blocked.add(r.stream)
                         rest.append(r)
                 pending = rest
                 off = arena.alloc(need) if batch else None
                 if batch and off is None:       # fragmented: retry after a completion
-                    pending = batch + pending
+                    pending = sorted(batch + pending, key=lambda r: (r.t_arrival, r.rid))
                     batch = []
                 if batch:
                     ts = now()
@@ -201,6 +223,8 @@ class Server:
                     slot = (slot + 1) % self.max_inflight
                     for r in batch:
                         r.t_start = ts
+                        live[r.stream] = live.get(r.stream, 0) + 1
+                        self.max_stream_inflight = max(self.max_stream_inflight, live[r.stream])
                     inflight.append((tok, batch, off))
                     batches.append(len(batch))
             if realtime and not pending and not inflight and nxt < len(reqs):
@@ -249,28 +273,31 @@ class GpuExecutor(Executor):
     ``graph``, each batch replays the graph of its stream and capacity
     bucket).
 
-    Every stream of the trace owns resident device buffers: its input frame
-    and an output ring of ``ring`` frames (default slots + 1, so that
-    consecutive frames of a stream in flight together, one per batch, write
-    different slots).  One workspace of
-    ``ws_bytes`` (the admission budget) is shared by the in-flight batches;
-    the server hands each batch a disjoint range of it.
+    Every stream of the trace owns resident device buffers: its input frames
+    (one frame, or a list that frame ``seq`` of the stream reads at index
+    seq % len) and an output ring of ``ring`` frames (default slots + 1):
+    frame ``seq`` writes ring slot seq % ring, and at most ``ring`` frames of
+    a stream are in flight at once (``per_stream_cap``), so no two frames in
+    flight share an output.  One workspace of ``ws_bytes`` (the admission
+    budget) is shared by the in-flight batches; the server hands each batch a
+    disjoint range of it.
     """
 
-    def __init__(self, denoiser, stream_inputs: Dict[int, Dict[str, "object"]], ws_bytes: int,
+    def __init__(self, denoiser, stream_inputs: Dict[int, "object"], ws_bytes: int,
                  slots: int = 2, ring: Optional[int] = None, graph: bool = False):
         import torch
         from . import wskp
         self.torch = torch
         self.wskp = wskp
         self.dn = denoiser
-        self.inputs = stream_inputs
+        self.inputs = {s: (f if isinstance(f, (list, tuple)) else [f])
+                       for s, f in stream_inputs.items()}
         ring = slots + 1 if ring is None else ring
+        self.per_stream_cap = ring
         # graph replay: one HIP graph per stream and capacity bucket
         self.flags = wskp.BATCH_GRAPH if graph else 0
-        self.outputs = {s: [torch.empty_like(f["radiance"]) for _ in range(ring)]
-                        for s, f in stream_inputs.items()}
-        self.count = {s: 0 for s in stream_inputs}
+        self.outputs = {s: [torch.empty_like(f[0]["radiance"]) for _ in range(ring)]
+                        for s, f in self.inputs.items()}
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
         self._one: Dict[Tuple[int, int], int] = {}
@@ -288,13 +315,16 @@ class GpuExecutor(Executor):
         ring = self.outputs[stream]
         return ring[k % len(ring)]
 
+    def input_of(self, stream: int, k: int):
+        ins = self.inputs[stream]
+        return ins[k % len(ins)]
+
     def launch(self, reqs: List[Request], slot: int, ws_offset: int = 0):
         s = self.streams[slot]
         frames = []
         for r in reqs:
-            f = dict(self.inputs[r.stream])
-            f["out"] = self.output_of(r.stream, self.count[r.stream])
-            self.count[r.stream] += 1
+            f = {k: v for k, v in self.input_of(r.stream, r.seq).items() if k != "clean"}
+            f["out"] = self.output_of(r.stream, r.seq)
             frames.append(f)
         need = self.workspace_bytes(reqs)
         self.wskp.wskp_denoise_batch(self.dn.h, frames, self.ws[ws_offset:ws_offset + need],

@@ -28,6 +28,10 @@ BATCH_REVERSE_TILES = 1
 BATCH_GRAPH = 2
 
 _lib = None
+# number of kernel sizes M of each live handle (by handle value): the C
+# entry points that take a head record have no channel argument, so the
+# binding checks head tensors against the handle's 2M channels itself
+_handle_M: Dict[int, int] = {}
 
 
 class WskpError(RuntimeError):
@@ -165,11 +169,24 @@ def wskp_create(cfg: NetConfig, weights: np.ndarray, precision: str = "fp32",
     _check(lib().wskp_create(ctypes.byref(c), w.ctypes.data, w.size,
                              None if sc is None else sc.ctypes.data, device, ctypes.byref(h)),
            "wskp_create")
+    _handle_M[h.value] = cfg.M
     return h
 
 
 def wskp_destroy(h) -> None:
     _check(lib().wskp_destroy(h), "wskp_destroy")
+    _handle_M.pop(getattr(h, "value", h), None)
+
+
+def _check_head(h, head, name: str = "head") -> None:
+    """head must be [N,H,W,2M] for the handle's M (the kernels index it with
+    that stride; a narrower tensor would be read or written out of bounds)."""
+    M = _handle_M.get(getattr(h, "value", h))
+    if M is None:
+        raise ValueError("unknown handle (not created by this binding, or destroyed)")
+    if head.dim() != 4 or head.shape[-1] != 2 * M:
+        raise ValueError(f"{name} has shape {tuple(head.shape)}; expected [N,H,W,{2 * M}] "
+                         f"for a handle with M = {M}")
 
 
 def wskp_workspace_size(h, Hs: Sequence[int], Ws: Sequence[int]) -> int:
@@ -223,6 +240,7 @@ def wskp_denoise_batch(h, frames: List[Dict[str, torch.Tensor]], ws, flags: int 
 
 
 def wskp_decode(h, head, c, mod, out, stream=None) -> None:
+    _check_head(h, head)
     N, H, W, twoM = head.shape
     _check(lib().wskp_decode(h, _stream(stream), N, H, W, _ptr(head, "head"),
                              _ptr(c, "c", (N, H, W, 3)),
@@ -238,6 +256,7 @@ def wskp_backward_workspace_size(h, N: int, H: int, W: int) -> int:
 
 
 def wskp_backward(h, head, c, mod, grad_out, grad_head, grad_c, ws, stream=None) -> None:
+    _check_head(h, head)
     N, H, W, twoM = head.shape
     _check(lib().wskp_backward(h, _stream(stream), N, H, W, _ptr(head, "head"),
                                _ptr(c, "c", (N, H, W, 3)), _ptr(mod, "mod", (N, H, W, 3)),

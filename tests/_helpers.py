@@ -22,5 +22,8 @@ def to_dev(frame, device="cuda"):
 
 # FP32 path vs the FP64 oracle: relative L2 and relative max-norm.
 TOL_FP32 = 1e-5
-# BF16 convolutions vs the FP64 oracle: relative L2.
+# BF16 convolutions vs the FP64 oracle: relative L2, and the relative max
+# norm ||y - y*||_inf / ||y*||_inf (a gate on single tiles gone wrong; the
+# measured value at 720p is about 5e-3).
 TOL_BF16 = 1e-2
+TOL_BF16_MAX = 2e-2

@@ -115,3 +115,25 @@ def test_host_e4m3_encoder_matches_library_cast():
     np.testing.assert_array_equal(got, ref)
     sat = wskp.wskp_fp8_e4m3_encode(np.array([500.0, -1e9, 449.0], np.float32))
     np.testing.assert_array_equal(sat, [0x7E, 0xFE, 0x7E])
+
+
+def test_binding_rejects_head_with_wrong_channel_count():
+    """wskp_decode / wskp_backward index the head record with the handle's
+    2M channels; the binding rejects any other channel count before it
+    reaches the library (checked here with a registered stand-in handle
+    value: the check runs before any device call)."""
+    import torch
+    wskp = _wskp()
+    fake = ctypes.c_void_p(0x1234)
+    wskp._handle_M[fake.value] = 5
+    try:
+        head = torch.zeros(1, 8, 8, 6)
+        c = torch.zeros(1, 8, 8, 3)
+        with pytest.raises(ValueError, match="expected"):
+            wskp.wskp_decode(fake, head, c, None, torch.zeros_like(c))
+        with pytest.raises(ValueError, match="expected"):
+            wskp.wskp_backward(fake, head, c, None, c, head, c, torch.zeros(16, dtype=torch.uint8))
+        with pytest.raises(ValueError, match="unknown handle"):
+            wskp.wskp_decode(ctypes.c_void_p(0x5678), torch.zeros(1, 8, 8, 10), c, None, c)
+    finally:
+        wskp._handle_M.pop(fake.value, None)

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from paper_2202_05977_amd import synth
-from _helpers import rel_l2, max_rel, to_dev, TOL_FP32, TOL_BF16
+from _helpers import rel_l2, max_rel, to_dev, TOL_FP32, TOL_BF16, TOL_BF16_MAX
 
 pytestmark = pytest.mark.gpu
 
@@ -71,6 +71,7 @@ def test_hd_bf16_720p_end_to_end():
     err = rel_l2(out, y)
     print(f"bf16 720p rel-L2 vs FP64 oracle: {err:.3e}, max-rel {max_rel(out, y):.3e}")
     assert err <= TOL_BF16
+    assert max_rel(out, y) <= TOL_BF16_MAX
 
 
 @pytest.mark.parametrize("shape", [(8, 16384), (16384, 8), (8, 8)])
@@ -88,6 +89,7 @@ def test_extreme_frame_shapes(shape, prec):
         assert max_rel(out, y) <= TOL_FP32
     else:
         assert rel_l2(out, y) <= TOL_BF16
+        assert max_rel(out, y) <= TOL_BF16_MAX
 
 
 def test_hd_bf16_layers_and_pooled_copies():
@@ -120,6 +122,7 @@ def test_small_bf16_ragged():
     fr, y, _ = _oracle("small", 1, 72, 104)
     out = _run(_denoiser(synth.SMALL, "bf16"), fr)
     assert rel_l2(out, y) <= TOL_BF16
+    assert max_rel(out, y) <= TOL_BF16_MAX
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
@@ -181,14 +184,27 @@ def test_graph_replay_matches_eager(prec):
         torch.cuda.synchronize()
 
 
+def _check_oracle(out, cfg, fr, prec, what):
+    """One frame's result against the FP64 oracle, at the gates of its
+    precision."""
+    y = oracle.denoise(fr, synth.make_weights(cfg, 0), cfg)
+    o = out.cpu().numpy() if hasattr(out, "cpu") else out
+    assert np.all(np.isfinite(o)), what
+    if prec == "fp32":
+        assert rel_l2(o, y) <= TOL_FP32 and max_rel(o, y) <= TOL_FP32, what
+    else:
+        assert rel_l2(o, y) <= TOL_BF16 and max_rel(o, y) <= TOL_BF16_MAX, what
+
+
 def test_batch_mixed_sizes_equals_single_frames():
     """Each frame alone == in a mixed-resolution batch == with tiles walked in
-    reverse (bitwise)."""
+    reverse (bitwise), and every batched frame against the FP64 oracle."""
     from paper_2202_05977_amd import wskp
     cfg = synth.SMALL
     dn = _denoiser(cfg, "fp32")
     sizes = [(64, 64), (128, 96), (32, 160), (72, 104)]
-    frames = [to_dev(synth.make_frame(10 + i, H, W)) for i, (H, W) in enumerate(sizes)]
+    host = [synth.make_frame(10 + i, H, W) for i, (H, W) in enumerate(sizes)]
+    frames = [to_dev(f) for f in host]
     singles = []
     for f in frames:
         singles.append(dn(f).clone())
@@ -199,6 +215,28 @@ def test_batch_mixed_sizes_equals_single_frames():
         torch.cuda.synchronize()
         for f, s in zip(frames, singles):
             assert torch.equal(f["out"], s)
+    for i, f in enumerate(frames):
+        _check_oracle(f["out"], cfg, host[i], "fp32", f"frame {i} {sizes[i]}")
+
+
+def test_batch_hd_bf16_with_360p_frame_against_oracle():
+    """A mixed bf16 batch of the hd net that holds a 640x360 frame (the
+    smallest serving resolution) beside smaller ones: each batched frame
+    equals the frame alone bitwise and meets the BF16 gates against the FP64
+    oracle."""
+    cfg = synth.HD
+    dn = _denoiser(cfg, "bf16")
+    sizes = [(360, 640), (64, 96), (128, 160), (8, 8)]
+    host = [synth.make_frame(20 + i, H, W) for i, (H, W) in enumerate(sizes)]
+    frames = [to_dev(f) for f in host]
+    singles = [dn(f).clone() for f in frames]
+    for f in frames:
+        f["out"] = torch.full_like(f["radiance"], float("nan"))
+    dn.batch(frames)
+    torch.cuda.synchronize()
+    for i, (f, s) in enumerate(zip(frames, singles)):
+        assert torch.equal(f["out"], s), i
+        _check_oracle(f["out"], cfg, host[i], "bf16", f"frame {i} {sizes[i]}")
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
@@ -211,9 +249,11 @@ def test_batch_graph_replay_equals_single_frames(prec):
     cfg = synth.SMALL
     dn = _denoiser(cfg, prec)
     sizes = [(64, 64), (128, 96), (32, 160), (72, 104), (16, 16), (128, 160)]
-    frames = [to_dev(synth.make_frame(40 + i, H, W)) for i, (H, W) in enumerate(sizes)]
+    host = [synth.make_frame(40 + i, H, W) for i, (H, W) in enumerate(sizes)]
+    frames = [to_dev(f) for f in host]
     singles = [dn(f).clone() for f in frames]
     batches = [[0, 1, 2, 3], [3, 2, 1, 0], [0, 1, 2], [5], [4, 5, 0], [0, 1, 2, 3], [4]]
+    checked = set()
     streams = [torch.cuda.Stream(), torch.cuda.Stream()]
     wss = [torch.empty(wskp.wskp_workspace_size(dn.h, [H for H, _ in sizes], [W for _, W in sizes]),
                        dtype=torch.uint8, device="cuda") for _ in streams]
@@ -228,6 +268,9 @@ def test_batch_graph_replay_equals_single_frames(prec):
             torch.cuda.synchronize()
             for i, f in zip(b, fb):
                 assert torch.equal(f["out"], singles[i]), (rep, j, i)
+                if i not in checked:
+                    _check_oracle(f["out"], cfg, host[i], prec, f"replayed frame {i}")
+                    checked.add(i)
             dn(frames[(j + 1) % len(frames)])          # eager work between replays
 
 
@@ -263,25 +306,32 @@ def test_shape_errors():
 @pytest.mark.parametrize("graph", [False, True])
 def test_served_results_equal_single_frames(graph):
     """Frames pushed through the continuous-batching server (mixed sizes,
-    two streams in flight, shared workspace arena; direct launches or graph
-    replay) equal the same frames denoised alone, bitwise."""
+    two batches in flight, shared workspace arena; direct launches or graph
+    replay).  Every request has its own input (a frame seed per request) and
+    its own output slot; each served result equals that input denoised alone
+    (bitwise) and meets the BF16 gates against the FP64 oracle."""
     from paper_2202_05977_amd import serve, wskp
     cfg = synth.SMALL
     dn = _denoiser(cfg, "bf16")
     res = [(64, 64), (128, 96), (32, 160), (72, 104)]
-    sizes, reqs = serve.poisson_trace(8, 6, 4000.0, res, seed=5)
-    inputs = {s: {k: v for k, v in to_dev(synth.make_frame(300 + s, *sizes[s])).items()
-                  if k != "clean"} for s in range(8)}
+    nf = 6
+    sizes, reqs = serve.poisson_trace(8, nf, 4000.0, res, seed=5)
+    host = {s: [synth.make_frame(300 + 10 * s + k, *sizes[s]) for k in range(nf)]
+            for s in range(8)}
+    inputs = {s: [to_dev(f) for f in host[s]] for s in range(8)}
     budget = 4 * wskp.wskp_workspace_size(dn.h, [128] * 3, [160] * 3)
-    ex = serve.GpuExecutor(dn, inputs, budget, slots=2, ring=2, graph=graph)
-    st = serve.Server(ex, budget, max_inflight=2, max_batch=5).run(reqs, realtime=False)
+    ex = serve.GpuExecutor(dn, inputs, budget, slots=2, ring=nf, graph=graph)
+    srv = serve.Server(ex, budget, max_inflight=2, max_batch=5)
+    st = srv.run(reqs, realtime=False)
     torch.cuda.synchronize()
     assert st.errors == 0 and st.frames == len(reqs) and st.max_batch > 1
-    for s in range(8):
-        alone = dn(inputs[s]).clone()
+    assert srv.max_stream_inflight <= nf
+    for r in reqs:
+        alone = dn(inputs[r.stream][r.seq]).clone()
         torch.cuda.synchronize()
-        for k in range(2):
-            assert torch.equal(ex.output_of(s, k), alone), (s, k)
+        got = ex.output_of(r.stream, r.seq)
+        assert torch.equal(got, alone), (r.stream, r.seq)
+        _check_oracle(got, cfg, host[r.stream][r.seq], "bf16", f"stream {r.stream} frame {r.seq}")
 
 
 def test_hd_fp8_720p_reported_error():
@@ -314,6 +364,7 @@ def test_hd_1080p_every_precision_against_oracle():
     assert rel_l2(out, y) <= TOL_FP32 and max_rel(out, y) <= TOL_FP32
     out = _run(wskp.Denoiser(cfg, blob, "bf16"), fr)
     assert rel_l2(out, y) <= TOL_BF16
+    assert max_rel(out, y) <= TOL_BF16_MAX
     scales = wskp.calibrate_fp8_scales(cfg, blob, to_dev(synth.make_frame(999, 1080, 1920)))
     out = _run(wskp.Denoiser(cfg, blob, "fp8", act_scales=scales), fr)
     err = rel_l2(out, y)
@@ -328,6 +379,7 @@ def test_hd_1440p_bf16_against_oracle():
     out = _run(_denoiser(synth.HD, "bf16"), fr)
     assert np.all(np.isfinite(out))
     assert rel_l2(out, y) <= TOL_BF16
+    assert max_rel(out, y) <= TOL_BF16_MAX
 
 
 def test_fp8_needs_scales_and_32_wide_levels():

@@ -161,3 +161,40 @@ def test_arena_first_fit():
     a.free(o1)
     assert a.alloc(256) == 0
     assert a.used == 512
+
+
+def test_per_stream_cap_bounds_frames_in_flight(virtual_sleep):
+    """With a per-stream cap (the size of a stream's output ring), no stream
+    ever has more frames in flight than the cap, even when one batch could
+    take many of its frames, and each stream's frames still start in order."""
+    clock = VClock()
+    virtual_sleep["clock"] = clock
+    _, reqs = trace(n_streams=4, frames=30, rate=20000.0)   # heavily overloaded
+    ex = FakeExecutor(clock, per_px=2e-8)
+    ex.per_stream_cap = 2
+    srv = serve.Server(ex, 1 << 40, max_inflight=3, max_batch=64, clock=clock)
+    st = srv.run(reqs)
+    assert st.frames == len(reqs) and st.errors == 0
+    assert srv.max_stream_inflight <= 2
+    # over the whole run: at any launch, a stream's frames launched but not
+    # done never exceed the cap
+    for s in range(4):
+        mine = sorted((r for r in reqs if r.stream == s), key=lambda r: r.seq)
+        starts = [r.t_start for r in mine]
+        assert starts == sorted(starts)
+        for r in mine:
+            overlapping = [q for q in mine if q.t_start <= r.t_start < q.t_done]
+            assert len(overlapping) <= 2
+    # without the cap the same load puts more frames of a stream in flight
+    _, reqs2 = trace(n_streams=4, frames=30, rate=20000.0)
+    srv2 = serve.Server(FakeExecutor(clock, per_px=2e-8), 1 << 40, max_inflight=3, max_batch=64,
+                        clock=clock)
+    srv2.run(reqs2)
+    assert srv2.max_stream_inflight > 2
+
+
+def test_trace_frame_index_per_stream():
+    sizes, reqs = serve.poisson_trace(8, 12, 500.0, ((36, 64),), seed=1)
+    for s in range(8):
+        seqs = [r.seq for r in sorted((r for r in reqs if r.stream == s), key=lambda r: r.t_arrival)]
+        assert seqs == list(range(12))
