@@ -154,6 +154,29 @@ wskp_status_t wskp_denoise(wskp_handle_t h, void *stream, int H, int W, const fl
                            const float *albedo, const float *normal, const float *depth,
                            float *out, void *ws, size_t ws_bytes);
 
+/* Size of the device-resident scratch that wskp_denoise_static uses (each
+ * device holds one, until the process ends). */
+#define WSKP_STATIC_SCRATCH_BYTES (256ull << 20)
+
+/* wskp_denoise without a workspace argument, for callers that cannot
+ * allocate device memory (code under graph capture, serving loops that
+ * forbid allocation): the intermediate maps and the head record live in a
+ * scratch array of WSKP_STATIC_SCRATCH_BYTES in device memory that the
+ * library holds for each device (its address is looked up by wskp_create).
+ * Same arguments, result and layout rules as wskp_denoise; it allocates
+ * nothing.  A frame whose workspace (wskp_workspace_size(h, 1, &H, &W))
+ * exceeds the scratch returns WSKP_E_BUDGET (e.g. 1280x720 fits with bf16
+ * or FP8 convolutions, not with FP32).  Every call on one device shares
+ * that device's scratch: calls that overlap in time on one device (other
+ * streams, other handles, other host threads) race and give undefined
+ * results; the caller must order them (e.g. one stream). */
+wskp_status_t wskp_denoise_static(wskp_handle_t h, void *stream, int H, int W,
+                                  const float *radiance, const float *albedo, const float *normal,
+                                  const float *depth, float *out);
+
+/* WSKP_STATIC_SCRATCH_BYTES, as built into the library. */
+size_t wskp_static_scratch_bytes(void);
+
 #define WSKP_BATCH_REVERSE_TILES 1u /* walk tiles in reverse order (result must not change) */
 #define WSKP_BATCH_GRAPH 2u         /* replay one HIP graph per stream and capacity bucket */
 

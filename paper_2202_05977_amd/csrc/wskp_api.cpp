@@ -128,6 +128,19 @@ struct wskp_ctx {
     int t_max_calls = 0, t_calls = 0;
 };
 
+// ---------------------------------------------------------------------------
+// Device-resident scratch of wskp_denoise_static: the workspace of one frame
+// for callers that cannot allocate.  Each device the library runs on holds
+// its own copy until the process ends.  Host code never passes the array's
+// name to a kernel or a copy (on the host it is only a stand-in): it uses
+// the device address that hipGetSymbolAddress returns, looked up once per
+// device in wskp_create with that device current.
+static constexpr size_t kStaticScratchBytes = WSKP_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
 static constexpr int kRingSlots = 8;
 static constexpr int kMaxBatch = 1024;
 static constexpr size_t kTableHeader = 256;   // frame count, tile count of each launch; padded
@@ -273,6 +286,16 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(WSKP_E_DEVICE, std::string("device is ") + prop.gcnArchName + ", need gfx950");
     if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (device >= kMaxDevices) return fail(WSKP_E_DEVICE, "device index beyond the library's table");
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_ptr[device]) {
+            void *p = nullptr;
+            if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess || !p)
+                return hip_fail(e, "hipGetSymbolAddress(static scratch)");
+            g_scratch_ptr[device] = p;
+        }
+    }
 
     wskp_ctx *h = new wskp_ctx();
     h->cfg = *cfg;
@@ -639,6 +662,40 @@ extern "C" wskp_status_t wskp_denoise(wskp_handle_t h, void *stream, int H, int 
     if (ws_bytes < need)
         return fail(WSKP_E_BUDGET, "workspace too small: need " + std::to_string(need) + " bytes");
     if ((st = set_device(h)) != WSKP_OK) return st;
+    wskp_frame_t f{H, W, radiance, albedo, normal, depth, out};
+    FrameArg fa{};
+    fa.table = nullptr;
+    fa.n = 1;
+    fa.reverse = 0;
+    fill_frame(h, fa.one, static_cast<char *>(ws) + table_bytes(1), f);
+    return run_frames(h, fa, 1, &H, &W, static_cast<hipStream_t>(stream));
+}
+
+extern "C" size_t wskp_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
+extern "C" wskp_status_t wskp_denoise_static(wskp_handle_t h, void *stream, int H, int W,
+                                             const float *radiance, const float *albedo,
+                                             const float *normal, const float *depth, float *out)
+{
+    if (!h) return fail(WSKP_E_INVALID_ARG, "handle is NULL");
+    if (!radiance || !albedo || !normal || !depth || !out)
+        return fail(WSKP_E_INVALID_ARG, "NULL tensor pointer");
+    wskp_status_t st = check_frame_size(h, H, W);
+    if (st != WSKP_OK) return st;
+    const size_t need = table_bytes(1) + frame_bytes(h, H, W, nullptr, nullptr, nullptr);
+    if (need > kStaticScratchBytes)
+        return fail(WSKP_E_BUDGET, "frame needs " + std::to_string(need) +
+                                       " bytes of workspace; the static scratch holds " +
+                                       std::to_string(kStaticScratchBytes));
+    if ((st = set_device(h)) != WSKP_OK) return st;
+    void *ws;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        ws = g_scratch_ptr[h->device];
+    }
+    if (!ws) return fail(WSKP_E_INTERNAL, "static scratch address not set up");
+    // every intermediate map is written in full before it is read: nothing
+    // in the scratch needs clearing
     wskp_frame_t f{H, W, radiance, albedo, normal, depth, out};
     FrameArg fa{};
     fa.table = nullptr;

@@ -82,6 +82,9 @@ def lib():
         L.wskp_destroy.argtypes = [vp]
         L.wskp_workspace_size.argtypes = [vp, i32, ip, ip, ctypes.POINTER(sz)]
         L.wskp_denoise.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, sz]
+        L.wskp_denoise_static.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp]
+        L.wskp_static_scratch_bytes.argtypes = []
+        L.wskp_static_scratch_bytes.restype = sz
         L.wskp_denoise_batch.argtypes = [vp, vp, i32, ctypes.POINTER(wskp_frame_t),
                                          ctypes.c_uint32, vp, sz]
         L.wskp_decode.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp]
@@ -100,7 +103,7 @@ def lib():
         L.wskp_last_error.argtypes = []
         L.wskp_last_error.restype = ctypes.c_char_p
         for name in ("wskp_create", "wskp_destroy", "wskp_workspace_size", "wskp_denoise",
-                     "wskp_denoise_batch", "wskp_decode", "wskp_backward",
+                     "wskp_denoise_static", "wskp_denoise_batch", "wskp_decode", "wskp_backward",
                      "wskp_backward_workspace_size", "wskp_workspace_tensor",
                      "wskp_timing_enable", "wskp_timing_read"):
             getattr(L, name).restype = ctypes.c_int
@@ -220,6 +223,20 @@ def wskp_denoise(h, radiance, albedo, normal, depth, out, ws, stream=None) -> No
                               _ptr(out, "out", (H, W, 3)),
                               ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size()),
            "wskp_denoise")
+
+
+def wskp_denoise_static(h, radiance, albedo, normal, depth, out, stream=None) -> None:
+    H, W = radiance.shape[:2]
+    _check(lib().wskp_denoise_static(h, _stream(stream), H, W,
+                                     _ptr(radiance, "radiance", (H, W, 3)),
+                                     _ptr(albedo, "albedo", (H, W, 3)),
+                                     _ptr(normal, "normal", (H, W, 3)),
+                                     _ptr(depth, "depth", (H, W, 1)),
+                                     _ptr(out, "out", (H, W, 3))), "wskp_denoise_static")
+
+
+def wskp_static_scratch_bytes() -> int:
+    return int(lib().wskp_static_scratch_bytes())
 
 
 def wskp_denoise_batch(h, frames: List[Dict[str, torch.Tensor]], ws, flags: int = 0,
