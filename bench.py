@@ -379,6 +379,84 @@ def mode_serve(args):
     dn.close()
 
 
+def mode_kernels(args):
+    """Reconstruction time against the number of fused kernel sizes (the time
+    halves of the paper's kernel-count figures, Sec. 6 and Sec. 7.1) and the
+    explicit kernel-map comparison of Sec. 5.3, at 1280x720: for M = 1..6
+    sizes k = 3, 5, ..., 2M+1 (and a single k = 9) with exp weights, the
+    decode's time inside the bf16 frame path; then, for the paper's six
+    sizes, the weight-sharing decode against a reconstruction that reads
+    every pixel's explicit k x k kernels (same inputs, same result)."""
+    import dataclasses
+    import torch
+    from paper_2202_05977_amd import synth, wskp
+    H, W = args.height, args.width
+    fr = {k: torch.from_numpy(v).cuda() for k, v in synth.make_frame(1, H, W).items()}
+    out = torch.empty((H, W, 3), dtype=torch.float32, device="cuda")
+    sets = [(9,)] + [tuple(range(3, 2 * m + 2, 2)) for m in range(1, 7)]
+    sweep = []
+    for ks in sets:
+        cfg = dataclasses.replace(synth.HD, kernel_sizes=ks, weight_act="exp")
+        dn = wskp.Denoiser(cfg, synth.make_weights(cfg, 0), "bf16")
+        for _ in range(args.warmup):
+            dn(fr, out)
+        torch.cuda.synchronize()
+        n = max(1, min(args.steps, 100))
+        wskp.wskp_timing_enable(dn.h, n)
+        for _ in range(n):
+            dn(fr, out)
+        ms, nc = wskp.wskp_timing_read(dn.h)
+        wskp.wskp_timing_enable(dn.h, 0)
+        dec = 1e3 * ms["decode"] / nc
+        net = 1e3 * sum(v for k, v in ms.items() if k != "decode") / nc
+        bytes_ = H * W * (8 * len(ks) + 36)
+        sweep.append({"kernel_sizes": list(ks), "M": len(ks), "decode_us": dec, "net_us": net,
+                      "decode_GBps": bytes_ / dec / 1e3})
+        log(f"[kernels] k={ks}: decode {dec:.1f} us ({bytes_ / dec / 1e3:.0f} GB/s), net {net:.1f} us")
+        dn.close()
+    # explicit kernel maps vs weight sharing, the paper's six sizes
+    ks = (3, 5, 7, 9, 11, 13)
+    cfg = dataclasses.replace(synth.HD, kernel_sizes=ks)
+    dn = wskp.Denoiser(cfg, synth.make_weights(cfg, 0), "fp32")
+    M = len(ks)
+    head = torch.from_numpy(synth.make_head(5, 1, H, W, M)).cuda()
+    c = torch.rand(1, H, W, 3, generator=torch.Generator().manual_seed(6)).cuda()
+    mod = torch.rand(1, H, W, 3, generator=torch.Generator().manual_seed(7)).cuda() + 0.1
+    y_ws, y_kp = torch.empty_like(c), torch.empty_like(c)
+    nb = wskp.wskp_kp_map_bytes(dn.h, H, W)
+    maps = torch.empty(nb // 4, dtype=torch.float32, device="cuda")
+    wskp.wskp_kp_expand(dn.h, head, maps)
+    s = torch.cuda.current_stream()
+
+    def timed(fn, reps=20):
+        ts = []
+        fn()
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            fn()
+            e1.record(s)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e3)
+        return float(np.median(ts))
+
+    t_ws = timed(lambda: wskp.wskp_decode(dn.h, head, c, mod, y_ws))
+    t_kp = timed(lambda: wskp.wskp_kp_decode(dn.h, maps, head, c, mod, y_kp))
+    torch.cuda.synchronize()
+    diff = float((y_ws - y_kp).norm() / y_ws.norm())
+    ws_in = H * W * (8 * M + 24)            # head 2M floats + c + mod
+    kp_in = nb + H * W * (4 * M + 24)       # maps + logits + c + mod
+    comp = {"kernel_sizes": list(ks), "weight_sharing_us": t_ws, "explicit_maps_us": t_kp,
+            "speedup": t_kp / t_ws, "weight_sharing_input_bytes": ws_in,
+            "explicit_input_bytes": kp_in, "memory_ratio": kp_in / ws_in,
+            "rel_l2_between_forms": diff}
+    log(f"[kernels] explicit maps {t_kp:.1f} us ({kp_in / 1e9:.2f} GB of input) vs weight sharing "
+        f"{t_ws:.1f} us ({ws_in / 1e6:.1f} MB): {t_kp / t_ws:.1f}x; rel-L2 between them {diff:.1e}")
+    dn.close()
+    print(json.dumps({"mode": "kernels", "workload": f"{W}x{H}, hd net, bf16 convs, exp weights",
+                      "sweep": sweep, "explicit_kernel_maps": comp}), flush=True)
+
+
 def dataclasses_replace(r):
     import dataclasses
     return dataclasses.replace(r)
@@ -495,9 +573,11 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes 5 times (reference "
                          "kernel for scaling HBM traffic counters) and exit")
-    ap.add_argument("--mode", default="headline", choices=["headline", "sweep", "train", "serve"],
+    ap.add_argument("--mode", default="headline",
+                    choices=["headline", "sweep", "train", "serve", "kernels"],
                     help="headline: the 720p JSON line; sweep: 1080p precisions vs oracle; "
-                         "train: decode adjoint on 8x256^2 crops; serve: 64-stream trace")
+                         "train: decode adjoint on 8x256^2 crops; serve: 64-stream trace; "
+                         "kernels: decode time vs number of kernel sizes, explicit kernel maps")
     ap.add_argument("--serve-frames", type=int, default=300)
     ap.add_argument("--fifo-frames", type=int, default=2000)
     ap.add_argument("--max-batch", type=int, default=64,
@@ -531,7 +611,8 @@ def main():
         return
 
     if args.mode != "headline":
-        {"sweep": mode_sweep, "train": mode_train, "serve": mode_serve}[args.mode](args)
+        {"sweep": mode_sweep, "train": mode_train, "serve": mode_serve,
+         "kernels": mode_kernels}[args.mode](args)
         return
 
     H, W = args.height, args.width

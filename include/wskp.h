@@ -222,6 +222,29 @@ wskp_status_t wskp_backward(wskp_handle_t h, void *stream, int N, int H, int W, 
  * (16 * M bytes per pixel: per-centre adjoint terms of every kernel size). */
 wskp_status_t wskp_backward_workspace_size(wskp_handle_t h, int N, int H, int W, size_t *bytes);
 
+/* Explicit kernel-map reconstruction, the baseline of the memory and time
+ * comparison in Sec. 5.3 (a kernel-prediction network without weight
+ * sharing predicts every pixel's full k_i x k_i kernel).  Not part of the
+ * denoising path; for benchmarks and checks.
+ * wskp_kp_map_bytes: size of the maps for one H x W frame:
+ *   4 * H * W * sum_i k_i^2 bytes (1280 x 720 with k = 3..13: 1.67 GB).
+ * wskp_kp_expand: fills the maps from a head record [1,H,W,2M] in the
+ *   layout of wskp_decode: the weight of neighbour q in the kernel of
+ *   centre p is W_i(q), 0 outside the image; planar per size and tap,
+ *   maps[i][t][H][W] with t = (dy + r_i) k_i + (dx + r_i).
+ * wskp_kp_decode: Eq. 4-5 and the remodulation from explicit maps: for each
+ *   centre and size, the map-weighted sum of c over the window divided by
+ *   max(sum of the weights, eps_norm), softmax-blended with the head's
+ *   logits, times mod (NULL = 1).  With maps from wskp_kp_expand the result
+ *   equals wskp_decode's up to rounding.  All pointers are device pointers,
+ *   H x W at most 2^26 pixels. */
+wskp_status_t wskp_kp_map_bytes(wskp_handle_t h, int H, int W, size_t *bytes);
+wskp_status_t wskp_kp_expand(wskp_handle_t h, void *stream, int H, int W, const float *head, float *maps,
+                             size_t map_bytes);
+wskp_status_t wskp_kp_decode(wskp_handle_t h, void *stream, int H, int W, const float *maps,
+                             size_t map_bytes, const float *head, const float *c, const float *mod,
+                             float *out);
+
 /* Location of an intermediate tensor of frame `frame` inside the workspace
  * of the last-planned batch layout for frames of sizes H[i] x W[i]: which =
  * 0..L-1 for encoder output e_l, 100 + l for decoder output u_l (shape

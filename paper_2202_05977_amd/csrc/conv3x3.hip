@@ -132,10 +132,9 @@ template <int EPI>
 __device__ __forceinline__ float epilogue(float v, int co, int M)
 {
     if (EPI == EPI_RELU) return fmaxf(v, 0.f);
-    if (co < M) {
-        if (EPI == EPI_HEAD_EXP) return expf(v);
-        return softplus_f(v);
-    }
+    // exp weights: the raw pre-activation is stored; the decode takes the
+    // exponential with a per-tile shift (no overflow for any finite h)
+    if (co < M && EPI == EPI_HEAD_SOFTPLUS) return softplus_f(v);
     return v;
 }
 

@@ -1,28 +1,24 @@
 // Weight-sharing kernel construction + filtering + fusion + remodulation
-// (Sec. 4.2; Eq. 3, Eq. 4, Eq. 5) in one memory-bound pass.
+// (Sec. 4.2; Eq. 3, Eq. 4, Eq. 5) in one memory-bound pass, and its adjoint.
 //
 // The normalised kernel weight of Eq. 3 depends on the neighbour only
 // through its own scalar W_i(q) and on the centre only through the window
 // sum, so every filtered value is a ratio of two box sums:
 //     out_i(p) = sum_{q in Omega_i(p)} W_i(q) c(q) / max(sum_{q in Omega_i(p)} W_i(q), eps)
-// with windows truncated at the image border.  No k x k kernel map is ever
-// formed.  Each workgroup owns a 32 x kDTY tile of centres.  Every thread
-// keeps the irradiance of its share of the (32+2R) x (kDTY+2R) halo (R =
-// largest radius) in registers and fetches each weight map one size ahead.
-// For each kernel size, each thread writes the plane (W_i, W_i c) of its
-// halo pixels to LDS, a horizontal pass
-// forms row sums into LDS and a vertical pass sums those, each thread
-// summing a run of neighbouring outputs in registers, and softmax(logits)_i
-// * out_i accumulates in registers: two barriers per size.  The last step
-// multiplies by the remodulation factor.
+// with windows truncated at the border.  No k x k kernel map is ever formed.
 //
+// Forward (decode_tile_kernel): a workgroup of 512 threads owns a tile of
+// 40 x 45 centres (1280 x 720: 512 tiles, two per CU), keeps the irradiance
+// of its halo in registers, and for each kernel size sums the plane
+// (W_i, W_i c) in LDS down the columns, then along the rows; see the kernel.
 // Two input forms:
 //   frames   c = r / (a + eps_a) is formed while staging; mod = a + eps_a;
-//            head, r, a and out come from the frame descriptors
-//            (decode_fwd_kernel, one tile per workgroup)
-//   tensors  head, c, mod (optional) and out are plain [N,H,W,*] tensors
-//            (decode_stream_kernel, persistent; decode_fwd_kernel for the
-//            first half of the adjoint)
+//            head (planar [2M][H][W]), r, a and out come from the frame
+//            descriptors of a batch
+//   tensors  head [N,H,W,2M], c, mod (optional) and out are plain tensors
+// Adjoint: decode_fwd_kernel<DK_ADJ_A> (32 x 16 tiles; the forward window
+// sums plus the per-centre adjoint terms) and decode_adj_b_kernel (the same
+// box sums of those terms).
 #include "wskp_internal.h"
 
 namespace wskp {
@@ -149,8 +145,9 @@ __device__ __forceinline__ float4 f4add(float4 a, float4 b)
 template <int K, int N, typename LD>
 __device__ __forceinline__ void box_run(LD v, float4 *s)
 {
-    // v(j) reads value j where it is needed, so that only the running
-    // partial sums stay live (not all K + N - 1 inputs)
+    // v(j) reads value j where it is needed; the partial sums are formed in
+    // an order that keeps only the outputs and two running sums live:
+    //   s[t] = (v(t) + ... + v(N-2)) + C + (v(K) + ... + v(K+t-1))
     if constexpr (K < N || K <= 3) {
 #pragma unroll
         for (int t = 0; t < N; ++t) {
@@ -163,19 +160,23 @@ __device__ __forceinline__ void box_run(LD v, float4 *s)
         float4 C = v(N - 1);
 #pragma unroll
         for (int j = N; j < K; ++j) C = f4add(C, v(j));
-        float4 L[N], Rt[N];
-        L[N - 1] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if constexpr (N >= 2) L[N - 2] = v(N - 2);
+        s[N - 1] = C;
+        if constexpr (N >= 2) {
+            float4 L = v(N - 2);
+            s[N - 2] = f4add(L, C);
 #pragma unroll
-        for (int t = N - 3; t >= 0; --t) L[t] = f4add(v(t), L[t + 1]);
-        Rt[0] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if constexpr (N >= 2) Rt[1] = v(K);
+            for (int t = N - 3; t >= 0; --t) {
+                L = f4add(v(t), L);
+                s[t] = f4add(L, C);
+            }
+            float4 Rt = v(K);
+            s[1] = f4add(s[1], Rt);
 #pragma unroll
-        for (int t = 2; t < N; ++t) Rt[t] = f4add(Rt[t - 1], v(K + t - 1));
-        s[0] = (N >= 2) ? f4add(L[0], C) : C;
-#pragma unroll
-        for (int t = 1; t < N - 1; ++t) s[t] = f4add(f4add(L[t], C), Rt[t]);
-        if constexpr (N >= 2) s[N - 1] = f4add(C, Rt[N - 1]);
+            for (int t = 2; t < N; ++t) {
+                Rt = f4add(Rt, v(K + t - 1));
+                s[t] = f4add(s[t], Rt);
+            }
+        }
     }
 }
 
@@ -527,137 +528,346 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
     }
 }
 
-// Forward decode of the tensor form (stacks of equal frames), persistent
-// and software-pipelined.  Each workgroup walks the tiles u = blockIdx.x,
-// blockIdx.x + gridDim.x, ...  Every input of a tile (irradiance and all M
-// weight maps over the halo, logits and remodulation factor of the centres)
-// is loaded into registers one tile ahead: while tile u is filtered, its
-// successor's requests are in flight, so that memory traffic and the
-// LDS/VALU work of the box sums overlap within a workgroup instead of
-// alternating across the whole device.  The arithmetic is that of
-// decode_fwd_kernel.
-template <int M, int RM>
-__global__ __launch_bounds__(kThreads, 2) void decode_stream_kernel(DecodeCfg dc, DecodeTensors dt,
-                                                                     int ntiles)
+// ---------------------------------------------------------------------------
+// Forward decode, one tile of TW x TH centres per workgroup of 512 threads.
+//
+// Separable window sums, horizontal first.  Per kernel size i, r = r_i:
+//   1. each thread writes the plane (W_i, W_i c) of its halo pixels into
+//      LDS, P[hy][hx] (row stride HXS, odd);
+//   2. horizontal pass: thread (halo row hy, run of kNR columns) sums the
+//      r-windows of the TW output columns into the row-sum buffer
+//      S[hy][x] (rows R-r .. R+TH+r-1: the rows the vertical pass reads);
+//   3. vertical pass: thread (column x, run of kNC rows) sums r-windows of
+//      the row sums down its column: the k x k window sums of its kNC
+//      centres, which it normalises and blends into their fusion state.
+// Two barriers per size: after 1 (the plane is complete) and after 2 (the
+// row sums are complete).  The vertical pass of size i and the plane write
+// of size i + 1 use different buffers and run in the same phase.
+// The thread of step 3 owns those centres for the whole kernel: their
+// logits, fusion state and output.  Its lanes hold consecutive columns, so
+// the centres' global loads and stores are coalesced row segments.  The
+// irradiance c of the thread's halo pixels stays in registers; each size's
+// weight map is fetched one size ahead, its logits while its plane is built.
+//
+// Fusion (Eq. 5) is an online softmax: the state of a centre is the largest
+// logit seen so far (m, in base-2 units), the sum of the numerators 2^(l-m)
+// and the numerator-weighted sum of the filtered values; a larger logit
+// rescales both by 2^(m_old - m_new).  Only the first size's logits are
+// needed before filtering starts.
+//
+// EXPW: the head holds raw pre-activations h and W = exp(h).  Window ratios
+// are unchanged by a common factor, so each tile uses W = exp(h - m_i) with
+// m_i the largest h_i over its halo (no overflow for any finite h) and the
+// floor eps e^{-m_i} in place of eps: out = N / max(S, eps) as with exp(h).
+constexpr int kFThreads = 512;
+constexpr int kFSlots = 6;          // halo pixels per thread: HXS * (TH + 2R) <= 3072
+constexpr int kNR = 5;              // row sums per thread (horizontal run)
+constexpr int kNC = 5;              // centres per thread (vertical run)
+constexpr int kTileW = 40;          // centres per tile row (multiple of kNR)
+constexpr int kSRow = kTileW + 1;   // row-sum buffer stride (float4): odd
+constexpr float kLog2e = 1.4426950408889634f;
+
+enum DecodeForm { DF_FRAMES = 0, DF_TENSORS = 1 };
+
+__device__ __forceinline__ float wave_max(float v)
 {
-    const FrameArg fa{};
-    constexpr int kMaxPix = max_pix<RM>();
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+template <int M, int FORM, int RM, bool EXPW>
+__global__ __launch_bounds__(kFThreads, 4) void decode_tile_kernel(DecodeCfg dc, FrameArg fa,
+                                                                    DecodeTensors dt)
+{
     extern __shared__ float4 lds4[];
-    const int R = dc.R;
-    const int HX = halo_stride(R), HXY = HX * (kDTY + 2 * R);
-    float4 *pr = lds4;
-    float4 *hb = pr + HXY;
-    const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+    __shared__ float red[2][kFThreads / 64];
+    constexpr bool FR = FORM == DF_FRAMES;
+    const int TW = dc.tw, TH = dc.th, HXS = dc.hxs, R = dc.R;
+    const int HX = TW + 2 * R, HY = TH + 2 * R, HXY = HXS * HY;
+    const int tid = threadIdx.x;
 
-    // one tile's inputs, as loaded (pixels outside the image or the halo
-    // read pixel 0; gp < 0 marks them)
-    struct Raw {
-        int gp[kMaxPix];
-        float x[kMaxPix][3];                       // c
-        float w[M][kMaxPix];
-        float lg[kRun][M];                         // centre logits
-        float m[kRun][3];                          // centre remodulation factor
-    };
-    auto fetch = [&](const DecodeIO &io, int x0, int y0, Raw &rw) {
-        halo_pixels<RM>(x0, y0, R, HX, HXY, io.H, io.W, rw.gp);
-#pragma unroll
-        for (int k = 0; k < kMaxPix; ++k) {
-            const size_t q = (size_t)(rw.gp[k] >= 0 ? rw.gp[k] : 0);
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) rw.x[k][ch] = gload(io.c + q * 3 + ch);
-#pragma unroll
-            for (int i = 0; i < M; ++i) rw.w[i][k] = gload(io.head + q * io.hs_pix + i * io.hs_map);
-        }
-#pragma unroll
-        for (int o = 0; o < kRun; ++o) {
-            const int y = y0 + kRun * ty + o, x = x0 + tx;
-            const bool in = y < io.H && x < io.W;
-            const size_t pix = in ? (size_t)y * io.W + x : 0;
-#pragma unroll
-            for (int i = 0; i < M; ++i) rw.lg[o][i] = gload(io.head + pix * io.hs_pix + (M + i) * io.hs_map);
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) rw.m[o][ch] = io.mod ? gload(io.mod + pix * 3 + ch) : 1.f;
-        }
-    };
-
-    int u = blockIdx.x;
-    if (u >= ntiles) return;
+    // ---- tile -> frame, origin, I/O
     DecodeIO io;
     int x0, y0;
-    decode_locate_at<false>(dc, fa, dt, u, ntiles, io, x0, y0);
-    Raw cur;
-    fetch(io, x0, y0, cur);
-    for (;;) {
-        // this tile's masked irradiance and weights
-        float cv[kMaxPix][3], wv[M][kMaxPix];
-#pragma unroll
-        for (int k = 0; k < kMaxPix; ++k) {
-            const bool live = cur.gp[k] >= 0;
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) cv[k][ch] = live ? cur.x[k][ch] : 0.f;
-#pragma unroll
-            for (int i = 0; i < M; ++i) wv[i][k] = live ? cur.w[i][k] : 0.f;
+    {
+        auto tiles = [&](int H, int W) { return ((W + TW - 1) / TW) * ((H + TH - 1) / TH); };
+        const int twoM = 2 * M;
+        int t;
+        if constexpr (FR) {
+            int n;
+            t = batch_tile_id(fa, blockIdx.x, gridDim.x, n);
+            if (t < 0) return;
+            const int f = batch_frame(fa, n, t, tiles);
+            if (f < 0) return;
+            const FrameDesc &fd = frame_at(fa, f);
+            io.H = fd.H;
+            io.W = fd.W;
+            io.head = fd.head;
+            io.hs_pix = 1;
+            io.hs_map = (size_t)fd.H * fd.W;
+            io.r = fd.r;
+            io.a = fd.a;
+            io.c = nullptr;
+            io.mod = nullptr;
+            io.out = fd.out;
+        } else {
+            t = xcd_logical_id(blockIdx.x, gridDim.x);
+            const int cnt = tiles(dt.H, dt.W);
+            const int f = t / cnt;
+            if (f >= dt.N) return;
+            t -= f * cnt;
+            const size_t P = (size_t)dt.H * dt.W;
+            io.H = dt.H;
+            io.W = dt.W;
+            io.head = dt.head + (size_t)f * P * twoM;
+            io.hs_pix = twoM;
+            io.hs_map = 1;
+            io.r = io.a = nullptr;
+            io.c = dt.c + (size_t)f * P * 3;
+            io.mod = dt.mod ? dt.mod + (size_t)f * P * 3 : nullptr;
+            io.out = dt.out + (size_t)f * P * 3;
         }
-        float lmax[kRun], esum[kRun], F[kRun][3], mo[kRun][3], lg[kRun][M];
-#pragma unroll
-        for (int o = 0; o < kRun; ++o) {
-            float m = -INFINITY;
-#pragma unroll
-            for (int i = 0; i < M; ++i) {
-                lg[o][i] = cur.lg[o][i];
-                m = fmaxf(m, lg[o][i]);
-            }
-            lmax[o] = m;
-            esum[o] = 0.f;
-            F[o][0] = F[o][1] = F[o][2] = 0.f;
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) mo[o][ch] = cur.m[o][ch];
-        }
-        const DecodeIO iot = io;
-        const int xt = x0, yt = y0;
+        const int txn = (io.W + TW - 1) / TW;
+        x0 = (t % txn) * TW;
+        y0 = (t / txn) * TH;
+    }
+    const int H = io.H, W = io.W;
+    const unsigned P = (unsigned)(H * W);
 
-        // the next tile's requests go out before this tile is filtered
-        const int un = u + gridDim.x;
-        const bool more = un < ntiles;
-        if (more) {
-            decode_locate_at<false>(dc, fa, dt, un, ntiles, io, x0, y0);
-            fetch(io, x0, y0, cur);
+    // ---- this thread's halo slots p = tid + k * 512: row-major over
+    // [HY][HXS].  gp[k] is the slot's pixel index in the frame, or -1 (a
+    // slot outside the image, a padding column hx >= HX, or past the plane):
+    // such slots hold W = 0.  Slots past the plane write their zeros to the
+    // plane's last cell, a padding column (TW + 2R is even, so HXS = HX + 1)
+    // that no pass reads.
+    int gp[kFSlots];
+    {
+        const int sy = kFThreads / HXS, sx = kFThreads - sy * HXS;
+        int ly = tid / HXS, lx = tid - ly * HXS;
+#pragma unroll
+        for (int k = 0; k < kFSlots; ++k) {
+            const int gy = y0 - R + ly, gx = x0 - R + lx;
+            gp[k] = (ly < HY && lx < HX && gy >= 0 && gy < H && gx >= 0 && gx < W) ? gy * W + gx : -1;
+            lx += sx;
+            ly += sy;
+            if (lx >= HXS) {
+                lx -= HXS;
+                ++ly;
+            }
         }
+    }
+    // the thread's centres: column cx of the tile, rows cy .. cy + kNC - 1
+    // (the last run of a column is moved up to end at row TH - 1; centres it
+    // shares with the run above are computed, and stored, twice with the
+    // same values).  nc: how many of them lie in the image.
+    const int nv_items = TW * ((TH + kNC - 1) / kNC);
+    const bool owner = tid < nv_items;
+    const int cx = tid % TW, cy = min((tid / TW) * kNC, TH - kNC);
+    const int gcx = x0 + cx, gcy = y0 + cy;
+    const int nc = (owner && gcx < W) ? max(0, min(kNC, H - gcy)) : 0;
+    auto centre_off = [&](int q) { return q < nc ? (unsigned)((gcy + q) * W + gcx) * 4u : kNoPixel; };
+    auto centre_pix = [&](int q) { return q < nc ? (size_t)(gcy + q) * W + gcx : (size_t)0; };
 
+    // ---- loads: irradiance of the halo slots, the first weight map
+    float cv[kFSlots][3], wv[kFSlots];
+    auto load_w = [&](int i) {
+        if constexpr (FR) {
+            const rsrc_t rs = make_rsrc(io.head + (size_t)i * P, P * 4u);
 #pragma unroll
-        for (int i = 0; i < M; ++i) {
+            for (int k = 0; k < kFSlots; ++k)
+                wv[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                    rs, gp[k] >= 0 ? (unsigned)gp[k] * 4u : kNoPixel, 0, 0));
+        } else {
 #pragma unroll
-            for (int k = 0; k < kMaxPix; ++k) {
-                const int p = tid + k * kThreads;
-                if (p < HXY)
-                    pr[p] = make_float4(wv[i][k], wv[i][k] * cv[k][0], wv[i][k] * cv[k][1], wv[i][k] * cv[k][2]);
-            }
-            lds_sync();
-            float4 acc[kRun];
-#define WSKP_WS(KK) window_sums4<KK>(R, HX, pr, hb, acc)
-            WSKP_SWITCH_K(RM, 2 * dc.radius[i] + 1, WSKP_WS)
-#undef WSKP_WS
+            for (int k = 0; k < kFSlots; ++k)
+                wv[k] = gload(io.head + (size_t)(gp[k] >= 0 ? gp[k] : 0) * io.hs_pix + i);
+        }
+    };
+    auto load_logit = [&](int i, float *lg) {
+        if constexpr (FR) {
+            const rsrc_t rs = make_rsrc(io.head + (size_t)(M + i) * P, P * 4u);
 #pragma unroll
-            for (int o = 0; o < kRun; ++o) {
-                const float inv = __builtin_amdgcn_rcpf(fmaxf(acc[o].x, dc.eps_norm));
-                const float e = exp_softmax(lg[o][i] - lmax[o]);
-                esum[o] += e;
-                F[o][0] += e * (acc[o].y * inv);
-                F[o][1] += e * (acc[o].z * inv);
-                F[o][2] += e * (acc[o].w * inv);
+            for (int q = 0; q < kNC; ++q)
+                lg[q] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, centre_off(q), 0, 0));
+        } else {
+#pragma unroll
+            for (int q = 0; q < kNC; ++q) lg[q] = gload(io.head + centre_pix(q) * io.hs_pix + M + i);
+        }
+    };
+    float lg[kNC];
+    if constexpr (FR) {
+        const rsrc_t rr = make_rsrc(io.r, P * 12u), ra = make_rsrc(io.a, P * 12u);
+        float av[kFSlots][3];
+#pragma unroll
+        for (int k = 0; k < kFSlots; ++k) {
+            const unsigned o3 = gp[k] >= 0 ? (unsigned)gp[k] * 12u : kNoPixel;
+            const auto r3 = __builtin_amdgcn_raw_buffer_load_b96(rr, o3, 0, 0);
+            const auto a3 = __builtin_amdgcn_raw_buffer_load_b96(ra, o3, 0, 0);
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                cv[k][ch] = __uint_as_float(r3[ch]);
+                av[k][ch] = __uint_as_float(a3[ch]);
             }
         }
+        load_w(0);
+        load_logit(0, lg);
 #pragma unroll
-        for (int o = 0; o < kRun; ++o) {
-            const int y = yt + kRun * ty + o, x = xt + tx;
-            if (y >= iot.H || x >= iot.W) continue;
-            const size_t pix = (size_t)y * iot.W + x;
-            const float inv = 1.f / esum[o];
+        for (int k = 0; k < kFSlots; ++k)
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) gstore(iot.out + pix * 3 + ch, mo[o][ch] * (F[o][ch] * inv));
+            for (int ch = 0; ch < 3; ++ch) {
+                // c = r / (a + eps_a) by the hardware reciprocal; slots outside
+                // the image hold c = 0 (also when eps_a = 0, where the
+                // reciprocal of their zero albedo is infinite)
+                const float c = cv[k][ch] * __builtin_amdgcn_rcpf(av[k][ch] + dc.eps_albedo);
+                cv[k][ch] = gp[k] >= 0 ? c : 0.f;
+            }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kFSlots; ++k) {
+            const size_t q = (size_t)(gp[k] >= 0 ? gp[k] : 0) * 3;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) cv[k][ch] = gload(io.c + q + ch);
         }
-        if (!more) break;
-        u = un;
+        load_w(0);
+        load_logit(0, lg);
+#pragma unroll
+        for (int k = 0; k < kFSlots; ++k)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) cv[k][ch] = gp[k] >= 0 ? cv[k][ch] : 0.f;
+    }
+
+    // ---- online fusion state of the thread's centres
+    float lm[kNC], esum[kNC], F[kNC][3];
+#pragma unroll
+    for (int q = 0; q < kNC; ++q) {
+        lm[q] = -INFINITY;
+        esum[q] = 0.f;
+        F[q][0] = F[q][1] = F[q][2] = 0.f;
+    }
+
+    float4 *pl = lds4;                  // plane [HY][HXS]
+    float4 *sr = lds4 + HXY;            // row sums [HY][kSRow]
+    const int wave = tid >> 6;
+    // EXPW: the halo maximum of the loaded map, per wave into red[buf]
+    auto wave_max_to_lds = [&](int buf) {
+        float m = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < kFSlots; ++k) m = gp[k] >= 0 ? fmaxf(m, wv[k]) : m;
+        m = wave_max(m);
+        if ((tid & 63) == 0) red[buf][wave] = m;
+    };
+    if constexpr (EXPW) {
+        wave_max_to_lds(0);
+        lds_sync();
+    }
+    float mv[kNC][3];                   // remodulation factor of the centres
+
+#pragma unroll 1
+    for (int i = 0; i < M; ++i) {
+        const int r = dc.radius[i];
+        float eps = dc.eps_norm;
+        // 1. the plane (W_i, W_i c) of the halo slots
+        {
+            float mi = 0.f;
+            if constexpr (EXPW) {
+                mi = red[i & 1][0];
+#pragma unroll
+                for (int w = 1; w < kFThreads / 64; ++w) mi = fmaxf(mi, red[i & 1][w]);
+                // a tile without image pixels in its halo has nothing to filter
+                mi = mi == -INFINITY ? 0.f : mi;
+                eps = fmaxf(eps * __builtin_amdgcn_exp2f(-mi * kLog2e), 1.17549435e-38f);
+            }
+#pragma unroll
+            for (int k = 0; k < kFSlots; ++k) {
+                const int p = min(tid + k * kFThreads, HXY - 1);
+                float w = wv[k];
+                if constexpr (EXPW) w = __builtin_amdgcn_exp2f((w - mi) * kLog2e);
+                w = gp[k] >= 0 ? w : 0.f;
+                pl[p] = make_float4(w, w * cv[k][0], w * cv[k][1], w * cv[k][2]);
+            }
+        }
+        // this size's logits (used after the horizontal pass) and the next
+        // size's weights go out now; before the last size, the centres'
+        // remodulation factors
+        if (i > 0) load_logit(i, lg);
+        if (i + 1 < M) {
+            load_w(i + 1);
+        } else {
+            if constexpr (FR) {
+                const rsrc_t ra = make_rsrc(io.a, P * 12u);
+#pragma unroll
+                for (int q = 0; q < kNC; ++q) {
+                    const unsigned o = centre_off(q);
+                    const auto a3 =
+                        __builtin_amdgcn_raw_buffer_load_b96(ra, o == kNoPixel ? kNoPixel : o * 3u, 0, 0);
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch) mv[q][ch] = __uint_as_float(a3[ch]) + dc.eps_albedo;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < kNC; ++q)
+#pragma unroll
+                    for (int ch = 0; ch < 3; ++ch)
+                        mv[q][ch] = io.mod ? gload(io.mod + centre_pix(q) * 3 + ch) : 1.f;
+            }
+        }
+        lds_sync();
+
+        // 2. horizontal pass: halo row hy (of the TH + 2r the vertical pass
+        // reads), output columns x .. x + kNR - 1, into the row-sum buffer
+        {
+            const int nrows = TH + 2 * r;
+            if (tid < nrows * (TW / kNR)) {
+                const int hrow = R - r + tid % nrows;
+                const int hx = (tid / nrows) * kNR;
+                const int base = hrow * HXS + R - r + hx;
+                float4 hs[kNR];
+#define WSKP_H(KK) box_run<KK, kNR>([&](int j) { return pl[base + j]; }, hs)
+                WSKP_SWITCH_K(RM, 2 * r + 1, WSKP_H)
+#undef WSKP_H
+#pragma unroll
+                for (int t = 0; t < kNR; ++t) sr[hrow * kSRow + hx + t] = hs[t];
+            }
+        }
+        if constexpr (EXPW) {
+            if (i + 1 < M) wave_max_to_lds((i + 1) & 1);
+        }
+        lds_sync();
+
+        // 3. vertical pass over the row sums: the kNC centres' window sums
+        // (S, N_0, N_1, N_2), normalised and blended
+        if (owner) {
+            float4 acc[kNC];
+            const int base = (cy + R - r) * kSRow + cx;
+#define WSKP_V(KK) box_run<KK, kNC>([&](int j) { return sr[base + j * kSRow]; }, acc)
+            WSKP_SWITCH_K(RM, 2 * r + 1, WSKP_V)
+#undef WSKP_V
+#pragma unroll
+            for (int q = 0; q < kNC; ++q) {
+                const float inv = __builtin_amdgcn_rcpf(fmaxf(acc[q].x, eps));
+                const float l2 = lg[q] * kLog2e;
+                const float mn = fmaxf(lm[q], l2);
+                const float sc = __builtin_amdgcn_exp2f(lm[q] - mn);   // 0 for the first size
+                const float e = __builtin_amdgcn_exp2f(l2 - mn);
+                lm[q] = mn;
+                esum[q] = esum[q] * sc + e;
+                const float ei = e * inv;
+                F[q][0] = F[q][0] * sc + ei * acc[q].y;
+                F[q][1] = F[q][1] * sc + ei * acc[q].z;
+                F[q][2] = F[q][2] * sc + ei * acc[q].w;
+            }
+        }
+    }
+
+    // ---- remodulation (y = mod * F / sum of numerators) and store
+#pragma unroll
+    for (int q = 0; q < kNC; ++q) {
+        if (q >= nc) break;
+        const float inv = 1.f / esum[q];
+        float *op = io.out + centre_pix(q) * 3;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) gstore(op + ch, mv[q][ch] * (F[q][ch] * inv));
     }
 }
 
@@ -787,57 +997,84 @@ static hipError_t launch_decode(const DecodeCfg &dc, const FrameArg &fa, const D
     return hipGetLastError();
 }
 
-int decode_grid(int n, const int *H, const int *W)
+// Tile shape of the forward decode for the handle's largest radius: 40
+// centres wide; as tall as the workgroup's 512 threads allow (at most 45
+// rows): every thread holds at most kFSlots halo pixels, one horizontal run
+// and one vertical run.  At 720p, 1080p and 1440p with R <= 6 the 45-row
+// tiles divide the frame exactly (1280 x 720: 32 x 16 = 512 tiles).
+void decode_tile_shape(DecodeCfg &dc)
+{
+    dc.tw = kTileW;
+    dc.hxs = (dc.tw + 2 * dc.R) | 1;   // odd row stride: lanes on consecutive rows hit distinct banks
+    int th = 45;
+    auto lds = [&](int t) { return sizeof(float4) * (size_t)(dc.hxs + kSRow) * (t + 2 * dc.R) + 64; };
+    while (th > kNC && (dc.hxs * (th + 2 * dc.R) > kFSlots * kFThreads ||
+                        (th + 2 * dc.R) * (dc.tw / kNR) > kFThreads ||
+                        dc.tw * ((th + kNC - 1) / kNC) > kFThreads ||
+                        2 * lds(th) > 160 * 1024))      // two workgroups per CU
+        --th;
+    dc.th = th;
+}
+
+int decode_grid(const DecodeCfg &dc, int n, const int *H, const int *W)
 {
     long total = 0;
     for (int f = 0; f < n; ++f)
-        total += (long)((W[f] + kDTX - 1) / kDTX) * ((H[f] + kDTY - 1) / kDTY);
+        total += (long)((W[f] + dc.tw - 1) / dc.tw) * ((H[f] + dc.th - 1) / dc.th);
     return (int)total;
 }
 
-// Forward decode of the tensor form over `tiles` tiles with the persistent
-// kernel: at most dc.grid_cap workgroups, each walking its share of the tiles.
-// (The frames form uses the one-tile-per-workgroup kernel, which measured
-// faster there: the persistent one would hold the next tile's radiance and
-// albedo as well, at lower occupancy.)
-static hipError_t launch_stream(const DecodeCfg &dc, const DecodeTensors &dt, int tiles, hipStream_t s)
+static size_t tile_lds_bytes(const DecodeCfg &dc)
 {
-    if (tiles <= 0) return hipSuccess;
-    const size_t lds = decode_lds_bytes(dc);
-    const int grid = tiles < dc.grid_cap ? tiles : dc.grid_cap;
-    const bool r5 = dc.R <= 5;
+    // the plane [HY][HXS] and the row sums [HY][kSRow]
+    return sizeof(float4) * (size_t)(dc.hxs + kSRow) * (dc.th + 2 * dc.R);
+}
+
+template <int M, int FORM, int RM, bool EXPW>
+static hipError_t launch_tile_inst(const DecodeCfg &dc, const FrameArg &fa, const DecodeTensors &dt,
+                                   int blocks, hipStream_t s)
+{
+    const size_t lds = tile_lds_bytes(dc);
+    allow_lds(decode_tile_kernel<M, FORM, RM, EXPW>, lds);
+    hipLaunchKernelGGL((decode_tile_kernel<M, FORM, RM, EXPW>), dim3(blocks), dim3(kFThreads), lds, s,
+                       dc, fa, dt);
+    return hipGetLastError();
+}
+
+template <int FORM>
+static hipError_t launch_tile(const DecodeCfg &dc, const FrameArg &fa, const DecodeTensors &dt,
+                              int blocks, hipStream_t s)
+{
+    // one instantiation covers every kernel size up to 15 (the size only
+    // selects the window-sum code; the registers do not depend on it)
+    if (blocks <= 0) return hipSuccess;
+    const bool ex = FORM == DF_FRAMES && dc.exp_weights;
     switch (dc.M) {
-#define WSKP_M(m)                                                                                 \
-    case m:                                                                                       \
-        if (r5) {                                                                                 \
-            allow_lds(decode_stream_kernel<m, 5>, lds);                                           \
-            hipLaunchKernelGGL((decode_stream_kernel<m, 5>), dim3(grid), dim3(kThreads), lds, s,  \
-                               dc, dt, tiles);                                                    \
-        } else {                                                                                  \
-            allow_lds(decode_stream_kernel<m, 7>, lds);                                           \
-            hipLaunchKernelGGL((decode_stream_kernel<m, 7>), dim3(grid), dim3(kThreads), lds, s,  \
-                               dc, dt, tiles);                                                    \
-        }                                                                                         \
-        break;
+#define WSKP_M(m)                                                                              \
+    case m:                                                                                    \
+        if constexpr (FORM == DF_FRAMES) {                                                     \
+            if (ex) return launch_tile_inst<m, FORM, 7, true>(dc, fa, dt, blocks, s);          \
+        }                                                                                      \
+        return launch_tile_inst<m, FORM, 7, false>(dc, fa, dt, blocks, s);
         WSKP_M(1) WSKP_M(2) WSKP_M(3) WSKP_M(4) WSKP_M(5) WSKP_M(6) WSKP_M(7) WSKP_M(8)
 #undef WSKP_M
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_decode_frames(const DecodeCfg &dc, const FrameArg &fa, int blocks, hipStream_t s)
 {
     DecodeTensors dt{};
-    return launch_decode<DK_FRAMES>(dc, fa, dt, blocks, s);
+    return launch_tile<DF_FRAMES>(dc, fa, dt, blocks, s);
 }
 
 hipError_t launch_decode_tensors(const DecodeCfg &dc, int N, int H, int W, const float *head,
                                  const float *c, const float *mod, float *out, hipStream_t s)
 {
     DecodeTensors dt{N, H, W, head, c, mod, out, nullptr, nullptr, nullptr};
-    const int blocks = N * ((W + kDTX - 1) / kDTX) * ((H + kDTY - 1) / kDTY);
-    return launch_stream(dc, dt, blocks, s);
+    FrameArg fa{};
+    const int blocks = N * ((W + dc.tw - 1) / dc.tw) * ((H + dc.th - 1) / dc.th);
+    return launch_tile<DF_TENSORS>(dc, fa, dt, blocks, s);
 }
 
 size_t decode_backward_scratch_bytes(const DecodeCfg &dc, int N, int H, int W)

@@ -416,10 +416,10 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
     }
     h->dc.eps_norm = cfg->eps_norm;
     h->dc.eps_albedo = cfg->eps_albedo;
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1)
-        cus = 256;
-    h->dc.grid_cap = 2 * cus;
+    // with exp weights the head conv stores the raw pre-activations and the
+    // decode exponentiates them with a per-tile shift
+    h->dc.exp_weights = cfg->weight_act == WSKP_ACT_EXP ? 1 : 0;
+    decode_tile_shape(h->dc);
     *out = h;
     return WSKP_OK;
 }
@@ -588,7 +588,7 @@ static wskp_status_t run_frames(wskp_ctx *h, const FrameArg &fa, int n, const in
         if (e != hipSuccess) return hip_fail(e, "conv launch", WSKP_E_LAUNCH);
         if (ev) (void)hipEventRecord(ev[++k], s);
     }
-    hipError_t e = launch_decode_frames(h->dc, fa, decode_grid(n, Hs, Ws), s);
+    hipError_t e = launch_decode_frames(h->dc, fa, decode_grid(h->dc, n, Hs, Ws), s);
     if (e != hipSuccess) return hip_fail(e, "decode launch", WSKP_E_LAUNCH);
     if (ev) (void)hipEventRecord(ev[++k], s);
     return WSKP_OK;
@@ -801,7 +801,7 @@ extern "C" wskp_status_t wskp_denoise_batch(wskp_handle_t h, void *stream, int n
     if (flags & WSKP_BATCH_GRAPH) {
         std::vector<int> caps;
         for (const LayerPlan &lp : h->layers) tiles.push_back(conv_grid(lp.L, n, Hs.data(), Ws.data()));
-        tiles.push_back(decode_grid(n, Hs.data(), Ws.data()));
+        tiles.push_back(decode_grid(h->dc, n, Hs.data(), Ws.data()));
         for (int t : tiles) caps.push_back(next_pow2(t));
         for (auto &c : h->graphs)
             if (c.s == s && c.reverse == reverse && c.caps == caps) g = &c;
@@ -888,6 +888,43 @@ extern "C" wskp_status_t wskp_backward(wskp_handle_t h, void *stream, int N, int
     hipError_t e = launch_decode_backward(h->dc, N, H, W, head, c, mod, grad_out, grad_head, grad_c,
                                           ws, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "backward launch", WSKP_E_LAUNCH);
+    return WSKP_OK;
+}
+
+extern "C" wskp_status_t wskp_kp_map_bytes(wskp_handle_t h, int H, int W, size_t *bytes)
+{
+    if (!h || !bytes) return fail(WSKP_E_INVALID_ARG, "NULL argument");
+    if (H < 1 || W < 1 || (long)H * W > (1L << 26)) return fail(WSKP_E_SHAPE, "H, W out of range");
+    *bytes = kp_map_floats(h->dc, H, W) * sizeof(float);
+    return WSKP_OK;
+}
+
+extern "C" wskp_status_t wskp_kp_expand(wskp_handle_t h, void *stream, int H, int W, const float *head,
+                                        float *maps, size_t map_bytes)
+{
+    if (!h || !head || !maps) return fail(WSKP_E_INVALID_ARG, "NULL argument");
+    if (H < 1 || W < 1 || (long)H * W > (1L << 26)) return fail(WSKP_E_SHAPE, "H, W out of range");
+    if (map_bytes < kp_map_floats(h->dc, H, W) * sizeof(float))
+        return fail(WSKP_E_BUDGET, "kernel-map buffer too small");
+    wskp_status_t st = set_device(h);
+    if (st != WSKP_OK) return st;
+    hipError_t e = launch_kp_expand(h->dc, H, W, head, maps, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "kp expand launch", WSKP_E_LAUNCH);
+    return WSKP_OK;
+}
+
+extern "C" wskp_status_t wskp_kp_decode(wskp_handle_t h, void *stream, int H, int W, const float *maps,
+                                        size_t map_bytes, const float *head, const float *c,
+                                        const float *mod, float *out)
+{
+    if (!h || !maps || !head || !c || !out) return fail(WSKP_E_INVALID_ARG, "NULL argument");
+    if (H < 1 || W < 1 || (long)H * W > (1L << 26)) return fail(WSKP_E_SHAPE, "H, W out of range");
+    if (map_bytes < kp_map_floats(h->dc, H, W) * sizeof(float))
+        return fail(WSKP_E_BUDGET, "kernel-map buffer too small");
+    wskp_status_t st = set_device(h);
+    if (st != WSKP_OK) return st;
+    hipError_t e = launch_kp_decode(h->dc, H, W, maps, head, c, mod, out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "kp decode launch", WSKP_E_LAUNCH);
     return WSKP_OK;
 }
 

@@ -202,7 +202,9 @@ struct DecodeCfg {
     int radius[kMaxKernels];  // (k_i - 1)/2
     float eps_norm;
     float eps_albedo;
-    int grid_cap;             // workgroups of the persistent forward decode (resident capacity)
+    int exp_weights;          // frames form: the head holds h, W = exp(h) (per-tile shift)
+    int tw, th;               // forward decode tile: centres per row, rows
+    int hxs;                  // row stride (float4) of its LDS plane
 };
 
 // ---- launchers (defined in the .hip files) --------------------------------
@@ -217,7 +219,9 @@ int conv_blocks_per_group(int prec, int mode, int CK, int nblk, int level);
 // Decode + fusion + remodulation over frames of fa (denoise mode: c and mod
 // derive from r, a) -- or over plain tensors (decode mode).
 hipError_t launch_decode_frames(const DecodeCfg &dc, const FrameArg &fa, int blocks, hipStream_t s);
-int decode_grid(int n, const int *H, const int *W);
+// Sets dc.tw, dc.th, dc.hxs from dc.R (the forward decode's tile shape).
+void decode_tile_shape(DecodeCfg &dc);
+int decode_grid(const DecodeCfg &dc, int n, const int *H, const int *W);
 hipError_t launch_decode_tensors(const DecodeCfg &dc, int N, int H, int W, const float *head,
                                  const float *c, const float *mod, float *out, hipStream_t s);
 hipError_t launch_decode_backward(const DecodeCfg &dc, int N, int H, int W, const float *head,
@@ -225,6 +229,11 @@ hipError_t launch_decode_backward(const DecodeCfg &dc, int N, int H, int W, cons
                                   float *grad_head, float *grad_c, void *scratch,
                                   hipStream_t s);
 size_t decode_backward_scratch_bytes(const DecodeCfg &dc, int N, int H, int W);
+// Explicit kernel-map reconstruction (the comparison of Sec. 5.3, kp.hip).
+size_t kp_map_floats(const DecodeCfg &dc, int H, int W);
+hipError_t launch_kp_expand(const DecodeCfg &dc, int H, int W, const float *head, float *maps, hipStream_t s);
+hipError_t launch_kp_decode(const DecodeCfg &dc, int H, int W, const float *maps, const float *head,
+                            const float *c, const float *mod, float *out, hipStream_t s);
 
 // Tile geometry of the conv kernels (host and device agree on these).
 constexpr int kConvTW = 32;  // output columns per tile (two 16-pixel MFMA blocks)

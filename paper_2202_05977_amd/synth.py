@@ -63,7 +63,13 @@ class NetConfig:
 # differentiation batch.
 SMALL = NetConfig(levels=3, channels=(16, 32, 64), kernel_sizes=(3, 5, 7))
 HD = NetConfig(levels=4, channels=(32, 64, 96, 128), kernel_sizes=(3, 5, 7, 9, 11))
-CONFIGS: Dict[str, NetConfig] = {"small": SMALL, "hd": HD}
+# The paper's own kernel set (Sec. 5.3: six weight maps and six fusion
+# weights; Sec. 4.2 "Kernel Fusion": k_i = k_b + i k_s with k_b = 3, k_s = 2)
+# and its literal weight form (Eq. 3: the window softmax, W = exp(h)), on the
+# hd U-Net.
+PAPER6 = NetConfig(levels=4, channels=(32, 64, 96, 128), kernel_sizes=(3, 5, 7, 9, 11, 13),
+                   weight_act="exp")
+CONFIGS: Dict[str, NetConfig] = {"small": SMALL, "hd": HD, "paper6": PAPER6}
 
 SERVE_RESOLUTIONS: Tuple[Tuple[int, int], ...] = ((360, 640), (720, 1280), (1080, 1920), (1440, 2560))
 

@@ -90,6 +90,9 @@ def lib():
         L.wskp_decode.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp]
         L.wskp_backward.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, sz]
         L.wskp_backward_workspace_size.argtypes = [vp, i32, i32, i32, ctypes.POINTER(sz)]
+        L.wskp_kp_map_bytes.argtypes = [vp, i32, i32, ctypes.POINTER(sz)]
+        L.wskp_kp_expand.argtypes = [vp, vp, i32, i32, vp, vp, sz]
+        L.wskp_kp_decode.argtypes = [vp, vp, i32, i32, vp, sz, vp, vp, vp, vp]
         L.wskp_workspace_tensor.argtypes = [vp, i32, ip, ip, i32, i32, ctypes.POINTER(sz),
                                             ip, ip, ip, ip]
         L.wskp_timing_enable.argtypes = [vp, i32]
@@ -105,6 +108,7 @@ def lib():
         for name in ("wskp_create", "wskp_destroy", "wskp_workspace_size", "wskp_denoise",
                      "wskp_denoise_static", "wskp_denoise_batch", "wskp_decode", "wskp_backward",
                      "wskp_backward_workspace_size", "wskp_workspace_tensor",
+                     "wskp_kp_map_bytes", "wskp_kp_expand", "wskp_kp_decode",
                      "wskp_timing_enable", "wskp_timing_read"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -282,6 +286,32 @@ def wskp_backward(h, head, c, mod, grad_out, grad_head, grad_c, ws, stream=None)
                                _ptr(grad_c, "grad_c", (N, H, W, 3)),
                                ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size()),
            "wskp_backward")
+
+
+def wskp_kp_map_bytes(h, H: int, W: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().wskp_kp_map_bytes(h, H, W, ctypes.byref(out)), "wskp_kp_map_bytes")
+    return out.value
+
+
+def wskp_kp_expand(h, head, maps, stream=None) -> None:
+    _check_head(h, head)
+    N, H, W, _ = head.shape
+    if N != 1:
+        raise ValueError("wskp_kp_expand takes one frame")
+    _check(lib().wskp_kp_expand(h, _stream(stream), H, W, _ptr(head, "head"), _ptr(maps, "maps"),
+                                maps.numel() * 4), "wskp_kp_expand")
+
+
+def wskp_kp_decode(h, maps, head, c, mod, out, stream=None) -> None:
+    _check_head(h, head)
+    N, H, W, _ = head.shape
+    if N != 1:
+        raise ValueError("wskp_kp_decode takes one frame")
+    _check(lib().wskp_kp_decode(h, _stream(stream), H, W, _ptr(maps, "maps"), maps.numel() * 4,
+                                _ptr(head, "head"), _ptr(c, "c", (1, H, W, 3)),
+                                _ptr(mod, "mod", (1, H, W, 3)), _ptr(out, "out", (1, H, W, 3))),
+           "wskp_kp_decode")
 
 
 def wskp_fp8_e4m3_encode(x: np.ndarray) -> np.ndarray:

@@ -152,3 +152,29 @@ def test_autograd_function_l1_training_batch():
         rh, rc = oracle.decode_vjp(head[n], c[n], mod[n], ks, g[n])
         assert rel_l2(th.grad[n].cpu().numpy(), rh) <= TOL_FP32
         assert rel_l2(tc.grad[n].cpu().numpy(), rc) <= TOL_FP32
+
+
+def test_explicit_kernel_map_decode_matches_oracle():
+    """The explicit kernel-map reconstruction (Sec. 5.3's comparison: every
+    pixel's full k x k kernel stored) with maps expanded from the weight
+    maps gives the oracle's Eq. 3-5 result, and the weight-sharing decode's;
+    its map memory is 4 * sum k_i^2 bytes per pixel."""
+    from paper_2202_05977_amd import wskp
+    ks = (3, 5, 7, 9, 11, 13)
+    h = _handle(ks)
+    N, H, W = 1, 45, 83
+    head, c, mod = _case(31, N, H, W, len(ks))
+    nbytes = wskp.wskp_kp_map_bytes(h, H, W)
+    assert nbytes == 4 * H * W * sum(k * k for k in ks)
+    maps = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    d = lambda a: torch.from_numpy(a).cuda()
+    th = d(head)
+    wskp.wskp_kp_expand(h, th, maps)
+    out = torch.empty((N, H, W, 3), dtype=torch.float32, device="cuda")
+    wskp.wskp_kp_decode(h, maps, th, d(c), d(mod), out)
+    torch.cuda.synchronize()
+    y = out.cpu().numpy()
+    ref = oracle.decode(head[0], c[0], mod[0], ks)
+    assert rel_l2(y[0], ref) <= TOL_FP32 and max_rel(y[0], ref) <= TOL_FP32
+    ws_form = _gpu_decode(h, head, c, mod)
+    assert rel_l2(y, ws_form) <= TOL_FP32

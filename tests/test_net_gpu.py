@@ -391,3 +391,79 @@ def test_fp8_needs_scales_and_32_wide_levels():
         wskp.Denoiser(synth.SMALL, synth.make_weights(synth.SMALL), "fp8",
                       act_scales=np.ones(6, np.float32))
     assert ei.value.status == -3
+
+
+@pytest.mark.parametrize("shift", [0.0, 120.0, -120.0])
+def test_exp_weights_end_to_end_against_oracle(shift):
+    """The literal Eq. 3 form (W = exp(h)) through the whole path in fp32.
+    The head biases of the weight channels are moved by `shift`: at +120 a
+    plain fp32 exp of h would overflow (e^120 > 3.4e38); the kernel takes
+    exp(h - m) with a per-tile maximum m and scales the floor eps the same
+    way, so the result is the oracle's FP64 exp(h) ratio, including at -120
+    where every window sum falls below eps and the floor binds."""
+    import dataclasses
+    from paper_2202_05977_amd import wskp
+    cfg = dataclasses.replace(synth.SMALL, weight_act="exp")
+    blob = synth.make_weights(cfg, 0).copy()
+    M = cfg.M
+    blob[len(blob) - 2 * M:len(blob) - M] += np.float32(shift)
+    H, W = 72, 104
+    fr = synth.make_frame(5, H, W)
+    y = oracle.denoise(fr, blob, cfg)
+    dn = wskp.Denoiser(cfg, blob, "fp32")
+    out = _run(dn, fr)
+    assert np.all(np.isfinite(out))
+    if shift < 0:
+        # eps binds: out = mod * N / eps with N ~ e^-120: zero to within fp32
+        assert np.abs(y).max() < 1e-30 and np.abs(out).max() < 1e-30
+    else:
+        assert rel_l2(out, y) <= TOL_FP32 and max_rel(out, y) <= TOL_FP32
+    dn.close()
+
+
+def test_exp_weights_hd_bf16_against_oracle():
+    """exp weights with the hd net in bf16 at 1280x720 (BF16 gates)."""
+    import dataclasses
+    from paper_2202_05977_amd import wskp
+    cfg = dataclasses.replace(synth.HD, weight_act="exp")
+    blob = synth.make_weights(cfg, 0)
+    fr = synth.make_frame(1, 720, 1280)
+    y = oracle.denoise(fr, blob, cfg)
+    out = _run(wskp.Denoiser(cfg, blob, "bf16"), fr)
+    assert np.all(np.isfinite(out))
+    assert rel_l2(out, y) <= TOL_BF16 and max_rel(out, y) <= TOL_BF16_MAX
+
+
+def test_zero_albedo_epsilon_against_oracle():
+    """eps_albedo = 0 with strictly positive albedo (the synthetic albedo
+    lies in [0.1, 0.9]): c = r / a exactly; halo pixels outside the image
+    must contribute nothing (not 0 * rcp(0))."""
+    import dataclasses
+    from paper_2202_05977_amd import wskp
+    cfg = dataclasses.replace(synth.SMALL, eps_albedo=0.0)
+    blob = synth.make_weights(cfg, 0)
+    fr = synth.make_frame(6, 72, 104)
+    assert fr["albedo"].min() > 0
+    y = oracle.denoise(fr, blob, cfg)
+    out = _run(wskp.Denoiser(cfg, blob, "fp32"), fr)
+    assert np.all(np.isfinite(out))
+    assert rel_l2(out, y) <= TOL_FP32 and max_rel(out, y) <= TOL_FP32
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_paper_kernel_set_720p_against_oracle(prec):
+    """The paper's configuration of the reconstruction: six kernel sizes
+    3, 5, ..., 13 with exp weights (the window softmax of Eq. 3) and six
+    fusion logits, end to end at 1280x720 against the FP64 oracle."""
+    from paper_2202_05977_amd import wskp
+    cfg = synth.PAPER6
+    blob = synth.make_weights(cfg, 0)
+    fr, y, _ = _oracle("paper6", 1, 720, 1280)
+    out = _run(wskp.Denoiser(cfg, blob, prec), fr)
+    assert np.all(np.isfinite(out))
+    err, mx = rel_l2(out, y), max_rel(out, y)
+    print(f"paper kernel set 720p {prec}: rel-L2 {err:.3e}, max-rel {mx:.3e}")
+    if prec == "fp32":
+        assert err <= TOL_FP32 and mx <= TOL_FP32
+    else:
+        assert err <= TOL_BF16 and mx <= TOL_BF16_MAX
