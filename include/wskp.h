@@ -122,9 +122,12 @@ typedef struct {
  * Returns 0 for an invalid config. */
 size_t wskp_num_weights(const wskp_config_t *cfg);
 
-/* Creates a handle on HIP device `device`: validates cfg, copies the host
- * weight blob (n_weights floats, owned by the caller, not retained) to the
- * device in the layout the kernels read.  Synchronous.
+/* Creates a handle on HIP device `device` for the prediction network of
+ * Sec. 4.1 (Eq. 2: the network maps the noisy frame and its auxiliary
+ * buffers to the per-pixel scalars that define every kernel) and the kernel
+ * set of Sec. 4.2: validates cfg, copies the host weight blob (n_weights
+ * floats, owned by the caller, not retained) to the device in the layout
+ * the kernels read.  Synchronous.
  * host_act_scales: for WSKP_PREC_FP8_E4M3 only (ignored otherwise, may be
  * NULL), one positive float per conv in blob order: the scale s of that
  * conv's input activations, which are stored as e4m3(x / s) (values beyond
@@ -209,7 +212,8 @@ wskp_status_t wskp_denoise_batch(wskp_handle_t h, void *stream, int n, const wsk
 wskp_status_t wskp_decode(wskp_handle_t h, void *stream, int N, int H, int W, const float *head,
                           const float *c, const float *mod, float *out);
 
-/* Vector-Jacobian product of wskp_decode: given grad_out = dL/dout
+/* Vector-Jacobian product of wskp_decode (the gradient of Eq. 3-5, through
+ * which the paper trains its network, Sec. 5.2): given grad_out = dL/dout
  * [N,H,W,3], writes grad_head = dL/dhead [N,H,W,2M] (weights, then
  * logits) and grad_c = dL/dc [N,H,W,3] (mod is treated as a constant).
  * Both outputs are overwritten, not accumulated.  ws is a device scratch
@@ -221,6 +225,38 @@ wskp_status_t wskp_backward(wskp_handle_t h, void *stream, int N, int H, int W, 
 /* Bytes of device scratch wskp_backward needs for N frames of H x W
  * (16 * M bytes per pixel: per-centre adjoint terms of every kernel size). */
 wskp_status_t wskp_backward_workspace_size(wskp_handle_t h, int N, int H, int W, size_t *bytes);
+
+/* Temporal accumulation before denoising (Sec. 4.1, last paragraph): the
+ * previous frame's accumulated radiance is reprojected to this frame with
+ * the motion vectors and, where the geometry agrees, blended with this
+ * frame's noisy radiance; elsewhere the noisy radiance is kept.  Its output
+ * is the radiance input of wskp_denoise for this frame and the history of
+ * the next one.
+ *   radiance, normal, wpos [H,W,3]   this frame (noisy radiance, shading
+ *                                    normal, world position)
+ *   motion [H,W,2]                   per pixel, the offset (x, y) in pixels
+ *                                    to where its surface point was in the
+ *                                    previous frame
+ *   prev_radiance [H,W,3], prev_length [H,W]   the previous call's outputs;
+ *   prev_normal, prev_wpos [H,W,3]   the previous frame's geometry
+ *   out_radiance [H,W,3], out_length [H,W]     (must not alias the inputs)
+ * With prev_radiance == NULL (first frame, or a cut) out = radiance and
+ * length 1, and only radiance is read.  Otherwise, per pixel p with
+ * q = p + motion(p): of the four pixels around q (bilinear weights), those
+ * inside the image whose world position lies within pos_tol of p's and
+ * whose normal has a dot product >= normal_tol with p's count; S is their
+ * weight.  If S > 0, with h and L the S-normalised weighted means of their
+ * accumulated radiance and length, alpha = max(1/(L+1), alpha_min):
+ * out = (1 - alpha) h + alpha radiance, length L + 1; if S = 0: out =
+ * radiance, length 1.  (The paper gives no blend factor or tolerances;
+ * alpha_min = 0.2, pos_tol = 0.02 world units, normal_tol = 0.9 are the
+ * values the tests and benchmark use.)  The tap tests are evaluated in
+ * double precision.  All pointers are device pointers; H x W <= 2^28. */
+wskp_status_t wskp_temporal(wskp_handle_t h, void *stream, int H, int W, const float *radiance,
+                            const float *normal, const float *wpos, const float *motion,
+                            const float *prev_radiance, const float *prev_length,
+                            const float *prev_normal, const float *prev_wpos, float alpha_min,
+                            float pos_tol, float normal_tol, float *out_radiance, float *out_length);
 
 /* Explicit kernel-map reconstruction, the baseline of the memory and time
  * comparison in Sec. 5.3 (a kernel-prediction network without weight

@@ -63,6 +63,8 @@ def _load():
                                   _dp, _dp, _dp]
         lib.wo_decode_vjp.argtypes = [_L, _L, ctypes.c_int, _ip, _dp, _dp, _dp,
                                       ctypes.c_double, _dp, _dp, _dp]
+        lib.wo_temporal.argtypes = [_L, _L, _fp, _fp, _fp, _fp, _fp, _fp, _fp, _fp,
+                                    ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _dp]
         lib.wo_l1.argtypes = [_L, _dp, _dp, _dp]
         lib.wo_l1.restype = ctypes.c_double
         _lib = lib
@@ -198,6 +200,33 @@ def decode_vjp(head, c, mod, kernel_sizes: Sequence[int], g, eps: float = 1e-10)
     _load().wo_decode_vjp(H, W, M, _ints(kernel_sizes), _ptr(head), _ptr(c), modp, eps,
                           _ptr(g), _ptr(dhead), _ptr(dc))
     return dhead, dc
+
+
+def temporal(radiance, normal, wpos, motion, prev=None, alpha_min: float = 0.2,
+             pos_tol: float = 0.02, normal_tol: float = 0.9):
+    """Temporal accumulation of one frame: (radiance [H,W,3], length [H,W]).
+
+    ``prev`` is None (first frame) or a dict with the previous frame's
+    accumulated ``radiance`` [H,W,3] and ``length`` [H,W] (float32, as the
+    GPU path stores them) and its ``normal`` and ``wpos`` [H,W,3].
+    ``motion`` [H,W,2]: offset (x, y) in pixels from a pixel to its surface
+    point's position in the previous frame.  The three parameters are
+    float32 values (as the library's interface takes them), widened.
+    """
+    alpha_min, pos_tol, normal_tol = (float(np.float32(v)) for v in (alpha_min, pos_tol, normal_tol))
+    r, n, wp, mv = _f(radiance), _f(normal), _f(wpos), _f(motion)
+    H, W = r.shape[:2]
+    out = np.empty((H, W, 3))
+    ln = np.empty((H, W))
+    if prev is None:
+        pr = pl = pn = pw = None
+    else:
+        pr, pl = _f(prev["radiance"]), _f(prev["length"])
+        pn, pw = _f(prev["normal"]), _f(prev["wpos"])
+    fp = lambda a: None if a is None else _ptr(a, _fp)
+    _load().wo_temporal(H, W, _ptr(r, _fp), _ptr(n, _fp), _ptr(wp, _fp), _ptr(mv, _fp), fp(pr), fp(pl),
+                        fp(pn), fp(pw), alpha_min, pos_tol, normal_tol, _ptr(out), _ptr(ln))
+    return out, ln
 
 
 def l1(y, t):

@@ -355,3 +355,74 @@ double wo_l1(long n, const double *y, const double *t, double *g)
     }
     return s / (double)n;
 }
+
+/* ------------------------------------------------------------------------
+ * Temporal accumulation before denoising (Sec. 4.1, last paragraph): the
+ * previous frame's accumulated radiance is reprojected to the current frame
+ * with the motion vector; where the geometry agrees (world position and
+ * shading normal) it is blended with the current 1-spp radiance, elsewhere
+ * the current radiance is kept.  The paper gives no formulas; the reading
+ * taken here (the usual one for such filters):
+ *   q = p + mv(p)            position of p's surface point in the previous
+ *                            frame (pixel-centre units)
+ *   taps: the 4 pixels around q with bilinear weights; a tap counts if it
+ *   lies in the image, |wp_prev(tap) - wp(p)|^2 <= pos_tol^2 and
+ *   n_prev(tap) . n(p) >= normal_tol
+ *   with S = sum of the counted weights:
+ *     S > 0:  h = sum w prev_r / S,  L = sum w prev_len / S,
+ *             alpha = max(1 / (L + 1), alpha_min),
+ *             out = (1 - alpha) h + alpha r,  len = L + 1
+ *     S = 0:  out = r,  len = 1
+ *   prev_r == NULL (first frame): out = r, len = 1 everywhere.
+ * The tap tests take fp32 inputs; their squared distance and dot product
+ * are exact or correctly rounded in double, so any implementation that
+ * evaluates them in double reaches the same decisions.
+ * ---------------------------------------------------------------------- */
+void wo_temporal(long H, long W, const float *r, const float *n, const float *wp, const float *mv,
+                 const float *prev_r, const float *prev_len, const float *prev_n,
+                 const float *prev_wp, double alpha_min, double pos_tol, double normal_tol,
+                 double *out, double *len)
+{
+#pragma omp parallel for schedule(static)
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x) {
+            const long p = y * W + x;
+            if (!prev_r) {
+                for (int ch = 0; ch < 3; ++ch) out[p * 3 + ch] = (double)r[p * 3 + ch];
+                len[p] = 1.0;
+                continue;
+            }
+            const double qx = (double)x + (double)mv[p * 2 + 0];
+            const double qy = (double)y + (double)mv[p * 2 + 1];
+            const double x0 = floor(qx), y0 = floor(qy);
+            const double fx = qx - x0, fy = qy - y0;
+            double S = 0.0, L = 0.0, h[3] = {0.0, 0.0, 0.0};
+            for (int t = 0; t < 4; ++t) {
+                const long tx = (long)x0 + (t & 1), ty = (long)y0 + (t >> 1);
+                const double w = ((t & 1) ? fx : 1.0 - fx) * ((t >> 1) ? fy : 1.0 - fy);
+                if (tx < 0 || tx >= W || ty < 0 || ty >= H) continue;
+                const long q = ty * W + tx;
+                double d2 = 0.0, dot = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    const double d = (double)prev_wp[q * 3 + k] - (double)wp[p * 3 + k];
+                    d2 += d * d;
+                    dot += (double)prev_n[q * 3 + k] * (double)n[p * 3 + k];
+                }
+                if (!(d2 <= pos_tol * pos_tol && dot >= normal_tol)) continue;
+                S += w;
+                L += w * (double)prev_len[q];
+                for (int ch = 0; ch < 3; ++ch) h[ch] += w * (double)prev_r[q * 3 + ch];
+            }
+            if (S > 0.0) {
+                L /= S;
+                double a = 1.0 / (L + 1.0);
+                if (a < alpha_min) a = alpha_min;
+                for (int ch = 0; ch < 3; ++ch)
+                    out[p * 3 + ch] = (1.0 - a) * (h[ch] / S) + a * (double)r[p * 3 + ch];
+                len[p] = L + 1.0;
+            } else {
+                for (int ch = 0; ch < 3; ++ch) out[p * 3 + ch] = (double)r[p * 3 + ch];
+                len[p] = 1.0;
+            }
+        }
+}

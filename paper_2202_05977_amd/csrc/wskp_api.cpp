@@ -891,6 +891,30 @@ extern "C" wskp_status_t wskp_backward(wskp_handle_t h, void *stream, int N, int
     return WSKP_OK;
 }
 
+extern "C" wskp_status_t wskp_temporal(wskp_handle_t h, void *stream, int H, int W, const float *radiance,
+                                       const float *normal, const float *wpos, const float *motion,
+                                       const float *prev_radiance, const float *prev_length,
+                                       const float *prev_normal, const float *prev_wpos, float alpha_min,
+                                       float pos_tol, float normal_tol, float *out_radiance,
+                                       float *out_length)
+{
+    if (!h) return fail(WSKP_E_INVALID_ARG, "handle is NULL");
+    if (!radiance || !out_radiance || !out_length) return fail(WSKP_E_INVALID_ARG, "NULL tensor pointer");
+    const bool first = !prev_radiance;
+    if (!first && (!normal || !wpos || !motion || !prev_length || !prev_normal || !prev_wpos))
+        return fail(WSKP_E_INVALID_ARG, "with a previous frame every geometry buffer is needed");
+    if (H < 1 || W < 1 || (long)H * W > (1L << 28)) return fail(WSKP_E_SHAPE, "H, W out of range");
+    if (!(alpha_min > 0.f && alpha_min <= 1.f) || !(pos_tol >= 0.f) || !(normal_tol >= -1.f && normal_tol <= 1.f))
+        return fail(WSKP_E_INVALID_ARG, "alpha_min in (0, 1], pos_tol >= 0, normal_tol in [-1, 1]");
+    wskp_status_t st = set_device(h);
+    if (st != WSKP_OK) return st;
+    hipError_t e = launch_temporal(H, W, radiance, normal, wpos, motion, prev_radiance, prev_length, prev_normal,
+                                   prev_wpos, alpha_min, pos_tol, normal_tol, out_radiance, out_length,
+                                   static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "temporal launch", WSKP_E_LAUNCH);
+    return WSKP_OK;
+}
+
 extern "C" wskp_status_t wskp_kp_map_bytes(wskp_handle_t h, int H, int W, size_t *bytes)
 {
     if (!h || !bytes) return fail(WSKP_E_INVALID_ARG, "NULL argument");

@@ -229,6 +229,10 @@ hipError_t launch_decode_backward(const DecodeCfg &dc, int N, int H, int W, cons
                                   float *grad_head, float *grad_c, void *scratch,
                                   hipStream_t s);
 size_t decode_backward_scratch_bytes(const DecodeCfg &dc, int N, int H, int W);
+// Temporal accumulation of one frame (temporal.hip); pr == nullptr: first frame.
+hipError_t launch_temporal(int H, int W, const float *r, const float *n, const float *wp, const float *mv,
+                           const float *pr, const float *pl, const float *pn, const float *pw, float alpha_min,
+                           float pos_tol, float normal_tol, float *out, float *len, hipStream_t s);
 // Explicit kernel-map reconstruction (the comparison of Sec. 5.3, kp.hip).
 size_t kp_map_floats(const DecodeCfg &dc, int H, int W);
 hipError_t launch_kp_expand(const DecodeCfg &dc, int H, int W, const float *head, float *maps, hipStream_t s);

@@ -284,7 +284,8 @@ class GpuExecutor(Executor):
     """
 
     def __init__(self, denoiser, stream_inputs: Dict[int, "object"], ws_bytes: int,
-                 slots: int = 2, ring: Optional[int] = None, graph: bool = False):
+                 slots: int = 2, ring: Optional[int] = None, graph: bool = False,
+                 temporal: bool = False):
         import torch
         from . import wskp
         self.torch = torch
@@ -294,6 +295,17 @@ class GpuExecutor(Executor):
                        for s, f in stream_inputs.items()}
         ring = slots + 1 if ring is None else ring
         self.per_stream_cap = ring
+        # temporal accumulation (Sec. 4.1): each stream keeps its accumulated
+        # radiance and history length on the device, in two slots that
+        # consecutive frames alternate between; a frame reads the previous
+        # frame's slot, so a stream has one frame in flight at a time
+        self.temporal = temporal
+        if temporal:
+            self.per_stream_cap = 1
+            self.state = {s: [(torch.empty_like(f[0]["radiance"]),
+                               torch.empty(f[0]["radiance"].shape[:2], dtype=torch.float32,
+                                           device=f[0]["radiance"].device)) for _ in range(2)]
+                          for s, f in self.inputs.items()}
         # graph replay: one HIP graph per stream and capacity bucket
         self.flags = wskp.BATCH_GRAPH if graph else 0
         self.outputs = {s: [torch.empty_like(f[0]["radiance"]) for _ in range(ring)]
@@ -323,7 +335,18 @@ class GpuExecutor(Executor):
         s = self.streams[slot]
         frames = []
         for r in reqs:
-            f = {k: v for k, v in self.input_of(r.stream, r.seq).items() if k != "clean"}
+            src = self.input_of(r.stream, r.seq)
+            f = {k: src[k] for k in ("radiance", "albedo", "normal", "depth")}
+            if self.temporal:
+                acc, ln = self.state[r.stream][r.seq % 2]
+                prev = None
+                if r.seq > 0:
+                    pa, pl = self.state[r.stream][(r.seq - 1) % 2]
+                    ps = self.input_of(r.stream, r.seq - 1)
+                    prev = {"radiance": pa, "length": pl, "normal": ps["normal"], "wpos": ps["wpos"]}
+                self.wskp.wskp_temporal(self.dn.h, src["radiance"], src["normal"], src["wpos"],
+                                        src["motion"], prev, acc, ln, stream=s)
+                f["radiance"] = acc
             f["out"] = self.output_of(r.stream, r.seq)
             frames.append(f)
         need = self.workspace_bytes(reqs)

@@ -186,6 +186,90 @@ def make_frame(seed: int, H: int, W: int) -> Dict[str, np.ndarray]:
     }
 
 
+def make_sequence(seed: int, H: int, W: int, T: int, pan=(1.37, -0.61), obj_vel=(2.3, 1.1)):
+    """T consecutive synthetic 1-spp frames of a moving scene, for temporal
+    accumulation (Sec. 4.1, last paragraph).
+
+    The camera pans across the procedural scene of ``make_frame`` by
+    ``pan`` pixels per frame and a disk (radius 0.12 min(H, W), a flat
+    surface at depth 1.2 with its own albedo) moves over it by ``obj_vel``
+    pixels per frame.  Each frame has fresh noise and, besides the keys of
+    ``make_frame``, ``wpos`` [H,W,3] (world position: scene x and y in units
+    of 1000 pixels, depth / 100) and ``motion`` [H,W,2] (offset in pixels from a
+    pixel to where its surface point was in the previous frame: ``pan`` on
+    the background, ``pan - obj_vel`` on the disk; zero in frame 0).  Where
+    the disk uncovers background, the previous frame showed the disk there
+    and the world positions disagree.
+    """
+    rng = np.random.default_rng(seed)
+    A = rng.uniform(0.02, 0.12, size=8)
+    fx = rng.uniform(-12.0, 12.0, size=8)
+    fy = rng.uniform(-12.0, 12.0, size=8)
+    ph = rng.uniform(0.0, 2 * np.pi, size=8)
+    tint = rng.uniform(0.8, 1.2, size=3)
+    sites = rng.uniform(0.0, 1.0, size=(12, 2))
+    colours = rng.uniform(0.1, 0.9, size=(12, 3))
+    B = rng.uniform(0.005, 0.02, size=4)
+    g = rng.uniform(-6.0, 6.0, size=(4, 2))
+    psi = rng.uniform(0.0, 2 * np.pi, size=4)
+    s1, s2 = rng.uniform(1.0, 4.0, size=2)
+    t1, t2 = rng.uniform(0.0, 2 * np.pi, size=2)
+    obj_albedo = np.array([0.8, 0.35, 0.2])
+    rad = 0.12 * min(H, W)
+    c0 = np.array([0.3 * W, 0.4 * H])
+    xs, ys = np.meshgrid(np.arange(W, dtype=np.float64) + 0.5, np.arange(H, dtype=np.float64) + 0.5)
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    frames = []
+    for t in range(T):
+        # background: the scene at pixel coordinates shifted by the pan
+        px, py = xs + t * pan[0], ys + t * pan[1]
+        u, v = px / W, py / H
+        E = np.full((H, W), 0.25)
+        for j in range(8):
+            E += A[j] * (1.0 + np.sin(2 * np.pi * (fx[j] * u + fy[j] * v) + ph[j]))
+        best = np.full((H, W), np.inf)
+        label = np.zeros((H, W), dtype=np.int64)
+        for k in range(12):
+            dist = (px - sites[k, 0] * W) ** 2 + (py - sites[k, 1] * H) ** 2
+            closer = dist < best
+            best = np.where(closer, dist, best)
+            label = np.where(closer, k, label)
+        albedo = colours[label]
+        hx = np.zeros((H, W))
+        hy = np.zeros((H, W))
+        for j in range(4):
+            arg = 2 * np.pi * (g[j, 0] * u + g[j, 1] * v) + psi[j]
+            hx += B[j] * np.cos(arg) * 2 * np.pi * g[j, 0]
+            hy += B[j] * np.cos(arg) * 2 * np.pi * g[j, 1]
+        nrm = np.stack([-hx, -hy, np.ones_like(hx)], axis=-1)
+        nrm /= np.linalg.norm(nrm, axis=-1, keepdims=True)
+        dd = 0.5 + 0.25 * (np.sin(2 * np.pi * u * s1 + t1) + np.sin(2 * np.pi * v * s2 + t2))
+        depth = 1.0 + 9.0 * np.clip(dd, 0.0, 1.0)
+        wpos = np.stack([px / 1000.0, py / 1000.0, depth / 100.0], axis=-1)
+        motion = np.broadcast_to(np.array(pan, dtype=np.float64), (H, W, 2)).copy()
+        # the moving disk (screen space)
+        cx, cy = c0[0] + t * obj_vel[0], c0[1] + t * obj_vel[1]
+        inside = (xs - cx) ** 2 + (ys - cy) ** 2 <= rad * rad
+        E = np.where(inside, 0.6, E)
+        albedo = np.where(inside[..., None], obj_albedo[None, None, :], albedo)
+        nrm = np.where(inside[..., None], np.array([0.0, 0.0, 1.0])[None, None, :], nrm)
+        depth = np.where(inside, 1.2, depth)
+        obj_w = np.stack([(xs - cx + c0[0] + t * obj_vel[0]) / 1000.0,
+                          (ys - cy + c0[1] + t * obj_vel[1]) / 1000.0, np.full((H, W), 0.012)], axis=-1)
+        wpos = np.where(inside[..., None], obj_w, wpos)
+        motion = np.where(inside[..., None], np.array([pan[0] - obj_vel[0], pan[1] - obj_vel[1]]), motion)
+        if t == 0:
+            motion = np.zeros_like(motion)
+        clean = albedo * tint[None, None, :] * E[..., None]
+        G = rng.gamma(0.5, 2.0, size=(H, W, 3))
+        fire = rng.random(size=(H, W)) < 1e-3
+        G = G * np.where(fire, 50.0, 1.0)[..., None]
+        frames.append({"radiance": f32(clean * G), "albedo": f32(albedo), "normal": f32(nrm),
+                       "depth": f32(depth[..., None]), "clean": f32(clean), "wpos": f32(wpos),
+                       "motion": f32(motion)})
+    return frames
+
+
 def make_frame_batch(seeds, H: int, W: int) -> Dict[str, np.ndarray]:
     """Stack frames of one size along a leading batch axis."""
     frames = [make_frame(s, H, W) for s in seeds]

@@ -90,6 +90,8 @@ def lib():
         L.wskp_decode.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp]
         L.wskp_backward.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, sz]
         L.wskp_backward_workspace_size.argtypes = [vp, i32, i32, i32, ctypes.POINTER(sz)]
+        L.wskp_temporal.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp,
+                                    ctypes.c_float, ctypes.c_float, ctypes.c_float, vp, vp]
         L.wskp_kp_map_bytes.argtypes = [vp, i32, i32, ctypes.POINTER(sz)]
         L.wskp_kp_expand.argtypes = [vp, vp, i32, i32, vp, vp, sz]
         L.wskp_kp_decode.argtypes = [vp, vp, i32, i32, vp, sz, vp, vp, vp, vp]
@@ -108,7 +110,7 @@ def lib():
         for name in ("wskp_create", "wskp_destroy", "wskp_workspace_size", "wskp_denoise",
                      "wskp_denoise_static", "wskp_denoise_batch", "wskp_decode", "wskp_backward",
                      "wskp_backward_workspace_size", "wskp_workspace_tensor",
-                     "wskp_kp_map_bytes", "wskp_kp_expand", "wskp_kp_decode",
+                     "wskp_kp_map_bytes", "wskp_kp_expand", "wskp_kp_decode", "wskp_temporal",
                      "wskp_timing_enable", "wskp_timing_read"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -286,6 +288,29 @@ def wskp_backward(h, head, c, mod, grad_out, grad_head, grad_c, ws, stream=None)
                                _ptr(grad_c, "grad_c", (N, H, W, 3)),
                                ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size()),
            "wskp_backward")
+
+
+TEMPORAL_DEFAULTS = {"alpha_min": 0.2, "pos_tol": 0.02, "normal_tol": 0.9}
+
+
+def wskp_temporal(h, radiance, normal, wpos, motion, prev, out_radiance, out_length,
+                  alpha_min: float = 0.2, pos_tol: float = 0.02, normal_tol: float = 0.9,
+                  stream=None) -> None:
+    """prev: None (first frame) or a dict with the previous call's
+    ``radiance`` and ``length`` and the previous frame's ``normal`` and
+    ``wpos``."""
+    H, W = radiance.shape[:2]
+    p = prev or {}
+    _check(lib().wskp_temporal(
+        h, _stream(stream), H, W, _ptr(radiance, "radiance", (H, W, 3)),
+        _ptr(normal, "normal", (H, W, 3)), _ptr(wpos, "wpos", (H, W, 3)),
+        _ptr(motion, "motion", (H, W, 2)),
+        _ptr(p.get("radiance"), "prev radiance", (H, W, 3)),
+        _ptr(p.get("length"), "prev length", (H, W)),
+        _ptr(p.get("normal"), "prev normal", (H, W, 3)),
+        _ptr(p.get("wpos"), "prev wpos", (H, W, 3)),
+        alpha_min, pos_tol, normal_tol, _ptr(out_radiance, "out radiance", (H, W, 3)),
+        _ptr(out_length, "out length", (H, W))), "wskp_temporal")
 
 
 def wskp_kp_map_bytes(h, H: int, W: int) -> int:
