@@ -226,6 +226,21 @@ wskp_status_t wskp_backward(wskp_handle_t h, void *stream, int N, int H, int W, 
  * (16 * M bytes per pixel: per-centre adjoint terms of every kernel size). */
 wskp_status_t wskp_backward_workspace_size(wskp_handle_t h, int N, int H, int W, size_t *bytes);
 
+/* Multi-resolution reconstruction (Sec. 5.2, the paper's network for
+ * high-spp input): the irradiance is filtered at L resolutions, level l
+ * with its own head record (wskp_decode on the 2x2-pooled irradiance, mod
+ * NULL), and adjacent levels are combined from the coarsest by Eq. 7:
+ *   o_p = fine_p - alpha_p [U D fine]_p + alpha_p [U coarse]_p
+ * with D the 2x2 mean and U nearest-neighbour upsampling.
+ * wskp_pool2: out [H/2,W/2,3] = 2x2 means of in [H,W,3].
+ * wskp_mr_blend: fine [H,W,3], coarse [H/2,W/2,3], alpha [H,W] -> out
+ *   [H,W,3] by Eq. 7, times mod [H,W,3] if mod is not NULL (the
+ *   remodulation, for the finest level).  out must not alias fine.
+ * H and W even; device pointers. */
+wskp_status_t wskp_pool2(wskp_handle_t h, void *stream, int H, int W, const float *in, float *out);
+wskp_status_t wskp_mr_blend(wskp_handle_t h, void *stream, int H, int W, const float *fine,
+                            const float *coarse, const float *alpha, const float *mod, float *out);
+
 /* Temporal accumulation before denoising (Sec. 4.1, last paragraph): the
  * previous frame's accumulated radiance is reprojected to this frame with
  * the motion vectors and, where the geometry agrees, blended with this

@@ -65,6 +65,7 @@ def _load():
                                       ctypes.c_double, _dp, _dp, _dp]
         lib.wo_temporal.argtypes = [_L, _L, _fp, _fp, _fp, _fp, _fp, _fp, _fp, _fp,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _dp]
+        lib.wo_mr_blend.argtypes = [_L, _L, _dp, _dp, _dp, _dp]
         lib.wo_l1.argtypes = [_L, _dp, _dp, _dp]
         lib.wo_l1.restype = ctypes.c_double
         _lib = lib
@@ -227,6 +228,36 @@ def temporal(radiance, normal, wpos, motion, prev=None, alpha_min: float = 0.2,
     _load().wo_temporal(H, W, _ptr(r, _fp), _ptr(n, _fp), _ptr(wp, _fp), _ptr(mv, _fp), fp(pr), fp(pl),
                         fp(pn), fp(pw), alpha_min, pos_tol, normal_tol, _ptr(out), _ptr(ln))
     return out, ln
+
+
+def mr_blend(fine, coarse, alpha) -> np.ndarray:
+    """Eq. 7: o = fine - alpha * U(D(fine)) + alpha * U(coarse); fine
+    [H,W,3], coarse [H/2,W/2,3], alpha [H,W] (H, W even)."""
+    fine, coarse, alpha = _d(fine), _d(coarse), _d(alpha)
+    H, W = fine.shape[:2]
+    assert H % 2 == 0 and W % 2 == 0 and coarse.shape == (H // 2, W // 2, 3)
+    assert alpha.shape == (H, W)
+    out = np.empty((H, W, 3))
+    _load().wo_mr_blend(H, W, _ptr(fine), _ptr(coarse), _ptr(alpha), _ptr(out))
+    return out
+
+
+def mr_reconstruct(heads, c, alphas, mod, kernel_sizes: Sequence[int], eps: float = 1e-10):
+    """Multi-resolution reconstruction (Sec. 5.2): level l filters the
+    irradiance pooled l times, c_l = D^l c, with its own head record
+    heads[l] [H>>l, W>>l, 2M] (the weight-sharing decode of Eq. 3-5 without
+    remodulation), and the levels are blended from the coarsest with
+    Eq. 7 using alphas[l] [H>>l, W>>l] for l < L-1; the result is
+    remodulated with mod [H,W,3] (None = 1)."""
+    L = len(heads)
+    cs = [_d(c)]
+    for _ in range(1, L):
+        cs.append(avgpool2(cs[-1]))
+    i = [decode(heads[l], cs[l], None, kernel_sizes, eps) for l in range(L)]
+    o = i[L - 1]
+    for l in range(L - 2, -1, -1):
+        o = mr_blend(i[l], o, alphas[l])
+    return o if mod is None else o * _d(mod)
 
 
 def l1(y, t):

@@ -426,3 +426,32 @@ void wo_temporal(long H, long W, const float *r, const float *n, const float *wp
             }
         }
 }
+
+/* ------------------------------------------------------------------------
+ * Multi-resolution blend (Eq. 7, Sec. 5.2): filtered images of two adjacent
+ * resolutions, fine i^f [H,W,3] and coarse i^c [H/2,W/2,3], are combined
+ * with a per-pixel weight alpha [H,W] as
+ *   o_p = i^f_p - alpha_p [U D i^f]_p + alpha_p [U i^c]_p
+ * D: 2x2 mean (downsampling), U: nearest-neighbour upsampling, so for fine
+ * pixel (y, x) both bracketed terms are taken at coarse pixel (y/2, x/2).
+ * H and W are even.
+ * ---------------------------------------------------------------------- */
+void wo_mr_blend(long H, long W, const double *fine, const double *coarse, const double *alpha,
+                 double *out)
+{
+    const long Wc = W / 2;
+#pragma omp parallel for schedule(static)
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x) {
+            const long yc = y / 2, xc = x / 2;
+            const double a = alpha[y * W + x];
+            for (int ch = 0; ch < 3; ++ch) {
+                const double dfine = 0.25 * (fine[IDX(2 * yc, 2 * xc, ch, W, 3)] +
+                                             fine[IDX(2 * yc, 2 * xc + 1, ch, W, 3)] +
+                                             fine[IDX(2 * yc + 1, 2 * xc, ch, W, 3)] +
+                                             fine[IDX(2 * yc + 1, 2 * xc + 1, ch, W, 3)]);
+                out[IDX(y, x, ch, W, 3)] =
+                    fine[IDX(y, x, ch, W, 3)] - a * dfine + a * coarse[IDX(yc, xc, ch, Wc, 3)];
+            }
+        }
+}

@@ -891,6 +891,31 @@ extern "C" wskp_status_t wskp_backward(wskp_handle_t h, void *stream, int N, int
     return WSKP_OK;
 }
 
+extern "C" wskp_status_t wskp_pool2(wskp_handle_t h, void *stream, int H, int W, const float *in, float *out)
+{
+    if (!h || !in || !out) return fail(WSKP_E_INVALID_ARG, "NULL argument");
+    if (H < 2 || W < 2 || H % 2 || W % 2 || (long)H * W > (1L << 28))
+        return fail(WSKP_E_SHAPE, "H and W must be even, >= 2");
+    wskp_status_t st = set_device(h);
+    if (st != WSKP_OK) return st;
+    hipError_t e = launch_pool2(H, W, in, out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "pool2 launch", WSKP_E_LAUNCH);
+    return WSKP_OK;
+}
+
+extern "C" wskp_status_t wskp_mr_blend(wskp_handle_t h, void *stream, int H, int W, const float *fine,
+                                       const float *coarse, const float *alpha, const float *mod, float *out)
+{
+    if (!h || !fine || !coarse || !alpha || !out) return fail(WSKP_E_INVALID_ARG, "NULL argument");
+    if (H < 2 || W < 2 || H % 2 || W % 2 || (long)H * W > (1L << 28))
+        return fail(WSKP_E_SHAPE, "H and W must be even, >= 2");
+    wskp_status_t st = set_device(h);
+    if (st != WSKP_OK) return st;
+    hipError_t e = launch_mr_blend(H, W, fine, coarse, alpha, mod, out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "mr blend launch", WSKP_E_LAUNCH);
+    return WSKP_OK;
+}
+
 extern "C" wskp_status_t wskp_temporal(wskp_handle_t h, void *stream, int H, int W, const float *radiance,
                                        const float *normal, const float *wpos, const float *motion,
                                        const float *prev_radiance, const float *prev_length,

@@ -229,6 +229,11 @@ hipError_t launch_decode_backward(const DecodeCfg &dc, int N, int H, int W, cons
                                   float *grad_head, float *grad_c, void *scratch,
                                   hipStream_t s);
 size_t decode_backward_scratch_bytes(const DecodeCfg &dc, int N, int H, int W);
+// Multi-resolution reconstruction pieces (mr.hip): 2x2 mean of a 3-channel
+// image, and the Eq. 7 blend (optionally remodulated).
+hipError_t launch_pool2(int H, int W, const float *in, float *out, hipStream_t s);
+hipError_t launch_mr_blend(int H, int W, const float *fine, const float *coarse, const float *alpha,
+                           const float *mod, float *out, hipStream_t s);
 // Temporal accumulation of one frame (temporal.hip); pr == nullptr: first frame.
 hipError_t launch_temporal(int H, int W, const float *r, const float *n, const float *wp, const float *mv,
                            const float *pr, const float *pl, const float *pn, const float *pw, float alpha_min,

@@ -90,6 +90,8 @@ def lib():
         L.wskp_decode.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp]
         L.wskp_backward.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, sz]
         L.wskp_backward_workspace_size.argtypes = [vp, i32, i32, i32, ctypes.POINTER(sz)]
+        L.wskp_pool2.argtypes = [vp, vp, i32, i32, vp, vp]
+        L.wskp_mr_blend.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp]
         L.wskp_temporal.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp,
                                     ctypes.c_float, ctypes.c_float, ctypes.c_float, vp, vp]
         L.wskp_kp_map_bytes.argtypes = [vp, i32, i32, ctypes.POINTER(sz)]
@@ -111,6 +113,7 @@ def lib():
                      "wskp_denoise_static", "wskp_denoise_batch", "wskp_decode", "wskp_backward",
                      "wskp_backward_workspace_size", "wskp_workspace_tensor",
                      "wskp_kp_map_bytes", "wskp_kp_expand", "wskp_kp_decode", "wskp_temporal",
+                     "wskp_pool2", "wskp_mr_blend",
                      "wskp_timing_enable", "wskp_timing_read"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -288,6 +291,49 @@ def wskp_backward(h, head, c, mod, grad_out, grad_head, grad_c, ws, stream=None)
                                _ptr(grad_c, "grad_c", (N, H, W, 3)),
                                ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size()),
            "wskp_backward")
+
+
+def wskp_pool2(h, x, out, stream=None) -> None:
+    H, W = x.shape[:2]
+    _check(lib().wskp_pool2(h, _stream(stream), H, W, _ptr(x, "in", (H, W, 3)),
+                            _ptr(out, "out", (H // 2, W // 2, 3))), "wskp_pool2")
+
+
+def wskp_mr_blend(h, fine, coarse, alpha, mod, out, stream=None) -> None:
+    H, W = fine.shape[:2]
+    _check(lib().wskp_mr_blend(h, _stream(stream), H, W, _ptr(fine, "fine", (H, W, 3)),
+                               _ptr(coarse, "coarse", (H // 2, W // 2, 3)),
+                               _ptr(alpha, "alpha", (H, W)), _ptr(mod, "mod", (H, W, 3)),
+                               _ptr(out, "out", (H, W, 3))), "wskp_mr_blend")
+
+
+def mr_reconstruct(h, heads, c, alphas, mod, stream=None):
+    """Multi-resolution reconstruction through the C entry points (argument
+    marshalling only): heads[l] [1, H>>l, W>>l, 2M] activated head records,
+    c [H,W,3] irradiance, alphas[l] [H>>l, W>>l] for the L-1 finer levels,
+    mod [H,W,3] or None.  Pools c L-1 times (wskp_pool2), filters each level
+    (wskp_decode) and blends from the coarsest (wskp_mr_blend)."""
+    L = len(heads)
+    cs = [c]
+    for _ in range(1, L):
+        Hc, Wc = cs[-1].shape[0] // 2, cs[-1].shape[1] // 2
+        nxt = torch.empty((Hc, Wc, 3), dtype=torch.float32, device=c.device)
+        wskp_pool2(h, cs[-1], nxt, stream)
+        cs.append(nxt)
+    outs = []
+    for l in range(L):
+        o = torch.empty((1,) + tuple(cs[l].shape), dtype=torch.float32, device=c.device)
+        m = mod.unsqueeze(0) if (L == 1 and mod is not None) else None
+        wskp_decode(h, heads[l], cs[l].unsqueeze(0), m, o, stream)
+        outs.append(o[0])
+    o = outs[L - 1]
+    if L == 1:
+        return o
+    for l in range(L - 2, -1, -1):
+        nxt = torch.empty_like(outs[l])
+        wskp_mr_blend(h, outs[l], o, alphas[l], mod if l == 0 else None, nxt, stream)
+        o = nxt
+    return o
 
 
 TEMPORAL_DEFAULTS = {"alpha_min": 0.2, "pos_tol": 0.02, "normal_tol": 0.9}
