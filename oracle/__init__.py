@@ -66,6 +66,13 @@ def _load():
         lib.wo_temporal.argtypes = [_L, _L, _fp, _fp, _fp, _fp, _fp, _fp, _fp, _fp,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp, _dp]
         lib.wo_mr_blend.argtypes = [_L, _L, _dp, _dp, _dp, _dp]
+        lib.wo_smape.argtypes = [_L, _dp, _dp, ctypes.c_double, _dp]
+        lib.wo_smape.restype = ctypes.c_double
+        lib.wo_conv3x3_backward.argtypes = [_L, _L, _L, _L, _dp, _dp, _dp, _dp, _dp, _dp]
+        lib.wo_avgpool2_backward.argtypes = [_L, _L, _L, _dp, _dp]
+        lib.wo_upsample2_backward.argtypes = [_L, _L, _L, _dp, _dp]
+        lib.wo_adam.argtypes = [_L, _dp, _dp, _dp, _dp, _L, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_double]
         lib.wo_l1.argtypes = [_L, _dp, _dp, _dp]
         lib.wo_l1.restype = ctypes.c_double
         _lib = lib
@@ -318,3 +325,130 @@ def unet_layers(X, blob, cfg) -> Dict[str, np.ndarray]:
         out[f"u{l}"] = u
     out["h"] = conv3x3(u, *convs[-1], relu=False)
     return out
+
+
+# ---------------------------------------------------------------- training
+def smape(y, t, eps: float = 0.01):
+    """(SMAPE (Eq. 6), its gradient with respect to y)."""
+    y, t = _d(y), _d(t)
+    g = np.empty_like(y)
+    v = _load().wo_smape(y.size, _ptr(y), _ptr(t), eps, _ptr(g))
+    return v, g
+
+
+def conv3x3_backward(x, w, g, need_dx: bool = True):
+    """(dx, dw, db) of out = conv3x3(x; w, b) for upstream gradient g."""
+    x, w, g = _d(x), _d(w), _d(g)
+    H, W, Cin = x.shape
+    Cout = w.shape[0]
+    dx = np.empty_like(x) if need_dx else None
+    dw = np.empty_like(w)
+    db = np.empty(Cout)
+    _load().wo_conv3x3_backward(H, W, Cin, Cout, _ptr(x), _ptr(w), _ptr(g),
+                                _ptr(dx) if need_dx else None, _ptr(dw), _ptr(db))
+    return dx, dw, db
+
+
+def avgpool2_backward(dout) -> np.ndarray:
+    dout = _d(dout)
+    Ho, Wo, C = dout.shape
+    din = np.empty((2 * Ho, 2 * Wo, C))
+    _load().wo_avgpool2_backward(2 * Ho, 2 * Wo, C, _ptr(dout), _ptr(din))
+    return din
+
+
+def upsample2_backward(dout) -> np.ndarray:
+    dout = _d(dout)
+    H2, W2, C = dout.shape
+    din = np.empty((H2 // 2, W2 // 2, C))
+    _load().wo_upsample2_backward(H2 // 2, W2 // 2, C, _ptr(dout), _ptr(din))
+    return din
+
+
+def adam(w, g, m, v, t: int, lr: float = 1e-3, b1: float = 0.9, b2: float = 0.999,
+         eps: float = 1e-8):
+    """One Adam step in place on float64 arrays w, m, v (t >= 1)."""
+    for a in (w, m, v):
+        assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    g = _d(g)
+    _load().wo_adam(w.size, _ptr(w), _ptr(g), _ptr(m), _ptr(v), t, lr, b1, b2, eps)
+
+
+def _convs(blob, cfg, in_ch: int = 10):
+    """[(w [Co,Ci,3,3], b [Co])] in blob order, as float64."""
+    blob = _d(blob)
+    L, ch = cfg.levels, cfg.channels
+    cin = [in_ch] + [ch[l - 1] for l in range(1, L)] + \
+          [ch[l + 1] + ch[l] for l in range(L - 2, -1, -1)] + [ch[0]]
+    cout = [ch[l] for l in range(L)] + [ch[l] for l in range(L - 2, -1, -1)] + \
+           [2 * len(cfg.kernel_sizes)]
+    out, off = [], 0
+    for ci, co in zip(cin, cout):
+        w = blob[off:off + co * ci * 9].reshape(co, ci, 3, 3)
+        off += co * ci * 9
+        b = blob[off:off + co]
+        off += co
+        out.append((w, b))
+    return out
+
+
+def train_grads(frame: Dict[str, np.ndarray], target, blob, cfg, eps_smape: float = 0.01,
+                cotangent=None):
+    """(SMAPE loss, gradient of the loss with respect to the weight blob)
+    for one frame: the whole per-frame path forward (preprocess, U-Net,
+    weight activation, decode, fusion, remodulation), SMAPE against the
+    reference ``target`` [H,W,3], and the chain rule back through every step
+    (Eq. 1 minimised over the network parameters).  The gradient has the
+    blob's layout.  With ``cotangent`` g [H,W,3] the loss is instead the
+    linear functional sum(g * y) (a smooth loss, for finite differences)."""
+    L, ch, M = cfg.levels, cfg.channels, len(cfg.kernel_sizes)
+    X, c, mod = preprocess(frame["radiance"], frame["albedo"], frame["normal"], frame["depth"],
+                           cfg.gamma, cfg.depth_near, cfg.depth_far, cfg.eps_albedo)
+    lay = unet_layers(X, blob, cfg)
+    h = lay["h"]
+    head = activate(h, M, cfg.weight_act)
+    y = decode(head, c, mod, cfg.kernel_sizes, cfg.eps_norm)
+    if cotangent is None:
+        loss, gy = smape(y, target, eps_smape)
+    else:
+        gy = _d(cotangent)
+        loss = float(np.sum(gy * y))
+    dhead, _ = decode_vjp(head, c, mod, cfg.kernel_sizes, gy, cfg.eps_norm)
+    dh = dhead.copy()
+    if cfg.weight_act == "exp":
+        dh[..., :M] *= head[..., :M]
+    else:
+        dh[..., :M] *= 1.0 / (1.0 + np.exp(-h[..., :M]))      # softplus' = logistic
+    convs = _convs(blob, cfg)
+    grads = [None] * len(convs)
+    e = [lay[f"e{l}"] for l in range(L)]
+    u = [lay[f"u{l}"] for l in range(L - 1)] + [e[L - 1]]
+    # head
+    du = [np.zeros_like(x) for x in u]
+    de = [np.zeros_like(x) for x in e]
+    dx, dw, db = conv3x3_backward(u[0], convs[-1][0], dh)
+    grads[-1] = (dw, db)
+    du[0] += dx
+    # decoders, finest first (blob index L + j for level l = L - 2 - j)
+    for l in range(0, L - 1):
+        j = L - 2 - l
+        gpre = du[l] * (u[l] > 0.0)
+        cat = np.concatenate([upsample2(u[l + 1]), e[l]], axis=-1)
+        dcat, dw, db = conv3x3_backward(cat, convs[L + j][0], gpre)
+        grads[L + j] = (dw, db)
+        du[l + 1] += upsample2_backward(dcat[..., :ch[l + 1]])
+        de[l] += dcat[..., ch[l + 1]:]
+    de[L - 1] += du[L - 1] if L > 1 else 0.0
+    if L == 1:
+        de[0] = du[0]
+    # encoders, coarsest first
+    for l in range(L - 1, 0, -1):
+        gpre = de[l] * (e[l] > 0.0)
+        dpool, dw, db = conv3x3_backward(avgpool2(e[l - 1]), convs[l][0], gpre)
+        grads[l] = (dw, db)
+        de[l - 1] += avgpool2_backward(dpool)
+    gpre = de[0] * (e[0] > 0.0)
+    _, dw, db = conv3x3_backward(X, convs[0][0], gpre, need_dx=False)
+    grads[0] = (dw, db)
+    flat = np.concatenate([np.concatenate([dw.ravel(), db]) for dw, db in grads])
+    return loss, flat

@@ -455,3 +455,117 @@ void wo_mr_blend(long H, long W, const double *fine, const double *coarse, const
             }
         }
 }
+
+/* ------------------------------------------------------------------------
+ * Training (Eq. 1: the network's parameters minimise the loss between the
+ * reconstruction and the reference; Eq. 6: SMAPE; Sec. 5.3: Adam).  Plain
+ * definitions of each step's derivative.
+ * ---------------------------------------------------------------------- */
+
+/* SMAPE over n = 3N values (Eq. 6) and its gradient with respect to R:
+ *   s = (1/n) sum |R - t| / (|R| + |t| + eps)
+ *   ds/dR = (1/n) [sign(R - t) (|R| + |t| + eps) - |R - t| sign(R)] / (|R| + |t| + eps)^2
+ * with sign(0) = 0. */
+double wo_smape(long n, const double *R, const double *t, double eps, double *g)
+{
+    double s = 0.0;
+    for (long i = 0; i < n; ++i) {
+        const double d = R[i] - t[i];
+        const double den = fabs(R[i]) + fabs(t[i]) + eps;
+        s += fabs(d) / den;
+        if (g) {
+            const double sd = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
+            const double sr = R[i] > 0.0 ? 1.0 : (R[i] < 0.0 ? -1.0 : 0.0);
+            g[i] = (sd * den - fabs(d) * sr) / (den * den) / (double)n;
+        }
+    }
+    return s / (double)n;
+}
+
+/* Backward of out = conv3x3(in; w, b) (before any ReLU):
+ *   din[y][x][ci] = sum_{co,ky,kx} g[y-ky+1][x-kx+1][co] w[co][ci][ky][kx]
+ *   dw[co][ci][ky][kx] = sum_{y,x} g[y][x][co] in[y+ky-1][x+kx-1][ci]
+ *   db[co] = sum_{y,x} g[y][x][co]
+ * (zero padding; din may be NULL).  dw and db are overwritten. */
+void wo_conv3x3_backward(long H, long W, long Cin, long Cout, const double *in, const double *w,
+                         const double *g, double *din, double *dw, double *db)
+{
+    if (din) {
+#pragma omp parallel for schedule(static)
+        for (long y = 0; y < H; ++y)
+            for (long x = 0; x < W; ++x)
+                for (long ci = 0; ci < Cin; ++ci) {
+                    double acc = 0.0;
+                    for (int ky = 0; ky < 3; ++ky) {
+                        const long yy = y - ky + 1;
+                        if (yy < 0 || yy >= H) continue;
+                        for (int kx = 0; kx < 3; ++kx) {
+                            const long xx = x - kx + 1;
+                            if (xx < 0 || xx >= W) continue;
+                            for (long co = 0; co < Cout; ++co)
+                                acc += g[IDX(yy, xx, co, W, Cout)] * w[((co * Cin + ci) * 3 + ky) * 3 + kx];
+                        }
+                    }
+                    din[IDX(y, x, ci, W, Cin)] = acc;
+                }
+    }
+#pragma omp parallel for schedule(static)
+    for (long co = 0; co < Cout; ++co) {
+        double sb = 0.0;
+        for (long p = 0; p < H * W; ++p) sb += g[p * Cout + co];
+        db[co] = sb;
+        for (long ci = 0; ci < Cin; ++ci)
+            for (int ky = 0; ky < 3; ++ky)
+                for (int kx = 0; kx < 3; ++kx) {
+                    double acc = 0.0;
+                    for (long y = 0; y < H; ++y) {
+                        const long yy = y + ky - 1;
+                        if (yy < 0 || yy >= H) continue;
+                        for (long x = 0; x < W; ++x) {
+                            const long xx = x + kx - 1;
+                            if (xx < 0 || xx >= W) continue;
+                            acc += g[IDX(y, x, co, W, Cout)] * in[IDX(yy, xx, ci, W, Cin)];
+                        }
+                    }
+                    dw[((co * Cin + ci) * 3 + ky) * 3 + kx] = acc;
+                }
+    }
+}
+
+/* Backward of the 2x2 mean: din[y][x] = dout[y/2][x/2] / 4 (din [H,W,C]). */
+void wo_avgpool2_backward(long H, long W, long C, const double *dout, double *din)
+{
+    const long Wo = W / 2;
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x)
+            for (long ch = 0; ch < C; ++ch)
+                din[IDX(y, x, ch, W, C)] = 0.25 * dout[IDX(y / 2, x / 2, ch, Wo, C)];
+}
+
+/* Backward of nearest x2 upsampling: din[y][x] = sum of dout over the 2x2
+ * block (din [H,W,C], dout [2H,2W,C]). */
+void wo_upsample2_backward(long H, long W, long C, const double *dout, double *din)
+{
+    const long W2 = 2 * W;
+    for (long y = 0; y < H; ++y)
+        for (long x = 0; x < W; ++x)
+            for (long ch = 0; ch < C; ++ch)
+                din[IDX(y, x, ch, W, C)] = dout[IDX(2 * y, 2 * x, ch, W2, C)] +
+                                           dout[IDX(2 * y, 2 * x + 1, ch, W2, C)] +
+                                           dout[IDX(2 * y + 1, 2 * x, ch, W2, C)] +
+                                           dout[IDX(2 * y + 1, 2 * x + 1, ch, W2, C)];
+}
+
+/* Adam (Kingma and Ba; Sec. 5.3 trains with it): for step t >= 1,
+ *   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+ *   w -= lr (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps). */
+void wo_adam(long n, double *w, const double *g, double *m, double *v, long t, double lr, double b1,
+             double b2, double eps)
+{
+    const double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+    for (long i = 0; i < n; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        w[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
+}
