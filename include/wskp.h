@@ -226,6 +226,35 @@ wskp_status_t wskp_backward(wskp_handle_t h, void *stream, int N, int H, int W, 
  * (16 * M bytes per pixel: per-centre adjoint terms of every kernel size). */
 wskp_status_t wskp_backward_workspace_size(wskp_handle_t h, int N, int H, int W, size_t *bytes);
 
+/* Training (Eq. 1: the network's weights minimise a loss between its
+ * reconstruction and the reference; Eq. 6: SMAPE; Sec. 5.3: Adam).  For
+ * handles with WSKP_PREC_FP32 and WSKP_ACT_SOFTPLUS (others:
+ * WSKP_E_UNSUPPORTED).  The handle keeps the weight blob (the layout of
+ * wskp_num_weights) on the device as the trained parameters.
+ * wskp_train_workspace_size: workspace bytes of wskp_train_grads for n
+ *   frames of sizes H[i] x W[i].
+ * wskp_train_grads: forward pass of the n frames (each frame's `out`
+ *   receives its reconstruction), loss = SMAPE(out, target) over all
+ *   frames' values (Eq. 6 with eps_smape; N = all pixels of the batch) into
+ *   the device scalar *loss, and its gradient with respect to every weight
+ *   and bias into grad (device, wskp_num_weights floats, overwritten).
+ *   targets: HOST array of n device pointers to [H_i,W_i,3] references.
+ *   Gradients are accumulated over frames in a fixed order (run-to-run
+ *   identical).
+ * wskp_adam: one Adam step (step >= 1) on the handle's weights with the
+ *   gradient grad and the moment buffers m, v (device, wskp_num_weights
+ *   floats each, zero before step 1, updated in place); afterwards every
+ *   denoising call uses the new weights.
+ * wskp_get_weights: copies the handle's current weight blob to the device
+ *   buffer dst (wskp_num_weights floats) on `stream`. */
+wskp_status_t wskp_train_workspace_size(wskp_handle_t h, int n, const int *H, const int *W, size_t *bytes);
+wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, const wskp_frame_t *frames,
+                               const float *const *targets, float eps_smape, float *grad, float *loss,
+                               void *ws, size_t ws_bytes);
+wskp_status_t wskp_adam(wskp_handle_t h, void *stream, const float *grad, float *m, float *v, int step,
+                        float lr, float beta1, float beta2, float eps);
+wskp_status_t wskp_get_weights(wskp_handle_t h, void *stream, float *dst);
+
 /* Multi-resolution reconstruction (Sec. 5.2, the paper's network for
  * high-spp input): the irradiance is filtered at L resolutions, level l
  * with its own head record (wskp_decode on the 2x2-pooled irradiance, mod

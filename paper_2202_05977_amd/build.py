@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwskp.so")
-SOURCES = ["conv3x3.hip", "decode.hip", "kp.hip", "temporal.hip", "mr.hip", "wskp_api.cpp"]
+SOURCES = ["conv3x3.hip", "decode.hip", "kp.hip", "temporal.hip", "mr.hip", "train.hip", "wskp_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

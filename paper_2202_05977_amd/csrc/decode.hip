@@ -669,30 +669,29 @@ __global__ __launch_bounds__(kFThreads, 4) void decode_tile_kernel(DecodeCfg dc,
     auto centre_off = [&](int q) { return q < nc ? (unsigned)((gcy + q) * W + gcx) * 4u : kNoPixel; };
     auto centre_pix = [&](int q) { return q < nc ? (size_t)(gcy + q) * W + gcx : (size_t)0; };
 
-    // ---- loads: irradiance of the halo slots, the first weight map
+    // ---- loads: irradiance of the halo slots, the first weight map.  All
+    // are buffer loads from 32-bit byte offsets (kNoPixel outside the image:
+    // reads zeros).  Map j of pixel q: frames at (j P + q) * 4 (planar), tensors
+    // at (q 2M + j) * 4 (interleaved).
+    const unsigned hstride = FR ? 4u : 8u * M;
+    auto map_rsrc = [&](int j) {
+        return FR ? make_rsrc(io.head + (size_t)j * P, P * 4u) : make_rsrc(io.head + j, P * hstride - 4u * j);
+    };
     float cv[kFSlots][3], wv[kFSlots];
     auto load_w = [&](int i) {
-        if constexpr (FR) {
-            const rsrc_t rs = make_rsrc(io.head + (size_t)i * P, P * 4u);
+        const rsrc_t rs = map_rsrc(i);
 #pragma unroll
-            for (int k = 0; k < kFSlots; ++k)
-                wv[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
-                    rs, gp[k] >= 0 ? (unsigned)gp[k] * 4u : kNoPixel, 0, 0));
-        } else {
-#pragma unroll
-            for (int k = 0; k < kFSlots; ++k)
-                wv[k] = gload(io.head + (size_t)(gp[k] >= 0 ? gp[k] : 0) * io.hs_pix + i);
-        }
+        for (int k = 0; k < kFSlots; ++k)
+            wv[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+                rs, gp[k] >= 0 ? (unsigned)gp[k] * hstride : kNoPixel, 0, 0));
     };
     auto load_logit = [&](int i, float *lg) {
-        if constexpr (FR) {
-            const rsrc_t rs = make_rsrc(io.head + (size_t)(M + i) * P, P * 4u);
+        const rsrc_t rs = map_rsrc(M + i);
 #pragma unroll
-            for (int q = 0; q < kNC; ++q)
-                lg[q] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, centre_off(q), 0, 0));
-        } else {
-#pragma unroll
-            for (int q = 0; q < kNC; ++q) lg[q] = gload(io.head + centre_pix(q) * io.hs_pix + M + i);
+        for (int q = 0; q < kNC; ++q) {
+            const unsigned o = centre_off(q);
+            lg[q] = __uint_as_float(
+                __builtin_amdgcn_raw_buffer_load_b32(rs, o == kNoPixel ? kNoPixel : (o >> 2) * hstride, 0, 0));
         }
     };
     float lg[kNC];
@@ -723,18 +722,16 @@ __global__ __launch_bounds__(kFThreads, 4) void decode_tile_kernel(DecodeCfg dc,
                 cv[k][ch] = gp[k] >= 0 ? c : 0.f;
             }
     } else {
+        const rsrc_t rc = make_rsrc(io.c, P * 12u);
 #pragma unroll
         for (int k = 0; k < kFSlots; ++k) {
-            const size_t q = (size_t)(gp[k] >= 0 ? gp[k] : 0) * 3;
+            const auto c3 =
+                __builtin_amdgcn_raw_buffer_load_b96(rc, gp[k] >= 0 ? (unsigned)gp[k] * 12u : kNoPixel, 0, 0);
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) cv[k][ch] = gload(io.c + q + ch);
+            for (int ch = 0; ch < 3; ++ch) cv[k][ch] = __uint_as_float(c3[ch]);
         }
         load_w(0);
         load_logit(0, lg);
-#pragma unroll
-        for (int k = 0; k < kFSlots; ++k)
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) cv[k][ch] = gp[k] >= 0 ? cv[k][ch] : 0.f;
     }
 
     // ---- online fusion state of the thread's centres
@@ -808,8 +805,18 @@ __global__ __launch_bounds__(kFThreads, 4) void decode_tile_kernel(DecodeCfg dc,
 #pragma unroll
                 for (int q = 0; q < kNC; ++q)
 #pragma unroll
-                    for (int ch = 0; ch < 3; ++ch)
-                        mv[q][ch] = io.mod ? gload(io.mod + centre_pix(q) * 3 + ch) : 1.f;
+                    for (int ch = 0; ch < 3; ++ch) mv[q][ch] = 1.f;
+                if (io.mod) {
+                    const rsrc_t rm = make_rsrc(io.mod, P * 12u);
+#pragma unroll
+                    for (int q = 0; q < kNC; ++q) {
+                        const unsigned o = centre_off(q);
+                        const auto m3 =
+                            __builtin_amdgcn_raw_buffer_load_b96(rm, o == kNoPixel ? kNoPixel : o * 3u, 0, 0);
+#pragma unroll
+                        for (int ch = 0; ch < 3; ++ch) mv[q][ch] = __uint_as_float(m3[ch]);
+                    }
+                }
             }
         }
         lds_sync();

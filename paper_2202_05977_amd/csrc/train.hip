@@ -1,0 +1,467 @@
+// One training step of the network (Eq. 1: the network's parameters are
+// fitted by minimising a loss between the reconstruction and the reference;
+// Eq. 6: the SMAPE loss; Sec. 5.3: Adam), FP32 throughout.
+//
+// The forward pass is the fp32 denoising path (its workspace keeps every
+// layer's output).  The backward pass, per frame:
+//   SMAPE gradient at the output -> adjoint of decode and fusion (decode.hip)
+//   -> derivative of the weight activation -> for each conv, from the head
+//   back to the first encoder: the ReLU mask of its output, the weight and
+//   bias gradient (accumulated over the frames of the batch) and the input
+//   gradient, which the adjoints of the nearest x2 upsampling, the channel
+//   concatenation and the 2x2 mean distribute to the layers that fed it.
+// A layer's input (the network input, a 2x2 mean, an [upsampled, skip]
+// concatenation) is written out once for its two gradient kernels.
+//
+// Gradient kernels (NHWC fp32, zero padding, conv = 3x3 cross-correlation):
+//   dgrad  gin[p][ci] = sum_{tap,co} gm[p - off(tap)][co] w[co][ci][tap]
+//          one wave per 4 pixels x 64 input channels (a lane per channel);
+//          the kernel's weight slice for 16 output channels is staged in
+//          LDS and each value read serves the wave's 4 pixels
+//   wgrad  dw[co][ci][tap] = sum_p gm[p][co] in[p + off(tap)][ci],
+//          db[co] = sum_p gm[p][co]: one wave per (64 input channels, 8
+//          output channels, chunk of pixels), 72 accumulators per lane; the
+//          chunks' partial sums are added in a fixed order by a second pass,
+//          so the result does not depend on scheduling
+#include "wskp_internal.h"
+
+namespace wskp {
+
+constexpr int kTrThreads = 256;
+
+static inline int tr_blocks(long n) { return (int)((n + kTrThreads - 1) / kTrThreads); }
+
+// network input X [P][10] (Sec. 5.1), as the first conv's staging forms it
+__global__ __launch_bounds__(kTrThreads) void tr_pack_kernel(long P, const float *r, const float *a, const float *n,
+                                                              const float *d, float inv_gamma, float dnear, float dinv,
+                                                              float *X)
+{
+    const long p = (long)blockIdx.x * kTrThreads + threadIdx.x;
+    if (p >= P) return;
+    float x[10];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        const float rv = fminf(fmaxf(gload(r + p * 3 + ch), 0.f), 1.f);
+        x[ch] = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(rv) * inv_gamma);
+        x[3 + ch] = gload(a + p * 3 + ch);
+        x[6 + ch] = (gload(n + p * 3 + ch) + 1.f) * 0.5f;
+    }
+    x[9] = fminf(fmaxf((gload(d + p) - dnear) * dinv, 0.f), 1.f);
+#pragma unroll
+    for (int ch = 0; ch < 10; ++ch) gstore(X + p * 10 + ch, x[ch]);
+}
+
+// out [H/2][W/2][C] = 2x2 means of in [H][W][C]
+__global__ __launch_bounds__(kTrThreads) void tr_pool_kernel(int H, int W, int C, const float *in, float *out)
+{
+    const int Wo = W / 2;
+    const long n = (long)(H / 2) * Wo * C;
+    const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
+    if (i >= n) return;
+    const int ch = (int)(i % C);
+    const long q = i / C;
+    const int y = (int)(q / Wo), x = (int)(q % Wo);
+    const float *s = in + ((long)(2 * y) * W + 2 * x) * C + ch;
+    gstore(out + i, 0.25f * (((gload(s) + gload(s + C)) + gload(s + (long)W * C)) + gload(s + (long)W * C + C)));
+}
+
+// out [H][W][Cu + Ce] = [nearest x2 upsample of u [H/2][W/2][Cu], e [H][W][Ce]]
+__global__ __launch_bounds__(kTrThreads) void tr_cat_kernel(int H, int W, int Cu, int Ce, const float *u,
+                                                             const float *e, float *out)
+{
+    const int C = Cu + Ce;
+    const long n = (long)H * W * C;
+    const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
+    if (i >= n) return;
+    const int ch = (int)(i % C);
+    const long p = i / C;
+    const int y = (int)(p / W), x = (int)(p % W);
+    const float v = ch < Cu ? gload(u + ((long)(y / 2) * (W / 2) + x / 2) * Cu + ch) : gload(e + p * Ce + (ch - Cu));
+    gstore(out + i, v);
+}
+
+// interleaved head [P][2M] from the planar record [2M][P]; c = r/(a+eps_a),
+// mod = a + eps_a (the decode adjoint's inputs)
+__global__ __launch_bounds__(kTrThreads) void tr_head_prep_kernel(long P, int M, const float *planar, const float *r,
+                                                                   const float *a, float eps_a, float *head,
+                                                                   float *c, float *mod)
+{
+    const long p = (long)blockIdx.x * kTrThreads + threadIdx.x;
+    if (p >= P) return;
+    for (int j = 0; j < 2 * M; ++j) gstore(head + p * 2 * M + j, gload(planar + (long)j * P + p));
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        const float m = gload(a + p * 3 + ch) + eps_a;
+        gstore(mod + p * 3 + ch, m);
+        gstore(c + p * 3 + ch, gload(r + p * 3 + ch) / m);
+    }
+}
+
+// SMAPE (Eq. 6) gradient g = dL/dy for n values with mean weight inv_n, and
+// the block's share of the loss in partial[blockIdx.x]
+__global__ __launch_bounds__(kTrThreads) void tr_smape_kernel(long n, const float *y, const float *t, float eps,
+                                                               float inv_n, float *g, float *partial)
+{
+    __shared__ float red[kTrThreads];
+    const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
+    float l = 0.f;
+    if (i < n) {
+        const float yv = gload(y + i), tv = gload(t + i);
+        const float d = yv - tv, den = fabsf(yv) + fabsf(tv) + eps;
+        const float sd = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+        const float sr = yv > 0.f ? 1.f : (yv < 0.f ? -1.f : 0.f);
+        l = fabsf(d) / den;
+        gstore(g + i, (sd * den - fabsf(d) * sr) / (den * den) * inv_n);
+    }
+    red[threadIdx.x] = l;
+    __syncthreads();
+    for (int s = kTrThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) gstore(partial + blockIdx.x, red[0] * inv_n);
+}
+
+// loss[0] (+)= sum of partial[0..nb) in order (one thread: a fixed order)
+__global__ void tr_sum_kernel(int nb, const float *partial, float *loss, int accumulate)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float s = accumulate ? gload(loss) : 0.f;
+    for (int b = 0; b < nb; ++b) s += gload(partial + b);
+    gstore(loss, s);
+}
+
+// gradient at the head conv's output: weight channels through softplus'
+// (the logistic of h, = 1 - e^{-W} = -expm1(-W) in terms of W = softplus(h),
+// accurate also where W is tiny); logits as is
+__global__ __launch_bounds__(kTrThreads) void tr_head_act_bwd_kernel(long P, int M, const float *grad_head,
+                                                                      const float *planar, float *dh)
+{
+    const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
+    if (i >= P * 2 * M) return;
+    const int j = (int)(i % (2 * M));
+    const long p = i / (2 * M);
+    float g = gload(grad_head + i);
+    if (j < M) g *= -expm1f(-gload(planar + (long)j * P + p));
+    gstore(dh + i, g);
+}
+
+// gm = g * (act > 0) (the ReLU's derivative; act == nullptr: none)
+__global__ __launch_bounds__(kTrThreads) void tr_mask_kernel(long n, const float *g, const float *act, float *gm)
+{
+    const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
+    if (i >= n) return;
+    const float v = gload(g + i);
+    gstore(gm + i, act ? (gload(act + i) > 0.f ? v : 0.f) : v);
+}
+
+// input gradient of a 3x3 conv.  Block: 4 waves; wave w handles pixels
+// 4*(4*blockIdx.x + w) .. +3 (in raster order) for input channels
+// 64*blockIdx.y + lane.  Output channels in chunks of 16 whose weights
+// [16][9][64] are staged in LDS.
+constexpr int kDgPix = 4;
+__global__ __launch_bounds__(kTrThreads) void tr_dgrad_kernel(int H, int W, int Ci, int Co, const float *gm,
+                                                               const float *w, float *gin)
+{
+    __shared__ float ws[16][9][64];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ci = blockIdx.y * 64 + lane;
+    const long P = (long)H * W;
+    const long p0 = ((long)blockIdx.x * 4 + wave) * kDgPix;
+    int py[kDgPix], px[kDgPix];
+#pragma unroll
+    for (int k = 0; k < kDgPix; ++k) {
+        const long p = p0 + k < P ? p0 + k : P - 1;
+        py[k] = (int)(p / W);
+        px[k] = (int)(p % W);
+    }
+    float acc[kDgPix] = {0.f, 0.f, 0.f, 0.f};
+    for (int c0 = 0; c0 < Co; c0 += 16) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < 16 * 9 * 64; i += kTrThreads) {
+            const int l = i & 63, t = (i >> 6) % 9, o = i / (9 * 64);
+            const int co = c0 + o, cc = blockIdx.y * 64 + l;
+            ws[o][t][l] = (co < Co && cc < Ci) ? gload(w + ((long)co * Ci + cc) * 9 + t) : 0.f;
+        }
+        __syncthreads();
+        const int nco = min(16, Co - c0);
+        for (int t = 0; t < 9; ++t) {
+            const int ky = t / 3, kx = t % 3;
+            // output pixel p feeds input pixel p' = p + off(tap): the input
+            // gradient at p' gathers from p = p' - off(tap) (wave-uniform)
+            const float *gp[kDgPix];
+            bool in[kDgPix];
+#pragma unroll
+            for (int k = 0; k < kDgPix; ++k) {
+                const int yy = py[k] - ky + 1, xx = px[k] - kx + 1;
+                in[k] = yy >= 0 && yy < H && xx >= 0 && xx < W;
+                gp[k] = gm + ((long)(in[k] ? yy : 0) * W + (in[k] ? xx : 0)) * Co + c0;
+            }
+            for (int o = 0; o < nco; ++o) {
+                const float wv = ws[o][t][lane];
+#pragma unroll
+                for (int k = 0; k < kDgPix; ++k) acc[k] += (in[k] ? gload(gp[k] + o) : 0.f) * wv;
+            }
+        }
+    }
+    if (ci >= Ci) return;
+#pragma unroll
+    for (int k = 0; k < kDgPix; ++k)
+        if (p0 + k < P) gstore(gin + (p0 + k) * Ci + ci, acc[k]);
+}
+
+// partial weight gradients: block (x: pixel chunk, y: 8-channel output
+// group, z: 64-channel input group) of one wave; part[chunk][co][ci][tap]
+constexpr int kWgCo = 8;
+__global__ __launch_bounds__(64) void tr_wgrad_kernel(int H, int W, int Ci, int Co, int chunk, const float *gm,
+                                                       const float *in, float *part, float *partb)
+{
+    const int lane = threadIdx.x;
+    const int ci = blockIdx.z * 64 + lane;
+    const int co0 = blockIdx.y * kWgCo;
+    const long P = (long)H * W;
+    const long pa = (long)blockIdx.x * chunk, pb = min(P, pa + chunk);
+    float acc[kWgCo][9], accb[kWgCo];
+#pragma unroll
+    for (int o = 0; o < kWgCo; ++o) {
+        accb[o] = 0.f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc[o][t] = 0.f;
+    }
+    const bool live = ci < Ci;
+    for (long p = pa; p < pb; ++p) {
+        const int y = (int)(p / W), x = (int)(p % W);
+        float v[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+            const bool ok = live && yy >= 0 && yy < H && xx >= 0 && xx < W;
+            v[t] = ok ? gload(in + ((long)yy * W + xx) * Ci + ci) : 0.f;
+        }
+#pragma unroll
+        for (int o = 0; o < kWgCo; ++o) {
+            const float g = co0 + o < Co ? gload(gm + p * Co + co0 + o) : 0.f;
+            accb[o] += g;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) acc[o][t] += g * v[t];
+        }
+    }
+    const long base = (long)blockIdx.x * Co * Ci * 9;
+#pragma unroll
+    for (int o = 0; o < kWgCo; ++o) {
+        const int co = co0 + o;
+        if (co >= Co) continue;
+        if (live)
+#pragma unroll
+            for (int t = 0; t < 9; ++t) gstore(part + base + ((long)co * Ci + ci) * 9 + t, acc[o][t]);
+        if (blockIdx.z == 0 && lane == 0) gstore(partb + (long)blockIdx.x * Co + co, accb[o]);
+    }
+}
+
+// dw (+)= sum over chunks of part (in chunk order), likewise db
+__global__ __launch_bounds__(kTrThreads) void tr_wgrad_reduce_kernel(long nw, int Co, int nchunk, const float *part,
+                                                                      const float *partb, float *dw, float *db)
+{
+    const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
+    if (i < nw) {
+        float s = gload(dw + i);
+        for (int c = 0; c < nchunk; ++c) s += gload(part + (long)c * nw + i);
+        gstore(dw + i, s);
+    } else if (i < nw + Co) {
+        const int co = (int)(i - nw);
+        float s = gload(db + co);
+        for (int c = 0; c < nchunk; ++c) s += gload(partb + (long)c * Co + co);
+        gstore(db + co, s);
+    }
+}
+
+// grad of the upsampled part of a concatenation: gu[y][x][c] += sum of
+// gcat[2y+i][2x+j][c] (c < Cu); of the skip part: ge[p][c] += gcat[p][Cu+c]
+__global__ __launch_bounds__(kTrThreads) void tr_cat_bwd_kernel(int H, int W, int Cu, int Ce, const float *gcat,
+                                                                 float *gu, float *ge)
+{
+    const int C = Cu + Ce;
+    const int Hc = H / 2, Wc = W / 2;
+    const long nu = (long)Hc * Wc * Cu, ne = (long)H * W * Ce;
+    const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
+    if (i < nu) {
+        const int c = (int)(i % Cu);
+        const long q = i / Cu;
+        const int y = (int)(q / Wc), x = (int)(q % Wc);
+        const float *s = gcat + ((long)(2 * y) * W + 2 * x) * C + c;
+        gstore(gu + i, gload(gu + i) + (((gload(s) + gload(s + C)) + gload(s + (long)W * C)) + gload(s + (long)W * C + C)));
+    } else if (i < nu + ne) {
+        const long j = i - nu;
+        const int c = (int)(j % Ce);
+        const long p = j / Ce;
+        gstore(ge + j, gload(ge + j) + gload(gcat + p * C + Cu + c));
+    }
+}
+
+// grad of a 2x2 mean: ge[y][x][c] += gp[y/2][x/2][c] / 4
+__global__ __launch_bounds__(kTrThreads) void tr_pool_bwd_kernel(int H, int W, int C, const float *gp, float *ge)
+{
+    const long n = (long)H * W * C;
+    const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
+    if (i >= n) return;
+    const int c = (int)(i % C);
+    const long p = i / C;
+    const int y = (int)(p / W), x = (int)(p % W);
+    gstore(ge + i, gload(ge + i) + 0.25f * gload(gp + ((long)(y / 2) * (W / 2) + x / 2) * C + c));
+}
+
+__global__ __launch_bounds__(kTrThreads) void tr_add_kernel(long n, const float *a, float *b)
+{
+    const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
+    if (i < n) gstore(b + i, gload(b + i) + gload(a + i));
+}
+
+__global__ __launch_bounds__(kTrThreads) void tr_fill_kernel(long n, float v, float *b)
+{
+    const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
+    if (i < n) gstore(b + i, v);
+}
+
+// Adam (Kingma and Ba): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+// w -= lr (m / c1) / (sqrt(v / c2) + eps) with c1 = 1 - b1^t, c2 = 1 - b2^t
+__global__ __launch_bounds__(kTrThreads) void tr_adam_kernel(long n, float *w, const float *g, float *m, float *v,
+                                                              float lr, float b1, float b2, float c1, float c2,
+                                                              float eps)
+{
+    const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
+    if (i >= n) return;
+    const float gi = gload(g + i);
+    const float mi = b1 * gload(m + i) + (1.f - b1) * gi;
+    const float vi = b2 * gload(v + i) + (1.f - b2) * gi * gi;
+    gstore(m + i, mi);
+    gstore(v + i, vi);
+    gstore(w + i, gload(w + i) - lr * (mi / c1) / (sqrtf(vi / c2) + eps));
+}
+
+// fp32 weights of one conv from the blob layout (OIHW, then bias) into the
+// layout the fp32 conv kernel reads: [chunk][tap][c][Cout_pad], zero padded;
+// bias copied
+__global__ __launch_bounds__(kTrThreads) void tr_repack_kernel(int Cin, int Cout, int CK, int nch, int Cout_pad,
+                                                                const float *blob, float *packed, float *bias)
+{
+    const long n = (long)nch * 9 * CK * Cout_pad;
+    const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
+    if (i < n) {
+        const int co = (int)(i % Cout_pad);
+        long q = i / Cout_pad;
+        const int c = (int)(q % CK);
+        q /= CK;
+        const int tap = (int)(q % 9);
+        const int cc = (int)(q / 9);
+        const int ci = cc * CK + c;
+        gstore(packed + i, (co < Cout && ci < Cin) ? gload(blob + ((long)co * Cin + ci) * 9 + tap) : 0.f);
+    } else if (i < n + Cout) {
+        const int co = (int)(i - n);
+        gstore(bias + co, gload(blob + (long)Cout * Cin * 9 + co));
+    }
+}
+
+// ---- launchers ---------------------------------------------------------------
+#define TR_LAUNCH(kernel, n, ...)                                                                          \
+    do {                                                                                                   \
+        const long n_ = (n);                                                                               \
+        if (n_ > 0) hipLaunchKernelGGL(kernel, dim3(tr_blocks(n_)), dim3(kTrThreads), 0, s, __VA_ARGS__); \
+    } while (0)
+
+hipError_t tr_pack(long P, const float *r, const float *a, const float *n, const float *d, float inv_gamma,
+                   float dnear, float dinv, float *X, hipStream_t s)
+{
+    TR_LAUNCH(tr_pack_kernel, P, P, r, a, n, d, inv_gamma, dnear, dinv, X);
+    return hipGetLastError();
+}
+hipError_t tr_pool(int H, int W, int C, const float *in, float *out, hipStream_t s)
+{
+    TR_LAUNCH(tr_pool_kernel, (long)(H / 2) * (W / 2) * C, H, W, C, in, out);
+    return hipGetLastError();
+}
+hipError_t tr_cat(int H, int W, int Cu, int Ce, const float *u, const float *e, float *out, hipStream_t s)
+{
+    TR_LAUNCH(tr_cat_kernel, (long)H * W * (Cu + Ce), H, W, Cu, Ce, u, e, out);
+    return hipGetLastError();
+}
+hipError_t tr_head_prep(long P, int M, const float *planar, const float *r, const float *a, float eps_a,
+                        float *head, float *c, float *mod, hipStream_t s)
+{
+    TR_LAUNCH(tr_head_prep_kernel, P, P, M, planar, r, a, eps_a, head, c, mod);
+    return hipGetLastError();
+}
+int tr_smape_blocks(long n) { return tr_blocks(n); }
+hipError_t tr_smape(long n, const float *y, const float *t, float eps, float inv_n, float *g, float *partial,
+                    float *loss, int accumulate, hipStream_t s)
+{
+    TR_LAUNCH(tr_smape_kernel, n, n, y, t, eps, inv_n, g, partial);
+    hipLaunchKernelGGL(tr_sum_kernel, dim3(1), dim3(64), 0, s, tr_blocks(n), partial, loss, accumulate);
+    return hipGetLastError();
+}
+hipError_t tr_head_act_bwd(long P, int M, const float *grad_head, const float *planar, float *dh, hipStream_t s)
+{
+    TR_LAUNCH(tr_head_act_bwd_kernel, P * 2 * M, P, M, grad_head, planar, dh);
+    return hipGetLastError();
+}
+hipError_t tr_mask(long n, const float *g, const float *act, float *gm, hipStream_t s)
+{
+    TR_LAUNCH(tr_mask_kernel, n, n, g, act, gm);
+    return hipGetLastError();
+}
+hipError_t tr_dgrad(int H, int W, int Ci, int Co, const float *gm, const float *w, float *gin, hipStream_t s)
+{
+    const long P = (long)H * W;
+    const dim3 grid((unsigned)((P + 4 * kDgPix - 1) / (4 * kDgPix)), (unsigned)((Ci + 63) / 64));
+    hipLaunchKernelGGL(tr_dgrad_kernel, grid, dim3(kTrThreads), 0, s, H, W, Ci, Co, gm, w, gin);
+    return hipGetLastError();
+}
+int tr_wgrad_chunks(long P) { return (int)((P + 255) / 256); }
+size_t tr_wgrad_part_floats(long P, int Ci, int Co) { return (size_t)tr_wgrad_chunks(P) * ((size_t)Co * Ci * 9 + Co); }
+hipError_t tr_wgrad(int H, int W, int Ci, int Co, const float *gm, const float *in, float *part, float *dw,
+                    float *db, hipStream_t s)
+{
+    const long P = (long)H * W;
+    const int nch = tr_wgrad_chunks(P);
+    const long nw = (long)Co * Ci * 9;
+    float *partb = part + (size_t)nch * nw;
+    const dim3 grid((unsigned)nch, (unsigned)((Co + kWgCo - 1) / kWgCo), (unsigned)((Ci + 63) / 64));
+    hipLaunchKernelGGL(tr_wgrad_kernel, grid, dim3(64), 0, s, H, W, Ci, Co, 256, gm, in, part, partb);
+    TR_LAUNCH(tr_wgrad_reduce_kernel, nw + Co, nw, Co, nch, part, partb, dw, db);
+    return hipGetLastError();
+}
+hipError_t tr_cat_bwd(int H, int W, int Cu, int Ce, const float *gcat, float *gu, float *ge, hipStream_t s)
+{
+    TR_LAUNCH(tr_cat_bwd_kernel, (long)(H / 2) * (W / 2) * Cu + (long)H * W * Ce, H, W, Cu, Ce, gcat, gu, ge);
+    return hipGetLastError();
+}
+hipError_t tr_pool_bwd(int H, int W, int C, const float *gp, float *ge, hipStream_t s)
+{
+    TR_LAUNCH(tr_pool_bwd_kernel, (long)H * W * C, H, W, C, gp, ge);
+    return hipGetLastError();
+}
+hipError_t tr_add(long n, const float *a, float *b, hipStream_t s)
+{
+    TR_LAUNCH(tr_add_kernel, n, n, a, b);
+    return hipGetLastError();
+}
+hipError_t tr_fill(long n, float v, float *b, hipStream_t s)
+{
+    TR_LAUNCH(tr_fill_kernel, n, n, v, b);
+    return hipGetLastError();
+}
+hipError_t tr_adam(long n, float *w, const float *g, float *m, float *v, float lr, float b1, float b2, float c1,
+                   float c2, float eps, hipStream_t s)
+{
+    TR_LAUNCH(tr_adam_kernel, n, n, w, g, m, v, lr, b1, b2, c1, c2, eps);
+    return hipGetLastError();
+}
+hipError_t tr_repack(int Cin, int Cout, int CK, int nch, int Cout_pad, const float *blob, float *packed, float *bias,
+                     hipStream_t s)
+{
+    TR_LAUNCH(tr_repack_kernel, (long)nch * 9 * CK * Cout_pad + Cout, Cin, Cout, CK, nch, Cout_pad, blob, packed,
+              bias);
+    return hipGetLastError();
+}
+
+}  // namespace wskp

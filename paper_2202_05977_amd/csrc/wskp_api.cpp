@@ -105,6 +105,8 @@ struct wskp_ctx {
     bool pooled = false;   // encoder epilogues write 2x2 means p_l; enc_{l+1} reads them plainly
     std::vector<LayerPlan> layers;
     void *dweights = nullptr;
+    float *dmaster = nullptr;     // fp32 handles: the weight blob (OIHW + bias, blob order), for training
+    std::vector<size_t> blob_off; // offset of each conv's weights in the blob
     DecodeCfg dc{};
     // pinned host staging for batch frame tables: per slot a header (the
     // frame count) and up to kMaxBatch descriptors
@@ -399,6 +401,23 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
         delete h;
         return hip_fail(e, "hipMemcpy(weights)");
     }
+    {
+        size_t o = 0;
+        for (auto &d : dims) {
+            h->blob_off.push_back(o);
+            o += (size_t)d.first * d.second * 9 + d.second;
+        }
+    }
+    if (h->prec == WSKP_PREC_FP32) {
+        const size_t nb = n_weights * sizeof(float);
+        if ((e = hipMalloc(reinterpret_cast<void **>(&h->dmaster), nb)) != hipSuccess ||
+            (e = hipMemcpy(h->dmaster, host_weights, nb, hipMemcpyHostToDevice)) != hipSuccess) {
+            if (h->dmaster) (void)hipFree(h->dmaster);
+            (void)hipFree(h->dweights);
+            delete h;
+            return hip_fail(e, "master weights", WSKP_E_OOM);
+        }
+    }
     for (auto &lp : h->layers) {
         lp.L.w = static_cast<char *>(h->dweights) + lp.w_off;
         lp.L.bias = reinterpret_cast<const float *>(static_cast<char *>(h->dweights) + lp.b_off);
@@ -438,6 +457,7 @@ extern "C" wskp_status_t wskp_destroy(wskp_handle_t h)
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     if (h->ring) (void)hipHostFree(h->ring);
     if (h->dweights) (void)hipFree(h->dweights);
+    if (h->dmaster) (void)hipFree(h->dmaster);
     delete h;
     return WSKP_OK;
 }
@@ -853,6 +873,9 @@ extern "C" wskp_status_t wskp_decode(wskp_handle_t h, void *stream, int N, int H
     if (!head || !c || !out) return fail(WSKP_E_INVALID_ARG, "NULL tensor pointer");
     if (N < 1 || H < 1 || W < 1 || (long)N * H * W > (1L << 30))
         return fail(WSKP_E_SHAPE, "N, H, W must be >= 1");
+    // the kernel addresses one frame's head record with 32-bit byte offsets
+    if ((long)H * W * 8 * h->cfg.num_kernels >= 0xfffffff0L)
+        return fail(WSKP_E_SHAPE, "frame too large: its head record would exceed 4 GiB");
     wskp_status_t st = set_device(h);
     if (st != WSKP_OK) return st;
     hipError_t e = launch_decode_tensors(h->dc, N, H, W, head, c, mod, out,
@@ -888,6 +911,230 @@ extern "C" wskp_status_t wskp_backward(wskp_handle_t h, void *stream, int N, int
     hipError_t e = launch_decode_backward(h->dc, N, H, W, head, c, mod, grad_out, grad_head, grad_c,
                                           ws, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "backward launch", WSKP_E_LAUNCH);
+    return WSKP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Training (fp32 handles with softplus weights): scratch of the backward
+// pass, sized for the largest frame of the batch.
+struct TrainScratch {
+    float *X, *head, *c, *mod, *gy, *gh, *gc, *dh, *dec, *partial, *gm, *in, *gin, *part;
+    float *ge[kMaxLevels], *gu[kMaxLevels];
+    size_t bytes;
+};
+
+static size_t train_plan(const wskp_ctx *h, int Hm, int Wm, char *base, TrainScratch *ts)
+{
+    const int L = h->cfg.levels, M = h->cfg.num_kernels;
+    const int *ch = h->cfg.channels;
+    const long P = (long)Hm * Wm;
+    size_t o = 0;
+    auto take = [&](size_t floats) {
+        float *p = base ? reinterpret_cast<float *>(base + o) : nullptr;
+        o += align_up(floats * sizeof(float));
+        return p;
+    };
+    size_t mx_gm = (size_t)2 * M * P, mx_in = 10 * (size_t)P, mx_part = tr_wgrad_part_floats(P, 10, ch[0]);
+    for (int l = 0; l < L; ++l) {
+        const long Pl = (long)(Hm >> l) * (Wm >> l);
+        mx_gm = std::max(mx_gm, (size_t)ch[l] * Pl);
+        if (l > 0) {
+            mx_in = std::max(mx_in, (size_t)ch[l - 1] * Pl);
+            mx_part = std::max(mx_part, tr_wgrad_part_floats(Pl, ch[l - 1], ch[l]));
+        }
+        if (l + 1 < L) {
+            mx_in = std::max(mx_in, (size_t)(ch[l + 1] + ch[l]) * Pl);
+            mx_part = std::max(mx_part, tr_wgrad_part_floats(Pl, ch[l + 1] + ch[l], ch[l]));
+        }
+    }
+    mx_in = std::max(mx_in, (size_t)ch[0] * P);
+    mx_part = std::max(mx_part, tr_wgrad_part_floats(P, ch[0], 2 * M));
+    TrainScratch t{};
+    t.X = take(10 * (size_t)P);
+    t.head = take((size_t)2 * M * P);
+    t.c = take(3 * (size_t)P);
+    t.mod = take(3 * (size_t)P);
+    t.gy = take(3 * (size_t)P);
+    t.gh = take((size_t)2 * M * P);
+    t.gc = take(3 * (size_t)P);
+    t.dh = take((size_t)2 * M * P);
+    t.dec = take(decode_backward_scratch_bytes(h->dc, 1, Hm, Wm) / sizeof(float));
+    t.partial = take((size_t)tr_smape_blocks(3 * P));
+    t.gm = take(mx_gm);
+    t.in = take(mx_in);
+    t.gin = take(mx_in);
+    t.part = take(mx_part);
+    for (int l = 0; l < L; ++l) {
+        const size_t n = (size_t)ch[l] * (Hm >> l) * (Wm >> l);
+        t.ge[l] = take(n);
+        t.gu[l] = l + 1 < L ? take(n) : nullptr;
+    }
+    t.bytes = o;
+    if (ts) *ts = t;
+    return o;
+}
+
+static wskp_status_t train_check(const wskp_ctx *h)
+{
+    if (h->prec != WSKP_PREC_FP32 || !h->dmaster)
+        return fail(WSKP_E_UNSUPPORTED, "training needs an fp32 handle");
+    if (h->cfg.weight_act != WSKP_ACT_SOFTPLUS) return fail(WSKP_E_UNSUPPORTED, "training needs softplus weights");
+    return WSKP_OK;
+}
+
+extern "C" wskp_status_t wskp_train_workspace_size(wskp_handle_t h, int n, const int *H, const int *W,
+                                                   size_t *bytes)
+{
+    if (!h || !H || !W || !bytes) return fail(WSKP_E_INVALID_ARG, "NULL argument");
+    wskp_status_t st = train_check(h);
+    if (st != WSKP_OK) return st;
+    size_t fwd;
+    if ((st = wskp_workspace_size(h, n, H, W, &fwd)) != WSKP_OK) return st;
+    long best = 0;
+    int Hm = 0, Wm = 0;
+    for (int i = 0; i < n; ++i)
+        if ((long)H[i] * W[i] > best) {
+            best = (long)H[i] * W[i];
+            Hm = H[i];
+            Wm = W[i];
+        }
+    // the backward scratch holds levels of the largest frame; every frame's
+    // levels are no larger in pixels (sizes are multiples of 2^(L-1))
+    size_t mx = 0;
+    for (int i = 0; i < n; ++i) mx = std::max(mx, train_plan(h, H[i], W[i], nullptr, nullptr));
+    (void)Hm;
+    (void)Wm;
+    *bytes = align_up(fwd) + mx;
+    return WSKP_OK;
+}
+
+extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, const wskp_frame_t *frames,
+                                          const float *const *targets, float eps_smape, float *grad, float *loss,
+                                          void *ws, size_t ws_bytes)
+{
+    if (!h || !frames || !targets || !grad || !loss || !ws) return fail(WSKP_E_INVALID_ARG, "NULL argument");
+    wskp_status_t st = train_check(h);
+    if (st != WSKP_OK) return st;
+    if (n < 1 || n > kMaxBatch) return fail(WSKP_E_INVALID_ARG, "n must be in 1..1024");
+    std::vector<int> Hs(n), Ws(n);
+    for (int i = 0; i < n; ++i) {
+        if (!targets[i]) return fail(WSKP_E_INVALID_ARG, "NULL target");
+        Hs[i] = frames[i].H;
+        Ws[i] = frames[i].W;
+    }
+    size_t need, fwd;
+    if ((st = wskp_train_workspace_size(h, n, Hs.data(), Ws.data(), &need)) != WSKP_OK) return st;
+    if (ws_bytes < need) return fail(WSKP_E_BUDGET, "workspace too small: need " + std::to_string(need) + " bytes");
+    if ((st = wskp_workspace_size(h, n, Hs.data(), Ws.data(), &fwd)) != WSKP_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // forward: the batched fp32 path; its workspace keeps every layer's output
+    if ((st = wskp_denoise_batch(h, stream, n, frames, 0, ws, fwd)) != WSKP_OK) return st;
+    const int L = h->cfg.levels, M = h->cfg.num_kernels;
+    const int *ch = h->cfg.channels;
+    long Ptot = 0;
+    for (int i = 0; i < n; ++i) Ptot += (long)Hs[i] * Ws[i];
+    const float inv_n = (float)(1.0 / (3.0 * (double)Ptot));
+    const size_t nw = wskp_num_weights(&h->cfg);
+    const float *mw = h->dmaster;
+    const size_t head_k = h->layers.size() - 1;
+    auto wofs = [&](size_t k) { return mw + h->blob_off[k]; };
+    auto gofs = [&](size_t k) { return grad + h->blob_off[k]; };
+    auto bofs = [&](size_t k, int Ci, int Co) { return grad + h->blob_off[k] + (size_t)Ci * Co * 9; };
+    hipError_t e = tr_fill((long)nw, 0.f, grad, s);
+    char *fbase = static_cast<char *>(ws) + table_bytes(n);
+    for (int f = 0; f < n && e == hipSuccess; ++f) {
+        const int H = Hs[f], W = Ws[f];
+        const long P = (long)H * W;
+        FrameDesc fd;
+        fill_frame(h, fd, fbase, frames[f]);
+        fbase += frame_bytes(h, H, W, nullptr, nullptr, nullptr);
+        TrainScratch t;
+        train_plan(h, H, W, static_cast<char *>(ws) + align_up(fwd), &t);
+        const float *e_[kMaxLevels], *u_[kMaxLevels];
+        for (int l = 0; l < L; ++l) {
+            e_[l] = static_cast<const float *>(fd.e[l]);
+            u_[l] = static_cast<const float *>(fd.u[l]);
+        }
+        // loss gradient, decode adjoint, weight activation
+        e = tr_head_prep(P, M, fd.head, fd.r, fd.a, h->cfg.eps_albedo, t.head, t.c, t.mod, s);
+        if (e == hipSuccess) e = tr_smape(3 * P, fd.out, targets[f], eps_smape, inv_n, t.gy, t.partial, loss, f > 0, s);
+        if (e == hipSuccess) e = launch_decode_backward(h->dc, 1, H, W, t.head, t.c, t.mod, t.gy, t.gh, t.gc, t.dec, s);
+        if (e == hipSuccess) e = tr_head_act_bwd(P, M, t.gh, fd.head, t.dh, s);
+        for (int l = 0; l < L && e == hipSuccess; ++l) {
+            const long n_l = (long)ch[l] * (H >> l) * (W >> l);
+            e = tr_fill(n_l, 0.f, t.ge[l], s);
+            if (e == hipSuccess && t.gu[l]) e = tr_fill(n_l, 0.f, t.gu[l], s);
+        }
+        // the gradient flowing into u_l (u_{L-1} is e_{L-1})
+        auto gu_of = [&](int l) { return l == L - 1 ? t.ge[l] : t.gu[l]; };
+        // head conv: input u_0, output 2M channels, no ReLU
+        if (e == hipSuccess) e = tr_wgrad(H, W, ch[0], 2 * M, t.dh, u_[0], t.part, gofs(head_k), bofs(head_k, ch[0], 2 * M), s);
+        if (e == hipSuccess) e = tr_dgrad(H, W, ch[0], 2 * M, t.dh, wofs(head_k), gu_of(0), s);
+        // decoders, finest first: dec_l is conv L + (L - 2 - l) in blob order
+        for (int l = 0; l + 1 < L && e == hipSuccess; ++l) {
+            const size_t k = (size_t)L + (L - 2 - l);
+            const int Hl = H >> l, Wl = W >> l, Ci = ch[l + 1] + ch[l], Co = ch[l];
+            e = tr_mask((long)Co * Hl * Wl, t.gu[l], u_[l], t.gm, s);
+            if (e == hipSuccess) e = tr_cat(Hl, Wl, ch[l + 1], ch[l], u_[l + 1], e_[l], t.in, s);
+            if (e == hipSuccess) e = tr_wgrad(Hl, Wl, Ci, Co, t.gm, t.in, t.part, gofs(k), bofs(k, Ci, Co), s);
+            if (e == hipSuccess) e = tr_dgrad(Hl, Wl, Ci, Co, t.gm, wofs(k), t.gin, s);
+            if (e == hipSuccess) e = tr_cat_bwd(Hl, Wl, ch[l + 1], ch[l], t.gin, gu_of(l + 1), t.ge[l], s);
+        }
+        // encoders, coarsest first: enc_l is conv l
+        for (int l = L - 1; l >= 1 && e == hipSuccess; --l) {
+            const int Hl = H >> l, Wl = W >> l, Ci = ch[l - 1], Co = ch[l];
+            e = tr_mask((long)Co * Hl * Wl, t.ge[l], e_[l], t.gm, s);
+            if (e == hipSuccess) e = tr_pool(H >> (l - 1), W >> (l - 1), Ci, e_[l - 1], t.in, s);
+            if (e == hipSuccess) e = tr_wgrad(Hl, Wl, Ci, Co, t.gm, t.in, t.part, gofs(l), bofs(l, Ci, Co), s);
+            if (e == hipSuccess) e = tr_dgrad(Hl, Wl, Ci, Co, t.gm, wofs(l), t.gin, s);
+            if (e == hipSuccess) e = tr_pool_bwd(H >> (l - 1), W >> (l - 1), Ci, t.gin, t.ge[l - 1], s);
+        }
+        // first encoder: the network input written out, weight gradient only
+        if (e == hipSuccess) e = tr_mask((long)ch[0] * P, t.ge[0], e_[0], t.gm, s);
+        if (e == hipSuccess)
+            e = tr_pack(P, fd.r, fd.a, fd.n, fd.d, 1.f / h->cfg.gamma, h->cfg.depth_near,
+                        1.f / (h->cfg.depth_far - h->cfg.depth_near), t.X, s);
+        if (e == hipSuccess) e = tr_wgrad(H, W, 10, ch[0], t.gm, t.X, t.part, gofs(0), bofs(0, 10, ch[0]), s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "training launch", WSKP_E_LAUNCH);
+    return WSKP_OK;
+}
+
+extern "C" wskp_status_t wskp_adam(wskp_handle_t h, void *stream, const float *grad, float *m, float *v, int step,
+                                   float lr, float beta1, float beta2, float eps)
+{
+    if (!h || !grad || !m || !v) return fail(WSKP_E_INVALID_ARG, "NULL argument");
+    wskp_status_t st = train_check(h);
+    if (st != WSKP_OK) return st;
+    if (step < 1) return fail(WSKP_E_INVALID_ARG, "step counts from 1");
+    if ((st = set_device(h)) != WSKP_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t nw = wskp_num_weights(&h->cfg);
+    const float c1 = (float)(1.0 - std::pow((double)beta1, step)), c2 = (float)(1.0 - std::pow((double)beta2, step));
+    hipError_t e = tr_adam((long)nw, h->dmaster, grad, m, v, lr, beta1, beta2, c1, c2, eps, s);
+    // the conv kernels read the weights in their own layout: repack each conv
+    std::vector<std::pair<int, int>> d;
+    conv_dims(&h->cfg, d);
+    for (size_t k = 0; k < h->layers.size() && e == hipSuccess; ++k) {
+        const LayerPlan &lp = h->layers[k];
+        const int nch = lp.L.Cin_pad / lp.L.CK;
+        e = tr_repack(d[k].first, d[k].second, lp.L.CK, nch, lp.L.Cout_pad, h->dmaster + h->blob_off[k],
+                      reinterpret_cast<float *>(static_cast<char *>(h->dweights) + lp.w_off),
+                      reinterpret_cast<float *>(static_cast<char *>(h->dweights) + lp.b_off), s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "adam launch", WSKP_E_LAUNCH);
+    return WSKP_OK;
+}
+
+extern "C" wskp_status_t wskp_get_weights(wskp_handle_t h, void *stream, float *dst)
+{
+    if (!h || !dst) return fail(WSKP_E_INVALID_ARG, "NULL argument");
+    wskp_status_t st = train_check(h);
+    if (st != WSKP_OK) return st;
+    if ((st = set_device(h)) != WSKP_OK) return st;
+    hipError_t e = hipMemcpyAsync(dst, h->dmaster, wskp_num_weights(&h->cfg) * sizeof(float),
+                                  hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(weights)");
     return WSKP_OK;
 }
 

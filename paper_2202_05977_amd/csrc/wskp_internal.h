@@ -229,6 +229,30 @@ hipError_t launch_decode_backward(const DecodeCfg &dc, int N, int H, int W, cons
                                   float *grad_head, float *grad_c, void *scratch,
                                   hipStream_t s);
 size_t decode_backward_scratch_bytes(const DecodeCfg &dc, int N, int H, int W);
+// Training kernels (train.hip): see the file's header for each operation.
+hipError_t tr_pack(long P, const float *r, const float *a, const float *n, const float *d, float inv_gamma,
+                   float dnear, float dinv, float *X, hipStream_t s);
+hipError_t tr_pool(int H, int W, int C, const float *in, float *out, hipStream_t s);
+hipError_t tr_cat(int H, int W, int Cu, int Ce, const float *u, const float *e, float *out, hipStream_t s);
+hipError_t tr_head_prep(long P, int M, const float *planar, const float *r, const float *a, float eps_a,
+                        float *head, float *c, float *mod, hipStream_t s);
+int tr_smape_blocks(long n);
+hipError_t tr_smape(long n, const float *y, const float *t, float eps, float inv_n, float *g, float *partial,
+                    float *loss, int accumulate, hipStream_t s);
+hipError_t tr_head_act_bwd(long P, int M, const float *grad_head, const float *planar, float *dh, hipStream_t s);
+hipError_t tr_mask(long n, const float *g, const float *act, float *gm, hipStream_t s);
+hipError_t tr_dgrad(int H, int W, int Ci, int Co, const float *gm, const float *w, float *gin, hipStream_t s);
+size_t tr_wgrad_part_floats(long P, int Ci, int Co);
+hipError_t tr_wgrad(int H, int W, int Ci, int Co, const float *gm, const float *in, float *part, float *dw,
+                    float *db, hipStream_t s);
+hipError_t tr_cat_bwd(int H, int W, int Cu, int Ce, const float *gcat, float *gu, float *ge, hipStream_t s);
+hipError_t tr_pool_bwd(int H, int W, int C, const float *gp, float *ge, hipStream_t s);
+hipError_t tr_add(long n, const float *a, float *b, hipStream_t s);
+hipError_t tr_fill(long n, float v, float *b, hipStream_t s);
+hipError_t tr_adam(long n, float *w, const float *g, float *m, float *v, float lr, float b1, float b2, float c1,
+                   float c2, float eps, hipStream_t s);
+hipError_t tr_repack(int Cin, int Cout, int CK, int nch, int Cout_pad, const float *blob, float *packed, float *bias,
+                     hipStream_t s);
 // Multi-resolution reconstruction pieces (mr.hip): 2x2 mean of a 3-channel
 // image, and the Eq. 7 blend (optionally remodulated).
 hipError_t launch_pool2(int H, int W, const float *in, float *out, hipStream_t s);

@@ -90,6 +90,12 @@ def lib():
         L.wskp_decode.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp]
         L.wskp_backward.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, sz]
         L.wskp_backward_workspace_size.argtypes = [vp, i32, i32, i32, ctypes.POINTER(sz)]
+        L.wskp_train_workspace_size.argtypes = [vp, i32, ip, ip, ctypes.POINTER(sz)]
+        L.wskp_train_grads.argtypes = [vp, vp, i32, ctypes.POINTER(wskp_frame_t),
+                                       ctypes.POINTER(vp), ctypes.c_float, vp, vp, vp, sz]
+        L.wskp_adam.argtypes = [vp, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float, ctypes.c_float]
+        L.wskp_get_weights.argtypes = [vp, vp, vp]
         L.wskp_pool2.argtypes = [vp, vp, i32, i32, vp, vp]
         L.wskp_mr_blend.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp]
         L.wskp_temporal.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp,
@@ -113,7 +119,8 @@ def lib():
                      "wskp_denoise_static", "wskp_denoise_batch", "wskp_decode", "wskp_backward",
                      "wskp_backward_workspace_size", "wskp_workspace_tensor",
                      "wskp_kp_map_bytes", "wskp_kp_expand", "wskp_kp_decode", "wskp_temporal",
-                     "wskp_pool2", "wskp_mr_blend",
+                     "wskp_pool2", "wskp_mr_blend", "wskp_train_workspace_size",
+                     "wskp_train_grads", "wskp_adam", "wskp_get_weights",
                      "wskp_timing_enable", "wskp_timing_read"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -291,6 +298,45 @@ def wskp_backward(h, head, c, mod, grad_out, grad_head, grad_c, ws, stream=None)
                                _ptr(grad_c, "grad_c", (N, H, W, 3)),
                                ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size()),
            "wskp_backward")
+
+
+def wskp_train_workspace_size(h, Hs, Ws) -> int:
+    n = len(Hs)
+    a = (ctypes.c_int * n)(*Hs)
+    b = (ctypes.c_int * n)(*Ws)
+    out = ctypes.c_size_t()
+    _check(lib().wskp_train_workspace_size(h, n, a, b, ctypes.byref(out)), "wskp_train_workspace_size")
+    return out.value
+
+
+def wskp_train_grads(h, frames, targets, grad, loss, ws, eps_smape: float = 0.01, stream=None) -> None:
+    """frames: dicts as for wskp_denoise_batch (with "out"); targets: [H,W,3]
+    device tensors; grad: [wskp_num_weights] float32; loss: [1] float32."""
+    n = len(frames)
+    arr = (wskp_frame_t * n)()
+    for i, f in enumerate(frames):
+        H, W = f["radiance"].shape[:2]
+        arr[i].H, arr[i].W = H, W
+        arr[i].radiance = _ptr(f["radiance"], "radiance", (H, W, 3)).value
+        arr[i].albedo = _ptr(f["albedo"], "albedo", (H, W, 3)).value
+        arr[i].normal = _ptr(f["normal"], "normal", (H, W, 3)).value
+        arr[i].depth = _ptr(f["depth"], "depth", (H, W, 1)).value
+        arr[i].out = _ptr(f["out"], "out", (H, W, 3)).value
+    tg = (ctypes.c_void_p * n)(*[_ptr(t, "target", tuple(frames[i]["radiance"].shape)).value
+                                 for i, t in enumerate(targets)])
+    _check(lib().wskp_train_grads(h, _stream(stream), n, arr, tg, eps_smape, _ptr(grad, "grad"),
+                                  _ptr(loss, "loss", (1,)), ctypes.c_void_p(ws.data_ptr()),
+                                  ws.numel() * ws.element_size()), "wskp_train_grads")
+
+
+def wskp_adam(h, grad, m, v, step: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-8, stream=None) -> None:
+    _check(lib().wskp_adam(h, _stream(stream), _ptr(grad, "grad"), _ptr(m, "m"), _ptr(v, "v"), step,
+                           lr, beta1, beta2, eps), "wskp_adam")
+
+
+def wskp_get_weights(h, dst, stream=None) -> None:
+    _check(lib().wskp_get_weights(h, _stream(stream), _ptr(dst, "dst")), "wskp_get_weights")
 
 
 def wskp_pool2(h, x, out, stream=None) -> None:
