@@ -307,13 +307,49 @@ def mode_train(args):
                                      np.linalg.norm(rh)),
            "grad_c_rel_l2": float(np.linalg.norm(gc[0].double().cpu().numpy() - rc) /
                                   np.linalg.norm(rc))}
+    # the whole training step of the network (Eq. 1, SMAPE of Eq. 6, Adam):
+    # forward of the 8 crops, loss, every layer's gradients, one Adam update
+    frames = []
+    for n in range(N):
+        f = {k: torch.from_numpy(fb[k][n]).cuda() for k in ("radiance", "albedo", "normal", "depth")}
+        f["out"] = torch.empty_like(f["radiance"])
+        frames.append(f)
+    targets = [t[n] for n in range(N)]
+    nw = blob.size
+    grad = torch.empty(nw, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    m1 = torch.zeros(nw, dtype=torch.float32, device="cuda")
+    v1 = torch.zeros(nw, dtype=torch.float32, device="cuda")
+    tws = torch.empty(wskp.wskp_train_workspace_size(dn.h, [H] * N, [W] * N), dtype=torch.uint8,
+                      device="cuda")
+    losses = []
+    for k in range(args.warmup):
+        wskp.wskp_train_grads(dn.h, frames, targets, grad, loss, tws)
+        wskp.wskp_adam(dn.h, grad, m1, v1, k + 1, lr=1e-3)
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 50))
+    t0 = time.perf_counter()
+    for k in range(steps):
+        wskp.wskp_train_grads(dn.h, frames, targets, grad, loss, tws)
+        wskp.wskp_adam(dn.h, grad, m1, v1, args.warmup + k + 1, lr=1e-3)
+        if k in (0, steps - 1):
+            losses.append(float(loss.item()))
+    torch.cuda.synchronize()
+    ms_train = (time.perf_counter() - t0) * 1e3 / steps
+    fl = conv_flops(cfg, H, W)
+    step_flops = 3.0 * N * sum(fl.values())   # forward + input and weight gradients
     print(json.dumps({
         "mode": "train_step", "workload": "8 crops of 256x256, decode+fusion forward, L1, adjoint",
         "crops_per_s": N * 1e3 / ms, "ms_per_step": ms,
         "decode_fwd_us": fwd_us, "adjoint_us": bwd_us,
         "decode_fwd_GBps": px * 76 / (fwd_us * 1e-6) / 1e9,
         "adjoint_GBps_algorithmic": px * 128 / (bwd_us * 1e-6) / 1e9,
-        "adjoint_vs_fp64_oracle": err}), flush=True)
+        "adjoint_vs_fp64_oracle": err,
+        "network_training_step": {
+            "workload": "8 crops of 256x256, hd net fp32, SMAPE loss, all layers' gradients, Adam",
+            "ms_per_step": ms_train, "crops_per_s": N * 1e3 / ms_train,
+            "conv_flops_per_step": step_flops, "achieved_TFLOPs": step_flops / ms_train / 1e9,
+            "loss_first_and_last_timed_step": losses}}), flush=True)
     dn.close()
 
 

@@ -115,9 +115,14 @@ def test_adam_step_updates_the_denoiser():
         # gradient is well above the fp32 noise of the sum (elsewhere its
         # sign, and so the direction of the move, is not determined)
         dg, dr = w_gpu - blob, w_ref - blob
-        big = np.abs(g_ref) > 1e-3 * np.abs(g_ref).max()
-        assert big.mean() > 0.5
-        assert rel_l2(dg[big], dr[big]) <= 1e-4, step
+        off = 0
+        for name, ci, co in synth.conv_shapes(cfg):
+            n = ci * co * 9 + co
+            gl = np.abs(g_ref[off:off + n])
+            big = gl > 1e-3 * gl.max()
+            assert big.mean() > 0.5, name
+            assert rel_l2(dg[off:off + n][big], dr[off:off + n][big]) <= 1e-4, (step, name)
+            off += n
         assert np.mean(np.sign(dg) != np.sign(dr)) <= 0.01, step
     fresh = wskp.Denoiser(cfg, cur.cpu().numpy(), "fp32")
     for f in frames:
