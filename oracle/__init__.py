@@ -53,10 +53,11 @@ def _load():
                                       ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                       _dp, _dp, _dp]
         lib.wo_conv3x3.argtypes = [_L, _L, _L, _L, _dp, _dp, _dp, ctypes.c_int, _dp]
+        lib.wo_conv2d.argtypes = [_L, _L, _L, _L, ctypes.c_int, _dp, _dp, _dp, ctypes.c_int, _dp]
         lib.wo_avgpool2.argtypes = [_L, _L, _L, _dp, _dp]
         lib.wo_upsample2.argtypes = [_L, _L, _L, _dp, _dp]
-        lib.wo_unet.argtypes = [_L, _L, ctypes.c_int, _ip, ctypes.c_int, ctypes.c_int, _fp,
-                                _dp, _dp]
+        lib.wo_unet.argtypes = [_L, _L, ctypes.c_int, _ip, ctypes.c_int, ctypes.c_int,
+                                ctypes.c_int, _fp, _dp, _dp]
         lib.wo_unet.restype = ctypes.c_int
         lib.wo_activate.argtypes = [_L, ctypes.c_int, ctypes.c_int, _dp, _dp]
         lib.wo_decode.argtypes = [_L, _L, ctypes.c_int, _ip, _dp, _dp, _dp, ctypes.c_double,
@@ -131,6 +132,18 @@ def conv3x3(x, w, b, relu: bool) -> np.ndarray:
     return out
 
 
+def conv2d(x, w, b, relu: bool = False) -> np.ndarray:
+    """k x k cross-correlation (k odd, from w's shape), zero pad (k-1)/2, +
+    bias; x [H,W,Cin], w [Cout,Cin,k,k]."""
+    x, w, b = _d(x), _d(w), _d(b)
+    H, W, Cin = x.shape
+    Cout, k = w.shape[0], w.shape[-1]
+    assert w.shape == (Cout, Cin, k, k) and k % 2 == 1 and b.shape == (Cout,)
+    out = np.empty((H, W, Cout))
+    _load().wo_conv2d(H, W, Cin, Cout, k, _ptr(x), _ptr(w), _ptr(b), int(relu), _ptr(out))
+    return out
+
+
 def avgpool2(x) -> np.ndarray:
     x = _d(x)
     H, W, C = x.shape
@@ -147,14 +160,16 @@ def upsample2(x) -> np.ndarray:
     return out
 
 
-def unet(X, blob, levels: int, channels: Sequence[int], out_channels: int) -> np.ndarray:
-    """Raw network output h [H,W,out_channels] for input X [H,W,Cin]."""
+def unet(X, blob, levels: int, channels: Sequence[int], out_channels: int,
+         conv_size: int = 3) -> np.ndarray:
+    """Raw network output h [H,W,out_channels] for input X [H,W,Cin]; every
+    conv is conv_size x conv_size."""
     X = _d(X)
     blob = _f(blob)
     H, W, Cin = X.shape
     h = np.empty((H, W, out_channels))
-    rc = _load().wo_unet(H, W, levels, _ints(channels), Cin, out_channels, _ptr(blob, _fp),
-                         _ptr(X), _ptr(h))
+    rc = _load().wo_unet(H, W, levels, _ints(channels), Cin, out_channels, int(conv_size),
+                         _ptr(blob, _fp), _ptr(X), _ptr(h))
     if rc != 0:
         raise ValueError(f"wo_unet failed ({rc}): H, W must be multiples of 2^(L-1)")
     return h
@@ -275,16 +290,24 @@ def l1(y, t):
     return v, g
 
 
-def denoise(frame: Dict[str, np.ndarray], blob, cfg, return_all: bool = False):
+def denoise(frame: Dict[str, np.ndarray], blob, cfg, return_all: bool = False,
+            branches=None):
     """Whole per-frame path for one frame: y [H,W,3] in float64.
 
     ``cfg`` carries levels, channels, kernel_sizes, eps_norm, eps_albedo,
-    gamma, depth_near, depth_far and weight_act.  With ``return_all`` the
-    intermediates (X, c, mod, h, head) come back in a dict as well.
+    gamma, depth_near, depth_far, weight_act and conv_size (3 if absent).
+    With ``branches`` (and ``blob`` None) the network is the training-time
+    RepVGG form: every conv is the multi-branch block of ``repvgg_block``.
+    With ``return_all`` the intermediates (X, c, mod, h, head) come back in a
+    dict as well.
     """
     X, c, mod = preprocess(frame["radiance"], frame["albedo"], frame["normal"], frame["depth"],
                            cfg.gamma, cfg.depth_near, cfg.depth_far, cfg.eps_albedo)
-    h = unet(X, blob, cfg.levels, cfg.channels, 2 * len(cfg.kernel_sizes))
+    if branches is not None:
+        h = repvgg_unet(X, branches, cfg)
+    else:
+        h = unet(X, blob, cfg.levels, cfg.channels, 2 * len(cfg.kernel_sizes),
+                 getattr(cfg, "conv_size", 3))
     head = activate(h, len(cfg.kernel_sizes), cfg.weight_act)
     y = decode(head, c, mod, cfg.kernel_sizes, cfg.eps_norm)
     if return_all:
@@ -306,25 +329,81 @@ def unet_layers(X, blob, cfg) -> Dict[str, np.ndarray]:
           [ch[l + 1] + ch[l] for l in range(L - 2, -1, -1)] + [ch[0]]
     cout = [ch[l] for l in range(L)] + [ch[l] for l in range(L - 2, -1, -1)] + \
            [2 * len(cfg.kernel_sizes)]
+    k = getattr(cfg, "conv_size", 3)
     for ci, co in zip(cin, cout):
-        w = blob[off:off + co * ci * 9].reshape(co, ci, 3, 3)
-        off += co * ci * 9
+        w = blob[off:off + co * ci * k * k].reshape(co, ci, k, k)
+        off += co * ci * k * k
         b = blob[off:off + co]
         off += co
         convs.append((w, b))
     out = {}
-    e = conv3x3(X, *convs[0], relu=True)
+    e = conv2d(X, *convs[0], relu=True)
     out["e0"] = e
     for l in range(1, L):
-        e = conv3x3(avgpool2(e), *convs[l], relu=True)
+        e = conv2d(avgpool2(e), *convs[l], relu=True)
         out[f"e{l}"] = e
     u = out[f"e{L - 1}"]
     for j, l in enumerate(range(L - 2, -1, -1)):
         cat = np.concatenate([upsample2(u), out[f"e{l}"]], axis=-1)
-        u = conv3x3(cat, *convs[L + j], relu=True)
+        u = conv2d(cat, *convs[L + j], relu=True)
         out[f"u{l}"] = u
-    out["h"] = conv3x3(u, *convs[-1], relu=False)
+    out["h"] = conv2d(u, *convs[-1], relu=False)
     return out
+
+
+# ---------------------------------------------------------------- RepVGG
+# A RepVGG block (Sec. 4.1, prediction phase) is, while training, the sum of
+# a 1x1, a 3x3 and a 5x5 conv branch (each with its bias) and, when it maps
+# C channels to C channels, the identity, followed by ReLU; for inference
+# the branches are merged into one 5x5 conv that computes the same map.
+# A block's parameters are a dict with "w1" [Co,Ci,1,1], "b1", "w3"
+# [Co,Ci,3,3], "b3", "w5" [Co,Ci,5,5], "b5" (a missing pair is an absent
+# branch) and "identity" (bool, only with Ci == Co).
+def repvgg_block(x, br, relu: bool = True) -> np.ndarray:
+    """The training-time block: each branch's conv of x, summed, plus x for
+    the identity branch, then ReLU (when ``relu``)."""
+    x = _d(x)
+    y = None
+    for k in (1, 3, 5):
+        if br.get(f"w{k}") is not None:
+            t = conv2d(x, br[f"w{k}"], br[f"b{k}"])
+            y = t if y is None else y + t
+    if br.get("identity"):
+        assert y is None or x.shape[-1] == y.shape[-1], "identity branch needs C_in == C_out"
+        y = x.copy() if y is None else y + x
+    return np.maximum(y, 0.0) if relu else y
+
+
+def repvgg_merge(br, cin: int, cout: int) -> Tuple[np.ndarray, np.ndarray]:
+    """The inference-time 5x5 conv (w [Co,Ci,5,5], b [Co]) of a block: each
+    branch's kernel placed at the centre of a zero 5x5 kernel, the identity
+    as a unit tap at the centre of (co, co), all summed; biases summed."""
+    w = np.zeros((cout, cin, 5, 5))
+    b = np.zeros(cout)
+    for k in (1, 3, 5):
+        if br.get(f"w{k}") is not None:
+            o = (5 - k) // 2
+            w[:, :, o:o + k, o:o + k] += _d(br[f"w{k}"])
+            b += _d(br[f"b{k}"])
+    if br.get("identity"):
+        assert cin == cout
+        for c in range(cout):
+            w[c, c, 2, 2] += 1.0
+    return w, b
+
+
+def repvgg_unet(X, branches, cfg) -> np.ndarray:
+    """Raw network output h of the U-Net whose every conv is a training-time
+    RepVGG block (branches in blob order; the head block has no ReLU)."""
+    L = cfg.levels
+    X = _d(X)
+    e = [repvgg_block(X, branches[0])]
+    for l in range(1, L):
+        e.append(repvgg_block(avgpool2(e[-1]), branches[l]))
+    u = e[L - 1]
+    for j, l in enumerate(range(L - 2, -1, -1)):
+        u = repvgg_block(np.concatenate([upsample2(u), e[l]], axis=-1), branches[L + j])
+    return repvgg_block(u, branches[-1], relu=False)
 
 
 # ---------------------------------------------------------------- training

@@ -62,29 +62,40 @@ void wo_preprocess(long H, long W, const float *r, const float *a, const float *
     }
 }
 
-/* 3x3 cross-correlation, stride 1, zero padding 1, plus bias (the usual CNN
- * convolution); optional ReLU.  out[y][x][co] = b[co] +
- *   sum_{ci,ky,kx} w[co][ci][ky][kx] * in[y+ky-1][x+kx-1][ci]. */
-void wo_conv3x3(long H, long W, long Cin, long Cout, const double *in,
-                const double *w, const double *b, int relu, double *out)
+/* k x k cross-correlation (k odd), stride 1, zero padding (k-1)/2, plus
+ * bias (the usual CNN convolution); optional ReLU.  With r = (k-1)/2:
+ *   out[y][x][co] = b[co] +
+ *     sum_{ci,ky,kx} w[co][ci][ky][kx] * in[y+ky-r][x+kx-r][ci].
+ * k = 3 is the prediction network's conv (Sec. 4.1); k = 1, 3 and 5 are the
+ * branches of a RepVGG block and k = 5 its merged inference form (Sec. 4.1,
+ * prediction phase). */
+void wo_conv2d(long H, long W, long Cin, long Cout, int k, const double *in,
+               const double *w, const double *b, int relu, double *out)
 {
+    const int r = (k - 1) / 2;
 #pragma omp parallel for schedule(static)
     for (long y = 0; y < H; ++y)
         for (long x = 0; x < W; ++x)
             for (long co = 0; co < Cout; ++co) {
                 double acc = b[co];
                 for (long ci = 0; ci < Cin; ++ci)
-                    for (int ky = 0; ky < 3; ++ky) {
-                        long yy = y + ky - 1;
+                    for (int ky = 0; ky < k; ++ky) {
+                        long yy = y + ky - r;
                         if (yy < 0 || yy >= H) continue;
-                        for (int kx = 0; kx < 3; ++kx) {
-                            long xx = x + kx - 1;
+                        for (int kx = 0; kx < k; ++kx) {
+                            long xx = x + kx - r;
                             if (xx < 0 || xx >= W) continue;
-                            acc += w[((co * Cin + ci) * 3 + ky) * 3 + kx] * in[IDX(yy, xx, ci, W, Cin)];
+                            acc += w[((co * Cin + ci) * k + ky) * k + kx] * in[IDX(yy, xx, ci, W, Cin)];
                         }
                     }
                 out[IDX(y, x, co, W, Cout)] = (relu && acc < 0.0) ? 0.0 : acc;
             }
+}
+
+void wo_conv3x3(long H, long W, long Cin, long Cout, const double *in,
+                const double *w, const double *b, int relu, double *out)
+{
+    wo_conv2d(H, W, Cin, Cout, 3, in, w, b, relu, out);
 }
 
 /* 2x2 mean, stride 2 (the D operator of Sec. 5.2). out is [H/2, W/2, C]. */
@@ -126,15 +137,15 @@ static double *widen(const float *src, long n)
     return d;
 }
 
-/* Runs one conv of the blob: reads w (Cout*Cin*9) then b (Cout) at *off. */
-static void blob_conv(const float *blob, long *off, long H, long W, long Cin, long Cout,
+/* Runs one k x k conv of the blob: reads w (Cout*Cin*k*k) then b (Cout) at *off. */
+static void blob_conv(const float *blob, long *off, long H, long W, long Cin, long Cout, int k,
                       const double *in, int relu, double *out)
 {
-    double *w = widen(blob + *off, Cout * Cin * 9);
-    *off += Cout * Cin * 9;
+    double *w = widen(blob + *off, Cout * Cin * k * k);
+    *off += Cout * Cin * k * k;
     double *b = widen(blob + *off, Cout);
     *off += Cout;
-    wo_conv3x3(H, W, Cin, Cout, in, w, b, relu, out);
+    wo_conv2d(H, W, Cin, Cout, k, in, w, b, relu, out);
     free(w);
     free(b);
 }
@@ -144,13 +155,14 @@ static void blob_conv(const float *blob, long *off, long H, long W, long Cin, lo
  *   e_0 = ReLU(conv(X));  e_l = ReLU(conv(pool(e_{l-1}))),  l = 1..L-1
  *   u_{L-1} = e_{L-1};    u_l = ReLU(conv([up(u_{l+1}), e_l])),  l = L-2..0
  *   h = conv(u_0)         (Cout = 2M raw outputs, no activation)
+ * Every conv is k x k (k = 3, or k = 5 for a net of merged RepVGG blocks).
  * H and W must be multiples of 2^(L-1).  Weights in blob order
  * enc0..enc_{L-1}, dec_{L-2}..dec_0, head.  Returns 0 on success.
  * ---------------------------------------------------------------------- */
-int wo_unet(long H, long W, int L, const int *ch, int Cin, int Cout, const float *blob,
+int wo_unet(long H, long W, int L, const int *ch, int Cin, int Cout, int k, const float *blob,
             const double *X, double *h)
 {
-    if (L < 1 || L > 8) return -1;
+    if (L < 1 || L > 8 || k < 1 || k % 2 == 0) return -1;
     double *e[8], *u[8];
     long Hl[8], Wl[8];
     long off = 0;
@@ -161,11 +173,11 @@ int wo_unet(long H, long W, int L, const int *ch, int Cin, int Cout, const float
         e[l] = (double *)malloc(sizeof(double) * (size_t)(Hl[l] * Wl[l] * ch[l]));
         u[l] = NULL;
     }
-    blob_conv(blob, &off, H, W, Cin, ch[0], X, 1, e[0]);
+    blob_conv(blob, &off, H, W, Cin, ch[0], k, X, 1, e[0]);
     for (int l = 1; l < L; ++l) {
         double *p = (double *)malloc(sizeof(double) * (size_t)(Hl[l] * Wl[l] * ch[l - 1]));
         wo_avgpool2(Hl[l - 1], Wl[l - 1], ch[l - 1], e[l - 1], p);
-        blob_conv(blob, &off, Hl[l], Wl[l], ch[l - 1], ch[l], p, 1, e[l]);
+        blob_conv(blob, &off, Hl[l], Wl[l], ch[l - 1], ch[l], k, p, 1, e[l]);
         free(p);
     }
     u[L - 1] = e[L - 1];
@@ -176,11 +188,11 @@ int wo_unet(long H, long W, int L, const int *ch, int Cin, int Cout, const float
         double *cat = (double *)malloc(sizeof(double) * (size_t)(P * (ch[l + 1] + ch[l])));
         wo_concat(P, ch[l + 1], up, ch[l], e[l], cat);
         u[l] = (double *)malloc(sizeof(double) * (size_t)(P * ch[l]));
-        blob_conv(blob, &off, Hl[l], Wl[l], ch[l + 1] + ch[l], ch[l], cat, 1, u[l]);
+        blob_conv(blob, &off, Hl[l], Wl[l], ch[l + 1] + ch[l], ch[l], k, cat, 1, u[l]);
         free(up);
         free(cat);
     }
-    blob_conv(blob, &off, H, W, ch[0], Cout, u[0], 0, h);
+    blob_conv(blob, &off, H, W, ch[0], Cout, k, u[0], 0, h);
     for (int l = 0; l < L; ++l) {
         if (u[l] && u[l] != e[l]) free(u[l]);
         free(e[l]);

@@ -43,6 +43,7 @@ class NetConfig:
     depth_near: float = 1.0
     depth_far: float = 10.0
     weight_act: str = "softplus"   # "softplus" or "exp" (Eq. 3)
+    conv_size: int = 3             # 3, or 5: every conv a merged RepVGG block (Sec. 4.1)
 
     @property
     def M(self) -> int:
@@ -69,6 +70,11 @@ HD = NetConfig(levels=4, channels=(32, 64, 96, 128), kernel_sizes=(3, 5, 7, 9, 1
 # hd U-Net.
 PAPER6 = NetConfig(levels=4, channels=(32, 64, 96, 128), kernel_sizes=(3, 5, 7, 9, 11, 13),
                    weight_act="exp")
+# RepVGG encoders and decoders (Sec. 4.1, prediction phase): every conv of
+# the U-Net is a RepVGG block, run as its merged 5x5 conv.
+REPVGG = NetConfig(levels=4, channels=(32, 64, 96, 128), kernel_sizes=(3, 5, 7, 9, 11),
+                   conv_size=5)
+REPVGG_SMALL = NetConfig(levels=3, channels=(16, 32, 64), kernel_sizes=(3, 5, 7), conv_size=5)
 CONFIGS: Dict[str, NetConfig] = {"small": SMALL, "hd": HD, "paper6": PAPER6}
 
 SERVE_RESOLUTIONS: Tuple[Tuple[int, int], ...] = ((360, 640), (720, 1280), (1080, 1920), (1440, 2560))
@@ -91,25 +97,46 @@ def conv_shapes(cfg: NetConfig) -> List[Tuple[str, int, int]]:
 
 
 def num_weights(cfg: NetConfig) -> int:
-    return sum(co * ci * 9 + co for _, ci, co in conv_shapes(cfg))
+    k2 = cfg.conv_size * cfg.conv_size
+    return sum(co * ci * k2 + co for _, ci, co in conv_shapes(cfg))
 
 
 def make_weights(cfg: NetConfig, seed: int = 0) -> np.ndarray:
-    """Flat float32 blob: for each conv, w[C_out][C_in][3][3] then b[C_out].
+    """Flat float32 blob: for each conv, w[C_out][C_in][k][k] then b[C_out]
+    (k = cfg.conv_size).
 
-    He-normal weights, N(0, 2 / (9 C_in)); biases U(-0.05, 0.05) so the bias
-    path is exercised.
+    He-normal weights, N(0, 2 / (k^2 C_in)); biases U(-0.05, 0.05) so the
+    bias path is exercised.
     """
     rng = np.random.default_rng(seed)
+    k = cfg.conv_size
     parts = []
     for _, ci, co in conv_shapes(cfg):
-        w = rng.normal(0.0, np.sqrt(2.0 / (9 * ci)), size=(co, ci, 3, 3))
+        w = rng.normal(0.0, np.sqrt(2.0 / (k * k * ci)), size=(co, ci, k, k))
         b = rng.uniform(-0.05, 0.05, size=(co,))
         parts.append(w.astype(np.float32).ravel())
         parts.append(b.astype(np.float32))
     blob = np.concatenate(parts)
     assert blob.size == num_weights(cfg)
     return blob
+
+
+def make_repvgg_branches(cfg: NetConfig, seed: int = 0) -> List[Dict[str, np.ndarray]]:
+    """Training-time RepVGG parameters for every conv of ``cfg`` (blob
+    order): 1x1, 3x3 and 5x5 branches, float32, each He-normal with a third
+    of the usual variance (the branches add up), biases U(-0.02, 0.02), and
+    the identity branch wherever C_in == C_out."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _, ci, co in conv_shapes(cfg):
+        br: Dict[str, np.ndarray] = {}
+        for k in (1, 3, 5):
+            br[f"w{k}"] = rng.normal(0.0, np.sqrt(2.0 / (3 * k * k * ci)),
+                                     size=(co, ci, k, k)).astype(np.float32)
+            br[f"b{k}"] = rng.uniform(-0.02, 0.02, size=(co,)).astype(np.float32)
+        br["identity"] = ci == co
+        out.append(br)
+    return out
 
 
 def make_frame(seed: int, H: int, W: int) -> Dict[str, np.ndarray]:
