@@ -12,7 +12,10 @@ with consecutive frames in flight on --streams HIP streams (frames/s on one
 stream, latency of single frames and the FP32 path are reported beside it),
 `roofline` is for the kernel that
 takes the most time per frame, `decode_roofline` for the decode kernel,
-`cpu_baseline` is the FP64 CPU oracle on the same frame.
+`serving` compares bf16 continuous batching with the plain per-frame loop
+(bf16 and fp32) on one 64-stream request trace of mixed resolutions (not
+part of the timed region), `cpu_baseline` is the FP64 CPU oracle on the
+same frame.
 """
 from __future__ import annotations
 
@@ -353,13 +356,12 @@ def mode_train(args):
     dn.close()
 
 
-def mode_serve(args):
-    """64 streams, Poisson 2000 frames/s: bf16 continuous batching vs the
-    plain fp32 per-frame loop on the same trace."""
+def serve_setup(args):
+    """The C4 workload: 64 streams with resolutions drawn from 360p..1440p,
+    Poisson arrivals at 2000 frames/s in total, ``--serve-frames`` frames per
+    stream, every stream's input frame resident on the device."""
     import torch
-    from paper_2202_05977_amd import serve, synth, wskp
-    cfg = synth.HD
-    blob = synth.make_weights(cfg, 0)
+    from paper_2202_05977_amd import serve, synth
     sizes, reqs = serve.poisson_trace(64, args.serve_frames, 2000.0, synth.SERVE_RESOLUTIONS,
                                       seed=7)
     proto = {}
@@ -367,17 +369,81 @@ def mode_serve(args):
         proto[(H, W)] = {k: torch.from_numpy(v).cuda()
                          for k, v in synth.make_frame(1000 + H, H, W).items() if k != "clean"}
     inputs = {s: {k: v.clone() for k, v in proto[sizes[s]].items()} for s in range(64)}
+    return sizes, reqs, proto, inputs
+
+
+def _warm(serve, ex, sizes, proto):
+    for (H, W) in proto:
+        tok = ex.launch([serve.Request(-1, sizes.index((H, W)), 0.0, H, W)], 0, 0)
+        ex.wait(tok)
+
+
+def _stats(st, **extra):
+    d = {"frames_per_s": st.frames_per_s, "p50_ms": st.p50_ms, "p99_ms": st.p99_ms,
+         "frames": st.frames, "errors": st.errors, "mean_batch": st.mean_batch,
+         "max_batch": st.max_batch, "wall_s": st.wall_s}
+    d.update(extra)
+    return d
+
+
+def serving_comparison(args):
+    """bf16 continuous batching against the plain per-frame loop (bf16 and
+    fp32) on the SAME request trace, all requests of it, arrivals in real
+    time.  Returns the dict the headline line carries under "serving"."""
+    import torch
+    from paper_2202_05977_amd import serve, synth, wskp
+    cfg = synth.HD
+    blob = synth.make_weights(cfg, 0)
+    sizes, reqs, proto, inputs = serve_setup(args)
+    budget = 64 << 30
+    out = {"workload": f"64 streams, Poisson 2000 frames/s, {args.serve_frames} frames/stream "
+                       f"({len(reqs)} requests), resolutions 360p/720p/1080p/1440p, "
+                       "64 GB admission budget, inputs resident on the device",
+           "mean_megapixels": float(np.mean([H * W for (H, W) in sizes])) / 1e6}
+    dn = wskp.Denoiser(cfg, blob, "bf16")
+    ex = serve.GpuExecutor(dn, inputs, budget, slots=args.inflight)
+    _warm(serve, ex, sizes, proto)
+    st = serve.Server(ex, budget, max_inflight=args.inflight, max_batch=args.max_batch).run(
+        [dataclasses_replace(r) for r in reqs])
+    out["bf16_continuous_batching"] = _stats(st, batches_in_flight=args.inflight)
+    log(f"[serve] bf16 continuous batching: {st}")
+    st = serve.Server(ex, budget, max_inflight=args.inflight, max_batch=args.max_batch).run(
+        [dataclasses_replace(r) for r in reqs], realtime=False)
+    out["bf16_capacity_frames_per_s"] = st.frames / st.wall_s
+    log(f"[serve] bf16 capacity (whole trace queued): {st.frames / st.wall_s:.1f} frames/s, "
+        f"mean batch {st.mean_batch:.1f}")
+    st = serve.fifo_single(ex, [dataclasses_replace(r) for r in reqs])
+    out["bf16_per_frame_loop"] = _stats(st)
+    log(f"[serve] bf16 per-frame loop: {st}")
+    del ex
+    dn.close()
+    dn = wskp.Denoiser(cfg, blob, "fp32")
+    ex = serve.GpuExecutor(dn, inputs, 8 << 30)
+    _warm(serve, ex, sizes, proto)
+    st = serve.fifo_single(ex, [dataclasses_replace(r) for r in reqs])
+    out["fp32_per_frame_loop"] = _stats(st)
+    log(f"[serve] fp32 per-frame loop: {st}")
+    del ex
+    dn.close()
+    torch.cuda.synchronize()
+    return out
+
+
+def mode_serve(args):
+    """The C4 trace through the bf16 server in more forms than the headline
+    line carries: direct launches, graph replay (two passes), capacity."""
+    from paper_2202_05977_amd import serve, synth, wskp
+    cfg = synth.HD
+    blob = synth.make_weights(cfg, 0)
+    sizes, reqs, proto, inputs = serve_setup(args)
     budget = 64 << 30
     res = {}
     dn = wskp.Denoiser(cfg, blob, "bf16")
     ex = serve.GpuExecutor(dn, inputs, budget, slots=args.inflight)
-    # warm up every resolution once
-    for (H, W) in proto:
-        tok = ex.launch([serve.Request(-1, sizes.index((H, W)), 0.0, H, W)], 0, 0)
-        ex.wait(tok)
+    _warm(serve, ex, sizes, proto)
     st = serve.Server(ex, budget, max_inflight=args.inflight, max_batch=args.max_batch).run(
         [dataclasses_replace(r) for r in reqs])
-    res["bf16_continuous_batching"] = st.__dict__
+    res["bf16_continuous_batching"] = _stats(st)
     log(f"[serve] bf16 batching: {st}")
     # the same server, every batch a graph replay (one graph per stream and
     # capacity bucket, captured on first use).  The first pass over the trace
@@ -387,32 +453,21 @@ def mode_serve(args):
     for k in range(2):
         st = serve.Server(exg, budget, max_inflight=args.inflight, max_batch=args.max_batch).run(
             [dataclasses_replace(r) for r in reqs])
-        res["bf16_continuous_batching_graph" + ("_first_pass" if k == 0 else "")] = st.__dict__
+        res["bf16_continuous_batching_graph" + ("_first_pass" if k == 0 else "")] = _stats(st)
         log(f"[serve] bf16 batching, graph replay, pass {k + 1}: {st}")
     del exg
-    # capacity: the whole trace queued at once, frames per wall-clock second
     st = serve.Server(ex, budget, max_inflight=args.inflight, max_batch=args.max_batch).run(
         [dataclasses_replace(r) for r in reqs], realtime=False)
-    res["bf16_batching_capacity_fps"] = st.frames / st.wall_s
+    res["bf16_capacity"] = _stats(st)
     log(f"[serve] bf16 batching capacity: {st.frames / st.wall_s:.1f} frames/s "
         f"(mean batch {st.mean_batch:.1f})")
-    n_fifo = min(len(reqs), args.fifo_frames)
-    st = serve.fifo_single(ex, [dataclasses_replace(r) for r in reqs[:n_fifo]])
-    res["bf16_fifo_single"] = {**st.__dict__, "requests": n_fifo}
-    log(f"[serve] bf16 fifo: {st}")
     del ex
     dn.close()
-    dn = wskp.Denoiser(cfg, blob, "fp32")
-    ex = serve.GpuExecutor(dn, inputs, 8 << 30)
-    st = serve.fifo_single(ex, [dataclasses_replace(r) for r in reqs[:n_fifo]])
-    res["fp32_fifo_single"] = {**st.__dict__, "requests": n_fifo}
-    log(f"[serve] fp32 fifo: {st}")
     mean_px = float(np.mean([H * W for (H, W) in sizes]))
     print(json.dumps({"mode": "serve", "workload": "64 streams, Poisson 2000 frames/s, "
                       f"{args.serve_frames} frames/stream, resolutions 360p..1440p, 64 GB budget",
                       "mean_megapixels": mean_px / 1e6, "batches_in_flight": args.inflight,
                       "max_batch": args.max_batch, "results": res}), flush=True)
-    dn.close()
 
 
 def mode_kernels(args):
@@ -614,8 +669,10 @@ def main():
                     help="headline: the 720p JSON line; sweep: 1080p precisions vs oracle; "
                          "train: decode adjoint on 8x256^2 crops; serve: 64-stream trace; "
                          "kernels: decode time vs number of kernel sizes, explicit kernel maps")
-    ap.add_argument("--serve-frames", type=int, default=300)
-    ap.add_argument("--fifo-frames", type=int, default=2000)
+    ap.add_argument("--serve-frames", type=int, default=300,
+                    help="serving trace: frames per stream (64 streams)")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="headline: skip the serving comparison")
     ap.add_argument("--max-batch", type=int, default=64,
                     help="serve: most frames one batch may hold")
     ap.add_argument("--streams", type=int, default=3,
@@ -700,6 +757,10 @@ def main():
         t = sum(v for k, v in res[p]["per_kernel_us"].items() if k != "decode") * 1e-6
         conv_mfma[p] = {"tflops": tot / t / 1e12, "frac_of_peak": tot / t / PEAK[p]}
 
+    serving = None
+    if not args.no_serve:
+        serving = serving_comparison(args)
+
     cpu = None
     errors = {}
     if not args.no_cpu_baseline:
@@ -746,6 +807,7 @@ def main():
                            "single_stream_frames_per_s": res[p]["single_stream_fps"],
                            "p50_ms": res[p]["p50_ms"], "p99_ms": res[p]["p99_ms"],
                            "per_kernel_us": res[p]["per_kernel_us"]} for p in precs},
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
