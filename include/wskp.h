@@ -86,6 +86,9 @@ typedef enum {
  *  eps_albedo     c = r / (a + eps_albedo); the same factor remodulates
  *  gamma          tone map of the network's radiance input: clamp(r,0,1)^(1/gamma)
  *  depth_near/far depth scaled as clamp((d - near)/(far - near), 0, 1)
+ *  conv_size      3, or 5: every conv is a k x k conv with k = conv_size; 5 is
+ *                 the inference form of a RepVGG block (Sec. 4.1, prediction
+ *                 phase; see wskp_repvgg_merge).  5 supports FP32 and BF16.
  * Network input channels (Sec. 5.1): [tonemapped r (3), albedo (3),
  * (normal + 1)/2 (3), scaled depth (1)]. */
 typedef struct {
@@ -101,6 +104,7 @@ typedef struct {
     float gamma;
     float depth_near;
     float depth_far;
+    int32_t conv_size;
 } wskp_config_t;
 
 /* One frame of a batch.  Device pointers, NHWC float32:
@@ -115,8 +119,8 @@ typedef struct {
 } wskp_frame_t;
 
 /* Number of float32 values in the weight blob for `cfg`.  Blob order:
- * enc0..enc_{L-1}, dec_{L-2}..dec_0, head; each conv is w[C_out][C_in][3][3]
- * followed by b[C_out].  enc0 has C_in = 10, enc_l has C_in = C_{l-1},
+ * enc0..enc_{L-1}, dec_{L-2}..dec_0, head; each conv is w[C_out][C_in][k][k]
+ * (k = conv_size) followed by b[C_out].  enc0 has C_in = 10, enc_l has C_in = C_{l-1},
  * dec_l has C_in = C_{l+1} + C_l (upsampled coarse features first), head
  * has C_in = C_0 and C_out = 2M (M weight channels, then M logits).
  * Returns 0 for an invalid config. */
@@ -135,6 +139,21 @@ size_t wskp_num_weights(const wskp_config_t *cfg);
  * s_w = max|w| / 448.  FP8 needs every level width to be a multiple of 32. */
 wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host_weights, size_t n_weights,
                           const float *host_act_scales, int device, wskp_handle_t *out);
+
+/* RepVGG re-parameterisation (Sec. 4.1, prediction phase): a block that is,
+ * during training, the sum of a 1x1, a 3x3 and a 5x5 conv branch (each with
+ * its bias, zero padding (k-1)/2) plus, when C_in == C_out, the identity,
+ * computes the same map as ONE 5x5 conv; this writes that conv's weights.
+ * Host arrays, OIHW: w1 [cout][cin][1][1], w3 [cout][cin][3][3],
+ * w5 [cout][cin][5][5], biases [cout]; a branch whose w or b is NULL is
+ * absent.  identity != 0 adds the identity branch (needs cin == cout).
+ * Output: w_out [cout][cin][5][5] (each branch's kernel centred, the identity
+ * a unit centre tap of (c, c)) and b_out [cout] (the biases summed), in the
+ * layout of one conv of the weight blob with conv_size = 5.  Pure host
+ * arithmetic in float32, synchronous, no device needed. */
+wskp_status_t wskp_repvgg_merge(int cin, int cout, const float *w1, const float *b1,
+                                const float *w3, const float *b3, const float *w5,
+                                const float *b5, int identity, float *w_out, float *b_out);
 
 /* Releases the handle's device memory.  Synchronises the device first. */
 wskp_status_t wskp_destroy(wskp_handle_t h);

@@ -1,14 +1,15 @@
-// 3x3 convolutions of the prediction network (Sec. 4.1, Eq. 2) as implicit
-// GEMMs on the gfx950 matrix cores.
+// Convolutions of the prediction network (Sec. 4.1, Eq. 2) as implicit
+// GEMMs on the gfx950 matrix cores: 3x3, or 5x5 for a net whose convs are
+// merged RepVGG blocks (Sec. 4.1, prediction phase).
 //
 // GEMM view of one layer: output pixels x output channels, reduction K =
-// 9 taps x C_in (the MFMAs take the weights as their first operand, so each
-// lane ends with 4 consecutive channels of one pixel, which the epilogue
-// stores directly).  A workgroup (4 wave64s) owns a tile of
+// KS*KS taps x C_in (the MFMAs take the weights as their first operand, so
+// each lane ends with 4 consecutive channels of one pixel, which the
+// epilogue stores directly).  A workgroup (4 wave64s) owns a tile of
 // TH x 32 output pixels and 16*NB output channels.  The reduction runs over
-// chunks of CK input channels: the (TH+2) x 34 input halo of the chunk and
-// the matching 9*CK x 16*NB weight slice are staged in LDS, then every wave
-// issues MFMAs over the 9 taps.  The operation that produces the layer's
+// chunks of CK input channels: the (TH+KS-1) x (32+KS-1) input halo of the
+// chunk and the matching KS*KS*CK x 16*NB weight slice are staged in LDS,
+// then every wave issues MFMAs over the taps.  The operation that produces the layer's
 // input is fused into the staging step, so that input never exists in
 // memory:
 //   CONV_PACK   network input (Sec. 5.1): gamma-tonemapped radiance, albedo,
@@ -208,17 +209,18 @@ __device__ __forceinline__ void pack_transform(const ConvLayer &L, float x[10])
 }
 
 // =============================================================================
-// Staging of one reduction chunk: the (TH+2) x 34 input halo (virtual
-// channels [cc*CK, cc*CK+CK)) and the weight slice.  init() computes each
+// Staging of one reduction chunk: the (TH+KS-1) x (32+KS-1) input halo
+// (virtual channels [cc*CK, cc*CK+CK)) and the weight slice.  init() computes each
 // item's source offsets once; fetch() only issues global loads into
 // registers (and, for pooling, averages them); commit() writes the registers
 // to LDS.  The main loop fetches chunk cc+1 while the MFMAs of chunk cc run.
 // =============================================================================
-template <int PREC, int MODE, int CK, int TH, int NB, typename SrcT>
+template <int PREC, int MODE, int CK, int TH, int NB, typename SrcT, int KS>
 struct Stage {
     static constexpr bool BF = PREC == 1;       // bf16 operands
     static constexpr bool F8 = PREC == 2;       // fp8 (e4m3) operands, bf16 activations in HBM
-    static constexpr int TW = kConvTW, HP = TH + 2, WP = TW + 2;
+    static constexpr int KR = KS / 2;           // halo width
+    static constexpr int TW = kConvTW, HP = TH + KS - 1, WP = TW + KS - 1;
     // input items: a 16-byte run of one pixel's channels (PACK: one pixel)
     static constexpr int G = (MODE == CONV_PACK) ? CK : 16 / (int)sizeof(SrcT);
     static constexpr int NG = CK / G;
@@ -229,7 +231,7 @@ struct Stage {
     static constexpr int PL = ((HP * WP - 16 + 31) / 32) * 32 + 16;     // fp32 plane stride
     static constexpr int PS = CK + 8;                                    // bf16 pixel stride (elements)
     static constexpr int PS8 = CK + 16;                                  // fp8 pixel stride (bytes)
-    static constexpr int KE = 9 * CK;
+    static constexpr int KE = KS * KS * CK;
     static constexpr int NR = KE / 32;                                   // fp8: runs of 32 K values
     static constexpr int NK = F8 ? (NR + 3) / 4 : (BF ? (KE + 31) / 32 : KE / 4);  // MFMAs per chunk
     static constexpr int BS = NB * 16 + ((NB % 2 == 0) ? 16 : 0);        // fp32 weight row stride
@@ -258,7 +260,7 @@ struct Stage {
             const int it = tid + k * kThreads;
             const int p = it / NG, cg = it - p * NG;
             const int ly = p / WP, lx = p - ly * WP;
-            const int gy = y0 - 1 + ly, gx = x0 - 1 + lx;
+            const int gy = y0 - KR + ly, gx = x0 - KR + lx;
             off0[k] = off1[k] = 0;
             if (it < TOT && gy >= 0 && gy < Hl && gx >= 0 && gx < Wl) {
                 live |= 1u << k;
@@ -435,14 +437,15 @@ struct Stage {
     }
 };
 
-// One chunk's MFMAs.  fp32: 9*CK/4 steps of v_mfma_f32_16x16x4f32 (K order
-// tap, channel); bf16: NK steps of v_mfma_f32_16x16x32_bf16, each covering
-// 32 consecutive K values as 4 runs of 8 channels (a run never crosses a tap
-// because CK is a multiple of 8; for CK = 16 one MFMA spans two taps).
-template <int PREC, int MODE, int CK, int TH, int NB, typename SrcT>
+// One chunk's MFMAs.  fp32: KS*KS*CK/4 steps of v_mfma_f32_16x16x4f32 (K
+// order tap, channel); bf16: NK steps of v_mfma_f32_16x16x32_bf16, each
+// covering 32 consecutive K values as 4 runs of 8 channels (a run never
+// crosses a tap because CK is a multiple of 8; for CK = 16 one MFMA spans
+// two taps).
+template <int PREC, int MODE, int CK, int TH, int NB, typename SrcT, int KS>
 __device__ __forceinline__ void chunk_mfma(const void *As_, const void *Bs_, f32x4 (*acc)[NB])
 {
-    using S = Stage<PREC, MODE, CK, TH, NB, SrcT>;
+    using S = Stage<PREC, MODE, CK, TH, NB, SrcT, KS>;
     constexpr int MB = TH / 2;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lj = lane & 15, lq = lane >> 4;
@@ -450,8 +453,8 @@ __device__ __forceinline__ void chunk_mfma(const void *As_, const void *Bs_, f32
         const float *As = static_cast<const float *>(As_);
         const float *Bs = static_cast<const float *>(Bs_);
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int dy = tap / 3, dx = tap % 3;
+        for (int tap = 0; tap < KS * KS; ++tap) {
+            const int dy = tap / KS, dx = tap % KS;
 #pragma unroll
             for (int c4 = 0; c4 < CK / 4; ++c4) {
                 float b[NB];
@@ -478,7 +481,7 @@ __device__ __forceinline__ void chunk_mfma(const void *As_, const void *Bs_, f32
             const int k0 = run * 32;
             const int tap = k0 / CK, c0 = k0 - tap * CK;
             const bool live = run < S::NR;
-            const int dy = live ? tap / 3 : 0, dx = live ? tap % 3 : 0;
+            const int dy = live ? tap / KS : 0, dx = live ? tap % KS : 0;
             i32x8 b[NB];
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
@@ -511,8 +514,8 @@ __device__ __forceinline__ void chunk_mfma(const void *As_, const void *Bs_, f32
         for (int s = 0; s < S::NK; ++s) {
             const int k0 = s * 32 + lq * 8;
             const int tap = k0 / CK, c0 = k0 - tap * CK;
-            const bool live = tap < 9;
-            const int dy = live ? tap / 3 : 0, dx = live ? tap % 3 : 0;
+            const bool live = tap < KS * KS;
+            const int dy = live ? tap / KS : 0, dx = live ? tap % KS : 0;
             bf16x8 b[NB];
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
@@ -685,13 +688,13 @@ __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDes
     }
 }
 
-template <int PREC, int MODE, int EPI, int TH, int CK, int NB, typename SrcT, typename OutT>
+template <int PREC, int MODE, int EPI, int TH, int CK, int NB, typename SrcT, typename OutT, int KS = 3>
 #ifndef WSKP_CONV_MIN_WG
 #define WSKP_CONV_MIN_WG 1
 #endif
-__global__ __launch_bounds__(kThreads, (MODE == CONV_PACK && PREC == 1) ? 4 : WSKP_CONV_MIN_WG) void conv3x3_kernel(ConvLayer L, FrameArg fa)
+__global__ __launch_bounds__(kThreads, (MODE == CONV_PACK && PREC == 1 && KS == 3) ? 4 : WSKP_CONV_MIN_WG) void conv3x3_kernel(ConvLayer L, FrameArg fa)
 {
-    using S = Stage<PREC, MODE, CK, TH, NB, SrcT>;
+    using S = Stage<PREC, MODE, CK, TH, NB, SrcT, KS>;
     constexpr int MB = TH / 2;
     constexpr int LDS_BYTES = S::A_BYTES + S::B_BYTES;
     __shared__ __attribute__((aligned(16))) unsigned char smem[LDS_BYTES];
@@ -722,14 +725,14 @@ __global__ __launch_bounds__(kThreads, (MODE == CONV_PACK && PREC == 1) ? 4 : WS
         st.commit(As, Bs, L.in_qscale);
         ec.load(L, g);
         lds_sync();
-        chunk_mfma<PREC, MODE, CK, TH, NB, SrcT>(As, Bs, acc);
+        chunk_mfma<PREC, MODE, CK, TH, NB, SrcT, KS>(As, Bs, acc);
     } else {
         for (int cc = 0; cc < nchunks; ++cc) {
             if (cc) __syncthreads();
             st.commit(As, Bs, L.in_qscale);
             __syncthreads();
             if (cc + 1 < nchunks) st.fetch(L, fd, s0, s1, cc + 1, Wl);
-            chunk_mfma<PREC, MODE, CK, TH, NB, SrcT>(As, Bs, acc);
+            chunk_mfma<PREC, MODE, CK, TH, NB, SrcT, KS>(As, Bs, acc);
         }
         ec.load(L, g);
     }
@@ -753,6 +756,11 @@ __global__ __launch_bounds__(kThreads, (MODE == CONV_PACK && PREC == 1) ? 4 : WS
 // Each lane realises the order by choosing which group it fetches.  Pixels outside the image
 // get an offset beyond the buffer's range, and the hardware returns zeros:
 // that is the conv's zero padding.
+
+#ifndef WSKP_DIRECT_SWZ
+#define WSKP_DIRECT_SWZ 1
+#endif
+constexpr int kDirectSwz = WSKP_DIRECT_SWZ;
 
 __device__ __forceinline__ void load_lds16(rsrc_t r, unsigned char *lds, unsigned voff)
 {
@@ -827,7 +835,7 @@ __global__ __launch_bounds__(kThreads, direct_min_wg(NB)) void conv3x3_bf16_dire
     const unsigned cp0 = (unsigned)L.C0 * 2u, rp0 = (unsigned)W0 * cp0;
     const unsigned cp1 = (unsigned)L.C1 * 2u, rp1 = (unsigned)Wl * cp1;
     const int slot0 = wave * 64 + lane, p0 = slot0 >> 2;
-    const unsigned goff = (unsigned)(((slot0 & 3) ^ ((p0 >> 1) & 3)) * 16);
+    const unsigned goff = (unsigned)(((slot0 & 3) ^ ((p0 >> kDirectSwz) & 3)) * 16);
     constexpr int SY = 64 / WP, SX = 64 - SY * WP;
     int ly = p0 / WP, lx = p0 - ly * WP;
     unsigned oa0[PW], oa1[PW];
@@ -888,7 +896,7 @@ __global__ __launch_bounds__(kThreads, direct_min_wg(NB)) void conv3x3_bf16_dire
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb) {
                     const int p = (wave * HW + rr) * WP + cb * 16 + lj + dx;
-                    const int slot = p * 4 + (lq ^ ((p >> 1) & 3));
+                    const int slot = p * 4 + (lq ^ ((p >> kDirectSwz) & 3));
                     a[rr][cb] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(As + slot * 16));
                 }
 #pragma unroll
@@ -948,9 +956,9 @@ constexpr int kTH = WSKP_CONV_TH;
 constexpr int kTHP = WSKP_PACK_TH;
 constexpr int kTHD = WSKP_DIRECT_TH;
 
-static bool uses_direct(int prec, int mode, int CK)
+static bool uses_direct(int prec, int mode, int CK, int ks)
 {
-    return WSKP_CONV_DIRECT && prec == 1 && CK == 32 && (mode == CONV_CAT || mode == CONV_PLAIN);
+    return WSKP_CONV_DIRECT && ks == 3 && prec == 1 && CK == 32 && (mode == CONV_CAT || mode == CONV_PLAIN);
 }
 
 // Tile rows per layer: the input layer uses kTHP; the direct-load kernel uses
@@ -960,10 +968,10 @@ static bool uses_direct(int prec, int mode, int CK)
 #ifndef WSKP_COARSE_LEVEL
 #define WSKP_COARSE_LEVEL 3
 #endif
-int conv_tile_rows(int prec, int mode, int CK, int level, bool pool)
+int conv_tile_rows(int prec, int mode, int CK, int level, bool pool, int ks)
 {
     if (mode == CONV_PACK) return kTHP;
-    if (!uses_direct(prec, mode, CK)) return kTH;
+    if (!uses_direct(prec, mode, CK, ks)) return kTH;
     return (level >= WSKP_COARSE_LEVEL && !pool) ? 4 : kTHD;
 }
 
@@ -985,11 +993,13 @@ int conv_chunk(int prec, int mode, int Cin, int C0)
 // reused across NB blocks); narrower groups give more workgroups and a
 // smaller stage, so more of them fit a CU.  The direct-load kernel measured
 // fastest with at most two blocks (stage <= 40 KiB, four workgroups per CU)
-// and one block on the coarsest levels.
-int conv_blocks_per_group(int prec, int mode, int CK, int nblk, int level)
+// and one block on the coarsest levels.  5x5 layers take one block per
+// group: their weight slices are 25/9 times larger.
+int conv_blocks_per_group(int prec, int mode, int CK, int nblk, int level, int ks)
 {
+    if (ks != 3) return 1;
     if (mode == CONV_PACK) return nblk % 2 == 0 ? 2 : 1;
-    const bool direct = uses_direct(prec, mode, CK);
+    const bool direct = uses_direct(prec, mode, CK, ks);
     if (direct && level >= WSKP_COARSE_LEVEL) return 1;
     for (int nb = direct ? WSKP_DIRECT_MAX_NB : WSKP_CONV_MAX_NB; nb > 1; --nb)
         if (nb <= 4 && nblk % nb == 0) return nb;
@@ -1009,6 +1019,15 @@ int conv_grid(const ConvLayer &L, int n, const int *H, const int *W)
 template <int PREC, int MODE, int EPI, int CK, int NB, typename OutT>
 static void launch_one(const ConvLayer &L, const FrameArg &fa, int blocks, hipStream_t s)
 {
+    using SrcT = typename std::conditional<PREC == 0, float, unsigned short>::type;
+    constexpr int TH = MODE == CONV_PACK ? kTHP : kTH;
+    if constexpr (NB == 1 && PREC != 2) {
+        if (L.ks == 5) {
+            hipLaunchKernelGGL((conv3x3_kernel<PREC, MODE, EPI, TH, CK, NB, SrcT, OutT, 5>), dim3(blocks),
+                               dim3(kThreads), 0, s, L, fa);
+            return;
+        }
+    }
     if constexpr (WSKP_CONV_DIRECT && PREC == 1 && CK == 32 && (MODE == CONV_CAT || MODE == CONV_PLAIN)) {
         if (L.th == 4)
             hipLaunchKernelGGL((conv3x3_bf16_direct<MODE, EPI, 4, NB, OutT>), dim3(blocks),
@@ -1020,8 +1039,6 @@ static void launch_one(const ConvLayer &L, const FrameArg &fa, int blocks, hipSt
     }
     // fp32 activations travel with the fp32 MFMA form; the bf16 and fp8 forms
     // keep bf16 activations in memory
-    using SrcT = typename std::conditional<PREC == 0, float, unsigned short>::type;
-    constexpr int TH = MODE == CONV_PACK ? kTHP : kTH;
     hipLaunchKernelGGL((conv3x3_kernel<PREC, MODE, EPI, TH, CK, NB, SrcT, OutT>), dim3(blocks),
                        dim3(kThreads), 0, s, L, fa);
 }
@@ -1076,6 +1093,8 @@ hipError_t launch_conv(const ConvLayer &L, int mode, int epi, int prec, const Fr
                        int blocks, hipStream_t s)
 {
     if (blocks <= 0) return hipSuccess;
+    // 5x5 layers run the register-staged kernel with one block per group
+    if (L.ks != 3 && (L.ks != 5 || L.NB != 1 || prec == 2)) return hipErrorInvalidValue;
     const bool ok = prec == 0   ? dispatch<0>(L, mode, epi, fa, blocks, s)
                     : prec == 1 ? dispatch<1>(L, mode, epi, fa, blocks, s)
                                 : dispatch<2>(L, mode, epi, fa, blocks, s);

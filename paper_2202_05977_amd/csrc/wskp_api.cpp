@@ -175,6 +175,8 @@ static wskp_status_t check_config(const wskp_config_t *c)
     if (!(c->eps_norm > 0.f) || !(c->eps_albedo >= 0.f) || !(c->gamma > 0.f) ||
         !(c->depth_far > c->depth_near))
         return fail(WSKP_E_INVALID_ARG, "eps_norm > 0, eps_albedo >= 0, gamma > 0, far > near");
+    if (c->conv_size != 3 && c->conv_size != 5)
+        return fail(WSKP_E_INVALID_ARG, "conv_size must be 3 or 5");
     return WSKP_OK;
 }
 
@@ -195,7 +197,8 @@ extern "C" size_t wskp_num_weights(const wskp_config_t *cfg)
     std::vector<std::pair<int, int>> d;
     conv_dims(cfg, d);
     size_t n = 0;
-    for (auto &p : d) n += (size_t)p.second * p.first * 9 + p.second;
+    const size_t k2 = (size_t)cfg->conv_size * cfg->conv_size;
+    for (auto &p : d) n += (size_t)p.second * p.first * k2 + p.second;
     return n;
 }
 
@@ -208,25 +211,26 @@ static void pack_layer(int prec, const LayerPlan &lp, const float *w, std::vecto
 {
     const ConvLayer &L = lp.L;
     const int CK = L.CK, nch = L.Cin_pad / CK, Cin = lp.Cin, Cout = L.Cout;
+    const int T = L.ks * L.ks;   // taps
     auto W = [&](int co, int ci, int tap) -> float {
         if (co >= Cout || ci >= Cin) return 0.f;
-        return w[((size_t)co * Cin + ci) * 9 + tap];
+        return w[((size_t)co * Cin + ci) * T + tap];
     };
     if (prec == WSKP_PREC_FP8_E4M3) {
         // [chunk][Cout_pad][NK*128] bytes, K = tap*CK + c, zero padded
-        const int NR = 9 * CK / 32, NK = (NR + 3) / 4, KR = NK * 128;
+        const int NR = T * CK / 32, NK = (NR + 3) / 4, KR = NK * 128;
         std::vector<float> sw(L.Cout_pad, 1.f);
         for (int co = 0; co < Cout; ++co) {
             float mx = 0.f;
             for (int ci = 0; ci < Cin; ++ci)
-                for (int t = 0; t < 9; ++t) mx = std::max(mx, std::fabs(W(co, ci, t)));
+                for (int t = 0; t < T; ++t) mx = std::max(mx, std::fabs(W(co, ci, t)));
             sw[co] = mx > 0.f ? mx / 448.f : 1.f;
         }
         out.assign((size_t)nch * L.Cout_pad * KR, 0);
         uint8_t *o = reinterpret_cast<uint8_t *>(out.data());
         for (int cc = 0; cc < nch; ++cc)
             for (int co = 0; co < L.Cout_pad; ++co)
-                for (int k = 0; k < 9 * CK; ++k) {
+                for (int k = 0; k < T * CK; ++k) {
                     const int tap = k / CK, c = k % CK;
                     o[((size_t)cc * L.Cout_pad + co) * KR + k] = host_e4m3(W(co, cc * CK + c, tap) / sw[co]);
                 }
@@ -236,27 +240,62 @@ static void pack_layer(int prec, const LayerPlan &lp, const float *w, std::vecto
         }
     } else if (prec == WSKP_PREC_FP32) {
         // [chunk][tap][c][Cout_pad]
-        out.assign((size_t)nch * 9 * CK * L.Cout_pad * 4, 0);
+        out.assign((size_t)nch * T * CK * L.Cout_pad * 4, 0);
         float *o = reinterpret_cast<float *>(out.data());
         for (int cc = 0; cc < nch; ++cc)
-            for (int tap = 0; tap < 9; ++tap)
+            for (int tap = 0; tap < T; ++tap)
                 for (int c = 0; c < CK; ++c)
                     for (int co = 0; co < L.Cout_pad; ++co)
-                        o[(((size_t)cc * 9 + tap) * CK + c) * L.Cout_pad + co] = W(co, cc * CK + c, tap);
+                        o[(((size_t)cc * T + tap) * CK + c) * L.Cout_pad + co] = W(co, cc * CK + c, tap);
     } else {
         // [chunk][Cout_pad][NK*32 + 8], K = tap*CK + c, zero padded; the 8
         // extra elements per row make the row stride in LDS bank-friendly and
         // let the kernels copy a group's rows as one contiguous block
-        const int NK = (9 * CK + 31) / 32, KR = NK * 32 + 8;
+        const int NK = (T * CK + 31) / 32, KR = NK * 32 + 8;
         out.assign((size_t)nch * L.Cout_pad * KR * 2, 0);
         uint16_t *o = reinterpret_cast<uint16_t *>(out.data());
         for (int cc = 0; cc < nch; ++cc)
             for (int co = 0; co < L.Cout_pad; ++co)
-                for (int k = 0; k < 9 * CK; ++k) {
+                for (int k = 0; k < T * CK; ++k) {
                     const int tap = k / CK, c = k % CK;
                     o[((size_t)cc * L.Cout_pad + co) * KR + k] = host_bf16(W(co, cc * CK + c, tap));
                 }
     }
+}
+
+// RepVGG re-parameterisation (Sec. 4.1, prediction phase): the 1x1, 3x3 and
+// 5x5 branch kernels are added into the centre of one 5x5 kernel, the
+// identity becomes a unit centre tap of (c, c), and the biases add up.  The
+// sum of the branch outputs is the output of that conv because convolution
+// is linear in its kernel and each branch's zero padding is the 5x5 kernel's
+// zero border around it.
+extern "C" wskp_status_t wskp_repvgg_merge(int cin, int cout, const float *w1, const float *b1,
+                                           const float *w3, const float *b3, const float *w5,
+                                           const float *b5, int identity, float *w_out, float *b_out)
+{
+    if (cin < 1 || cout < 1) return fail(WSKP_E_INVALID_ARG, "cin and cout must be >= 1");
+    if (!w_out || !b_out) return fail(WSKP_E_INVALID_ARG, "output pointer is NULL");
+    if (identity && cin != cout) return fail(WSKP_E_INVALID_ARG, "the identity branch needs cin == cout");
+    const size_t n = (size_t)cout * cin * 25;
+    std::fill(w_out, w_out + n, 0.f);
+    std::fill(b_out, b_out + cout, 0.f);
+    const float *ws[3] = {w1, w3, w5}, *bs[3] = {b1, b3, b5};
+    const int ksz[3] = {1, 3, 5};
+    for (int i = 0; i < 3; ++i) {
+        if (!ws[i] || !bs[i]) continue;
+        const int k = ksz[i], o = (5 - k) / 2;
+        for (int co = 0; co < cout; ++co) {
+            for (int ci = 0; ci < cin; ++ci)
+                for (int y = 0; y < k; ++y)
+                    for (int x = 0; x < k; ++x)
+                        w_out[(((size_t)co * cin + ci) * 5 + y + o) * 5 + x + o] +=
+                            ws[i][(((size_t)co * cin + ci) * k + y) * k + x];
+            b_out[co] += bs[i][co];
+        }
+    }
+    if (identity)
+        for (int c = 0; c < cout; ++c) w_out[(((size_t)c * cin + c) * 5 + 2) * 5 + 2] += 1.f;
+    return WSKP_OK;
 }
 
 extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host_weights,
@@ -273,6 +312,7 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
         for (int l = 0; l < cfg->levels; ++l)
             if (cfg->channels[l] % 32)
                 return fail(WSKP_E_UNSUPPORTED, "FP8 needs every level width to be a multiple of 32");
+        if (cfg->conv_size != 3) return fail(WSKP_E_UNSUPPORTED, "FP8 runs 3x3 convs only");
     }
     if (!host_weights) return fail(WSKP_E_INVALID_ARG, "weights pointer is NULL");
     if (n_weights != wskp_num_weights(cfg))
@@ -306,7 +346,7 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
     h->act_bytes = h->prec == WSKP_PREC_FP32 ? 4 : 2;   // bf16 activations for bf16 and fp8
 
     // ---- layer plan
-    const int L = cfg->levels, M = cfg->num_kernels;
+    const int L = cfg->levels, M = cfg->num_kernels, ks = cfg->conv_size;
     std::vector<std::pair<int, int>> dims;
     conv_dims(cfg, dims);
     auto add = [&](int mode, int level, int s0kind, int s0, int s1, int C0, int C1, int Cin, int Cout,
@@ -319,13 +359,14 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
         c.src1_idx = s1;
         c.C0 = C0;
         c.C1 = C1;
+        c.ks = ks;
         c.CK = conv_chunk(h->prec, mode, Cin, C0);
         c.Cin_pad = (Cin + c.CK - 1) / c.CK * c.CK;
         c.Cout = Cout;
         const int nblk = (Cout + 15) / 16;
-        c.NB = conv_blocks_per_group(h->prec, mode, c.CK, nblk, level);
+        c.NB = conv_blocks_per_group(h->prec, mode, c.CK, nblk, level, ks);
         c.groups = nblk / c.NB;
-        c.th = conv_tile_rows(h->prec, mode, c.CK, level, pool_idx >= 0);
+        c.th = conv_tile_rows(h->prec, mode, c.CK, level, pool_idx >= 0, ks);
         c.pool_idx = pool_idx;
         c.Cout_pad = nblk * 16;
         c.out_kind = okind;
@@ -344,8 +385,8 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
     // bf16: each encoder epilogue (a workgroup owning whole row pairs) also
     // writes the 2x2 means of its output, and the next encoder reads those
     // with the direct-load kernel (32-channel chunks)
-    h->pooled = h->prec == WSKP_PREC_BF16 && L > 1 && conv_tile_rows(h->prec, CONV_PACK, 16, 0, true) >= 8 &&
-                conv_tile_rows(h->prec, CONV_PLAIN, 32, 1, true) >= 8;
+    h->pooled = h->prec == WSKP_PREC_BF16 && L > 1 && conv_tile_rows(h->prec, CONV_PACK, 16, 0, true, ks) >= 8 &&
+                conv_tile_rows(h->prec, CONV_PLAIN, 32, 1, true, ks) >= 8;
     for (int l = 0; l + 1 < L && h->pooled; ++l)
         if (ch[l] % 32) h->pooled = false;
     if (h->pooled) {
@@ -377,7 +418,7 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
         const float s_in = f8 ? host_act_scales[i] : 1.f;
         pack_layer(h->prec, lp, host_weights + src, pk, s_in, f8 ? &dq : nullptr);
         lp.L.in_qscale = 1.f / s_in;
-        src += (size_t)Cout * Cin * 9;
+        src += (size_t)Cout * Cin * ks * ks;
         lp.w_off = align_up(blob.size());
         blob.resize(lp.w_off + pk.size());
         std::memcpy(blob.data() + lp.w_off, pk.data(), pk.size());
@@ -405,7 +446,7 @@ extern "C" wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host
         size_t o = 0;
         for (auto &d : dims) {
             h->blob_off.push_back(o);
-            o += (size_t)d.first * d.second * 9 + d.second;
+            o += (size_t)d.first * d.second * ks * ks + d.second;
         }
     }
     if (h->prec == WSKP_PREC_FP32) {
@@ -979,6 +1020,7 @@ static wskp_status_t train_check(const wskp_ctx *h)
     if (h->prec != WSKP_PREC_FP32 || !h->dmaster)
         return fail(WSKP_E_UNSUPPORTED, "training needs an fp32 handle");
     if (h->cfg.weight_act != WSKP_ACT_SOFTPLUS) return fail(WSKP_E_UNSUPPORTED, "training needs softplus weights");
+    if (h->cfg.conv_size != 3) return fail(WSKP_E_UNSUPPORTED, "training runs 3x3 convs only");
     return WSKP_OK;
 }
 

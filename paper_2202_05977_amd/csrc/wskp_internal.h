@@ -188,6 +188,7 @@ struct ConvLayer {
     int CK;            // input channels per reduction chunk (weights packed to match)
     int NB;            // 16-channel output blocks per workgroup
     int th;            // output rows per tile of the kernel that runs this layer
+    int ks;            // kernel size: 3, or 5 (a merged RepVGG block)
     int pool_idx;      // >= 0: the epilogue also writes the 2x2 means of the output to p[pool_idx]
     const void *w;     // packed weights
     const float *bias; // [Cout]
@@ -215,7 +216,7 @@ hipError_t launch_conv(const ConvLayer &L, int mode, int epi, int prec, const Fr
 int conv_grid(const ConvLayer &L, int n, const int *H, const int *W);
 int conv_chunk(int prec, int mode, int Cin, int C0);
 // 16-channel output blocks per workgroup for a layer with nblk blocks.
-int conv_blocks_per_group(int prec, int mode, int CK, int nblk, int level);
+int conv_blocks_per_group(int prec, int mode, int CK, int nblk, int level, int ks);
 // Decode + fusion + remodulation over frames of fa (denoise mode: c and mod
 // derive from r, a) -- or over plain tensors (decode mode).
 hipError_t launch_decode_frames(const DecodeCfg &dc, const FrameArg &fa, int blocks, hipStream_t s);
@@ -270,6 +271,6 @@ hipError_t launch_kp_decode(const DecodeCfg &dc, int H, int W, const float *maps
 
 // Tile geometry of the conv kernels (host and device agree on these).
 constexpr int kConvTW = 32;  // output columns per tile (two 16-pixel MFMA blocks)
-int conv_tile_rows(int prec, int mode, int CK, int level, bool pool);
+int conv_tile_rows(int prec, int mode, int CK, int level, bool pool, int ks);
 
 }  // namespace wskp

@@ -75,7 +75,8 @@ PAPER6 = NetConfig(levels=4, channels=(32, 64, 96, 128), kernel_sizes=(3, 5, 7, 
 REPVGG = NetConfig(levels=4, channels=(32, 64, 96, 128), kernel_sizes=(3, 5, 7, 9, 11),
                    conv_size=5)
 REPVGG_SMALL = NetConfig(levels=3, channels=(16, 32, 64), kernel_sizes=(3, 5, 7), conv_size=5)
-CONFIGS: Dict[str, NetConfig] = {"small": SMALL, "hd": HD, "paper6": PAPER6}
+CONFIGS: Dict[str, NetConfig] = {"small": SMALL, "hd": HD, "paper6": PAPER6, "repvgg": REPVGG,
+                                 "repvgg_small": REPVGG_SMALL}
 
 SERVE_RESOLUTIONS: Tuple[Tuple[int, int], ...] = ((360, 640), (720, 1280), (1080, 1920), (1440, 2560))
 

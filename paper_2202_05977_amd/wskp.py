@@ -54,6 +54,7 @@ class wskp_config_t(ctypes.Structure):
         ("gamma", ctypes.c_float),
         ("depth_near", ctypes.c_float),
         ("depth_far", ctypes.c_float),
+        ("conv_size", ctypes.c_int32),
     ]
 
 
@@ -96,6 +97,7 @@ def lib():
         L.wskp_adam.argtypes = [vp, vp, vp, vp, vp, i32, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float, ctypes.c_float]
         L.wskp_get_weights.argtypes = [vp, vp, vp]
+        L.wskp_repvgg_merge.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, i32, vp, vp]
         L.wskp_pool2.argtypes = [vp, vp, i32, i32, vp, vp]
         L.wskp_mr_blend.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp]
         L.wskp_temporal.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp,
@@ -120,7 +122,7 @@ def lib():
                      "wskp_backward_workspace_size", "wskp_workspace_tensor",
                      "wskp_kp_map_bytes", "wskp_kp_expand", "wskp_kp_decode", "wskp_temporal",
                      "wskp_pool2", "wskp_mr_blend", "wskp_train_workspace_size",
-                     "wskp_train_grads", "wskp_adam", "wskp_get_weights",
+                     "wskp_train_grads", "wskp_adam", "wskp_get_weights", "wskp_repvgg_merge",
                      "wskp_timing_enable", "wskp_timing_read"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -168,6 +170,7 @@ def make_config(cfg: NetConfig, precision: str = "fp32") -> wskp_config_t:
     c.gamma = cfg.gamma
     c.depth_near = cfg.depth_near
     c.depth_far = cfg.depth_far
+    c.conv_size = getattr(cfg, "conv_size", 3)
     return c
 
 
@@ -190,6 +193,40 @@ def wskp_create(cfg: NetConfig, weights: np.ndarray, precision: str = "fp32",
            "wskp_create")
     _handle_M[h.value] = cfg.M
     return h
+
+
+def wskp_repvgg_merge(branch: dict, cin: int, cout: int):
+    """The 5x5 conv (w [cout, cin, 5, 5] float32, b [cout]) that a RepVGG
+    block computes: ``branch`` holds "w1"/"b1", "w3"/"b3", "w5"/"b5" (a
+    missing pair is an absent branch) and "identity"."""
+    def arr(key, shape):
+        a = branch.get(key)
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        if a.shape != shape:
+            raise ValueError(f"{key} has shape {a.shape}, expected {shape}")
+        return a
+    parts = []
+    for k in (1, 3, 5):
+        parts += [arr(f"w{k}", (cout, cin, k, k)), arr(f"b{k}", (cout,))]
+    w = np.empty((cout, cin, 5, 5), np.float32)
+    b = np.empty((cout,), np.float32)
+    ptr = [None if a is None else a.ctypes.data for a in parts]
+    _check(lib().wskp_repvgg_merge(cin, cout, *ptr, int(bool(branch.get("identity"))),
+                                   w.ctypes.data, b.ctypes.data), "wskp_repvgg_merge")
+    return w, b
+
+
+def repvgg_blob(cfg: NetConfig, branches) -> np.ndarray:
+    """The weight blob of ``cfg`` (conv_size 5) from training-time RepVGG
+    parameters, one block per conv in blob order, merged by the library."""
+    from .synth import conv_shapes
+    parts = []
+    for (_, ci, co), br in zip(conv_shapes(cfg), branches):
+        w, b = wskp_repvgg_merge(br, ci, co)
+        parts += [w.ravel(), b]
+    return np.concatenate(parts)
 
 
 def wskp_destroy(h) -> None:

@@ -66,6 +66,8 @@ def test_config_validation():
         dataclasses.replace(synth.SMALL, kernel_sizes=(17,)),        # too large
         dataclasses.replace(synth.SMALL, channels=(16, 24, 64)),     # not a multiple of 16
         dataclasses.replace(synth.SMALL, kernel_sizes=tuple(range(1, 19, 2))),  # M = 9
+        dataclasses.replace(synth.SMALL, conv_size=4),               # conv size not 3 or 5
+        dataclasses.replace(synth.SMALL, conv_size=7),
     ]
     for cfg in bad:
         assert wskp.wskp_num_weights(cfg) == 0
@@ -137,3 +139,45 @@ def test_binding_rejects_head_with_wrong_channel_count():
             wskp.wskp_decode(ctypes.c_void_p(0x5678), torch.zeros(1, 8, 8, 10), c, None, c)
     finally:
         wskp._handle_M.pop(fake.value, None)
+
+
+def test_fp8_with_5x5_convs_is_unsupported():
+    """The FP8 plan runs 3x3 convs only; the check precedes any device use."""
+    wskp = _wskp()
+    cfg = synth.REPVGG
+    with pytest.raises(wskp.WskpError) as ei:
+        wskp.wskp_create(cfg, synth.make_weights(cfg), "fp8", act_scales=np.ones(9, np.float32))
+    assert ei.value.status == -3
+
+
+@pytest.mark.parametrize("ci,co,identity,absent", [(3, 3, True, ()), (4, 6, False, ()),
+                                                   (5, 5, True, ("w5",)), (2, 3, False, ("w1", "w3"))])
+def test_repvgg_merge_matches_the_oracle(ci, co, identity, absent):
+    """The library's host-side merge (float32) against the oracle's (float64)
+    on the same branch parameters, absent branches included."""
+    wskp = _wskp()
+    import oracle
+    rng = np.random.default_rng(ci * 10 + co)
+    br = {}
+    for k in (1, 3, 5):
+        if f"w{k}" in absent:
+            continue
+        br[f"w{k}"] = rng.normal(0, 0.5, size=(co, ci, k, k)).astype(np.float32)
+        br[f"b{k}"] = rng.uniform(-0.1, 0.1, size=(co,)).astype(np.float32)
+    br["identity"] = identity
+    w, b = wskp.wskp_repvgg_merge(br, ci, co)
+    wo, bo = oracle.repvgg_merge(br, ci, co)
+    # at most three float32 terms per element: a few float32 ulps
+    np.testing.assert_allclose(w, wo, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(b, bo, rtol=1e-6, atol=1e-7)
+
+
+def test_repvgg_merge_rejects_bad_arguments():
+    wskp = _wskp()
+    br = {"w3": np.zeros((2, 3, 3, 3), np.float32), "b3": np.zeros(2, np.float32), "identity": True}
+    with pytest.raises(wskp.WskpError) as ei:
+        wskp.wskp_repvgg_merge(br, 3, 2)        # identity with cin != cout
+    assert ei.value.status == -1
+    with pytest.raises(ValueError):
+        wskp.wskp_repvgg_merge({"w1": np.zeros((2, 2, 3, 3), np.float32),
+                                "b1": np.zeros(2, np.float32)}, 2, 2)   # wrong branch shape
