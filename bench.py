@@ -548,6 +548,40 @@ def mode_kernels(args):
                       "sweep": sweep, "explicit_kernel_maps": comp}), flush=True)
 
 
+def mode_repvgg(args):
+    """The U-Net with RepVGG blocks as encoders and decoders (every conv a
+    merged 5x5 conv, Sec. 4.1) at 1280x720: frames/s and per-kernel times in
+    bf16 and fp32 beside the 3x3 net, errors against the oracle's
+    multi-branch network when the CPU leg runs."""
+    import torch
+    from paper_2202_05977_amd import synth, wskp
+    H, W = args.height, args.width
+    fr = synth.make_frame(1, H, W)
+    dev = {k: torch.from_numpy(v).cuda() for k, v in fr.items()}
+    cfg = synth.REPVGG
+    br = synth.make_repvgg_branches(cfg, 0)
+    blob = wskp.repvgg_blob(cfg, br)
+    out = {}
+    for p in args.precisions.split(","):
+        r = time_precision(cfg, blob, dev, H, W, p, args.steps, args.warmup, min(args.steps, 100),
+                           args.streams)
+        flops = {k: v * 25.0 / 9.0 for k, v in conv_flops(cfg, H, W).items()}
+        t = sum(v for k, v in r["per_kernel_us"].items() if k != "decode") * 1e-6
+        out[p] = {"frames_per_s": r["fps"], "single_stream_frames_per_s": r["single_stream_fps"],
+                  "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"], "per_kernel_us": r["per_kernel_us"],
+                  "conv_tflops": sum(flops.values()) / t / 1e12,
+                  "conv_frac_of_peak": sum(flops.values()) / t / PEAK[p]}
+        log(f"[repvgg] {p}: {r['fps']:.1f} frames/s, per kernel (us): " +
+            ", ".join(f"{k} {v:.1f}" for k, v in r["per_kernel_us"].items()))
+        if not args.no_cpu_baseline:
+            import oracle
+            y = oracle.denoise(fr, None, cfg, branches=br)
+            out[p]["rel_l2_vs_oracle"] = float(np.linalg.norm(r["y"] - y) / np.linalg.norm(y))
+    print(json.dumps({"mode": "repvgg", "workload": f"{W}x{H} frame, 4-level U-Net 32/64/96/128 of "
+                      "RepVGG blocks (merged 5x5 convs), M=5 kernels k=3..11", "results": out}),
+          flush=True)
+
+
 def dataclasses_replace(r):
     import dataclasses
     return dataclasses.replace(r)
@@ -657,18 +691,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--precisions", default="bf16,fp32",
-                    help="first one is the headline value")
+    ap.add_argument("--precisions", default=None,
+                    help="first one is the headline value (default bf16,fp32; sweep: fp32,bf16,fp8)")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle leg (no error or CPU figures)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device copy of MB megabytes 5 times (reference "
                          "kernel for scaling HBM traffic counters) and exit")
     ap.add_argument("--mode", default="headline",
-                    choices=["headline", "sweep", "train", "serve", "kernels"],
+                    choices=["headline", "sweep", "train", "serve", "kernels", "repvgg"],
                     help="headline: the 720p JSON line; sweep: 1080p precisions vs oracle; "
                          "train: decode adjoint on 8x256^2 crops; serve: 64-stream trace; "
-                         "kernels: decode time vs number of kernel sizes, explicit kernel maps")
+                         "kernels: decode time vs number of kernel sizes, explicit kernel maps; "
+                         "repvgg: the U-Net of merged RepVGG (5x5) blocks")
     ap.add_argument("--serve-frames", type=int, default=300,
                     help="serving trace: frames per stream (64 streams)")
     ap.add_argument("--no-serve", action="store_true",
@@ -685,6 +720,8 @@ def main():
     ap.add_argument("--height", type=int, default=720)
     ap.add_argument("--width", type=int, default=1280)
     args = ap.parse_args()
+    if args.precisions is None:
+        args.precisions = "fp32,bf16,fp8" if args.mode == "sweep" else "bf16,fp32"
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); frames are "
               "independent, so several GPUs would each run this same loop.", file=sys.stderr)
@@ -705,7 +742,7 @@ def main():
 
     if args.mode != "headline":
         {"sweep": mode_sweep, "train": mode_train, "serve": mode_serve,
-         "kernels": mode_kernels}[args.mode](args)
+         "kernels": mode_kernels, "repvgg": mode_repvgg}[args.mode](args)
         return
 
     H, W = args.height, args.width
