@@ -613,7 +613,7 @@ __device__ __forceinline__ void conv_epilogue(const ConvLayer &L, const FrameDes
             float v[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) v[k] = epilogue<EPI>(acc[i][nb][k] * dq[nb][k] + bias[nb][k], co + k, L.M);
-            if constexpr (EPI != EPI_RELU) {
+            if constexpr (EPI == EPI_HEAD_SOFTPLUS || EPI == EPI_HEAD_EXP) {
                 // head record, planar [2M][H][W]: the 16 lanes of a channel
                 // write 16 consecutive pixels of its plane
                 if (in) {
@@ -1061,6 +1061,7 @@ static bool launch_ck_nb(const ConvLayer &L, const FrameArg &fa, int blocks, hip
         else { WSKP_CASE(16, 1) WSKP_CASE(16, 2) }
     } else if constexpr (MODE == CONV_PLAIN) {
         WSKP_CASE(16, 1)
+        if constexpr (PREC == 0 && EPI == EPI_LINEAR) { WSKP_CASE(16, 2) WSKP_CASE(16, 4) }
         if constexpr (PREC != 0) { WSKP_CASE(32, 1) }
         if constexpr (PREC == 1 && EPI == EPI_RELU) { WSKP_CASE(32, 2) WSKP_CASE(32, 3) WSKP_CASE(32, 4) }
     } else {
@@ -1083,6 +1084,10 @@ static bool dispatch(const ConvLayer &L, int mode, int epi, const FrameArg &fa, 
     case CONV_PLAIN:
         // encoders on pooled maps (bf16); the head record is fp32 in every precision
         if (epi == EPI_RELU) return launch_ck_nb<PREC, CONV_PLAIN, EPI_RELU, ActT>(L, fa, blocks, s);
+        if constexpr (PREC == 0) {
+            // training: the input gradient of a conv, fp32 NHWC
+            if (epi == EPI_LINEAR) return launch_ck_nb<PREC, CONV_PLAIN, EPI_LINEAR, float>(L, fa, blocks, s);
+        }
         if (epi == EPI_HEAD_EXP) return launch_ck_nb<PREC, CONV_PLAIN, EPI_HEAD_EXP, float>(L, fa, blocks, s);
         return launch_ck_nb<PREC, CONV_PLAIN, EPI_HEAD_SOFTPLUS, float>(L, fa, blocks, s);
     default: return false;

@@ -14,15 +14,21 @@
 // concatenation) is written out once for its two gradient kernels.
 //
 // Gradient kernels (NHWC fp32, zero padding, conv = 3x3 cross-correlation):
-//   dgrad  gin[p][ci] = sum_{tap,co} gm[p - off(tap)][co] w[co][ci][tap]
-//          one wave per 4 pixels x 64 input channels (a lane per channel);
-//          the kernel's weight slice for 16 output channels is staged in
-//          LDS and each value read serves the wave's 4 pixels
+//   dgrad  gin[p][ci] = sum_{tap,co} gm[p - off(tap)][co] w[co][ci][tap]:
+//          itself a 3x3 conv of gm with the kernel flipped and its channel
+//          axes swapped, so where Ci and Co are multiples of 16 it runs the
+//          fp32 forward conv kernel (MFMA, conv3x3.hip) on weights that
+//          tr_pack_dgrad lays out for it; otherwise (the head's 2M output
+//          channels) tr_dgrad_kernel: one wave per 4 pixels x 64 input
+//          channels, the weight slice of 16 output channels staged in LDS
 //   wgrad  dw[co][ci][tap] = sum_p gm[p][co] in[p + off(tap)][ci],
-//          db[co] = sum_p gm[p][co]: one wave per (64 input channels, 8
-//          output channels, chunk of pixels), 72 accumulators per lane; the
-//          chunks' partial sums are added in a fixed order by a second pass,
-//          so the result does not depend on scheduling
+//          db[co] = sum_p gm[p][co]: a GEMM over pixels.  Where Ci and Co
+//          are multiples of 16, tr_wgrad_mfma_kernel (v_mfma_f32_16x16x4f32,
+//          4 pixels per step); otherwise (the network input's 10 channels,
+//          the head) tr_wgrad_kernel on the VALU.  Either way each wave sums
+//          one chunk of 256 pixels and a second pass adds the chunks'
+//          partial sums in a fixed order, so the result does not depend on
+//          scheduling
 #include "wskp_internal.h"
 
 namespace wskp {
@@ -259,6 +265,69 @@ __global__ __launch_bounds__(64) void tr_wgrad_kernel(int H, int W, int Ci, int 
     }
 }
 
+// The same partial weight gradients on the matrix cores (Ci and Co
+// multiples of 16): a GEMM over pixels, D[co][ci] += sum_p gm[p][co] *
+// in[p + off(tap)][ci] for each tap, with v_mfma_f32_16x16x4f32 taking 4
+// pixels per step (lane (g, j): pixel g of the step; A = gm[p_g][co0 + j],
+// B = in[p_g + off][ci0 + j]).  One wave per (pixel chunk, CB output blocks
+// of 16, one input block of 16); the wave of input block 0 also sums gm
+// (B = 1) for the bias.  Lane (g, j) ends with D[4g + r][j], r = 0..3.
+typedef float trf32x4 __attribute__((ext_vector_type(4)));
+template <int CB>
+__global__ __launch_bounds__(64) void tr_wgrad_mfma_kernel(int H, int W, int Ci, int Co, int chunk, const float *gm,
+                                                            const float *in, float *part, float *partb)
+{
+    const int lane = threadIdx.x, g = lane >> 4, j = lane & 15;
+    const int co0 = blockIdx.y * (16 * CB), ci0 = blockIdx.z * 16;
+    const long P = (long)H * W;
+    const long pa = (long)blockIdx.x * chunk, pb = min(P, pa + chunk);
+    const bool bias = blockIdx.z == 0;
+    trf32x4 acc[CB][9], accb[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        accb[c] = trf32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc[c][t] = trf32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    // this lane's pixel p = q + g of the step at q, its row and column
+    int y = (int)((pa + g) / W), x = (int)((pa + g) - (long)y * W);
+    for (long q = pa; q < pb; q += 4) {
+        const long p = q + g;
+        const bool valid = p < pb;
+        float a[CB], b[9];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) a[c] = valid ? gload(gm + p * Co + co0 + c * 16 + j) : 0.f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+            const bool ok = valid && yy >= 0 && yy < H && xx >= 0 && xx < W;
+            b[t] = ok ? gload(in + ((long)yy * W + xx) * Ci + ci0 + j) : 0.f;
+        }
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+#pragma unroll
+            for (int t = 0; t < 9; ++t) acc[c][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b[t], acc[c][t], 0, 0, 0);
+            if (bias) accb[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], 1.f, accb[c], 0, 0, 0);
+        }
+        x += 4;
+        while (x >= W) {
+            x -= W;
+            ++y;
+        }
+    }
+    const long base = (long)blockIdx.x * Co * Ci * 9;
+    const int ci = ci0 + j;
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int co = co0 + c * 16 + 4 * g + r;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) gstore(part + base + ((long)co * Ci + ci) * 9 + t, acc[c][t][r]);
+            if (bias && j == 0) gstore(partb + (long)blockIdx.x * Co + co, accb[c][r]);
+        }
+}
+
 // dw (+)= sum over chunks of part (in chunk order), likewise db
 __global__ __launch_bounds__(kTrThreads) void tr_wgrad_reduce_kernel(long nw, int Co, int nchunk, const float *part,
                                                                       const float *partb, float *dw, float *db)
@@ -416,6 +485,25 @@ hipError_t tr_dgrad(int H, int W, int Ci, int Co, const float *gm, const float *
     hipLaunchKernelGGL(tr_dgrad_kernel, grid, dim3(kTrThreads), 0, s, H, W, Ci, Co, gm, w, gin);
     return hipGetLastError();
 }
+__global__ __launch_bounds__(kTrThreads) void tr_pack_dgrad_kernel(int Ci, int Co, int Cout_pad, const float *w,
+                                                                    float *packed)
+{
+    const long n = (long)Co * 9 * Cout_pad;   // Co is a multiple of the 16-channel chunk
+    const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
+    if (i >= n) return;
+    const int ci = (int)(i % Cout_pad);
+    const long ct = i / Cout_pad;            // (chunk * 9 + tap) * 16 + c
+    const int c16 = (int)(ct % 16), ctap = (int)(ct / 16);
+    const int t = ctap % 9, co = (ctap / 9) * 16 + c16;
+    gstore(packed + i, ci < Ci ? gload(w + ((long)co * Ci + ci) * 9 + (8 - t)) : 0.f);
+}
+
+hipError_t tr_pack_dgrad(int Ci, int Co, int Cout_pad, const float *w, float *packed, hipStream_t s)
+{
+    TR_LAUNCH(tr_pack_dgrad_kernel, (long)Co * 9 * Cout_pad, Ci, Co, Cout_pad, w, packed);
+    return hipGetLastError();
+}
+
 int tr_wgrad_chunks(long P) { return (int)((P + 255) / 256); }
 size_t tr_wgrad_part_floats(long P, int Ci, int Co) { return (size_t)tr_wgrad_chunks(P) * ((size_t)Co * Ci * 9 + Co); }
 hipError_t tr_wgrad(int H, int W, int Ci, int Co, const float *gm, const float *in, float *part, float *dw,
@@ -425,8 +513,17 @@ hipError_t tr_wgrad(int H, int W, int Ci, int Co, const float *gm, const float *
     const int nch = tr_wgrad_chunks(P);
     const long nw = (long)Co * Ci * 9;
     float *partb = part + (size_t)nch * nw;
-    const dim3 grid((unsigned)nch, (unsigned)((Co + kWgCo - 1) / kWgCo), (unsigned)((Ci + 63) / 64));
-    hipLaunchKernelGGL(tr_wgrad_kernel, grid, dim3(64), 0, s, H, W, Ci, Co, 256, gm, in, part, partb);
+    if (Ci % 16 == 0 && Co % 16 == 0) {
+        if ((Co / 16) % 2 == 0)
+            hipLaunchKernelGGL(tr_wgrad_mfma_kernel<2>, dim3((unsigned)nch, (unsigned)(Co / 32), (unsigned)(Ci / 16)),
+                               dim3(64), 0, s, H, W, Ci, Co, 256, gm, in, part, partb);
+        else
+            hipLaunchKernelGGL(tr_wgrad_mfma_kernel<1>, dim3((unsigned)nch, (unsigned)(Co / 16), (unsigned)(Ci / 16)),
+                               dim3(64), 0, s, H, W, Ci, Co, 256, gm, in, part, partb);
+    } else {
+        const dim3 grid((unsigned)nch, (unsigned)((Co + kWgCo - 1) / kWgCo), (unsigned)((Ci + 63) / 64));
+        hipLaunchKernelGGL(tr_wgrad_kernel, grid, dim3(64), 0, s, H, W, Ci, Co, 256, gm, in, part, partb);
+    }
     TR_LAUNCH(tr_wgrad_reduce_kernel, nw + Co, nw, Co, nch, part, partb, dw, db);
     return hipGetLastError();
 }

@@ -960,6 +960,7 @@ extern "C" wskp_status_t wskp_backward(wskp_handle_t h, void *stream, int N, int
 // pass, sized for the largest frame of the batch.
 struct TrainScratch {
     float *X, *head, *c, *mod, *gy, *gh, *gc, *dh, *dec, *partial, *gm, *in, *gin, *part;
+    float *wpk, *zb;   // packed weights of one input-gradient conv; zero bias
     float *ge[kMaxLevels], *gu[kMaxLevels];
     size_t bytes;
 };
@@ -990,6 +991,12 @@ static size_t train_plan(const wskp_ctx *h, int Hm, int Wm, char *base, TrainScr
     }
     mx_in = std::max(mx_in, (size_t)ch[0] * P);
     mx_part = std::max(mx_part, tr_wgrad_part_floats(P, ch[0], 2 * M));
+    // input-gradient convs on the matrix cores: C_out of the forward conv in,
+    // C_in out (encoders >= 1 and decoders)
+    size_t mx_wpk = 0;
+    for (int l = 1; l < L; ++l) mx_wpk = std::max(mx_wpk, (size_t)ch[l] * 9 * ((ch[l - 1] + 15) / 16 * 16));
+    for (int l = 0; l + 1 < L; ++l)
+        mx_wpk = std::max(mx_wpk, (size_t)ch[l] * 9 * ((ch[l + 1] + ch[l] + 15) / 16 * 16));
     TrainScratch t{};
     t.X = take(10 * (size_t)P);
     t.head = take((size_t)2 * M * P);
@@ -1005,6 +1012,8 @@ static size_t train_plan(const wskp_ctx *h, int Hm, int Wm, char *base, TrainScr
     t.in = take(mx_in);
     t.gin = take(mx_in);
     t.part = take(mx_part);
+    t.wpk = take(std::max(mx_wpk, (size_t)1));
+    t.zb = take(256);
     for (int l = 0; l < L; ++l) {
         const size_t n = (size_t)ch[l] * (Hm >> l) * (Wm >> l);
         t.ge[l] = take(n);
@@ -1083,6 +1092,46 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
     auto gofs = [&](size_t k) { return grad + h->blob_off[k]; };
     auto bofs = [&](size_t k, int Ci, int Co) { return grad + h->blob_off[k] + (size_t)Ci * Co * 9; };
     hipError_t e = tr_fill((long)nw, 0.f, grad, s);
+    // input gradient of a conv (Ci -> Co forward): gin = conv(gm, w flipped,
+    // in and out channels swapped), on the matrix cores with the fp32
+    // forward kernel where the channel counts fit its 16-channel chunks, else
+    // the VALU kernel (the head's 2M channels)
+    auto dgrad = [&](const TrainScratch &t, int Hl, int Wl, int Ci, int Co, const float *gm, const float *w,
+                     float *gin) -> hipError_t {
+        if (Co % 16 || Ci % 16) return tr_dgrad(Hl, Wl, Ci, Co, gm, w, gin, s);
+        ConvLayer c{};
+        c.level = 0;
+        c.src0_kind = 0;
+        c.src0_idx = 0;
+        c.src1_idx = 0;
+        c.C0 = Co;
+        c.C1 = 0;
+        c.ks = 3;
+        c.CK = 16;
+        c.Cin_pad = Co;
+        c.Cout = Ci;
+        const int nblk = Ci / 16;
+        c.NB = nblk % 4 == 0 ? 4 : (nblk % 2 == 0 ? 2 : 1);
+        c.groups = nblk / c.NB;
+        c.Cout_pad = nblk * 16;
+        c.th = conv_tile_rows(WSKP_PREC_FP32, CONV_PLAIN, 16, 0, false, 3);
+        c.pool_idx = -1;
+        c.out_kind = 0;
+        c.out_idx = 1;
+        c.M = 0;
+        c.in_qscale = 1.f;
+        c.w = t.wpk;
+        c.bias = t.zb;
+        hipError_t le = tr_pack_dgrad(Ci, Co, c.Cout_pad, w, t.wpk, s);
+        if (le != hipSuccess) return le;
+        FrameArg fa{};
+        fa.n = 1;
+        fa.one.H = Hl;
+        fa.one.W = Wl;
+        fa.one.e[0] = const_cast<float *>(gm);
+        fa.one.e[1] = gin;
+        return launch_conv(c, CONV_PLAIN, EPI_LINEAR, WSKP_PREC_FP32, fa, conv_grid(c, 1, &Hl, &Wl), s);
+    };
     char *fbase = static_cast<char *>(ws) + table_bytes(n);
     for (int f = 0; f < n && e == hipSuccess; ++f) {
         const int H = Hs[f], W = Ws[f];
@@ -1092,6 +1141,7 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
         fbase += frame_bytes(h, H, W, nullptr, nullptr, nullptr);
         TrainScratch t;
         train_plan(h, H, W, static_cast<char *>(ws) + align_up(fwd), &t);
+        if (e == hipSuccess) e = tr_fill(256, 0.f, t.zb, s);
         const float *e_[kMaxLevels], *u_[kMaxLevels];
         for (int l = 0; l < L; ++l) {
             e_[l] = static_cast<const float *>(fd.e[l]);
@@ -1119,7 +1169,7 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
             e = tr_mask((long)Co * Hl * Wl, t.gu[l], u_[l], t.gm, s);
             if (e == hipSuccess) e = tr_cat(Hl, Wl, ch[l + 1], ch[l], u_[l + 1], e_[l], t.in, s);
             if (e == hipSuccess) e = tr_wgrad(Hl, Wl, Ci, Co, t.gm, t.in, t.part, gofs(k), bofs(k, Ci, Co), s);
-            if (e == hipSuccess) e = tr_dgrad(Hl, Wl, Ci, Co, t.gm, wofs(k), t.gin, s);
+            if (e == hipSuccess) e = dgrad(t, Hl, Wl, Ci, Co, t.gm, wofs(k), t.gin);
             if (e == hipSuccess) e = tr_cat_bwd(Hl, Wl, ch[l + 1], ch[l], t.gin, gu_of(l + 1), t.ge[l], s);
         }
         // encoders, coarsest first: enc_l is conv l
@@ -1128,7 +1178,7 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
             e = tr_mask((long)Co * Hl * Wl, t.ge[l], e_[l], t.gm, s);
             if (e == hipSuccess) e = tr_pool(H >> (l - 1), W >> (l - 1), Ci, e_[l - 1], t.in, s);
             if (e == hipSuccess) e = tr_wgrad(Hl, Wl, Ci, Co, t.gm, t.in, t.part, gofs(l), bofs(l, Ci, Co), s);
-            if (e == hipSuccess) e = tr_dgrad(Hl, Wl, Ci, Co, t.gm, wofs(l), t.gin, s);
+            if (e == hipSuccess) e = dgrad(t, Hl, Wl, Ci, Co, t.gm, wofs(l), t.gin);
             if (e == hipSuccess) e = tr_pool_bwd(H >> (l - 1), W >> (l - 1), Ci, t.gin, t.ge[l - 1], s);
         }
         // first encoder: the network input written out, weight gradient only

@@ -168,7 +168,9 @@ __device__ __forceinline__ int batch_tile_id(const FrameArg &fa, int b, int nb, 
 
 
 enum ConvMode { CONV_PACK = 0, CONV_POOL = 1, CONV_CAT = 2, CONV_PLAIN = 3 };
-enum ConvEpi { EPI_RELU = 0, EPI_HEAD_SOFTPLUS = 1, EPI_HEAD_EXP = 2 };
+// EPI_LINEAR: bias only, NHWC fp32 store (the input gradient of a conv in
+// training runs the forward kernel with transposed, flipped weights).
+enum ConvEpi { EPI_RELU = 0, EPI_HEAD_SOFTPLUS = 1, EPI_HEAD_EXP = 2, EPI_LINEAR = 3 };
 enum ActType { ACT_F32 = 0, ACT_BF16 = 1 };
 
 // One 3x3 conv layer as the kernels see it.
@@ -243,6 +245,10 @@ hipError_t tr_smape(long n, const float *y, const float *t, float eps, float inv
 hipError_t tr_head_act_bwd(long P, int M, const float *grad_head, const float *planar, float *dh, hipStream_t s);
 hipError_t tr_mask(long n, const float *g, const float *act, float *gm, hipStream_t s);
 hipError_t tr_dgrad(int H, int W, int Ci, int Co, const float *gm, const float *w, float *gin, hipStream_t s);
+// Weights of the input-gradient conv in the fp32 forward kernels' packing
+// ([Co/16][9][16][Cout_pad], 16-channel chunks): element (c, t, ci) is
+// w[c][ci][8 - t], zero beyond Co or Ci.
+hipError_t tr_pack_dgrad(int Ci, int Co, int Cout_pad, const float *w, float *packed, hipStream_t s);
 size_t tr_wgrad_part_floats(long P, int Ci, int Co);
 hipError_t tr_wgrad(int H, int W, int Ci, int Co, const float *gm, const float *in, float *part, float *dw,
                     float *db, hipStream_t s);
