@@ -796,7 +796,12 @@ __global__ __launch_bounds__(kThreads, direct_min_wg(NB)) void conv3x3_bf16_dire
     constexpr int CK = 32, WP = kConvTW + 2, HP = TH + 2, NPIX = HP * WP;
     constexpr int A_SLOTS = NPIX * 4;
     constexpr int NK = 9;                                  // one tap (32 channels) per MFMA
-    constexpr int BSK = NK * 32 + 8;                       // padded weight row (elements)
+    // Weight rows are unpadded (9 taps x 32 channels = 576 B); in row co
+    // the 16-byte column groups are stored XOR-ed with 2 * ((co >> 2) & 1)
+    // (host packing), so the 16 rows x 4 groups of a B-fragment read fall
+    // on distinct banks (a 592-byte padded row costs 4 extra LDS cycles per
+    // read on gfx950).
+    constexpr int BSK = NK * 32;
     constexpr int B_SLOTS = NB * 16 * BSK / 8;
     // The stage is one array of 16-byte slots, halo first, weights right
     // after it; load instruction j fills slots [64j, 64j + 64).  The
@@ -816,6 +821,7 @@ __global__ __launch_bounds__(kThreads, direct_min_wg(NB)) void conv3x3_bf16_dire
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lj = lane & 15, lq = lane >> 4;
+    const int bq = lq ^ (((lj >> 2) & 1) << 1);   // swizzled weight column group
 
     const unsigned short *s0 =
         reinterpret_cast<const unsigned short *>(conv_src0(L, fd));
@@ -906,7 +912,7 @@ __global__ __launch_bounds__(kThreads, direct_min_wg(NB)) void conv3x3_bf16_dire
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
                     b[nb] = __builtin_bit_cast(
-                        bf16x8, *reinterpret_cast<const u16x8 *>(Bs + ((nb * 16 + lj) * BSK + s * 32 + lq * 8) * 2));
+                        bf16x8, *reinterpret_cast<const u16x8 *>(Bs + ((nb * 16 + lj) * BSK + s * 32 + bq * 8) * 2));
 #pragma unroll
                 for (int r = 0; r < HW; ++r)
 #pragma unroll
@@ -960,6 +966,8 @@ static bool uses_direct(int prec, int mode, int CK, int ks)
 {
     return WSKP_CONV_DIRECT && ks == 3 && prec == 1 && CK == 32 && (mode == CONV_CAT || mode == CONV_PLAIN);
 }
+
+bool conv_uses_direct(int prec, int mode, int CK, int ks) { return uses_direct(prec, mode, CK, ks); }
 
 // Tile rows per layer: the input layer uses kTHP; the direct-load kernel uses
 // kTHD, or 4 rows on the coarsest levels (>= WSKP_COARSE_LEVEL), which have

@@ -248,17 +248,22 @@ static void pack_layer(int prec, const LayerPlan &lp, const float *w, std::vecto
                     for (int co = 0; co < L.Cout_pad; ++co)
                         o[(((size_t)cc * T + tap) * CK + c) * L.Cout_pad + co] = W(co, cc * CK + c, tap);
     } else {
-        // [chunk][Cout_pad][NK*32 + 8], K = tap*CK + c, zero padded; the 8
-        // extra elements per row make the row stride in LDS bank-friendly and
-        // let the kernels copy a group's rows as one contiguous block
-        const int NK = (T * CK + 31) / 32, KR = NK * 32 + 8;
+        // [chunk][Cout_pad][KR], K = tap*CK + c, zero padded; the kernels
+        // copy a group's rows as one contiguous block.  Register-staged
+        // kernels: KR = NK*32 + 8 (the 8 extra elements make the row stride
+        // in LDS bank-friendly).  Direct-to-LDS kernel: KR = NK*32, and in
+        // row co the 8-element groups are stored at position g ^ (2 * ((co
+        // >> 2) & 1)), the bank-conflict-free order that kernel reads.
+        const bool direct = conv_uses_direct(prec, lp.mode, CK, L.ks);
+        const int NK = (T * CK + 31) / 32, KR = direct ? NK * 32 : NK * 32 + 8;
         out.assign((size_t)nch * L.Cout_pad * KR * 2, 0);
         uint16_t *o = reinterpret_cast<uint16_t *>(out.data());
         for (int cc = 0; cc < nch; ++cc)
             for (int co = 0; co < L.Cout_pad; ++co)
                 for (int k = 0; k < T * CK; ++k) {
                     const int tap = k / CK, c = k % CK;
-                    o[((size_t)cc * L.Cout_pad + co) * KR + k] = host_bf16(W(co, cc * CK + c, tap));
+                    const int pos = direct ? ((((k >> 3) ^ (((co >> 2) & 1) << 1))) << 3) | (k & 7) : k;
+                    o[((size_t)cc * L.Cout_pad + co) * KR + pos] = host_bf16(W(co, cc * CK + c, tap));
                 }
     }
 }

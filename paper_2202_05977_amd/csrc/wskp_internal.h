@@ -278,5 +278,8 @@ hipError_t launch_kp_decode(const DecodeCfg &dc, int H, int W, const float *maps
 // Tile geometry of the conv kernels (host and device agree on these).
 constexpr int kConvTW = 32;  // output columns per tile (two 16-pixel MFMA blocks)
 int conv_tile_rows(int prec, int mode, int CK, int level, bool pool, int ks);
+// true if the layer runs the direct-to-LDS bf16 kernel (its weights are
+// packed without row padding and with swizzled column groups)
+bool conv_uses_direct(int prec, int mode, int CK, int ks);
 
 }  // namespace wskp
