@@ -544,8 +544,44 @@ def mode_kernels(args):
     log(f"[kernels] explicit maps {t_kp:.1f} us ({kp_in / 1e9:.2f} GB of input) vs weight sharing "
         f"{t_ws:.1f} us ({ws_in / 1e6:.1f} MB): {t_kp / t_ws:.1f}x; rel-L2 between them {diff:.1e}")
     dn.close()
+    # temporal accumulation (Sec. 4.1) of a moving 720p frame against the
+    # previous frame's state; algorithmic bytes: current radiance, normal,
+    # world position (36 B), motion (8), the previous radiance, length,
+    # normal, world position (40) read once, radiance and length (16) written
+    seq = synth.make_sequence(3, H, W, 2)
+    dv = [{k: torch.from_numpy(v).cuda() for k, v in f.items() if k != "clean"} for f in seq]
+    acc = [torch.empty((H, W, 3), device="cuda") for _ in range(2)]
+    lng = [torch.empty((H, W), device="cuda") for _ in range(2)]
+    dn = wskp.Denoiser(synth.SMALL, synth.make_weights(synth.SMALL, 0), "fp32")
+    wskp.wskp_temporal(dn.h, dv[0]["radiance"], dv[0]["normal"], dv[0]["wpos"], dv[0]["motion"], None,
+                       acc[0], lng[0])
+    prev = {"radiance": acc[0], "length": lng[0], "normal": dv[0]["normal"], "wpos": dv[0]["wpos"]}
+    t_tmp = timed(lambda: wskp.wskp_temporal(dn.h, dv[1]["radiance"], dv[1]["normal"], dv[1]["wpos"],
+                                             dv[1]["motion"], prev, acc[1], lng[1]))
+    tb = H * W * 100
+    temporal = {"workload": f"{W}x{H} moving frame, previous state resident", "us": t_tmp,
+                "algorithmic_bytes": tb, "GBps": tb / t_tmp / 1e3, "frac_of_hbm_peak": tb / t_tmp / 1e3 / 8000.0,
+                "history_kept": float((lng[1] > 1.0).float().mean())}
+    log(f"[kernels] temporal accumulation {t_tmp:.1f} us ({tb / t_tmp / 1e3:.0f} GB/s), "
+        f"history kept for {temporal['history_kept']:.2f} of the pixels")
+    # multi-resolution reconstruction (Eq. 7): three levels, kernels {3, 5} at
+    # each (the paper's high-spp network), heads and blend weights given
+    ks2 = (3, 5)
+    cfg2 = dataclasses.replace(synth.HD, kernel_sizes=ks2)
+    dn2 = wskp.Denoiser(cfg2, synth.make_weights(cfg2, 0), "fp32")
+    heads = [torch.from_numpy(synth.make_head(20 + l, 1, H >> l, W >> l, 2)).cuda() for l in range(3)]
+    g = torch.Generator().manual_seed(8)
+    alphas = [torch.rand(H >> l, W >> l, generator=g).cuda() for l in range(2)]
+    c0 = c[0].contiguous()
+    t_mr = timed(lambda: wskp.mr_reconstruct(dn2.h, heads, c0, alphas, mod[0].contiguous()))
+    mr = {"workload": f"{W}x{H}, 3 levels, kernels (3, 5) per level", "us": t_mr,
+          "launches": "2 pools + 3 decodes + 2 blends"}
+    log(f"[kernels] multi-resolution reconstruction {t_mr:.1f} us")
+    dn.close()
+    dn2.close()
     print(json.dumps({"mode": "kernels", "workload": f"{W}x{H}, hd net, bf16 convs, exp weights",
-                      "sweep": sweep, "explicit_kernel_maps": comp}), flush=True)
+                      "sweep": sweep, "explicit_kernel_maps": comp, "temporal": temporal,
+                      "multiresolution": mr}), flush=True)
 
 
 def mode_repvgg(args):

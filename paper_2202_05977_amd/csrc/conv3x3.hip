@@ -782,21 +782,23 @@ __device__ __forceinline__ void wait_vmem()
 
 // Each wave computes HW = TH/4 output rows of the tile (both 16-pixel column
 // blocks, all NB output blocks).  For one column offset dx it reads the A
-// fragments of its HW+2 input rows once and uses each for up to three
-// vertical taps dy (input row r+dy feeds output row r), so a chunk costs
+// fragments of its HW+KS-1 input rows once and uses each for up to KS
+// vertical taps dy (input row r+dy feeds output row r), so a 3x3 chunk costs
 // 6 (HW+2) A fragment reads instead of 18 HW: the LDS bytes per MFMA, which
 // bound this loop, fall with HW.
 // Workgroups per CU that the stage's LDS admits at TH = 8 (40, 49 and 59 KiB
 // for 2, 3 and 4 output blocks); the register budget is capped to match.
-constexpr int direct_min_wg(int NB) { return NB <= 2 ? 4 : (NB == 3 ? 3 : 2); }
+// 5x5 layers (one output block, 52 KiB stage at TH = 8) fit three.
+constexpr int direct_min_wg(int NB, int KS) { return KS == 5 ? 3 : (NB <= 2 ? 4 : (NB == 3 ? 3 : 2)); }
 
-template <int MODE, int EPI, int TH, int NB, typename OutT>
-__global__ __launch_bounds__(kThreads, direct_min_wg(NB)) void conv3x3_bf16_direct(ConvLayer L, FrameArg fa)
+template <int MODE, int EPI, int TH, int NB, typename OutT, int KS = 3>
+__global__ __launch_bounds__(kThreads, direct_min_wg(NB, KS)) void conv3x3_bf16_direct(ConvLayer L, FrameArg fa)
 {
-    constexpr int CK = 32, WP = kConvTW + 2, HP = TH + 2, NPIX = HP * WP;
+    constexpr int CK = 32, WP = kConvTW + KS - 1, HP = TH + KS - 1, NPIX = HP * WP;
     constexpr int A_SLOTS = NPIX * 4;
-    constexpr int NK = 9;                                  // one tap (32 channels) per MFMA
-    // Weight rows are unpadded (9 taps x 32 channels = 576 B); in row co
+    constexpr int NK = KS * KS;                            // one tap (32 channels) per MFMA
+    // Weight rows are unpadded (k^2 taps x 32 channels: 576 B for 3x3,
+    // 1600 B for 5x5); in row co
     // the 16-byte column groups are stored XOR-ed with 2 * ((co >> 2) & 1)
     // (host packing), so the 16 rows x 4 groups of a B-fragment read fall
     // on distinct banks (a 592-byte padded row costs 4 extra LDS cycles per
@@ -847,7 +849,7 @@ __global__ __launch_bounds__(kThreads, direct_min_wg(NB)) void conv3x3_bf16_dire
     unsigned oa0[PW], oa1[PW];
 #pragma unroll
     for (int k = 0; k < PW; ++k) {
-        const int gy = y0 - 1 + ly, gx = x0 - 1 + lx;
+        const int gy = y0 - KS / 2 + ly, gx = x0 - KS / 2 + lx;
         const bool in = p0 + 64 * k < NPIX && (unsigned)gy < (unsigned)Hl && (unsigned)gx < (unsigned)Wl;
         if (MODE == CONV_CAT) {
             oa0[k] = in ? __umul24((unsigned)gy >> 1, rp0) + __umul24((unsigned)gx >> 1, cp0) + goff : kOutOfRange;
@@ -895,10 +897,10 @@ __global__ __launch_bounds__(kThreads, direct_min_wg(NB)) void conv3x3_bf16_dire
     auto compute = [&](const unsigned char *As) {
         const unsigned char *Bs = As + A_BYTES;
 #pragma unroll
-        for (int dx = 0; dx < 3; ++dx) {
-            bf16x8 a[HW + 2][2];
+        for (int dx = 0; dx < KS; ++dx) {
+            bf16x8 a[HW + KS - 1][2];
 #pragma unroll
-            for (int rr = 0; rr < HW + 2; ++rr)
+            for (int rr = 0; rr < HW + KS - 1; ++rr)
 #pragma unroll
                 for (int cb = 0; cb < 2; ++cb) {
                     const int p = (wave * HW + rr) * WP + cb * 16 + lj + dx;
@@ -906,8 +908,8 @@ __global__ __launch_bounds__(kThreads, direct_min_wg(NB)) void conv3x3_bf16_dire
                     a[rr][cb] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(As + slot * 16));
                 }
 #pragma unroll
-            for (int dy = 0; dy < 3; ++dy) {
-                const int s = dy * 3 + dx;
+            for (int dy = 0; dy < KS; ++dy) {
+                const int s = dy * KS + dx;
                 bf16x8 b[NB];
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
@@ -964,7 +966,8 @@ constexpr int kTHD = WSKP_DIRECT_TH;
 
 static bool uses_direct(int prec, int mode, int CK, int ks)
 {
-    return WSKP_CONV_DIRECT && ks == 3 && prec == 1 && CK == 32 && (mode == CONV_CAT || mode == CONV_PLAIN);
+    return WSKP_CONV_DIRECT && (ks == 3 || ks == 5) && prec == 1 && CK == 32 &&
+           (mode == CONV_CAT || mode == CONV_PLAIN);
 }
 
 bool conv_uses_direct(int prec, int mode, int CK, int ks) { return uses_direct(prec, mode, CK, ks); }
@@ -1029,6 +1032,17 @@ static void launch_one(const ConvLayer &L, const FrameArg &fa, int blocks, hipSt
 {
     using SrcT = typename std::conditional<PREC == 0, float, unsigned short>::type;
     constexpr int TH = MODE == CONV_PACK ? kTHP : kTH;
+    if constexpr (WSKP_CONV_DIRECT && NB == 1 && PREC == 1 && CK == 32 && (MODE == CONV_CAT || MODE == CONV_PLAIN)) {
+        if (L.ks == 5) {
+            if (L.th == 4)
+                hipLaunchKernelGGL((conv3x3_bf16_direct<MODE, EPI, 4, 1, OutT, 5>), dim3(blocks), dim3(kThreads), 0, s,
+                                   L, fa);
+            else
+                hipLaunchKernelGGL((conv3x3_bf16_direct<MODE, EPI, kTHD, 1, OutT, 5>), dim3(blocks), dim3(kThreads),
+                                   0, s, L, fa);
+            return;
+        }
+    }
     if constexpr (NB == 1 && PREC != 2) {
         if (L.ks == 5) {
             hipLaunchKernelGGL((conv3x3_kernel<PREC, MODE, EPI, TH, CK, NB, SrcT, OutT, 5>), dim3(blocks),
