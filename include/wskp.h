@@ -145,8 +145,9 @@ wskp_status_t wskp_create(const wskp_config_t *cfg, const float *host_weights, s
  * its bias, zero padding (k-1)/2) plus, when C_in == C_out, the identity,
  * computes the same map as ONE 5x5 conv; this writes that conv's weights.
  * Host arrays, OIHW: w1 [cout][cin][1][1], w3 [cout][cin][3][3],
- * w5 [cout][cin][5][5], biases [cout]; a branch whose w or b is NULL is
- * absent.  identity != 0 adds the identity branch (needs cin == cout).
+ * w5 [cout][cin][5][5], biases [cout]; a branch whose w and b are both NULL
+ * is absent (exactly one of them NULL: WSKP_E_INVALID_ARG).  identity != 0
+ * adds the identity branch (needs cin == cout).
  * Output: w_out [cout][cin][5][5] (each branch's kernel centred, the identity
  * a unit centre tap of (c, c)) and b_out [cout] (the biases summed), in the
  * layout of one conv of the weight blob with conv_size = 5.  Pure host

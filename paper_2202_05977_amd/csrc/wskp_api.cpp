@@ -281,6 +281,8 @@ extern "C" wskp_status_t wskp_repvgg_merge(int cin, int cout, const float *w1, c
     if (cin < 1 || cout < 1) return fail(WSKP_E_INVALID_ARG, "cin and cout must be >= 1");
     if (!w_out || !b_out) return fail(WSKP_E_INVALID_ARG, "output pointer is NULL");
     if (identity && cin != cout) return fail(WSKP_E_INVALID_ARG, "the identity branch needs cin == cout");
+    if (!w1 != !b1 || !w3 != !b3 || !w5 != !b5)
+        return fail(WSKP_E_INVALID_ARG, "a branch needs both its weights and its bias (or neither)");
     const size_t n = (size_t)cout * cin * 25;
     std::fill(w_out, w_out + n, 0.f);
     std::fill(b_out, b_out + cout, 0.f);

@@ -209,6 +209,8 @@ def wskp_repvgg_merge(branch: dict, cin: int, cout: int):
         return a
     parts = []
     for k in (1, 3, 5):
+        if (branch.get(f"w{k}") is None) != (branch.get(f"b{k}") is None):
+            raise ValueError(f"branch {k}x{k}: give both w{k} and b{k}, or neither")
         parts += [arr(f"w{k}", (cout, cin, k, k)), arr(f"b{k}", (cout,))]
     w = np.empty((cout, cin, 5, 5), np.float32)
     b = np.empty((cout,), np.float32)

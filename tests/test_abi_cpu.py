@@ -181,3 +181,12 @@ def test_repvgg_merge_rejects_bad_arguments():
     with pytest.raises(ValueError):
         wskp.wskp_repvgg_merge({"w1": np.zeros((2, 2, 3, 3), np.float32),
                                 "b1": np.zeros(2, np.float32)}, 2, 2)   # wrong branch shape
+    with pytest.raises(ValueError):
+        wskp.wskp_repvgg_merge({"w3": np.zeros((2, 2, 3, 3), np.float32)}, 2, 2)   # bias missing
+    # the C entry point itself rejects a half-given branch
+    w = np.zeros((2, 2, 3, 3), np.float32)
+    out_w = np.empty((2, 2, 5, 5), np.float32)
+    out_b = np.empty(2, np.float32)
+    st = wskp.lib().wskp_repvgg_merge(2, 2, None, None, w.ctypes.data, None, None, None, 0,
+                                      out_w.ctypes.data, out_b.ctypes.data)
+    assert st == -1
