@@ -7,15 +7,17 @@
 //     out_i(p) = sum_{q in Omega_i(p)} W_i(q) c(q) / max(sum_{q in Omega_i(p)} W_i(q), eps)
 // with windows truncated at the border.  No k x k kernel map is ever formed.
 //
-// Forward (decode_tile_kernel): a workgroup of 512 threads owns a tile of
-// 40 x 45 centres (1280 x 720: 512 tiles, two per CU), keeps the irradiance
-// of its halo in registers, and for each kernel size sums the plane
-// (W_i, W_i c) in LDS down the columns, then along the rows; see the kernel.
 // Two input forms:
-//   frames   c = r / (a + eps_a) is formed while staging; mod = a + eps_a;
+//   frames   (decode_tile_kernel, the denoising path) a workgroup of 512
+//            threads owns a tile of 40 x 45 centres (1280 x 720: 512 tiles,
+//            two per CU), forms c = r / (a + eps_a) while staging its halo,
+//            keeps it in registers, and for each kernel size sums the plane
+//            (W_i, W_i c) in LDS along the rows, then down the columns;
 //            head (planar [2M][H][W]), r, a and out come from the frame
-//            descriptors of a batch
-//   tensors  head [N,H,W,2M], c, mod (optional) and out are plain tensors
+//            descriptors of a batch; mod = a + eps_a
+//   tensors  (decode_fwd_kernel<DK_TENSORS>, wskp_decode) head [N,H,W,2M],
+//            c, mod (optional) and out are plain tensors of equal-size
+//            frames; 32 x 16-centre tiles of 256 threads
 // Adjoint: decode_fwd_kernel<DK_ADJ_A> (32 x 16 tiles; the forward window
 // sums plus the per-centre adjoint terms) and decode_adj_b_kernel (the same
 // box sums of those terms).
@@ -567,7 +569,6 @@ constexpr int kTileW = 40;          // centres per tile row (multiple of kNR)
 constexpr int kSRow = kTileW + 1;   // row-sum buffer stride (float4): odd
 constexpr float kLog2e = 1.4426950408889634f;
 
-enum DecodeForm { DF_FRAMES = 0, DF_TENSORS = 1 };
 
 __device__ __forceinline__ float wave_max(float v)
 {
@@ -576,13 +577,11 @@ __device__ __forceinline__ float wave_max(float v)
     return v;
 }
 
-template <int M, int FORM, int RM, bool EXPW>
-__global__ __launch_bounds__(kFThreads, 4) void decode_tile_kernel(DecodeCfg dc, FrameArg fa,
-                                                                    DecodeTensors dt)
+template <int M, int RM, bool EXPW>
+__global__ __launch_bounds__(kFThreads, 4) void decode_tile_kernel(DecodeCfg dc, FrameArg fa)
 {
     extern __shared__ float4 lds4[];
     __shared__ float red[2][kFThreads / 64];
-    constexpr bool FR = FORM == DF_FRAMES;
     const int TW = dc.tw, TH = dc.th, HXS = dc.hxs, R = dc.R;
     const int HX = TW + 2 * R, HY = TH + 2 * R, HXY = HXS * HY;
     const int tid = threadIdx.x;
@@ -592,42 +591,22 @@ __global__ __launch_bounds__(kFThreads, 4) void decode_tile_kernel(DecodeCfg dc,
     int x0, y0;
     {
         auto tiles = [&](int H, int W) { return ((W + TW - 1) / TW) * ((H + TH - 1) / TH); };
-        const int twoM = 2 * M;
-        int t;
-        if constexpr (FR) {
-            int n;
-            t = batch_tile_id(fa, blockIdx.x, gridDim.x, n);
-            if (t < 0) return;
-            const int f = batch_frame(fa, n, t, tiles);
-            if (f < 0) return;
-            const FrameDesc &fd = frame_at(fa, f);
-            io.H = fd.H;
-            io.W = fd.W;
-            io.head = fd.head;
-            io.hs_pix = 1;
-            io.hs_map = (size_t)fd.H * fd.W;
-            io.r = fd.r;
-            io.a = fd.a;
-            io.c = nullptr;
-            io.mod = nullptr;
-            io.out = fd.out;
-        } else {
-            t = xcd_logical_id(blockIdx.x, gridDim.x);
-            const int cnt = tiles(dt.H, dt.W);
-            const int f = t / cnt;
-            if (f >= dt.N) return;
-            t -= f * cnt;
-            const size_t P = (size_t)dt.H * dt.W;
-            io.H = dt.H;
-            io.W = dt.W;
-            io.head = dt.head + (size_t)f * P * twoM;
-            io.hs_pix = twoM;
-            io.hs_map = 1;
-            io.r = io.a = nullptr;
-            io.c = dt.c + (size_t)f * P * 3;
-            io.mod = dt.mod ? dt.mod + (size_t)f * P * 3 : nullptr;
-            io.out = dt.out + (size_t)f * P * 3;
-        }
+        int n;
+        int t = batch_tile_id(fa, blockIdx.x, gridDim.x, n);
+        if (t < 0) return;
+        const int f = batch_frame(fa, n, t, tiles);   // t becomes the tile within frame f
+        if (f < 0) return;
+        const FrameDesc &fd = frame_at(fa, f);
+        io.H = fd.H;
+        io.W = fd.W;
+        io.head = fd.head;
+        io.hs_pix = 1;
+        io.hs_map = (size_t)fd.H * fd.W;
+        io.r = fd.r;
+        io.a = fd.a;
+        io.c = nullptr;
+        io.mod = nullptr;
+        io.out = fd.out;
         const int txn = (io.W + TW - 1) / TW;
         x0 = (t % txn) * TW;
         y0 = (t / txn) * TH;
@@ -671,12 +650,9 @@ __global__ __launch_bounds__(kFThreads, 4) void decode_tile_kernel(DecodeCfg dc,
 
     // ---- loads: irradiance of the halo slots, the first weight map.  All
     // are buffer loads from 32-bit byte offsets (kNoPixel outside the image:
-    // reads zeros).  Map j of pixel q: frames at (j P + q) * 4 (planar), tensors
-    // at (q 2M + j) * 4 (interleaved).
-    const unsigned hstride = FR ? 4u : 8u * M;
-    auto map_rsrc = [&](int j) {
-        return FR ? make_rsrc(io.head + (size_t)j * P, P * 4u) : make_rsrc(io.head + j, P * hstride - 4u * j);
-    };
+    // reads zeros).  Map j of pixel q sits at (j P + q) * 4 (planar record).
+    const unsigned hstride = 4u;
+    auto map_rsrc = [&](int j) { return make_rsrc(io.head + (size_t)j * P, P * 4u); };
     float cv[kFSlots][3], wv[kFSlots];
     auto load_w = [&](int i) {
         const rsrc_t rs = map_rsrc(i);
@@ -695,7 +671,7 @@ __global__ __launch_bounds__(kFThreads, 4) void decode_tile_kernel(DecodeCfg dc,
         }
     };
     float lg[kNC];
-    if constexpr (FR) {
+    {
         const rsrc_t rr = make_rsrc(io.r, P * 12u), ra = make_rsrc(io.a, P * 12u);
         float av[kFSlots][3];
 #pragma unroll
@@ -721,17 +697,6 @@ __global__ __launch_bounds__(kFThreads, 4) void decode_tile_kernel(DecodeCfg dc,
                 const float c = cv[k][ch] * __builtin_amdgcn_rcpf(av[k][ch] + dc.eps_albedo);
                 cv[k][ch] = gp[k] >= 0 ? c : 0.f;
             }
-    } else {
-        const rsrc_t rc = make_rsrc(io.c, P * 12u);
-#pragma unroll
-        for (int k = 0; k < kFSlots; ++k) {
-            const auto c3 =
-                __builtin_amdgcn_raw_buffer_load_b96(rc, gp[k] >= 0 ? (unsigned)gp[k] * 12u : kNoPixel, 0, 0);
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) cv[k][ch] = __uint_as_float(c3[ch]);
-        }
-        load_w(0);
-        load_logit(0, lg);
     }
 
     // ---- online fusion state of the thread's centres
@@ -791,32 +756,13 @@ __global__ __launch_bounds__(kFThreads, 4) void decode_tile_kernel(DecodeCfg dc,
         if (i + 1 < M) {
             load_w(i + 1);
         } else {
-            if constexpr (FR) {
-                const rsrc_t ra = make_rsrc(io.a, P * 12u);
+            const rsrc_t ra = make_rsrc(io.a, P * 12u);
 #pragma unroll
-                for (int q = 0; q < kNC; ++q) {
-                    const unsigned o = centre_off(q);
-                    const auto a3 =
-                        __builtin_amdgcn_raw_buffer_load_b96(ra, o == kNoPixel ? kNoPixel : o * 3u, 0, 0);
+            for (int q = 0; q < kNC; ++q) {
+                const unsigned o = centre_off(q);
+                const auto a3 = __builtin_amdgcn_raw_buffer_load_b96(ra, o == kNoPixel ? kNoPixel : o * 3u, 0, 0);
 #pragma unroll
-                    for (int ch = 0; ch < 3; ++ch) mv[q][ch] = __uint_as_float(a3[ch]) + dc.eps_albedo;
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < kNC; ++q)
-#pragma unroll
-                    for (int ch = 0; ch < 3; ++ch) mv[q][ch] = 1.f;
-                if (io.mod) {
-                    const rsrc_t rm = make_rsrc(io.mod, P * 12u);
-#pragma unroll
-                    for (int q = 0; q < kNC; ++q) {
-                        const unsigned o = centre_off(q);
-                        const auto m3 =
-                            __builtin_amdgcn_raw_buffer_load_b96(rm, o == kNoPixel ? kNoPixel : o * 3u, 0, 0);
-#pragma unroll
-                        for (int ch = 0; ch < 3; ++ch) mv[q][ch] = __uint_as_float(m3[ch]);
-                    }
-                }
+                for (int ch = 0; ch < 3; ++ch) mv[q][ch] = __uint_as_float(a3[ch]) + dc.eps_albedo;
             }
         }
         lds_sync();
@@ -1037,51 +983,40 @@ static size_t tile_lds_bytes(const DecodeCfg &dc)
     return sizeof(float4) * (size_t)(dc.hxs + kSRow) * (dc.th + 2 * dc.R);
 }
 
-template <int M, int FORM, int RM, bool EXPW>
-static hipError_t launch_tile_inst(const DecodeCfg &dc, const FrameArg &fa, const DecodeTensors &dt,
-                                   int blocks, hipStream_t s)
+template <int M, int RM, bool EXPW>
+static hipError_t launch_tile_inst(const DecodeCfg &dc, const FrameArg &fa, int blocks, hipStream_t s)
 {
     const size_t lds = tile_lds_bytes(dc);
-    allow_lds(decode_tile_kernel<M, FORM, RM, EXPW>, lds);
-    hipLaunchKernelGGL((decode_tile_kernel<M, FORM, RM, EXPW>), dim3(blocks), dim3(kFThreads), lds, s,
-                       dc, fa, dt);
+    allow_lds(decode_tile_kernel<M, RM, EXPW>, lds);
+    hipLaunchKernelGGL((decode_tile_kernel<M, RM, EXPW>), dim3(blocks), dim3(kFThreads), lds, s, dc, fa);
     return hipGetLastError();
 }
 
-template <int FORM>
-static hipError_t launch_tile(const DecodeCfg &dc, const FrameArg &fa, const DecodeTensors &dt,
-                              int blocks, hipStream_t s)
+hipError_t launch_decode_frames(const DecodeCfg &dc, const FrameArg &fa, int blocks, hipStream_t s)
 {
     // one instantiation covers every kernel size up to 15 (the size only
     // selects the window-sum code; the registers do not depend on it)
     if (blocks <= 0) return hipSuccess;
-    const bool ex = FORM == DF_FRAMES && dc.exp_weights;
     switch (dc.M) {
-#define WSKP_M(m)                                                                              \
-    case m:                                                                                    \
-        if constexpr (FORM == DF_FRAMES) {                                                     \
-            if (ex) return launch_tile_inst<m, FORM, 7, true>(dc, fa, dt, blocks, s);          \
-        }                                                                                      \
-        return launch_tile_inst<m, FORM, 7, false>(dc, fa, dt, blocks, s);
+#define WSKP_M(m)                                                                 \
+    case m:                                                                       \
+        if (dc.exp_weights) return launch_tile_inst<m, 7, true>(dc, fa, blocks, s); \
+        return launch_tile_inst<m, 7, false>(dc, fa, blocks, s);
         WSKP_M(1) WSKP_M(2) WSKP_M(3) WSKP_M(4) WSKP_M(5) WSKP_M(6) WSKP_M(7) WSKP_M(8)
 #undef WSKP_M
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_decode_frames(const DecodeCfg &dc, const FrameArg &fa, int blocks, hipStream_t s)
-{
-    DecodeTensors dt{};
-    return launch_tile<DF_FRAMES>(dc, fa, dt, blocks, s);
-}
-
 hipError_t launch_decode_tensors(const DecodeCfg &dc, int N, int H, int W, const float *head,
                                  const float *c, const float *mod, float *out, hipStream_t s)
 {
+    // the 32 x 16-tile kernel: on equal-size stacks it measured faster than
+    // the 40 x 45 tile kernel (29 vs 35 us for 8 x 256^2, 42 vs 45 us at 720p)
     DecodeTensors dt{N, H, W, head, c, mod, out, nullptr, nullptr, nullptr};
     FrameArg fa{};
-    const int blocks = N * ((W + dc.tw - 1) / dc.tw) * ((H + dc.th - 1) / dc.th);
-    return launch_tile<DF_TENSORS>(dc, fa, dt, blocks, s);
+    const int blocks = N * ((W + kDTX - 1) / kDTX) * ((H + kDTY - 1) / kDTY);
+    return launch_decode<DK_TENSORS>(dc, fa, dt, blocks, s);
 }
 
 size_t decode_backward_scratch_bytes(const DecodeCfg &dc, int N, int H, int W)
