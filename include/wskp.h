@@ -290,6 +290,22 @@ wskp_status_t wskp_pool2(wskp_handle_t h, void *stream, int H, int W, const floa
 wskp_status_t wskp_mr_blend(wskp_handle_t h, void *stream, int H, int W, const float *fine,
                             const float *coarse, const float *alpha, const float *mod, float *out);
 
+/* The whole multi-resolution reconstruction in one call: L levels (1..6),
+ * H and W multiples of 2^(L-1).  heads: host array of L device pointers,
+ * heads[l] the activated head record of level l, [H>>l, W>>l, 2M]
+ * interleaved (as wskp_decode takes it); c [H,W,3] the irradiance; alphas:
+ * host array of L-1 device pointers, alphas[l] [H>>l, W>>l] the Eq. 7 blend
+ * weight of level l; mod [H,W,3] or NULL; out [H,W,3].  Pools c L-1 times,
+ * filters every level, blends from the coarsest and remodulates the finest
+ * result: the same launches, in the same order, as the composition of
+ * wskp_pool2, wskp_decode and wskp_mr_blend.  ws: device workspace of at
+ * least wskp_mr_workspace_size bytes (the pooled irradiance of levels
+ * 1..L-1, every level's filtered image, the intermediate blends). */
+wskp_status_t wskp_mr_workspace_size(wskp_handle_t h, int L, int H, int W, size_t *bytes);
+wskp_status_t wskp_mr_reconstruct(wskp_handle_t h, void *stream, int L, int H, int W,
+                                  const float *const *heads, const float *c, const float *const *alphas,
+                                  const float *mod, float *out, void *ws, size_t ws_bytes);
+
 /* Temporal accumulation before denoising (Sec. 4.1, last paragraph): the
  * previous frame's accumulated radiance is reprojected to this frame with
  * the motion vectors and, where the geometry agrees, blended with this

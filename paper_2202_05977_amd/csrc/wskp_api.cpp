@@ -1262,6 +1262,83 @@ extern "C" wskp_status_t wskp_mr_blend(wskp_handle_t h, void *stream, int H, int
     return WSKP_OK;
 }
 
+// Workspace of the multi-resolution reconstruction, float offsets: pooled
+// irradiance cs[l] (l >= 1), filtered images f[l], blends o[l] (1 <= l <= L-2;
+// level 0's blend is the caller's out).
+static wskp_status_t mr_plan(const wskp_ctx *h, int L, int H, int W, size_t *cs, size_t *f, size_t *o,
+                             size_t *total)
+{
+    if (L < 1 || L > WSKP_MAX_LEVELS) return fail(WSKP_E_INVALID_ARG, "L must be in 1..6");
+    const int a = 1 << (L - 1);
+    if (H < a || W < a || H % a || W % a || (long)H * W > (1L << 28))
+        return fail(WSKP_E_SHAPE, "H and W must be multiples of 2^(L-1)");
+    if ((long)H * W * 8 * h->cfg.num_kernels >= 0xfffffff0L)
+        return fail(WSKP_E_SHAPE, "frame too large: its head record would exceed 4 GiB");
+    size_t off = 0;
+    auto take = [&](int l) {
+        const size_t at = off;
+        off += align_up((size_t)(H >> l) * (W >> l) * 3 * sizeof(float)) / sizeof(float);
+        return at;
+    };
+    for (int l = 0; l < L; ++l) {
+        cs[l] = l ? take(l) : 0;
+        f[l] = take(l);
+        o[l] = (l >= 1 && l + 2 <= L) ? take(l) : 0;
+    }
+    *total = off * sizeof(float);
+    return WSKP_OK;
+}
+
+extern "C" wskp_status_t wskp_mr_workspace_size(wskp_handle_t h, int L, int H, int W, size_t *bytes)
+{
+    if (!h || !bytes) return fail(WSKP_E_INVALID_ARG, "NULL argument");
+    size_t cs[WSKP_MAX_LEVELS], f[WSKP_MAX_LEVELS], o[WSKP_MAX_LEVELS];
+    return mr_plan(h, L, H, W, cs, f, o, bytes);
+}
+
+extern "C" wskp_status_t wskp_mr_reconstruct(wskp_handle_t h, void *stream, int L, int H, int W,
+                                             const float *const *heads, const float *c,
+                                             const float *const *alphas, const float *mod, float *out,
+                                             void *ws, size_t ws_bytes)
+{
+    if (!h || !heads || !c || !out || (L > 1 && (!alphas || !ws)))
+        return fail(WSKP_E_INVALID_ARG, "NULL argument");
+    size_t cs[WSKP_MAX_LEVELS], f[WSKP_MAX_LEVELS], o[WSKP_MAX_LEVELS], need;
+    wskp_status_t st = mr_plan(h, L, H, W, cs, f, o, &need);
+    if (st != WSKP_OK) return st;
+    for (int l = 0; l < L; ++l)
+        if (!heads[l] || (l + 1 < L && !alphas[l])) return fail(WSKP_E_INVALID_ARG, "NULL level pointer");
+    if (L > 1 && ws_bytes < need) return fail(WSKP_E_BUDGET, "workspace too small: need " + std::to_string(need) + " bytes");
+    if ((st = set_device(h)) != WSKP_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipSuccess;
+    if (L == 1) {
+        e = launch_decode_tensors(h->dc, 1, H, W, heads[0], c, mod, out, s);
+        if (e != hipSuccess) return hip_fail(e, "decode launch", WSKP_E_LAUNCH);
+        return WSKP_OK;
+    }
+    float *base = static_cast<float *>(ws);
+    // pooled irradiance of every coarser level
+    const float *cl = c;
+    for (int l = 1; l < L && e == hipSuccess; ++l) {
+        e = launch_pool2(H >> (l - 1), W >> (l - 1), cl, base + cs[l], s);
+        cl = base + cs[l];
+    }
+    // every level filtered with its own head (no remodulation)
+    for (int l = 0; l < L && e == hipSuccess; ++l)
+        e = launch_decode_tensors(h->dc, 1, H >> l, W >> l, heads[l], l ? base + cs[l] : c, nullptr,
+                                  base + f[l], s);
+    // Eq. 7 from the coarsest; the finest blend is remodulated into out
+    const float *coarse = base + f[L - 1];
+    for (int l = L - 2; l >= 0 && e == hipSuccess; --l) {
+        float *dst = l ? base + o[l] : out;
+        e = launch_mr_blend(H >> l, W >> l, base + f[l], coarse, alphas[l], l ? nullptr : mod, dst, s);
+        coarse = dst;
+    }
+    if (e != hipSuccess) return hip_fail(e, "multi-resolution launch", WSKP_E_LAUNCH);
+    return WSKP_OK;
+}
+
 extern "C" wskp_status_t wskp_temporal(wskp_handle_t h, void *stream, int H, int W, const float *radiance,
                                        const float *normal, const float *wpos, const float *motion,
                                        const float *prev_radiance, const float *prev_length,

@@ -100,6 +100,8 @@ def lib():
         L.wskp_repvgg_merge.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, i32, vp, vp]
         L.wskp_pool2.argtypes = [vp, vp, i32, i32, vp, vp]
         L.wskp_mr_blend.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp]
+        L.wskp_mr_workspace_size.argtypes = [vp, i32, i32, i32, ctypes.POINTER(sz)]
+        L.wskp_mr_reconstruct.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, sz]
         L.wskp_temporal.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp,
                                     ctypes.c_float, ctypes.c_float, ctypes.c_float, vp, vp]
         L.wskp_kp_map_bytes.argtypes = [vp, i32, i32, ctypes.POINTER(sz)]
@@ -121,7 +123,8 @@ def lib():
                      "wskp_denoise_static", "wskp_denoise_batch", "wskp_decode", "wskp_backward",
                      "wskp_backward_workspace_size", "wskp_workspace_tensor",
                      "wskp_kp_map_bytes", "wskp_kp_expand", "wskp_kp_decode", "wskp_temporal",
-                     "wskp_pool2", "wskp_mr_blend", "wskp_train_workspace_size",
+                     "wskp_pool2", "wskp_mr_blend", "wskp_mr_workspace_size", "wskp_mr_reconstruct",
+                     "wskp_train_workspace_size",
                      "wskp_train_grads", "wskp_adam", "wskp_get_weights", "wskp_repvgg_merge",
                      "wskp_timing_enable", "wskp_timing_read"):
             getattr(L, name).restype = ctypes.c_int
@@ -392,33 +395,39 @@ def wskp_mr_blend(h, fine, coarse, alpha, mod, out, stream=None) -> None:
                                _ptr(out, "out", (H, W, 3))), "wskp_mr_blend")
 
 
-def mr_reconstruct(h, heads, c, alphas, mod, stream=None):
-    """Multi-resolution reconstruction through the C entry points (argument
-    marshalling only): heads[l] [1, H>>l, W>>l, 2M] activated head records,
-    c [H,W,3] irradiance, alphas[l] [H>>l, W>>l] for the L-1 finer levels,
-    mod [H,W,3] or None.  Pools c L-1 times (wskp_pool2), filters each level
-    (wskp_decode) and blends from the coarsest (wskp_mr_blend)."""
+def wskp_mr_workspace_size(h, L: int, H: int, W: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().wskp_mr_workspace_size(h, L, H, W, ctypes.byref(n)), "wskp_mr_workspace_size")
+    return int(n.value)
+
+
+def mr_reconstruct(h, heads, c, alphas, mod, stream=None, ws=None):
+    """Multi-resolution reconstruction (wskp_mr_reconstruct): heads[l]
+    [1, H>>l, W>>l, 2M] activated head records, c [H,W,3] irradiance,
+    alphas[l] [H>>l, W>>l] for the L-1 finer levels, mod [H,W,3] or None.
+    ``ws``: optional uint8 device workspace of wskp_mr_workspace_size bytes."""
     L = len(heads)
-    cs = [c]
-    for _ in range(1, L):
-        Hc, Wc = cs[-1].shape[0] // 2, cs[-1].shape[1] // 2
-        nxt = torch.empty((Hc, Wc, 3), dtype=torch.float32, device=c.device)
-        wskp_pool2(h, cs[-1], nxt, stream)
-        cs.append(nxt)
-    outs = []
+    H, W = c.shape[:2]
+    if len(alphas) != L - 1:
+        raise ValueError(f"{L} levels need {L - 1} blend weights, got {len(alphas)}")
+    hp = (ctypes.c_void_p * L)()
     for l in range(L):
-        o = torch.empty((1,) + tuple(cs[l].shape), dtype=torch.float32, device=c.device)
-        m = mod.unsqueeze(0) if (L == 1 and mod is not None) else None
-        wskp_decode(h, heads[l], cs[l].unsqueeze(0), m, o, stream)
-        outs.append(o[0])
-    o = outs[L - 1]
-    if L == 1:
-        return o
-    for l in range(L - 2, -1, -1):
-        nxt = torch.empty_like(outs[l])
-        wskp_mr_blend(h, outs[l], o, alphas[l], mod if l == 0 else None, nxt, stream)
-        o = nxt
-    return o
+        _check_head(h, heads[l], f"heads[{l}]")
+        hp[l] = _ptr(heads[l], f"heads[{l}]", (1, H >> l, W >> l, heads[l].shape[-1]))
+    ap = (ctypes.c_void_p * max(1, L - 1))()
+    for l in range(L - 1):
+        ap[l] = _ptr(alphas[l], f"alphas[{l}]", (H >> l, W >> l))
+    need = wskp_mr_workspace_size(h, L, H, W)
+    if ws is None:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=c.device)
+    elif ws.numel() < need:
+        raise ValueError(f"workspace of {ws.numel()} bytes, need {need}")
+    out = torch.empty((H, W, 3), dtype=torch.float32, device=c.device)
+    _check(lib().wskp_mr_reconstruct(h, _stream(stream), L, H, W, ctypes.cast(hp, ctypes.c_void_p),
+                                     _ptr(c, "c", (H, W, 3)), ctypes.cast(ap, ctypes.c_void_p),
+                                     _ptr(mod, "mod", (H, W, 3)), _ptr(out, "out", (H, W, 3)),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel()), "wskp_mr_reconstruct")
+    return out
 
 
 TEMPORAL_DEFAULTS = {"alpha_min": 0.2, "pos_tol": 0.02, "normal_tol": 0.9}

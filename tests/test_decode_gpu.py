@@ -201,3 +201,52 @@ def test_multiresolution_reconstruction_matches_oracle(shape, L):
     ref = oracle.mr_reconstruct([x[0] for x in heads], c, alphas, mod, ks)
     got = y.cpu().numpy()
     assert rel_l2(got, ref) <= TOL_FP32 and max_rel(got, ref) <= TOL_FP32
+
+
+def _mr_composed(wskp, h, heads, c, alphas, mod):
+    """The same reconstruction from the three single-step entry points
+    (wskp_pool2, wskp_decode, wskp_mr_blend) called one by one."""
+    L = len(heads)
+    cs = [c]
+    for _ in range(1, L):
+        nxt = torch.empty((cs[-1].shape[0] // 2, cs[-1].shape[1] // 2, 3), device="cuda")
+        wskp.wskp_pool2(h, cs[-1], nxt)
+        cs.append(nxt)
+    outs = []
+    for l in range(L):
+        o = torch.empty((1,) + tuple(cs[l].shape), device="cuda")
+        wskp.wskp_decode(h, heads[l], cs[l].unsqueeze(0), mod.unsqueeze(0) if L == 1 else None, o)
+        outs.append(o[0])
+    o = outs[-1]
+    for l in range(L - 2, -1, -1):
+        nxt = torch.empty_like(outs[l])
+        wskp.wskp_mr_blend(h, outs[l], o, alphas[l], mod if l == 0 else None, nxt)
+        o = nxt
+    return o
+
+
+@pytest.mark.parametrize("shape,L", [((96, 160), 4), ((64, 64), 3), ((32, 48), 1)])
+def test_multiresolution_single_call_equals_step_composition(shape, L):
+    """wskp_mr_reconstruct runs the same launches as the composition of the
+    single-step entry points: bitwise equal, and a workspace that is too
+    small or a missing blend weight is rejected."""
+    from paper_2202_05977_amd import wskp
+    h = _handle((3, 5))
+    H, W = shape
+    rng = np.random.default_rng(7 * H + L)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    heads = [d(synth.make_head(90 + l, 1, H >> l, W >> l, 2)) for l in range(L)]
+    alphas = [d(rng.uniform(0, 1, size=(H >> l, W >> l)).astype(np.float32)) for l in range(L - 1)]
+    c = d(rng.gamma(0.5, 2.0, size=(H, W, 3)).astype(np.float32))
+    mod = d(rng.uniform(0.05, 1.0, size=(H, W, 3)).astype(np.float32))
+    y = wskp.mr_reconstruct(h, heads, c, alphas, mod)
+    ref = _mr_composed(wskp, h, heads, c, alphas, mod)
+    torch.cuda.synchronize()
+    assert torch.equal(y, ref)
+    if L > 1:
+        need = wskp.wskp_mr_workspace_size(h, L, H, W)
+        with pytest.raises(ValueError):
+            wskp.mr_reconstruct(h, heads, c, alphas[:-1], mod)
+        small = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+        with pytest.raises(ValueError):
+            wskp.mr_reconstruct(h, heads, c, alphas, mod, ws=small)
