@@ -22,13 +22,12 @@
 //          channels) tr_dgrad_kernel: one wave per 4 pixels x 64 input
 //          channels, the weight slice of 16 output channels staged in LDS
 //   wgrad  dw[co][ci][tap] = sum_p gm[p][co] in[p + off(tap)][ci],
-//          db[co] = sum_p gm[p][co]: a GEMM over pixels.  Where Ci and Co
-//          are multiples of 16, tr_wgrad_mfma_kernel (v_mfma_f32_16x16x4f32,
-//          4 pixels per step); otherwise (the network input's 10 channels,
-//          the head) tr_wgrad_kernel on the VALU.  Either way each wave sums
-//          one chunk of 256 pixels and a second pass adds the chunks'
-//          partial sums in a fixed order, so the result does not depend on
-//          scheduling
+//          db[co] = sum_p gm[p][co]: a GEMM over pixels,
+//          tr_wgrad_mfma_kernel (v_mfma_f32_16x16x4f32, 4 pixels per step;
+//          channel counts that are not multiples of 16 are padded with
+//          zeros).  Each wave sums one chunk of 256 pixels and a second pass
+//          adds the chunks' partial sums in a fixed order, so the result
+//          does not depend on scheduling
 #include "wskp_internal.h"
 
 namespace wskp {
@@ -217,61 +216,15 @@ __global__ __launch_bounds__(kTrThreads) void tr_dgrad_kernel(int H, int W, int 
         if (p0 + k < P) gstore(gin + (p0 + k) * Ci + ci, acc[k]);
 }
 
-// partial weight gradients: block (x: pixel chunk, y: 8-channel output
-// group, z: 64-channel input group) of one wave; part[chunk][co][ci][tap]
-constexpr int kWgCo = 8;
-__global__ __launch_bounds__(64) void tr_wgrad_kernel(int H, int W, int Ci, int Co, int chunk, const float *gm,
-                                                       const float *in, float *part, float *partb)
-{
-    const int lane = threadIdx.x;
-    const int ci = blockIdx.z * 64 + lane;
-    const int co0 = blockIdx.y * kWgCo;
-    const long P = (long)H * W;
-    const long pa = (long)blockIdx.x * chunk, pb = min(P, pa + chunk);
-    float acc[kWgCo][9], accb[kWgCo];
-#pragma unroll
-    for (int o = 0; o < kWgCo; ++o) {
-        accb[o] = 0.f;
-#pragma unroll
-        for (int t = 0; t < 9; ++t) acc[o][t] = 0.f;
-    }
-    const bool live = ci < Ci;
-    for (long p = pa; p < pb; ++p) {
-        const int y = (int)(p / W), x = (int)(p % W);
-        float v[9];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-            const bool ok = live && yy >= 0 && yy < H && xx >= 0 && xx < W;
-            v[t] = ok ? gload(in + ((long)yy * W + xx) * Ci + ci) : 0.f;
-        }
-#pragma unroll
-        for (int o = 0; o < kWgCo; ++o) {
-            const float g = co0 + o < Co ? gload(gm + p * Co + co0 + o) : 0.f;
-            accb[o] += g;
-#pragma unroll
-            for (int t = 0; t < 9; ++t) acc[o][t] += g * v[t];
-        }
-    }
-    const long base = (long)blockIdx.x * Co * Ci * 9;
-#pragma unroll
-    for (int o = 0; o < kWgCo; ++o) {
-        const int co = co0 + o;
-        if (co >= Co) continue;
-        if (live)
-#pragma unroll
-            for (int t = 0; t < 9; ++t) gstore(part + base + ((long)co * Ci + ci) * 9 + t, acc[o][t]);
-        if (blockIdx.z == 0 && lane == 0) gstore(partb + (long)blockIdx.x * Co + co, accb[o]);
-    }
-}
-
-// The same partial weight gradients on the matrix cores (Ci and Co
-// multiples of 16): a GEMM over pixels, D[co][ci] += sum_p gm[p][co] *
-// in[p + off(tap)][ci] for each tap, with v_mfma_f32_16x16x4f32 taking 4
-// pixels per step (lane (g, j): pixel g of the step; A = gm[p_g][co0 + j],
-// B = in[p_g + off][ci0 + j]).  One wave per (pixel chunk, CB output blocks
-// of 16, one input block of 16); the wave of input block 0 also sums gm
-// (B = 1) for the bias.  Lane (g, j) ends with D[4g + r][j], r = 0..3.
+// Partial weight gradients on the matrix cores, part[chunk][co][ci][tap]
+// and partb[chunk][co]: a GEMM over
+// pixels, D[co][ci] += sum_p gm[p][co] * in[p + off(tap)][ci] for each tap,
+// with v_mfma_f32_16x16x4f32 taking 4 pixels per step (lane (g, j): pixel
+// g of the step; A = gm[p_g][co0 + j], B = in[p_g + off][ci0 + j]).  One
+// wave per (pixel chunk, CB output blocks of 16, one input block of 16);
+// channels beyond Co or Ci (the network input's 10, the head's 2M) enter as
+// zeros and are not stored.  The wave of input block 0 also sums gm (B = 1)
+// for the bias.  Lane (g, j) ends with D[4g + r][j], r = 0..3.
 typedef float trf32x4 __attribute__((ext_vector_type(4)));
 template <int CB>
 __global__ __launch_bounds__(64) void tr_wgrad_mfma_kernel(int H, int W, int Ci, int Co, int chunk, const float *gm,
@@ -296,11 +249,12 @@ __global__ __launch_bounds__(64) void tr_wgrad_mfma_kernel(int H, int W, int Ci,
         const bool valid = p < pb;
         float a[CB], b[9];
 #pragma unroll
-        for (int c = 0; c < CB; ++c) a[c] = valid ? gload(gm + p * Co + co0 + c * 16 + j) : 0.f;
+        for (int c = 0; c < CB; ++c)
+            a[c] = (valid && co0 + c * 16 + j < Co) ? gload(gm + p * Co + co0 + c * 16 + j) : 0.f;
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
             const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-            const bool ok = valid && yy >= 0 && yy < H && xx >= 0 && xx < W;
+            const bool ok = valid && ci0 + j < Ci && yy >= 0 && yy < H && xx >= 0 && xx < W;
             b[t] = ok ? gload(in + ((long)yy * W + xx) * Ci + ci0 + j) : 0.f;
         }
 #pragma unroll
@@ -322,8 +276,10 @@ __global__ __launch_bounds__(64) void tr_wgrad_mfma_kernel(int H, int W, int Ci,
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int co = co0 + c * 16 + 4 * g + r;
+            if (co >= Co) continue;
+            if (ci < Ci)
 #pragma unroll
-            for (int t = 0; t < 9; ++t) gstore(part + base + ((long)co * Ci + ci) * 9 + t, acc[c][t][r]);
+                for (int t = 0; t < 9; ++t) gstore(part + base + ((long)co * Ci + ci) * 9 + t, acc[c][t][r]);
             if (bias && j == 0) gstore(partb + (long)blockIdx.x * Co + co, accb[c][r]);
         }
 }
@@ -513,17 +469,13 @@ hipError_t tr_wgrad(int H, int W, int Ci, int Co, const float *gm, const float *
     const int nch = tr_wgrad_chunks(P);
     const long nw = (long)Co * Ci * 9;
     float *partb = part + (size_t)nch * nw;
-    if (Ci % 16 == 0 && Co % 16 == 0) {
-        if ((Co / 16) % 2 == 0)
-            hipLaunchKernelGGL(tr_wgrad_mfma_kernel<2>, dim3((unsigned)nch, (unsigned)(Co / 32), (unsigned)(Ci / 16)),
-                               dim3(64), 0, s, H, W, Ci, Co, 256, gm, in, part, partb);
-        else
-            hipLaunchKernelGGL(tr_wgrad_mfma_kernel<1>, dim3((unsigned)nch, (unsigned)(Co / 16), (unsigned)(Ci / 16)),
-                               dim3(64), 0, s, H, W, Ci, Co, 256, gm, in, part, partb);
-    } else {
-        const dim3 grid((unsigned)nch, (unsigned)((Co + kWgCo - 1) / kWgCo), (unsigned)((Ci + 63) / 64));
-        hipLaunchKernelGGL(tr_wgrad_kernel, grid, dim3(64), 0, s, H, W, Ci, Co, 256, gm, in, part, partb);
-    }
+    const unsigned cib = (unsigned)((Ci + 15) / 16), cob = (unsigned)((Co + 15) / 16);
+    if (cob % 2 == 0)
+        hipLaunchKernelGGL(tr_wgrad_mfma_kernel<2>, dim3((unsigned)nch, cob / 2, cib), dim3(64), 0, s, H, W, Ci, Co,
+                           256, gm, in, part, partb);
+    else
+        hipLaunchKernelGGL(tr_wgrad_mfma_kernel<1>, dim3((unsigned)nch, cob, cib), dim3(64), 0, s, H, W, Ci, Co, 256,
+                           gm, in, part, partb);
     TR_LAUNCH(tr_wgrad_reduce_kernel, nw + Co, nw, Co, nch, part, partb, dw, db);
     return hipGetLastError();
 }
