@@ -16,18 +16,17 @@
 // Gradient kernels (NHWC fp32, zero padding, conv = 3x3 cross-correlation):
 //   dgrad  gin[p][ci] = sum_{tap,co} gm[p - off(tap)][co] w[co][ci][tap]:
 //          itself a 3x3 conv of gm with the kernel flipped and its channel
-//          axes swapped, so where Ci and Co are multiples of 16 it runs the
-//          fp32 forward conv kernel (MFMA, conv3x3.hip) on weights that
-//          tr_pack_dgrad lays out for it; otherwise (the head's 2M output
-//          channels) tr_dgrad_kernel: one wave per 4 pixels x 64 input
-//          channels, the weight slice of 16 output channels staged in LDS
+//          axes swapped, run by the fp32 forward conv kernel (MFMA,
+//          conv3x3.hip) on weights that tr_pack_dgrad lays out for it; the
+//          head's 2M output channels are padded with zeros to a multiple
+//          of 16 (its gradient dh is written with that row stride)
 //   wgrad  dw[co][ci][tap] = sum_p gm[p][co] in[p + off(tap)][ci],
 //          db[co] = sum_p gm[p][co]: a GEMM over pixels,
 //          tr_wgrad_mfma_kernel (v_mfma_f32_16x16x4f32, 4 pixels per step;
 //          channel counts that are not multiples of 16 are padded with
-//          zeros).  Each wave sums one chunk of 256 pixels and a second pass
-//          adds the chunks' partial sums in a fixed order, so the result
-//          does not depend on scheduling
+//          zeros).  Each workgroup sums one chunk of 256 pixels and a
+//          second pass adds the chunks' partial sums in a fixed order, so
+//          the result does not depend on scheduling
 #include "wskp_internal.h"
 
 namespace wskp {
@@ -139,15 +138,18 @@ __global__ void tr_sum_kernel(int nb, const float *partial, float *loss, int acc
 // gradient at the head conv's output: weight channels through softplus'
 // (the logistic of h, = 1 - e^{-W} = -expm1(-W) in terms of W = softplus(h),
 // accurate also where W is tiny); logits as is
-__global__ __launch_bounds__(kTrThreads) void tr_head_act_bwd_kernel(long P, int M, const float *grad_head,
+__global__ __launch_bounds__(kTrThreads) void tr_head_act_bwd_kernel(long P, int M, int ld, const float *grad_head,
                                                                       const float *planar, float *dh)
 {
     const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
-    if (i >= P * 2 * M) return;
-    const int j = (int)(i % (2 * M));
-    const long p = i / (2 * M);
-    float g = gload(grad_head + i);
-    if (j < M) g *= -expm1f(-gload(planar + (long)j * P + p));
+    if (i >= P * ld) return;
+    const int j = (int)(i % ld);
+    const long p = i / ld;
+    float g = 0.f;
+    if (j < 2 * M) {
+        g = gload(grad_head + p * 2 * M + j);
+        if (j < M) g *= -expm1f(-gload(planar + (long)j * P + p));
+    }
     gstore(dh + i, g);
 }
 
@@ -160,119 +162,117 @@ __global__ __launch_bounds__(kTrThreads) void tr_mask_kernel(long n, const float
     gstore(gm + i, act ? (gload(act + i) > 0.f ? v : 0.f) : v);
 }
 
-// input gradient of a 3x3 conv.  Block: 4 waves; wave w handles pixels
-// 4*(4*blockIdx.x + w) .. +3 (in raster order) for input channels
-// 64*blockIdx.y + lane.  Output channels in chunks of 16 whose weights
-// [16][9][64] are staged in LDS.
-constexpr int kDgPix = 4;
-__global__ __launch_bounds__(kTrThreads) void tr_dgrad_kernel(int H, int W, int Ci, int Co, const float *gm,
-                                                               const float *w, float *gin)
-{
-    __shared__ float ws[16][9][64];
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int ci = blockIdx.y * 64 + lane;
-    const long P = (long)H * W;
-    const long p0 = ((long)blockIdx.x * 4 + wave) * kDgPix;
-    int py[kDgPix], px[kDgPix];
-#pragma unroll
-    for (int k = 0; k < kDgPix; ++k) {
-        const long p = p0 + k < P ? p0 + k : P - 1;
-        py[k] = (int)(p / W);
-        px[k] = (int)(p % W);
-    }
-    float acc[kDgPix] = {0.f, 0.f, 0.f, 0.f};
-    for (int c0 = 0; c0 < Co; c0 += 16) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < 16 * 9 * 64; i += kTrThreads) {
-            const int l = i & 63, t = (i >> 6) % 9, o = i / (9 * 64);
-            const int co = c0 + o, cc = blockIdx.y * 64 + l;
-            ws[o][t][l] = (co < Co && cc < Ci) ? gload(w + ((long)co * Ci + cc) * 9 + t) : 0.f;
-        }
-        __syncthreads();
-        const int nco = min(16, Co - c0);
-        for (int t = 0; t < 9; ++t) {
-            const int ky = t / 3, kx = t % 3;
-            // output pixel p feeds input pixel p' = p + off(tap): the input
-            // gradient at p' gathers from p = p' - off(tap) (wave-uniform)
-            const float *gp[kDgPix];
-            bool in[kDgPix];
-#pragma unroll
-            for (int k = 0; k < kDgPix; ++k) {
-                const int yy = py[k] - ky + 1, xx = px[k] - kx + 1;
-                in[k] = yy >= 0 && yy < H && xx >= 0 && xx < W;
-                gp[k] = gm + ((long)(in[k] ? yy : 0) * W + (in[k] ? xx : 0)) * Co + c0;
-            }
-            for (int o = 0; o < nco; ++o) {
-                const float wv = ws[o][t][lane];
-#pragma unroll
-                for (int k = 0; k < kDgPix; ++k) acc[k] += (in[k] ? gload(gp[k] + o) : 0.f) * wv;
-            }
-        }
-    }
-    if (ci >= Ci) return;
-#pragma unroll
-    for (int k = 0; k < kDgPix; ++k)
-        if (p0 + k < P) gstore(gin + (p0 + k) * Ci + ci, acc[k]);
-}
-
 // Partial weight gradients on the matrix cores, part[chunk][co][ci][tap]
 // and partb[chunk][co]: a GEMM over
 // pixels, D[co][ci] += sum_p gm[p][co] * in[p + off(tap)][ci] for each tap,
 // with v_mfma_f32_16x16x4f32 taking 4 pixels per step (lane (g, j): pixel
 // g of the step; A = gm[p_g][co0 + j], B = in[p_g + off][ci0 + j]).  One
-// wave per (pixel chunk, CB output blocks of 16, one input block of 16);
-// channels beyond Co or Ci (the network input's 10, the head's 2M) enter as
-// zeros and are not stored.  The wave of input block 0 also sums gm (B = 1)
-// for the bias.  Lane (g, j) ends with D[4g + r][j], r = 0..3.
+// workgroup per (chunk of kWgChunk pixels, CB output blocks of 16, one input
+// block of 16); its kWgWaves waves take consecutive quarters of the chunk,
+// each loading the operands of its next step before the MFMAs of the current
+// one, and add their sums in LDS in a fixed order, (w0 + w2) + (w1 + w3).
+// Channels beyond Co or Ci (the network input's 10, the head's 2M) and
+// pixels outside the image read a clamped in-bounds address and enter as
+// zeros, so every load is unconditional; they are not stored.  The
+// workgroups of input block 0 also sum gm (B = 1) for the bias.  Lane (g, j)
+// ends with D[4g + r][j], r = 0..3.
 typedef float trf32x4 __attribute__((ext_vector_type(4)));
+constexpr int kWgChunk = 256, kWgWaves = 4;
 template <int CB>
-__global__ __launch_bounds__(64) void tr_wgrad_mfma_kernel(int H, int W, int Ci, int Co, int chunk, const float *gm,
-                                                            const float *in, float *part, float *partb)
+__global__ __launch_bounds__(64 * kWgWaves) void tr_wgrad_mfma_kernel(int H, int W, int Ci, int Co, int ldg,
+                                                                      const float *gm, const float *in, float *part,
+                                                                      float *partb)
 {
-    const int lane = threadIdx.x, g = lane >> 4, j = lane & 15;
+    __shared__ trf32x4 red[2][CB * 10][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
     const int co0 = blockIdx.y * (16 * CB), ci0 = blockIdx.z * 16;
     const long P = (long)H * W;
-    const long pa = (long)blockIdx.x * chunk, pb = min(P, pa + chunk);
+    const long pa = (long)blockIdx.x * kWgChunk + wave * (kWgChunk / kWgWaves);
+    const long pb = min(P, pa + kWgChunk / kWgWaves);
     const bool bias = blockIdx.z == 0;
-    trf32x4 acc[CB][9], accb[CB];
+    // clamped channels: a lane past Co or Ci reads a valid channel, then zero
+    int cof[CB];
+    bool cok[CB];
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
-        accb[c] = trf32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int t = 0; t < 9; ++t) acc[c][t] = trf32x4{0.f, 0.f, 0.f, 0.f};
+        cok[c] = co0 + c * 16 + j < Co;
+        cof[c] = cok[c] ? co0 + c * 16 + j : Co - 1;
     }
-    // this lane's pixel p = q + g of the step at q, its row and column
-    int y = (int)((pa + g) / W), x = (int)((pa + g) - (long)y * W);
-    for (long q = pa; q < pb; q += 4) {
+    const bool ciok = ci0 + j < Ci;
+    const int cif = ciok ? ci0 + j : Ci - 1;
+    trf32x4 acc[CB][10];
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int t = 0; t < 10; ++t) acc[c][t] = trf32x4{0.f, 0.f, 0.f, 0.f};
+    float a[CB], b[9];
+    // operands of the step at q for this lane's pixel p = q + g at (y, x)
+    auto load = [&](long q, int y, int x, float (&av)[CB], float (&bv)[9]) {
         const long p = q + g;
         const bool valid = p < pb;
-        float a[CB], b[9];
+        const long pc = valid ? p : 0;
 #pragma unroll
-        for (int c = 0; c < CB; ++c)
-            a[c] = (valid && co0 + c * 16 + j < Co) ? gload(gm + p * Co + co0 + c * 16 + j) : 0.f;
+        for (int c = 0; c < CB; ++c) {
+            const float v = gload(gm + pc * ldg + cof[c]);
+            av[c] = valid && cok[c] ? v : 0.f;
+        }
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
             const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-            const bool ok = valid && ci0 + j < Ci && yy >= 0 && yy < H && xx >= 0 && xx < W;
-            b[t] = ok ? gload(in + ((long)yy * W + xx) * Ci + ci0 + j) : 0.f;
+            const bool ok = valid && ciok && yy >= 0 && yy < H && xx >= 0 && xx < W;
+            const float v = gload(in + (ok ? (long)yy * W + xx : 0) * Ci + cif);
+            bv[t] = ok ? v : 0.f;
         }
+    };
+    int y = (int)((pa + g) / W), x = (int)((pa + g) - (long)y * W);
+    if (pa < pb) load(pa, y, x, a, b);
+    for (long q = pa; q < pb; q += 4) {
+        int yn = y, xn = x + 4;
+        while (xn >= W) {
+            xn -= W;
+            ++yn;
+        }
+        float an[CB], bn[9];
+        load(q + 4, yn, xn, an, bn);
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
 #pragma unroll
             for (int t = 0; t < 9; ++t) acc[c][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b[t], acc[c][t], 0, 0, 0);
-            if (bias) accb[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], 1.f, accb[c], 0, 0, 0);
+            if (bias) acc[c][9] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], 1.f, acc[c][9], 0, 0, 0);
         }
-        x += 4;
-        while (x >= W) {
-            x -= W;
-            ++y;
-        }
+#pragma unroll
+        for (int c = 0; c < CB; ++c) a[c] = an[c];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) b[t] = bn[t];
+        y = yn;
+        x = xn;
     }
+    // (w0 + w2) + (w1 + w3)
+    if (wave >= 2)
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+#pragma unroll
+            for (int t = 0; t < 10; ++t) red[wave - 2][c * 10 + t][lane] = acc[c][t];
+    __syncthreads();
+    if (wave < 2)
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+#pragma unroll
+            for (int t = 0; t < 10; ++t) acc[c][t] += red[wave][c * 10 + t][lane];
+    __syncthreads();
+    if (wave == 1)
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+#pragma unroll
+            for (int t = 0; t < 10; ++t) red[0][c * 10 + t][lane] = acc[c][t];
+    __syncthreads();
+    if (wave != 0) return;
     const long base = (long)blockIdx.x * Co * Ci * 9;
     const int ci = ci0 + j;
 #pragma unroll
-    for (int c = 0; c < CB; ++c)
+    for (int c = 0; c < CB; ++c) {
+#pragma unroll
+        for (int t = 0; t < 10; ++t) acc[c][t] += red[0][c * 10 + t][lane];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int co = co0 + c * 16 + 4 * g + r;
@@ -280,24 +280,38 @@ __global__ __launch_bounds__(64) void tr_wgrad_mfma_kernel(int H, int W, int Ci,
             if (ci < Ci)
 #pragma unroll
                 for (int t = 0; t < 9; ++t) gstore(part + base + ((long)co * Ci + ci) * 9 + t, acc[c][t][r]);
-            if (bias && j == 0) gstore(partb + (long)blockIdx.x * Co + co, accb[c][r]);
+            if (bias && j == 0) gstore(partb + (long)blockIdx.x * Co + co, acc[c][9][r]);
         }
+    }
 }
 
-// dw (+)= sum over chunks of part (in chunk order), likewise db
+// dw (+)= sum over chunks of part, likewise db: 64 weights per workgroup,
+// its four waves take the chunks c = wave (mod 4) and each sums them in
+// order on two alternating accumulators; the waves' sums are added in a
+// fixed order, so the result does not depend on scheduling
 __global__ __launch_bounds__(kTrThreads) void tr_wgrad_reduce_kernel(long nw, int Co, int nchunk, const float *part,
                                                                       const float *partb, float *dw, float *db)
 {
-    const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
-    if (i < nw) {
-        float s = gload(dw + i);
-        for (int c = 0; c < nchunk; ++c) s += gload(part + (long)c * nw + i);
-        gstore(dw + i, s);
-    } else if (i < nw + Co) {
-        const int co = (int)(i - nw);
-        float s = gload(db + co);
-        for (int c = 0; c < nchunk; ++c) s += gload(partb + (long)c * Co + co);
-        gstore(db + co, s);
+    __shared__ float sred[4][64];
+    const int li = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const long i = (long)blockIdx.x * 64 + li;
+    const bool inw = i < nw, in = i < nw + Co;
+    const float *src = inw ? part + i : partb + (in ? i - nw : 0);
+    const long stride = inw ? nw : Co;
+    float s0 = 0.f, s1 = 0.f;
+    if (in) {
+        int c = grp;
+        for (; c + 4 < nchunk; c += 8) {
+            s0 += gload(src + (long)c * stride);
+            s1 += gload(src + (long)(c + 4) * stride);
+        }
+        if (c < nchunk) s0 += gload(src + (long)c * stride);
+    }
+    sred[grp][li] = s0 + s1;
+    __syncthreads();
+    if (grp == 0 && in) {
+        float *dst = inw ? dw + i : db + (i - nw);
+        gstore(dst, gload(dst) + ((sred[0][li] + sred[1][li]) + (sred[2][li] + sred[3][li])));
     }
 }
 
@@ -424,9 +438,10 @@ hipError_t tr_smape(long n, const float *y, const float *t, float eps, float inv
     hipLaunchKernelGGL(tr_sum_kernel, dim3(1), dim3(64), 0, s, tr_blocks(n), partial, loss, accumulate);
     return hipGetLastError();
 }
-hipError_t tr_head_act_bwd(long P, int M, const float *grad_head, const float *planar, float *dh, hipStream_t s)
+hipError_t tr_head_act_bwd(long P, int M, int ld, const float *grad_head, const float *planar, float *dh,
+                           hipStream_t s)
 {
-    TR_LAUNCH(tr_head_act_bwd_kernel, P * 2 * M, P, M, grad_head, planar, dh);
+    TR_LAUNCH(tr_head_act_bwd_kernel, P * ld, P, M, ld, grad_head, planar, dh);
     return hipGetLastError();
 }
 hipError_t tr_mask(long n, const float *g, const float *act, float *gm, hipStream_t s)
@@ -434,35 +449,28 @@ hipError_t tr_mask(long n, const float *g, const float *act, float *gm, hipStrea
     TR_LAUNCH(tr_mask_kernel, n, n, g, act, gm);
     return hipGetLastError();
 }
-hipError_t tr_dgrad(int H, int W, int Ci, int Co, const float *gm, const float *w, float *gin, hipStream_t s)
+__global__ __launch_bounds__(kTrThreads) void tr_pack_dgrad_kernel(int Ci, int Co, int Co_pad, int Cout_pad,
+                                                                    const float *w, float *packed)
 {
-    const long P = (long)H * W;
-    const dim3 grid((unsigned)((P + 4 * kDgPix - 1) / (4 * kDgPix)), (unsigned)((Ci + 63) / 64));
-    hipLaunchKernelGGL(tr_dgrad_kernel, grid, dim3(kTrThreads), 0, s, H, W, Ci, Co, gm, w, gin);
-    return hipGetLastError();
-}
-__global__ __launch_bounds__(kTrThreads) void tr_pack_dgrad_kernel(int Ci, int Co, int Cout_pad, const float *w,
-                                                                    float *packed)
-{
-    const long n = (long)Co * 9 * Cout_pad;   // Co is a multiple of the 16-channel chunk
+    const long n = (long)Co_pad * 9 * Cout_pad;
     const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
     if (i >= n) return;
     const int ci = (int)(i % Cout_pad);
     const long ct = i / Cout_pad;            // (chunk * 9 + tap) * 16 + c
     const int c16 = (int)(ct % 16), ctap = (int)(ct / 16);
     const int t = ctap % 9, co = (ctap / 9) * 16 + c16;
-    gstore(packed + i, ci < Ci ? gload(w + ((long)co * Ci + ci) * 9 + (8 - t)) : 0.f);
+    gstore(packed + i, ci < Ci && co < Co ? gload(w + ((long)co * Ci + ci) * 9 + (8 - t)) : 0.f);
 }
 
-hipError_t tr_pack_dgrad(int Ci, int Co, int Cout_pad, const float *w, float *packed, hipStream_t s)
+hipError_t tr_pack_dgrad(int Ci, int Co, int Co_pad, int Cout_pad, const float *w, float *packed, hipStream_t s)
 {
-    TR_LAUNCH(tr_pack_dgrad_kernel, (long)Co * 9 * Cout_pad, Ci, Co, Cout_pad, w, packed);
+    TR_LAUNCH(tr_pack_dgrad_kernel, (long)Co_pad * 9 * Cout_pad, Ci, Co, Co_pad, Cout_pad, w, packed);
     return hipGetLastError();
 }
 
-int tr_wgrad_chunks(long P) { return (int)((P + 255) / 256); }
+int tr_wgrad_chunks(long P) { return (int)((P + kWgChunk - 1) / kWgChunk); }
 size_t tr_wgrad_part_floats(long P, int Ci, int Co) { return (size_t)tr_wgrad_chunks(P) * ((size_t)Co * Ci * 9 + Co); }
-hipError_t tr_wgrad(int H, int W, int Ci, int Co, const float *gm, const float *in, float *part, float *dw,
+hipError_t tr_wgrad(int H, int W, int Ci, int Co, int ldg, const float *gm, const float *in, float *part, float *dw,
                     float *db, hipStream_t s)
 {
     const long P = (long)H * W;
@@ -471,12 +479,13 @@ hipError_t tr_wgrad(int H, int W, int Ci, int Co, const float *gm, const float *
     float *partb = part + (size_t)nch * nw;
     const unsigned cib = (unsigned)((Ci + 15) / 16), cob = (unsigned)((Co + 15) / 16);
     if (cob % 2 == 0)
-        hipLaunchKernelGGL(tr_wgrad_mfma_kernel<2>, dim3((unsigned)nch, cob / 2, cib), dim3(64), 0, s, H, W, Ci, Co,
-                           256, gm, in, part, partb);
+        hipLaunchKernelGGL(tr_wgrad_mfma_kernel<2>, dim3((unsigned)nch, cob / 2, cib), dim3(64 * kWgWaves), 0, s, H, W,
+                           Ci, Co, ldg, gm, in, part, partb);
     else
-        hipLaunchKernelGGL(tr_wgrad_mfma_kernel<1>, dim3((unsigned)nch, cob, cib), dim3(64), 0, s, H, W, Ci, Co, 256,
-                           gm, in, part, partb);
-    TR_LAUNCH(tr_wgrad_reduce_kernel, nw + Co, nw, Co, nch, part, partb, dw, db);
+        hipLaunchKernelGGL(tr_wgrad_mfma_kernel<1>, dim3((unsigned)nch, cob, cib), dim3(64 * kWgWaves), 0, s, H, W, Ci,
+                           Co, ldg, gm, in, part, partb);
+    hipLaunchKernelGGL(tr_wgrad_reduce_kernel, dim3((unsigned)((nw + Co + 63) / 64)), dim3(kTrThreads), 0, s, nw, Co,
+                       nch, part, partb, dw, db);
     return hipGetLastError();
 }
 hipError_t tr_cat_bwd(int H, int W, int Cu, int Ce, const float *gcat, float *gu, float *ge, hipStream_t s)

@@ -972,6 +972,10 @@ struct TrainScratch {
     size_t bytes;
 };
 
+// row stride of the head's gradient: its 2M channels padded to the conv
+// kernels' 16-channel chunk
+static int head_grad_stride(int M) { return (2 * M + 15) / 16 * 16; }
+
 static size_t train_plan(const wskp_ctx *h, int Hm, int Wm, char *base, TrainScratch *ts)
 {
     const int L = h->cfg.levels, M = h->cfg.num_kernels;
@@ -1004,6 +1008,8 @@ static size_t train_plan(const wskp_ctx *h, int Hm, int Wm, char *base, TrainScr
     for (int l = 1; l < L; ++l) mx_wpk = std::max(mx_wpk, (size_t)ch[l] * 9 * ((ch[l - 1] + 15) / 16 * 16));
     for (int l = 0; l + 1 < L; ++l)
         mx_wpk = std::max(mx_wpk, (size_t)ch[l] * 9 * ((ch[l + 1] + ch[l] + 15) / 16 * 16));
+    const int ldh = head_grad_stride(M);
+    mx_wpk = std::max(mx_wpk, (size_t)ldh * 9 * ((ch[0] + 15) / 16 * 16));
     TrainScratch t{};
     t.X = take(10 * (size_t)P);
     t.head = take((size_t)2 * M * P);
@@ -1012,7 +1018,7 @@ static size_t train_plan(const wskp_ctx *h, int Hm, int Wm, char *base, TrainScr
     t.gy = take(3 * (size_t)P);
     t.gh = take((size_t)2 * M * P);
     t.gc = take(3 * (size_t)P);
-    t.dh = take((size_t)2 * M * P);
+    t.dh = take((size_t)ldh * P);
     t.dec = take(decode_backward_scratch_bytes(h->dc, 1, Hm, Wm) / sizeof(float));
     t.partial = take((size_t)tr_smape_blocks(3 * P));
     t.gm = take(mx_gm);
@@ -1087,7 +1093,7 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
     hipStream_t s = static_cast<hipStream_t>(stream);
     // forward: the batched fp32 path; its workspace keeps every layer's output
     if ((st = wskp_denoise_batch(h, stream, n, frames, 0, ws, fwd)) != WSKP_OK) return st;
-    const int L = h->cfg.levels, M = h->cfg.num_kernels;
+    const int L = h->cfg.levels, M = h->cfg.num_kernels, ldh = head_grad_stride(M);
     const int *ch = h->cfg.channels;
     long Ptot = 0;
     for (int i = 0; i < n; ++i) Ptot += (long)Hs[i] * Ws[i];
@@ -1101,21 +1107,21 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
     hipError_t e = tr_fill((long)nw, 0.f, grad, s);
     // input gradient of a conv (Ci -> Co forward): gin = conv(gm, w flipped,
     // in and out channels swapped), on the matrix cores with the fp32
-    // forward kernel where the channel counts fit its 16-channel chunks, else
-    // the VALU kernel (the head's 2M channels)
-    auto dgrad = [&](const TrainScratch &t, int Hl, int Wl, int Ci, int Co, const float *gm, const float *w,
+    // forward kernel; gm has ldg >= Co channels (the head's 2M padded with
+    // zeros to a multiple of 16, the kernel's channel chunk; Ci, a network
+    // width, is one already)
+    auto dgrad = [&](const TrainScratch &t, int Hl, int Wl, int Ci, int Co, int ldg, const float *gm, const float *w,
                      float *gin) -> hipError_t {
-        if (Co % 16 || Ci % 16) return tr_dgrad(Hl, Wl, Ci, Co, gm, w, gin, s);
         ConvLayer c{};
         c.level = 0;
         c.src0_kind = 0;
         c.src0_idx = 0;
         c.src1_idx = 0;
-        c.C0 = Co;
+        c.C0 = ldg;
         c.C1 = 0;
         c.ks = 3;
         c.CK = 16;
-        c.Cin_pad = Co;
+        c.Cin_pad = ldg;
         c.Cout = Ci;
         const int nblk = Ci / 16;
         c.NB = nblk % 4 == 0 ? 4 : (nblk % 2 == 0 ? 2 : 1);
@@ -1129,7 +1135,7 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
         c.in_qscale = 1.f;
         c.w = t.wpk;
         c.bias = t.zb;
-        hipError_t le = tr_pack_dgrad(Ci, Co, c.Cout_pad, w, t.wpk, s);
+        hipError_t le = tr_pack_dgrad(Ci, Co, ldg, c.Cout_pad, w, t.wpk, s);
         if (le != hipSuccess) return le;
         FrameArg fa{};
         fa.n = 1;
@@ -1158,7 +1164,7 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
         e = tr_head_prep(P, M, fd.head, fd.r, fd.a, h->cfg.eps_albedo, t.head, t.c, t.mod, s);
         if (e == hipSuccess) e = tr_smape(3 * P, fd.out, targets[f], eps_smape, inv_n, t.gy, t.partial, loss, f > 0, s);
         if (e == hipSuccess) e = launch_decode_backward(h->dc, 1, H, W, t.head, t.c, t.mod, t.gy, t.gh, t.gc, t.dec, s);
-        if (e == hipSuccess) e = tr_head_act_bwd(P, M, t.gh, fd.head, t.dh, s);
+        if (e == hipSuccess) e = tr_head_act_bwd(P, M, ldh, t.gh, fd.head, t.dh, s);
         for (int l = 0; l < L && e == hipSuccess; ++l) {
             const long n_l = (long)ch[l] * (H >> l) * (W >> l);
             e = tr_fill(n_l, 0.f, t.ge[l], s);
@@ -1167,16 +1173,17 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
         // the gradient flowing into u_l (u_{L-1} is e_{L-1})
         auto gu_of = [&](int l) { return l == L - 1 ? t.ge[l] : t.gu[l]; };
         // head conv: input u_0, output 2M channels, no ReLU
-        if (e == hipSuccess) e = tr_wgrad(H, W, ch[0], 2 * M, t.dh, u_[0], t.part, gofs(head_k), bofs(head_k, ch[0], 2 * M), s);
-        if (e == hipSuccess) e = tr_dgrad(H, W, ch[0], 2 * M, t.dh, wofs(head_k), gu_of(0), s);
+        if (e == hipSuccess)
+            e = tr_wgrad(H, W, ch[0], 2 * M, ldh, t.dh, u_[0], t.part, gofs(head_k), bofs(head_k, ch[0], 2 * M), s);
+        if (e == hipSuccess) e = dgrad(t, H, W, ch[0], 2 * M, ldh, t.dh, wofs(head_k), gu_of(0));
         // decoders, finest first: dec_l is conv L + (L - 2 - l) in blob order
         for (int l = 0; l + 1 < L && e == hipSuccess; ++l) {
             const size_t k = (size_t)L + (L - 2 - l);
             const int Hl = H >> l, Wl = W >> l, Ci = ch[l + 1] + ch[l], Co = ch[l];
             e = tr_mask((long)Co * Hl * Wl, t.gu[l], u_[l], t.gm, s);
             if (e == hipSuccess) e = tr_cat(Hl, Wl, ch[l + 1], ch[l], u_[l + 1], e_[l], t.in, s);
-            if (e == hipSuccess) e = tr_wgrad(Hl, Wl, Ci, Co, t.gm, t.in, t.part, gofs(k), bofs(k, Ci, Co), s);
-            if (e == hipSuccess) e = dgrad(t, Hl, Wl, Ci, Co, t.gm, wofs(k), t.gin);
+            if (e == hipSuccess) e = tr_wgrad(Hl, Wl, Ci, Co, Co, t.gm, t.in, t.part, gofs(k), bofs(k, Ci, Co), s);
+            if (e == hipSuccess) e = dgrad(t, Hl, Wl, Ci, Co, Co, t.gm, wofs(k), t.gin);
             if (e == hipSuccess) e = tr_cat_bwd(Hl, Wl, ch[l + 1], ch[l], t.gin, gu_of(l + 1), t.ge[l], s);
         }
         // encoders, coarsest first: enc_l is conv l
@@ -1184,8 +1191,8 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
             const int Hl = H >> l, Wl = W >> l, Ci = ch[l - 1], Co = ch[l];
             e = tr_mask((long)Co * Hl * Wl, t.ge[l], e_[l], t.gm, s);
             if (e == hipSuccess) e = tr_pool(H >> (l - 1), W >> (l - 1), Ci, e_[l - 1], t.in, s);
-            if (e == hipSuccess) e = tr_wgrad(Hl, Wl, Ci, Co, t.gm, t.in, t.part, gofs(l), bofs(l, Ci, Co), s);
-            if (e == hipSuccess) e = dgrad(t, Hl, Wl, Ci, Co, t.gm, wofs(l), t.gin);
+            if (e == hipSuccess) e = tr_wgrad(Hl, Wl, Ci, Co, Co, t.gm, t.in, t.part, gofs(l), bofs(l, Ci, Co), s);
+            if (e == hipSuccess) e = dgrad(t, Hl, Wl, Ci, Co, Co, t.gm, wofs(l), t.gin);
             if (e == hipSuccess) e = tr_pool_bwd(H >> (l - 1), W >> (l - 1), Ci, t.gin, t.ge[l - 1], s);
         }
         // first encoder: the network input written out, weight gradient only
@@ -1193,7 +1200,7 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
         if (e == hipSuccess)
             e = tr_pack(P, fd.r, fd.a, fd.n, fd.d, 1.f / h->cfg.gamma, h->cfg.depth_near,
                         1.f / (h->cfg.depth_far - h->cfg.depth_near), t.X, s);
-        if (e == hipSuccess) e = tr_wgrad(H, W, 10, ch[0], t.gm, t.X, t.part, gofs(0), bofs(0, 10, ch[0]), s);
+        if (e == hipSuccess) e = tr_wgrad(H, W, 10, ch[0], ch[0], t.gm, t.X, t.part, gofs(0), bofs(0, 10, ch[0]), s);
     }
     if (e != hipSuccess) return hip_fail(e, "training launch", WSKP_E_LAUNCH);
     return WSKP_OK;

@@ -242,15 +242,17 @@ hipError_t tr_head_prep(long P, int M, const float *planar, const float *r, cons
 int tr_smape_blocks(long n);
 hipError_t tr_smape(long n, const float *y, const float *t, float eps, float inv_n, float *g, float *partial,
                     float *loss, int accumulate, hipStream_t s);
-hipError_t tr_head_act_bwd(long P, int M, const float *grad_head, const float *planar, float *dh, hipStream_t s);
+// dh[p][j] for j < 2M, zero for 2M <= j < ld (rows ld floats apart)
+hipError_t tr_head_act_bwd(long P, int M, int ld, const float *grad_head, const float *planar, float *dh,
+                           hipStream_t s);
 hipError_t tr_mask(long n, const float *g, const float *act, float *gm, hipStream_t s);
-hipError_t tr_dgrad(int H, int W, int Ci, int Co, const float *gm, const float *w, float *gin, hipStream_t s);
 // Weights of the input-gradient conv in the fp32 forward kernels' packing
-// ([Co/16][9][16][Cout_pad], 16-channel chunks): element (c, t, ci) is
+// ([Co_pad/16][9][16][Cout_pad], 16-channel chunks): element (c, t, ci) is
 // w[c][ci][8 - t], zero beyond Co or Ci.
-hipError_t tr_pack_dgrad(int Ci, int Co, int Cout_pad, const float *w, float *packed, hipStream_t s);
+hipError_t tr_pack_dgrad(int Ci, int Co, int Co_pad, int Cout_pad, const float *w, float *packed, hipStream_t s);
 size_t tr_wgrad_part_floats(long P, int Ci, int Co);
-hipError_t tr_wgrad(int H, int W, int Ci, int Co, const float *gm, const float *in, float *part, float *dw,
+// gm rows are ldg >= Co floats apart
+hipError_t tr_wgrad(int H, int W, int Ci, int Co, int ldg, const float *gm, const float *in, float *part, float *dw,
                     float *db, hipStream_t s);
 hipError_t tr_cat_bwd(int H, int W, int Cu, int Ce, const float *gcat, float *gu, float *ge, hipStream_t s);
 hipError_t tr_pool_bwd(int H, int W, int C, const float *gp, float *ge, hipStream_t s);
