@@ -166,18 +166,21 @@ __global__ __launch_bounds__(kTrThreads) void tr_mask_kernel(long n, const float
 // and partb[chunk][co]: a GEMM over
 // pixels, D[co][ci] += sum_p gm[p][co] * in[p + off(tap)][ci] for each tap,
 // with v_mfma_f32_16x16x4f32 taking 4 pixels per step (lane (g, j): pixel
-// g of the step; A = gm[p_g][co0 + j], B = in[p_g + off][ci0 + j]).  One
-// workgroup per (chunk of kWgChunk pixels, CB output blocks of 16, one input
-// block of 16); its kWgWaves waves take consecutive quarters of the chunk,
-// each loading the operands of its next step before the MFMAs of the current
-// one, and add their sums in LDS in a fixed order, (w0 + w2) + (w1 + w3).
-// Channels beyond Co or Ci (the network input's 10, the head's 2M) and
-// pixels outside the image read a clamped in-bounds address and enter as
-// zeros, so every load is unconditional; they are not stored.  The
-// workgroups of input block 0 also sum gm (B = 1) for the bias.  Lane (g, j)
-// ends with D[4g + r][j], r = 0..3.
+// g of the step; A = gm[p_g][co0 + j] (gm rows ldg floats apart),
+// B = in[p_g + off][ci0 + j]).  One workgroup per (chunk of kWgChunk
+// pixels, CB output blocks of 16, one input block of 16); its kWgWaves waves
+// take consecutive quarters of the chunk, each loading the operands of its
+// next step before the MFMAs of the current one, and add their sums in LDS
+// in a fixed order, (w0 + w2) + (w1 + w3).  Operands are raw buffer loads
+// over the chunk's window (its gm rows; its input rows and one image row
+// and pixel either side), 32-bit offsets from it: channels beyond Co or Ci
+// (the network input's 10, the head's 2M), taps outside the image and
+// pixels past the chunk take an offset beyond the window and read zeros,
+// so no load is conditional.  The workgroups of input block 0 also sum gm
+// (B = 1) for the bias.  Lane (g, j) ends with D[4g + r][j], r = 0..3.
 typedef float trf32x4 __attribute__((ext_vector_type(4)));
 constexpr int kWgChunk = 256, kWgWaves = 4;
+constexpr unsigned kWgOut = 0x80000000u;   // beyond every window (windows are < 2 GiB)
 template <int CB>
 __global__ __launch_bounds__(64 * kWgWaves) void tr_wgrad_mfma_kernel(int H, int W, int Ci, int Co, int ldg,
                                                                       const float *gm, const float *in, float *part,
@@ -187,50 +190,63 @@ __global__ __launch_bounds__(64 * kWgWaves) void tr_wgrad_mfma_kernel(int H, int
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
     const int co0 = blockIdx.y * (16 * CB), ci0 = blockIdx.z * 16;
     const long P = (long)H * W;
-    const long pa = (long)blockIdx.x * kWgChunk + wave * (kWgChunk / kWgWaves);
-    const long pb = min(P, pa + kWgChunk / kWgWaves);
+    const long c0 = (long)blockIdx.x * kWgChunk;
+    const int n = (int)min((long)kWgChunk, P - c0);
+    const long lo = max(0L, c0 - W - 1), hi = min(P, c0 + n + W + 1);
+    const rsrc_t rg = make_rsrc(gm + c0 * ldg, (unsigned)n * (unsigned)ldg * 4u);
+    const rsrc_t ri = make_rsrc(in + lo * Ci, (unsigned)(hi - lo) * (unsigned)Ci * 4u);
     const bool bias = blockIdx.z == 0;
-    // clamped channels: a lane past Co or Ci reads a valid channel, then zero
-    int cof[CB];
     bool cok[CB];
 #pragma unroll
-    for (int c = 0; c < CB; ++c) {
-        cok[c] = co0 + c * 16 + j < Co;
-        cof[c] = cok[c] ? co0 + c * 16 + j : Co - 1;
-    }
+    for (int c = 0; c < CB; ++c) cok[c] = co0 + c * 16 + j < Co;
     const bool ciok = ci0 + j < Ci;
-    const int cif = ciok ? ci0 + j : Ci - 1;
+    const int rel = (int)(c0 - lo);                 // the chunk's first pixel in the input window
+    const unsigned rowb = (unsigned)W * (unsigned)Ci * 4u, pixb = (unsigned)Ci * 4u;
     trf32x4 acc[CB][10];
 #pragma unroll
     for (int c = 0; c < CB; ++c)
 #pragma unroll
         for (int t = 0; t < 10; ++t) acc[c][t] = trf32x4{0.f, 0.f, 0.f, 0.f};
+    // this wave's pixels qa .. qb - 1 of the chunk
+    const int qa = wave * (kWgChunk / kWgWaves), qb = min(n, qa + kWgChunk / kWgWaves);
     float a[CB], b[9];
-    // operands of the step at q for this lane's pixel p = q + g at (y, x)
-    auto load = [&](long q, int y, int x, float (&av)[CB], float (&bv)[9]) {
-        const long p = q + g;
-        const bool valid = p < pb;
-        const long pc = valid ? p : 0;
+    // operands of the step at chunk pixel q, for this lane's pixel q + g at
+    // image position (y, x)
+    // (offsets are made out of range by setting bit 31, with no select, so
+    // that the compiler keeps every load unconditional)
+    auto out = [](bool ok) { return (0u - (unsigned)!ok) & kWgOut; };
+    auto load = [&](int q, int y, int x, float (&av)[CB], float (&bv)[9]) {
+        const int p = q + g;
+        const bool valid = p < qb;
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
-            const float v = gload(gm + pc * ldg + cof[c]);
-            av[c] = valid && cok[c] ? v : 0.f;
+            const unsigned off = ((unsigned)p * (unsigned)ldg + (unsigned)(co0 + c * 16 + j)) * 4u | out(valid & cok[c]);
+            av[c] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rg, off, 0, 0));
         }
+        const unsigned ctr = ((unsigned)(rel + p) * (unsigned)Ci + (unsigned)(ci0 + j)) * 4u;
+        const bool vc = valid & ciok;
+        const bool rok[3] = {y >= 1, true, y + 1 < H}, xok[3] = {x >= 1, true, x + 1 < W};
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
-            const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-            const bool ok = valid && ciok && yy >= 0 && yy < H && xx >= 0 && xx < W;
-            const float v = gload(in + (ok ? (long)yy * W + xx : 0) * Ci + cif);
-            bv[t] = ok ? v : 0.f;
+            const int dy = t / 3, dx = t % 3;
+            const unsigned off = (ctr + (unsigned)(dy - 1) * rowb + (unsigned)(dx - 1) * pixb) | out(vc & rok[dy] & xok[dx]);
+            bv[t] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ri, off, 0, 0));
         }
     };
-    int y = (int)((pa + g) / W), x = (int)((pa + g) - (long)y * W);
-    if (pa < pb) load(pa, y, x, a, b);
-    for (long q = pa; q < pb; q += 4) {
+    const long p0 = c0 + qa + g;
+    int y = (int)(p0 / W), x = (int)(p0 - (long)y * W);
+    load(qa, y, x, a, b);
+    for (int q = qa; q < qb; q += 4) {
         int yn = y, xn = x + 4;
-        while (xn >= W) {
-            xn -= W;
-            ++yn;
+        if (W >= 4) {
+            const bool wrap = xn >= W;
+            xn -= wrap ? W : 0;
+            yn += wrap ? 1 : 0;
+        } else {
+            while (xn >= W) {
+                xn -= W;
+                ++yn;
+            }
         }
         float an[CB], bn[9];
         load(q + 4, yn, xn, an, bn);
@@ -477,6 +493,8 @@ hipError_t tr_wgrad(int H, int W, int Ci, int Co, int ldg, const float *gm, cons
     const int nch = tr_wgrad_chunks(P);
     const long nw = (long)Co * Ci * 9;
     float *partb = part + (size_t)nch * nw;
+    // the kernel's buffer windows and offsets stay below 2 GiB
+    if ((double)(kWgChunk + 2.0 * W + 2.0) * std::max(Ci, ldg) * 4.0 >= 2147483648.0) return hipErrorInvalidValue;
     const unsigned cib = (unsigned)((Ci + 15) / 16), cob = (unsigned)((Co + 15) / 16);
     if (cob % 2 == 0)
         hipLaunchKernelGGL(tr_wgrad_mfma_kernel<2>, dim3((unsigned)nch, cob / 2, cib), dim3(64 * kWgWaves), 0, s, H, W,
