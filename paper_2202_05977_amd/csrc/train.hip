@@ -126,13 +126,20 @@ __global__ __launch_bounds__(kTrThreads) void tr_smape_kernel(long n, const floa
     if (threadIdx.x == 0) gstore(partial + blockIdx.x, red[0] * inv_n);
 }
 
-// loss[0] (+)= sum of partial[0..nb) in order (one thread: a fixed order)
-__global__ void tr_sum_kernel(int nb, const float *partial, float *loss, int accumulate)
+// loss[0] (+)= sum of partial[0..nb): thread i sums partial[i], [i + 256],
+// ... in order, then the 256 sums are added pairwise in LDS (a fixed order)
+__global__ __launch_bounds__(kTrThreads) void tr_sum_kernel(int nb, const float *partial, float *loss, int accumulate)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    float s = accumulate ? gload(loss) : 0.f;
-    for (int b = 0; b < nb; ++b) s += gload(partial + b);
-    gstore(loss, s);
+    __shared__ float red[kTrThreads];
+    float v = 0.f;
+    for (int b = threadIdx.x; b < nb; b += kTrThreads) v += gload(partial + b);
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = kTrThreads / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) gstore(loss, (accumulate ? gload(loss) : 0.f) + red[0]);
 }
 
 // gradient at the head conv's output: weight channels through softplus'
@@ -451,7 +458,7 @@ hipError_t tr_smape(long n, const float *y, const float *t, float eps, float inv
                     float *loss, int accumulate, hipStream_t s)
 {
     TR_LAUNCH(tr_smape_kernel, n, n, y, t, eps, inv_n, g, partial);
-    hipLaunchKernelGGL(tr_sum_kernel, dim3(1), dim3(64), 0, s, tr_blocks(n), partial, loss, accumulate);
+    hipLaunchKernelGGL(tr_sum_kernel, dim3(1), dim3(kTrThreads), 0, s, tr_blocks(n), partial, loss, accumulate);
     return hipGetLastError();
 }
 hipError_t tr_head_act_bwd(long P, int M, int ld, const float *grad_head, const float *planar, float *dh,

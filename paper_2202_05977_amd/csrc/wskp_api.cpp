@@ -967,7 +967,8 @@ extern "C" wskp_status_t wskp_backward(wskp_handle_t h, void *stream, int N, int
 // pass, sized for the largest frame of the batch.
 struct TrainScratch {
     float *X, *head, *c, *mod, *gy, *gh, *gc, *dh, *dec, *partial, *gm, *in, *gin, *part;
-    float *wpk, *zb;   // packed weights of one input-gradient conv; zero bias
+    float *wpk[2 * kMaxLevels];   // packed weights of each input-gradient conv (blob order)
+    float *zb;                    // zero bias
     float *ge[kMaxLevels], *gu[kMaxLevels];
     size_t bytes;
 };
@@ -1002,15 +1003,17 @@ static size_t train_plan(const wskp_ctx *h, int Hm, int Wm, char *base, TrainScr
     }
     mx_in = std::max(mx_in, (size_t)ch[0] * P);
     mx_part = std::max(mx_part, tr_wgrad_part_floats(P, ch[0], 2 * M));
-    // input-gradient convs on the matrix cores: C_out of the forward conv in,
-    // C_in out (encoders >= 1 and decoders)
-    size_t mx_wpk = 0;
-    for (int l = 1; l < L; ++l) mx_wpk = std::max(mx_wpk, (size_t)ch[l] * 9 * ((ch[l - 1] + 15) / 16 * 16));
-    for (int l = 0; l + 1 < L; ++l)
-        mx_wpk = std::max(mx_wpk, (size_t)ch[l] * 9 * ((ch[l + 1] + ch[l] + 15) / 16 * 16));
     const int ldh = head_grad_stride(M);
-    mx_wpk = std::max(mx_wpk, (size_t)ldh * 9 * ((ch[0] + 15) / 16 * 16));
+    // the input-gradient convs' packed weights (C_out of the forward conv
+    // in, C_in out: encoders >= 1, decoders, the head) and the zero bias
+    // come first, at offsets that do not depend on the frame size: they are
+    // written once per call and serve every frame
+    auto r16 = [](int c) { return (size_t)(c + 15) / 16 * 16; };
     TrainScratch t{};
+    for (int l = 1; l < L; ++l) t.wpk[l] = take((size_t)ch[l] * 9 * r16(ch[l - 1]));
+    for (int l = 0; l + 1 < L; ++l) t.wpk[L + (L - 2 - l)] = take((size_t)ch[l] * 9 * r16(ch[l + 1] + ch[l]));
+    t.wpk[2 * L - 1] = take((size_t)ldh * 9 * r16(ch[0]));
+    t.zb = take(256);
     t.X = take(10 * (size_t)P);
     t.head = take((size_t)2 * M * P);
     t.c = take(3 * (size_t)P);
@@ -1025,8 +1028,6 @@ static size_t train_plan(const wskp_ctx *h, int Hm, int Wm, char *base, TrainScr
     t.in = take(mx_in);
     t.gin = take(mx_in);
     t.part = take(mx_part);
-    t.wpk = take(std::max(mx_wpk, (size_t)1));
-    t.zb = take(256);
     for (int l = 0; l < L; ++l) {
         const size_t n = (size_t)ch[l] * (Hm >> l) * (Wm >> l);
         t.ge[l] = take(n);
@@ -1105,12 +1106,12 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
     auto gofs = [&](size_t k) { return grad + h->blob_off[k]; };
     auto bofs = [&](size_t k, int Ci, int Co) { return grad + h->blob_off[k] + (size_t)Ci * Co * 9; };
     hipError_t e = tr_fill((long)nw, 0.f, grad, s);
-    // input gradient of a conv (Ci -> Co forward): gin = conv(gm, w flipped,
+    // input gradient of conv k (Ci -> Co forward): gin = conv(gm, w flipped,
     // in and out channels swapped), on the matrix cores with the fp32
-    // forward kernel; gm has ldg >= Co channels (the head's 2M padded with
-    // zeros to a multiple of 16, the kernel's channel chunk; Ci, a network
-    // width, is one already)
-    auto dgrad = [&](const TrainScratch &t, int Hl, int Wl, int Ci, int Co, int ldg, const float *gm, const float *w,
+    // forward kernel on the weights packed for it; gm has ldg >= Co channels
+    // (the head's 2M padded with zeros to a multiple of 16, the kernel's
+    // channel chunk; Ci, a network width, is one already)
+    auto dgrad = [&](const TrainScratch &t, size_t k, int Hl, int Wl, int Ci, int ldg, const float *gm,
                      float *gin) -> hipError_t {
         ConvLayer c{};
         c.level = 0;
@@ -1133,10 +1134,8 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
         c.out_idx = 1;
         c.M = 0;
         c.in_qscale = 1.f;
-        c.w = t.wpk;
+        c.w = t.wpk[k];
         c.bias = t.zb;
-        hipError_t le = tr_pack_dgrad(Ci, Co, ldg, c.Cout_pad, w, t.wpk, s);
-        if (le != hipSuccess) return le;
         FrameArg fa{};
         fa.n = 1;
         fa.one.H = Hl;
@@ -1145,6 +1144,18 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
         fa.one.e[1] = gin;
         return launch_conv(c, CONV_PLAIN, EPI_LINEAR, WSKP_PREC_FP32, fa, conv_grid(c, 1, &Hl, &Wl), s);
     };
+    {
+        TrainScratch t;
+        train_plan(h, Hs[0], Ws[0], static_cast<char *>(ws) + align_up(fwd), &t);
+        if (e == hipSuccess) e = tr_fill(256, 0.f, t.zb, s);
+        if (e == hipSuccess) e = tr_pack_dgrad(ch[0], 2 * M, ldh, ch[0], wofs(head_k), t.wpk[head_k], s);
+        for (int l = 0; l + 1 < L && e == hipSuccess; ++l) {
+            const size_t k = (size_t)L + (L - 2 - l);
+            e = tr_pack_dgrad(ch[l + 1] + ch[l], ch[l], ch[l], ch[l + 1] + ch[l], wofs(k), t.wpk[k], s);
+        }
+        for (int l = 1; l < L && e == hipSuccess; ++l)
+            e = tr_pack_dgrad(ch[l - 1], ch[l], ch[l], ch[l - 1], wofs(l), t.wpk[l], s);
+    }
     char *fbase = static_cast<char *>(ws) + table_bytes(n);
     for (int f = 0; f < n && e == hipSuccess; ++f) {
         const int H = Hs[f], W = Ws[f];
@@ -1154,7 +1165,6 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
         fbase += frame_bytes(h, H, W, nullptr, nullptr, nullptr);
         TrainScratch t;
         train_plan(h, H, W, static_cast<char *>(ws) + align_up(fwd), &t);
-        if (e == hipSuccess) e = tr_fill(256, 0.f, t.zb, s);
         const float *e_[kMaxLevels], *u_[kMaxLevels];
         for (int l = 0; l < L; ++l) {
             e_[l] = static_cast<const float *>(fd.e[l]);
@@ -1175,7 +1185,7 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
         // head conv: input u_0, output 2M channels, no ReLU
         if (e == hipSuccess)
             e = tr_wgrad(H, W, ch[0], 2 * M, ldh, t.dh, u_[0], t.part, gofs(head_k), bofs(head_k, ch[0], 2 * M), s);
-        if (e == hipSuccess) e = dgrad(t, H, W, ch[0], 2 * M, ldh, t.dh, wofs(head_k), gu_of(0));
+        if (e == hipSuccess) e = dgrad(t, head_k, H, W, ch[0], ldh, t.dh, gu_of(0));
         // decoders, finest first: dec_l is conv L + (L - 2 - l) in blob order
         for (int l = 0; l + 1 < L && e == hipSuccess; ++l) {
             const size_t k = (size_t)L + (L - 2 - l);
@@ -1183,7 +1193,7 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
             e = tr_mask((long)Co * Hl * Wl, t.gu[l], u_[l], t.gm, s);
             if (e == hipSuccess) e = tr_cat(Hl, Wl, ch[l + 1], ch[l], u_[l + 1], e_[l], t.in, s);
             if (e == hipSuccess) e = tr_wgrad(Hl, Wl, Ci, Co, Co, t.gm, t.in, t.part, gofs(k), bofs(k, Ci, Co), s);
-            if (e == hipSuccess) e = dgrad(t, Hl, Wl, Ci, Co, Co, t.gm, wofs(k), t.gin);
+            if (e == hipSuccess) e = dgrad(t, k, Hl, Wl, Ci, Co, t.gm, t.gin);
             if (e == hipSuccess) e = tr_cat_bwd(Hl, Wl, ch[l + 1], ch[l], t.gin, gu_of(l + 1), t.ge[l], s);
         }
         // encoders, coarsest first: enc_l is conv l
@@ -1192,7 +1202,7 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
             e = tr_mask((long)Co * Hl * Wl, t.ge[l], e_[l], t.gm, s);
             if (e == hipSuccess) e = tr_pool(H >> (l - 1), W >> (l - 1), Ci, e_[l - 1], t.in, s);
             if (e == hipSuccess) e = tr_wgrad(Hl, Wl, Ci, Co, Co, t.gm, t.in, t.part, gofs(l), bofs(l, Ci, Co), s);
-            if (e == hipSuccess) e = dgrad(t, Hl, Wl, Ci, Co, Co, t.gm, wofs(l), t.gin);
+            if (e == hipSuccess) e = dgrad(t, (size_t)l, Hl, Wl, Ci, Co, t.gm, t.gin);
             if (e == hipSuccess) e = tr_pool_bwd(H >> (l - 1), W >> (l - 1), Ci, t.gin, t.ge[l - 1], s);
         }
         // first encoder: the network input written out, weight gradient only
