@@ -786,13 +786,21 @@ __device__ __forceinline__ void wait_vmem()
 // vertical taps dy (input row r+dy feeds output row r), so a 3x3 chunk costs
 // 6 (HW+2) A fragment reads instead of 18 HW: the LDS bytes per MFMA, which
 // bound this loop, fall with HW.
-// Workgroups per CU that the stage's LDS admits at TH = 8 (40, 49 and 59 KiB
-// for 2, 3 and 4 output blocks); the register budget is capped to match.
-// 5x5 layers (one output block, 52 KiB stage at TH = 8) fit three.
-constexpr int direct_min_wg(int NB, int KS) { return KS == 5 ? 3 : (NB <= 2 ? 4 : (NB == 3 ? 3 : 2)); }
+// Workgroups per CU that the stage's LDS (160 KiB per CU) admits, at most
+// four (at TH = 8: 40, 49 and 58 KiB for 2, 3 and 4 output blocks, so 4, 3
+// and 2; 5x5 layers with one output block, 52 KiB, 3); the register budget
+// is capped to match.
+constexpr int direct_stage_bytes(int NB, int KS, int TH)
+{
+    return ((TH + KS - 1) * (kConvTW + KS - 1) * 64 + NB * 16 * KS * KS * 64 + 1023) / 1024 * 1024;
+}
+constexpr int direct_min_wg(int NB, int KS, int TH)
+{
+    return 163840 / direct_stage_bytes(NB, KS, TH) < 4 ? 163840 / direct_stage_bytes(NB, KS, TH) : 4;
+}
 
 template <int MODE, int EPI, int TH, int NB, typename OutT, int KS = 3>
-__global__ __launch_bounds__(kThreads, direct_min_wg(NB, KS)) void conv3x3_bf16_direct(ConvLayer L, FrameArg fa)
+__global__ __launch_bounds__(kThreads, direct_min_wg(NB, KS, TH)) void conv3x3_bf16_direct(ConvLayer L, FrameArg fa)
 {
     constexpr int CK = 32, WP = kConvTW + KS - 1, HP = TH + KS - 1, NPIX = HP * WP;
     constexpr int A_SLOTS = NPIX * 4;
@@ -813,6 +821,7 @@ __global__ __launch_bounds__(kThreads, direct_min_wg(NB, KS)) void conv3x3_bf16_
     constexpr int INS = (SLOTS + 63) / 64;
     constexpr int PW = (INS + 3) / 4;                      // load instructions per wave
     constexpr int A_BYTES = A_SLOTS * 16, STAGE = INS * 1024;
+    static_assert(STAGE == direct_stage_bytes(NB, KS, TH), "stage size");
     constexpr int MB = TH / 2, NC = NB * 16, HW = TH / 4;
     static_assert(TH % 4 == 0, "each wave owns TH/4 whole rows");
     __shared__ __attribute__((aligned(1024))) unsigned char smem[STAGE];
