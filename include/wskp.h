@@ -243,7 +243,7 @@ wskp_status_t wskp_backward(wskp_handle_t h, void *stream, int N, int H, int W, 
                             float *grad_head, float *grad_c, void *ws, size_t ws_bytes);
 
 /* Bytes of device scratch wskp_backward needs for N frames of H x W
- * (16 * M bytes per pixel: per-centre adjoint terms of every kernel size). */
+ * (20 * M bytes per pixel: per-centre adjoint terms of every kernel size). */
 wskp_status_t wskp_backward_workspace_size(wskp_handle_t h, int N, int H, int W, size_t *bytes);
 
 /* Training (Eq. 1: the network's weights minimise a loss between its

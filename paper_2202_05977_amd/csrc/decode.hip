@@ -47,6 +47,7 @@ struct DecodeIO {
     const float *g;
     float *grad_head;
     float4 *scratch;
+    float *dlogit;
 };
 
 struct DecodeTensors {
@@ -57,6 +58,7 @@ struct DecodeTensors {
     const float *g;     // dL/dout [N,H,W,3]
     float *grad_head;   // [N,H,W,2M]
     float4 *scratch;    // [N,M,H,W] x (u_0, u_1, u_2, dS)
+    float *dlogit;      // [N,M,H,W]: the logits' gradients, pass A to pass B
 };
 
 // Tile u of nbk (u in launch order) -> frame, tile origin and I/O pointers.
@@ -88,6 +90,7 @@ __device__ __forceinline__ bool decode_locate_at(const DecodeCfg &dc, const Fram
         io.g = nullptr;
         io.grad_head = nullptr;
         io.scratch = nullptr;
+        io.dlogit = nullptr;
     } else {
         // equal-size frames: the frame index is a division
         const int cnt = tiles(dt.H, dt.W);
@@ -107,6 +110,7 @@ __device__ __forceinline__ bool decode_locate_at(const DecodeCfg &dc, const Fram
         io.g = dt.g ? dt.g + (size_t)f * P * 3 : nullptr;
         io.grad_head = dt.grad_head ? dt.grad_head + (size_t)f * P * twoM : nullptr;
         io.scratch = dt.scratch ? dt.scratch + (size_t)f * P * dc.M : nullptr;
+        io.dlogit = dt.dlogit ? dt.dlogit + (size_t)f * P * dc.M : nullptr;
     }
     const int txn = (io.W + kDTX - 1) / kDTX;
     x0 = (t % txn) * kDTX;
@@ -299,10 +303,12 @@ __device__ __forceinline__ void load_w(const DecodeIO &io, int i, const int *gp,
 //   DK_FRAMES / DK_TENSORS: forward, writes out.
 //   DK_ADJ_A: first half of the vector-Jacobian product.  Per centre p,
 //     with dF = g * mod, da_i = <dF, out_i>:
-//       dlogit_i   = alpha_i (da_i - sum_j alpha_j da_j)      -> grad_head[p][M+i]
+//       dlogit_i   = alpha_i (da_i - sum_j alpha_j da_j)
 //       u_i,ch(p)  = alpha_i dF_ch / max(S_i, eps)
 //       dS_i(p)    = -[S_i > eps] sum_ch u_i,ch(p) out_i,ch(p)
-//     (u_i, dS_i) go to scratch; decode_adj_b_kernel box-sums them.
+//     (u_i, dS_i) and dlogit_i go to scratch (planes per size, coalesced
+//     stores); decode_adj_b_kernel box-sums (u_i, dS_i) and writes each
+//     pixel's whole grad_head record.
 template <int M, int KIND, int RM>
 __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kernel(DecodeCfg dc, FrameArg fa,
                                                                DecodeTensors dt)
@@ -510,11 +516,10 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
                 da[i] = dF[0] * outv[o][i][0] + dF[1] * outv[o][i][1] + dF[2] * outv[o][i][2];
                 adot += alpha[o][i] * da[i];
             }
-            float *gh = io.grad_head + pix * (2 * M);
             const size_t P = (size_t)H * W;
 #pragma unroll
             for (int i = 0; i < M; ++i) {
-                gstore(gh + M + i, alpha[o][i] * (da[i] - adot));
+                gstore(io.dlogit + (size_t)i * P + pix, alpha[o][i] * (da[i] - adot));
                 const float S = Sv[o][i];
                 const float inv = 1.f / fmaxf(S, dc.eps_norm);
                 float4 v;
@@ -853,9 +858,21 @@ __global__ __launch_bounds__(kThreads) void decode_adj_b_kernel(DecodeCfg dc, De
     constexpr int kMaxPix = max_pix<RM>();
     int gp[kMaxPix];
     halo_pixels<RM>(x0, y0, R, HX, HXY, H, W, gp);
-    float dcv[kRun][3];
+    // the centres' irradiance and weights, read once; dW_i and dc summed
+    // over the sizes in registers
+    float cvv[kRun][3], wvv[kRun][M], dwv[kRun][M], dcv[kRun][3];
 #pragma unroll
-    for (int o = 0; o < kRun; ++o) dcv[o][0] = dcv[o][1] = dcv[o][2] = 0.f;
+    for (int o = 0; o < kRun; ++o) {
+        const int y = y0 + kRun * ty + o, x = x0 + tx;
+        const size_t pix = (y < H && x < W) ? (size_t)y * W + x : 0;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            cvv[o][ch] = gload(io.c + pix * 3 + ch);
+            dcv[o][ch] = 0.f;
+        }
+#pragma unroll
+        for (int i = 0; i < M; ++i) wvv[o][i] = gload(io.head + pix * (2 * M) + i);
+    }
 #pragma unroll
     for (int i = 0; i < M; ++i) {
         const float4 *sp = io.scratch + (size_t)i * P;
@@ -877,25 +894,30 @@ __global__ __launch_bounds__(kThreads) void decode_adj_b_kernel(DecodeCfg dc, De
 #undef WSKP_WS
 #pragma unroll
         for (int o = 0; o < kRun; ++o) {
-            const int y = y0 + kRun * ty + o, x = x0 + tx;
-            if (y < H && x < W) {
-                const size_t pix = (size_t)y * W + x;
-                const float *cp = io.c + pix * 3;
-                const float w = gload(io.head + pix * (2 * M) + i);
-                // acc = box sums of (u_0, u_1, u_2, dS)
-                gstore(io.grad_head + pix * (2 * M) + i,
-                       gload(cp) * acc[o].x + gload(cp + 1) * acc[o].y + gload(cp + 2) * acc[o].z + acc[o].w);
-                dcv[o][0] += w * acc[o].x;
-                dcv[o][1] += w * acc[o].y;
-                dcv[o][2] += w * acc[o].z;
-            }
+            // acc = box sums of (u_0, u_1, u_2, dS)
+            dwv[o][i] = cvv[o][0] * acc[o].x + cvv[o][1] * acc[o].y + cvv[o][2] * acc[o].z + acc[o].w;
+            dcv[o][0] += wvv[o][i] * acc[o].x;
+            dcv[o][1] += wvv[o][i] * acc[o].y;
+            dcv[o][2] += wvv[o][i] * acc[o].z;
         }
     }
+    // each centre's record [dW_0 .. dW_{M-1}, dlogit_0 .. dlogit_{M-1}] in
+    // consecutive stores, so that its lines are written whole (grad_head
+    // needs only the 4-byte alignment of a float)
 #pragma unroll
     for (int o = 0; o < kRun; ++o) {
         const int y = y0 + kRun * ty + o, x = x0 + tx;
         if (y < H && x < W) {
             const size_t pix = (size_t)y * W + x;
+            float rec[2 * M];
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                rec[i] = dwv[o][i];
+                rec[M + i] = gload(io.dlogit + (size_t)i * P + pix);
+            }
+            float *gh = io.grad_head + pix * (2 * M);
+#pragma unroll
+            for (int j = 0; j < 2 * M; ++j) gstore(gh + j, rec[j]);
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) gstore(gc + pix * 3 + ch, dcv[o][ch]);
         }
@@ -1013,7 +1035,7 @@ hipError_t launch_decode_tensors(const DecodeCfg &dc, int N, int H, int W, const
 {
     // the 32 x 16-tile kernel: on equal-size stacks it measured faster than
     // the 40 x 45 tile kernel (29 vs 35 us for 8 x 256^2, 42 vs 45 us at 720p)
-    DecodeTensors dt{N, H, W, head, c, mod, out, nullptr, nullptr, nullptr};
+    DecodeTensors dt{N, H, W, head, c, mod, out, nullptr, nullptr, nullptr, nullptr};
     FrameArg fa{};
     const int blocks = N * ((W + kDTX - 1) / kDTX) * ((H + kDTY - 1) / kDTY);
     return launch_decode<DK_TENSORS>(dc, fa, dt, blocks, s);
@@ -1021,7 +1043,8 @@ hipError_t launch_decode_tensors(const DecodeCfg &dc, int N, int H, int W, const
 
 size_t decode_backward_scratch_bytes(const DecodeCfg &dc, int N, int H, int W)
 {
-    return (size_t)N * dc.M * H * W * sizeof(float4);
+    // (u_i, dS_i) as float4 and dlogit_i as float, per size and pixel
+    return (size_t)N * dc.M * H * W * (sizeof(float4) + sizeof(float));
 }
 
 hipError_t launch_decode_backward(const DecodeCfg &dc, int N, int H, int W, const float *head,
@@ -1029,8 +1052,9 @@ hipError_t launch_decode_backward(const DecodeCfg &dc, int N, int H, int W, cons
                                   float *grad_head, float *grad_c, void *scratch, hipStream_t s)
 {
     FrameArg fa{};
-    DecodeTensors dt{N, H, W, head, c, mod, nullptr, g, grad_head,
-                     reinterpret_cast<float4 *>(scratch)};
+    float4 *s4 = reinterpret_cast<float4 *>(scratch);
+    DecodeTensors dt{N, H, W, head, c, mod, nullptr, g, grad_head, s4,
+                     reinterpret_cast<float *>(s4 + (size_t)N * dc.M * H * W)};
     const int blocks = N * ((W + kDTX - 1) / kDTX) * ((H + kDTY - 1) / kDTY);
     hipError_t e = launch_decode<DK_ADJ_A>(dc, fa, dt, blocks, s);
     if (e != hipSuccess) return e;
