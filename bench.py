@@ -286,20 +286,25 @@ def mode_train(args):
         step()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    # kernel-only times with events on the launch stream
+    # kernel times with events on the launch stream: 20 calls of each queued
+    # back to back between two events (one call between events would also
+    # time its own launch from the host), median over 5 such rounds
     s = torch.cuda.current_stream()
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     g = torch.sign(out - t) / out.numel()
     fw, bw = [], []
-    for _ in range(20):
-        e[0].record(s)
+    for _ in range(5):
         wskp.wskp_decode(dn.h, head, c, mod, out)
+        e[0].record(s)
+        for _ in range(20):
+            wskp.wskp_decode(dn.h, head, c, mod, out)
         e[1].record(s)
-        wskp.wskp_backward(dn.h, head, c, mod, g, gh, gc, ws)
+        for _ in range(20):
+            wskp.wskp_backward(dn.h, head, c, mod, g, gh, gc, ws)
         e[2].record(s)
         e[2].synchronize()
-        fw.append(e[0].elapsed_time(e[1]))
-        bw.append(e[1].elapsed_time(e[2]))
+        fw.append(e[0].elapsed_time(e[1]) / 20)
+        bw.append(e[1].elapsed_time(e[2]) / 20)
     px = N * H * W
     fwd_us, bwd_us = 1e3 * float(np.median(fw)), 1e3 * float(np.median(bw))
     # adjoint against the oracle VJP on crop 0 with the same cotangent
