@@ -524,16 +524,20 @@ def mode_kernels(args):
     wskp.wskp_kp_expand(dn.h, head, maps)
     s = torch.cuda.current_stream()
 
-    def timed(fn, reps=20):
+    def timed(fn, rounds=5, calls=10):
+        """us per call: `calls` calls queued back to back between two events
+        (one call between events would also time its launch from the host),
+        median over `rounds`."""
         ts = []
         fn()
-        for _ in range(reps):
+        for _ in range(rounds):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(s)
-            fn()
+            for _ in range(calls):
+                fn()
             e1.record(s)
             e1.synchronize()
-            ts.append(e0.elapsed_time(e1) * 1e3)
+            ts.append(e0.elapsed_time(e1) * 1e3 / calls)
         return float(np.median(ts))
 
     t_ws = timed(lambda: wskp.wskp_decode(dn.h, head, c, mod, y_ws))

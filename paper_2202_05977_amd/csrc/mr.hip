@@ -28,7 +28,9 @@ __global__ __launch_bounds__(kMrThreads) void pool2_kernel(int H, int W, const f
 
 // One thread per 2x2 block of fine pixels: the block's mean of the fine
 // image is formed once and serves its four outputs.  mod (optional)
-// remodulates the result.
+// remodulates the result.  The four outputs are stored after all loads,
+// each pixel's three channels in consecutive stores, so that the L2
+// receives whole lines rather than parts of them spread over the kernel.
 __global__ __launch_bounds__(kMrThreads) void mr_blend_kernel(int H, int W, const float *fine, const float *coarse,
                                                                const float *alpha, const float *mod, float *out)
 {
@@ -41,21 +43,32 @@ __global__ __launch_bounds__(kMrThreads) void mr_blend_kernel(int H, int W, cons
     q[1] = q[0] + 1;
     q[2] = q[0] + W;
     q[3] = q[2] + 1;
+    float f[4][3], a[4], c[3];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        a[k] = gload(alpha + q[k]);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) f[k][ch] = gload(fine + q[k] * 3 + ch);
+    }
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) c[ch] = gload(coarse + (size_t)p * 3 + ch);
+    float o[4][3];
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-        float f[4];
+        const float df = 0.25f * (((f[0][ch] + f[1][ch]) + f[2][ch]) + f[3][ch]);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) f[k] = gload(fine + q[k] * 3 + ch);
-        const float df = 0.25f * (((f[0] + f[1]) + f[2]) + f[3]);
-        const float c = gload(coarse + (size_t)p * 3 + ch);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const float a = gload(alpha + q[k]);
-            float o = f[k] - a * df + a * c;
-            if (mod) o *= gload(mod + q[k] * 3 + ch);
-            gstore(out + q[k] * 3 + ch, o);
-        }
+        for (int k = 0; k < 4; ++k) o[k][ch] = f[k][ch] - a[k] * df + a[k] * c[ch];
     }
+    if (mod) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) o[k][ch] *= gload(mod + q[k] * 3 + ch);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) gstore(out + q[k] * 3 + ch, o[k][ch]);
 }
 
 hipError_t launch_pool2(int H, int W, const float *in, float *out, hipStream_t s)
