@@ -6,10 +6,13 @@
 // layer's output).  The backward pass, per frame:
 //   SMAPE gradient at the output -> adjoint of decode and fusion (decode.hip)
 //   -> derivative of the weight activation -> for each conv, from the head
-//   back to the first encoder: the ReLU mask of its output, the weight and
-//   bias gradient (accumulated over the frames of the batch) and the input
-//   gradient, which the adjoints of the nearest x2 upsampling, the channel
-//   concatenation and the 2x2 mean distribute to the layers that fed it.
+//   back to the first encoder: the weight and bias gradient (accumulated
+//   over the frames of the batch) and the input gradient, which the adjoints
+//   of the nearest x2 upsampling, the channel concatenation and the 2x2 mean
+//   distribute to the layers that fed it.  The adjoint that writes the last
+//   contribution to an activation's gradient also applies that activation's
+//   ReLU mask, and the first contribution overwrites, so no gradient buffer
+//   is cleared and no separate mask pass runs (except the head's input).
 // A layer's input (the network input, a 2x2 mean, an [upsampled, skip]
 // concatenation) is written out once for its two gradient kernels.
 //
@@ -338,10 +341,12 @@ __global__ __launch_bounds__(kTrThreads) void tr_wgrad_reduce_kernel(long nw, in
     }
 }
 
-// grad of the upsampled part of a concatenation: gu[y][x][c] += sum of
-// gcat[2y+i][2x+j][c] (c < Cu); of the skip part: ge[p][c] += gcat[p][Cu+c]
+// adjoint of [upsample(u), e]: the upsampled part's gradient, the sum of
+// gcat[2y+i][2x+j][c] (c < Cu), masked by u's ReLU (its only contribution)
+// into gu[y][x][c]; the skip part's, gcat[p][Cu+c], into ge[p][c] (its first
+// contribution: both overwrite)
 __global__ __launch_bounds__(kTrThreads) void tr_cat_bwd_kernel(int H, int W, int Cu, int Ce, const float *gcat,
-                                                                 float *gu, float *ge)
+                                                                 const float *act_u, float *gu, float *ge)
 {
     const int C = Cu + Ce;
     const int Hc = H / 2, Wc = W / 2;
@@ -352,17 +357,21 @@ __global__ __launch_bounds__(kTrThreads) void tr_cat_bwd_kernel(int H, int W, in
         const long q = i / Cu;
         const int y = (int)(q / Wc), x = (int)(q % Wc);
         const float *s = gcat + ((long)(2 * y) * W + 2 * x) * C + c;
-        gstore(gu + i, gload(gu + i) + (((gload(s) + gload(s + C)) + gload(s + (long)W * C)) + gload(s + (long)W * C + C)));
+        const float v = ((gload(s) + gload(s + C)) + gload(s + (long)W * C)) + gload(s + (long)W * C + C);
+        gstore(gu + i, gload(act_u + i) > 0.f ? v : 0.f);
     } else if (i < nu + ne) {
         const long j = i - nu;
         const int c = (int)(j % Ce);
         const long p = j / Ce;
-        gstore(ge + j, gload(ge + j) + gload(gcat + p * C + Cu + c));
+        gstore(ge + j, gload(gcat + p * C + Cu + c));
     }
 }
 
-// grad of a 2x2 mean: ge[y][x][c] += gp[y/2][x/2][c] / 4
-__global__ __launch_bounds__(kTrThreads) void tr_pool_bwd_kernel(int H, int W, int C, const float *gp, float *ge)
+// ge[p][c] = (act[p][c] > 0) (ge[p][c] + gp[p/2][c] / 4): the 2x2 mean's
+// adjoint added to what the concatenation's adjoint wrote, then the ReLU mask
+// of e (its last contribution)
+__global__ __launch_bounds__(kTrThreads) void tr_pool_bwd_kernel(int H, int W, int C, const float *gp,
+                                                                  const float *act, float *ge)
 {
     const long n = (long)H * W * C;
     const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
@@ -370,7 +379,8 @@ __global__ __launch_bounds__(kTrThreads) void tr_pool_bwd_kernel(int H, int W, i
     const int c = (int)(i % C);
     const long p = i / C;
     const int y = (int)(p / W), x = (int)(p % W);
-    gstore(ge + i, gload(ge + i) + 0.25f * gload(gp + ((long)(y / 2) * (W / 2) + x / 2) * C + c));
+    const float v = gload(ge + i) + 0.25f * gload(gp + ((long)(y / 2) * (W / 2) + x / 2) * C + c);
+    gstore(ge + i, gload(act + i) > 0.f ? v : 0.f);
 }
 
 __global__ __launch_bounds__(kTrThreads) void tr_add_kernel(long n, const float *a, float *b)
@@ -513,14 +523,15 @@ hipError_t tr_wgrad(int H, int W, int Ci, int Co, int ldg, const float *gm, cons
                        nch, part, partb, dw, db);
     return hipGetLastError();
 }
-hipError_t tr_cat_bwd(int H, int W, int Cu, int Ce, const float *gcat, float *gu, float *ge, hipStream_t s)
+hipError_t tr_cat_bwd(int H, int W, int Cu, int Ce, const float *gcat, const float *act_u, float *gu, float *ge,
+                      hipStream_t s)
 {
-    TR_LAUNCH(tr_cat_bwd_kernel, (long)(H / 2) * (W / 2) * Cu + (long)H * W * Ce, H, W, Cu, Ce, gcat, gu, ge);
+    TR_LAUNCH(tr_cat_bwd_kernel, (long)(H / 2) * (W / 2) * Cu + (long)H * W * Ce, H, W, Cu, Ce, gcat, act_u, gu, ge);
     return hipGetLastError();
 }
-hipError_t tr_pool_bwd(int H, int W, int C, const float *gp, float *ge, hipStream_t s)
+hipError_t tr_pool_bwd(int H, int W, int C, const float *gp, const float *act, float *ge, hipStream_t s)
 {
-    TR_LAUNCH(tr_pool_bwd_kernel, (long)H * W * C, H, W, C, gp, ge);
+    TR_LAUNCH(tr_pool_bwd_kernel, (long)H * W * C, H, W, C, gp, act, ge);
     return hipGetLastError();
 }
 hipError_t tr_add(long n, const float *a, float *b, hipStream_t s)

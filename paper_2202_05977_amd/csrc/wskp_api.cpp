@@ -966,7 +966,7 @@ extern "C" wskp_status_t wskp_backward(wskp_handle_t h, void *stream, int N, int
 // Training (fp32 handles with softplus weights): scratch of the backward
 // pass, sized for the largest frame of the batch.
 struct TrainScratch {
-    float *X, *head, *c, *mod, *gy, *gh, *gc, *dh, *dec, *partial, *gm, *in, *gin, *part;
+    float *X, *head, *c, *mod, *gy, *gh, *gc, *dh, *dec, *partial, *in, *gin, *part;
     float *wpk[2 * kMaxLevels];   // packed weights of each input-gradient conv (blob order)
     float *zb;                    // zero bias
     float *ge[kMaxLevels], *gu[kMaxLevels];
@@ -988,10 +988,9 @@ static size_t train_plan(const wskp_ctx *h, int Hm, int Wm, char *base, TrainScr
         o += align_up(floats * sizeof(float));
         return p;
     };
-    size_t mx_gm = (size_t)2 * M * P, mx_in = 10 * (size_t)P, mx_part = tr_wgrad_part_floats(P, 10, ch[0]);
+    size_t mx_in = 10 * (size_t)P, mx_part = tr_wgrad_part_floats(P, 10, ch[0]);
     for (int l = 0; l < L; ++l) {
         const long Pl = (long)(Hm >> l) * (Wm >> l);
-        mx_gm = std::max(mx_gm, (size_t)ch[l] * Pl);
         if (l > 0) {
             mx_in = std::max(mx_in, (size_t)ch[l - 1] * Pl);
             mx_part = std::max(mx_part, tr_wgrad_part_floats(Pl, ch[l - 1], ch[l]));
@@ -1024,7 +1023,6 @@ static size_t train_plan(const wskp_ctx *h, int Hm, int Wm, char *base, TrainScr
     t.dh = take((size_t)ldh * P);
     t.dec = take(decode_backward_scratch_bytes(h->dc, 1, Hm, Wm) / sizeof(float));
     t.partial = take((size_t)tr_smape_blocks(3 * P));
-    t.gm = take(mx_gm);
     t.in = take(mx_in);
     t.gin = take(mx_in);
     t.part = take(mx_part);
@@ -1175,42 +1173,47 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
         if (e == hipSuccess) e = tr_smape(3 * P, fd.out, targets[f], eps_smape, inv_n, t.gy, t.partial, loss, f > 0, s);
         if (e == hipSuccess) e = launch_decode_backward(h->dc, 1, H, W, t.head, t.c, t.mod, t.gy, t.gh, t.gc, t.dec, s);
         if (e == hipSuccess) e = tr_head_act_bwd(P, M, ldh, t.gh, fd.head, t.dh, s);
-        for (int l = 0; l < L && e == hipSuccess; ++l) {
-            const long n_l = (long)ch[l] * (H >> l) * (W >> l);
-            e = tr_fill(n_l, 0.f, t.ge[l], s);
-            if (e == hipSuccess && t.gu[l]) e = tr_fill(n_l, 0.f, t.gu[l], s);
-        }
-        // the gradient flowing into u_l (u_{L-1} is e_{L-1})
+        // Gradients of the activations, kept as gradients of their
+        // pre-activations (the ReLU mask applied by the kernel that writes
+        // the last contribution): gu[l] of u_l (l < L - 1; u_{L-1} is e_{L-1},
+        // whose gradient is ge[L-1]), ge[l] of e_l.  Every buffer's first
+        // contribution overwrites it, so none is cleared.
         auto gu_of = [&](int l) { return l == L - 1 ? t.ge[l] : t.gu[l]; };
-        // head conv: input u_0, output 2M channels, no ReLU
+        auto act_of = [&](int l) { return l == L - 1 ? e_[L - 1] : u_[l]; };
+        // head conv: input u_0, output 2M channels, no ReLU; u_0's gradient
+        // has one contribution, masked in place
         if (e == hipSuccess)
             e = tr_wgrad(H, W, ch[0], 2 * M, ldh, t.dh, u_[0], t.part, gofs(head_k), bofs(head_k, ch[0], 2 * M), s);
         if (e == hipSuccess) e = dgrad(t, head_k, H, W, ch[0], ldh, t.dh, gu_of(0));
-        // decoders, finest first: dec_l is conv L + (L - 2 - l) in blob order
+        if (e == hipSuccess) e = tr_mask((long)ch[0] * P, gu_of(0), act_of(0), gu_of(0), s);
+        // decoders, finest first: dec_l is conv L + (L - 2 - l) in blob order;
+        // the concatenation's adjoint writes u_{l+1}'s gradient (masked, its
+        // only contribution) and the first part of e_l's
         for (int l = 0; l + 1 < L && e == hipSuccess; ++l) {
             const size_t k = (size_t)L + (L - 2 - l);
             const int Hl = H >> l, Wl = W >> l, Ci = ch[l + 1] + ch[l], Co = ch[l];
-            e = tr_mask((long)Co * Hl * Wl, t.gu[l], u_[l], t.gm, s);
-            if (e == hipSuccess) e = tr_cat(Hl, Wl, ch[l + 1], ch[l], u_[l + 1], e_[l], t.in, s);
-            if (e == hipSuccess) e = tr_wgrad(Hl, Wl, Ci, Co, Co, t.gm, t.in, t.part, gofs(k), bofs(k, Ci, Co), s);
-            if (e == hipSuccess) e = dgrad(t, k, Hl, Wl, Ci, Co, t.gm, t.gin);
-            if (e == hipSuccess) e = tr_cat_bwd(Hl, Wl, ch[l + 1], ch[l], t.gin, gu_of(l + 1), t.ge[l], s);
+            const float *gm = t.gu[l];
+            e = tr_cat(Hl, Wl, ch[l + 1], ch[l], u_[l + 1], e_[l], t.in, s);
+            if (e == hipSuccess) e = tr_wgrad(Hl, Wl, Ci, Co, Co, gm, t.in, t.part, gofs(k), bofs(k, Ci, Co), s);
+            if (e == hipSuccess) e = dgrad(t, k, Hl, Wl, Ci, Co, gm, t.gin);
+            if (e == hipSuccess)
+                e = tr_cat_bwd(Hl, Wl, ch[l + 1], ch[l], t.gin, act_of(l + 1), gu_of(l + 1), t.ge[l], s);
         }
-        // encoders, coarsest first: enc_l is conv l
+        // encoders, coarsest first: enc_l is conv l; the 2x2 mean's adjoint
+        // adds the last part of e_{l-1}'s gradient and masks it
         for (int l = L - 1; l >= 1 && e == hipSuccess; --l) {
             const int Hl = H >> l, Wl = W >> l, Ci = ch[l - 1], Co = ch[l];
-            e = tr_mask((long)Co * Hl * Wl, t.ge[l], e_[l], t.gm, s);
-            if (e == hipSuccess) e = tr_pool(H >> (l - 1), W >> (l - 1), Ci, e_[l - 1], t.in, s);
-            if (e == hipSuccess) e = tr_wgrad(Hl, Wl, Ci, Co, Co, t.gm, t.in, t.part, gofs(l), bofs(l, Ci, Co), s);
-            if (e == hipSuccess) e = dgrad(t, (size_t)l, Hl, Wl, Ci, Co, t.gm, t.gin);
-            if (e == hipSuccess) e = tr_pool_bwd(H >> (l - 1), W >> (l - 1), Ci, t.gin, t.ge[l - 1], s);
+            const float *gm = t.ge[l];
+            e = tr_pool(H >> (l - 1), W >> (l - 1), Ci, e_[l - 1], t.in, s);
+            if (e == hipSuccess) e = tr_wgrad(Hl, Wl, Ci, Co, Co, gm, t.in, t.part, gofs(l), bofs(l, Ci, Co), s);
+            if (e == hipSuccess) e = dgrad(t, (size_t)l, Hl, Wl, Ci, Co, gm, t.gin);
+            if (e == hipSuccess) e = tr_pool_bwd(H >> (l - 1), W >> (l - 1), Ci, t.gin, e_[l - 1], t.ge[l - 1], s);
         }
         // first encoder: the network input written out, weight gradient only
-        if (e == hipSuccess) e = tr_mask((long)ch[0] * P, t.ge[0], e_[0], t.gm, s);
         if (e == hipSuccess)
             e = tr_pack(P, fd.r, fd.a, fd.n, fd.d, 1.f / h->cfg.gamma, h->cfg.depth_near,
                         1.f / (h->cfg.depth_far - h->cfg.depth_near), t.X, s);
-        if (e == hipSuccess) e = tr_wgrad(H, W, 10, ch[0], ch[0], t.gm, t.X, t.part, gofs(0), bofs(0, 10, ch[0]), s);
+        if (e == hipSuccess) e = tr_wgrad(H, W, 10, ch[0], ch[0], t.ge[0], t.X, t.part, gofs(0), bofs(0, 10, ch[0]), s);
     }
     if (e != hipSuccess) return hip_fail(e, "training launch", WSKP_E_LAUNCH);
     return WSKP_OK;

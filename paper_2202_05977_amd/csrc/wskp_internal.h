@@ -254,8 +254,11 @@ size_t tr_wgrad_part_floats(long P, int Ci, int Co);
 // gm rows are ldg >= Co floats apart
 hipError_t tr_wgrad(int H, int W, int Ci, int Co, int ldg, const float *gm, const float *in, float *part, float *dw,
                     float *db, hipStream_t s);
-hipError_t tr_cat_bwd(int H, int W, int Cu, int Ce, const float *gcat, float *gu, float *ge, hipStream_t s);
-hipError_t tr_pool_bwd(int H, int W, int C, const float *gp, float *ge, hipStream_t s);
+// gu = (act_u > 0) * (the upsampled part's gradient); ge = the skip part's
+hipError_t tr_cat_bwd(int H, int W, int Cu, int Ce, const float *gcat, const float *act_u, float *gu, float *ge,
+                      hipStream_t s);
+// ge = (act > 0) * (ge + the 2x2 mean's adjoint of gp)
+hipError_t tr_pool_bwd(int H, int W, int C, const float *gp, const float *act, float *ge, hipStream_t s);
 hipError_t tr_add(long n, const float *a, float *b, hipStream_t s);
 hipError_t tr_fill(long n, float v, float *b, hipStream_t s);
 hipError_t tr_adam(long n, float *w, const float *g, float *m, float *v, float lr, float b1, float b2, float c1,
