@@ -58,32 +58,40 @@ __global__ __launch_bounds__(kTrThreads) void tr_pack_kernel(long P, const float
     for (int ch = 0; ch < 10; ++ch) gstore(X + p * 10 + ch, x[ch]);
 }
 
-// out [H/2][W/2][C] = 2x2 means of in [H][W][C]
-__global__ __launch_bounds__(kTrThreads) void tr_pool_kernel(int H, int W, int C, const float *in, float *out)
+// Kernels over nf frames of one size: frame f's operand X sits at X + f sX
+// (floats); outputs are contiguous per frame.
+
+// out [nf][H/2][W/2][C] = 2x2 means of in [H][W][C] (frame stride sin)
+__global__ __launch_bounds__(kTrThreads) void tr_pool_kernel(int H, int W, int C, int nf, const float *in, long sin,
+                                                              float *out)
 {
     const int Wo = W / 2;
     const long n = (long)(H / 2) * Wo * C;
     const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
-    if (i >= n) return;
-    const int ch = (int)(i % C);
-    const long q = i / C;
+    if (i >= n * nf) return;
+    const long f = i / n, j = i - f * n;
+    const int ch = (int)(j % C);
+    const long q = j / C;
     const int y = (int)(q / Wo), x = (int)(q % Wo);
-    const float *s = in + ((long)(2 * y) * W + 2 * x) * C + ch;
+    const float *s = in + f * sin + ((long)(2 * y) * W + 2 * x) * C + ch;
     gstore(out + i, 0.25f * (((gload(s) + gload(s + C)) + gload(s + (long)W * C)) + gload(s + (long)W * C + C)));
 }
 
-// out [H][W][Cu + Ce] = [nearest x2 upsample of u [H/2][W/2][Cu], e [H][W][Ce]]
-__global__ __launch_bounds__(kTrThreads) void tr_cat_kernel(int H, int W, int Cu, int Ce, const float *u,
-                                                             const float *e, float *out)
+// out [nf][H][W][Cu + Ce] = [nearest x2 upsample of u [H/2][W/2][Cu],
+// e [H][W][Ce]] (frame strides su, se)
+__global__ __launch_bounds__(kTrThreads) void tr_cat_kernel(int H, int W, int Cu, int Ce, int nf, const float *u,
+                                                             long su, const float *e, long se, float *out)
 {
     const int C = Cu + Ce;
     const long n = (long)H * W * C;
     const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
-    if (i >= n) return;
-    const int ch = (int)(i % C);
-    const long p = i / C;
+    if (i >= n * nf) return;
+    const long f = i / n, j = i - f * n;
+    const int ch = (int)(j % C);
+    const long p = j / C;
     const int y = (int)(p / W), x = (int)(p % W);
-    const float v = ch < Cu ? gload(u + ((long)(y / 2) * (W / 2) + x / 2) * Cu + ch) : gload(e + p * Ce + (ch - Cu));
+    const float v = ch < Cu ? gload(u + f * su + ((long)(y / 2) * (W / 2) + x / 2) * Cu + ch)
+                            : gload(e + f * se + p * Ce + (ch - Cu));
     gstore(out + i, v);
 }
 
@@ -163,13 +171,16 @@ __global__ __launch_bounds__(kTrThreads) void tr_head_act_bwd_kernel(long P, int
     gstore(dh + i, g);
 }
 
-// gm = g * (act > 0) (the ReLU's derivative; act == nullptr: none)
-__global__ __launch_bounds__(kTrThreads) void tr_mask_kernel(long n, const float *g, const float *act, float *gm)
+// gm = g * (act > 0) (the ReLU's derivative) over nf frames of n values
+// (g and gm contiguous, act frame stride sa)
+__global__ __launch_bounds__(kTrThreads) void tr_mask_kernel(long n, int nf, const float *g, const float *act, long sa,
+                                                              float *gm)
 {
     const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n * nf) return;
+    const long f = i / n, j = i - f * n;
     const float v = gload(g + i);
-    gstore(gm + i, act ? (gload(act + i) > 0.f ? v : 0.f) : v);
+    gstore(gm + i, gload(act + f * sa + j) > 0.f ? v : 0.f);
 }
 
 // Partial weight gradients on the matrix cores, part[chunk][co][ci][tap]
@@ -193,14 +204,19 @@ constexpr int kWgChunk = 256, kWgWaves = 4;
 constexpr unsigned kWgOut = 0x80000000u;   // beyond every window (windows are < 2 GiB)
 template <int CB>
 __global__ __launch_bounds__(64 * kWgWaves) void tr_wgrad_mfma_kernel(int H, int W, int Ci, int Co, int ldg,
-                                                                      const float *gm, const float *in, float *part,
+                                                                      int nch, const float *gm, long sgm,
+                                                                      const float *in, long sin, float *part,
                                                                       float *partb)
 {
     __shared__ trf32x4 red[2][CB * 10][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
     const int co0 = blockIdx.y * (16 * CB), ci0 = blockIdx.z * 16;
     const long P = (long)H * W;
-    const long c0 = (long)blockIdx.x * kWgChunk;
+    // workgroup x: frame f, chunk x - f nch of that frame; partial sum x
+    const int fr = blockIdx.x / nch;
+    gm += fr * sgm;
+    in += fr * sin;
+    const long c0 = (long)(blockIdx.x - fr * nch) * kWgChunk;
     const int n = (int)min((long)kWgChunk, P - c0);
     const long lo = max(0L, c0 - W - 1), hi = min(P, c0 + n + W + 1);
     const rsrc_t rg = make_rsrc(gm + c0 * ldg, (unsigned)n * (unsigned)ldg * 4u);
@@ -345,42 +361,63 @@ __global__ __launch_bounds__(kTrThreads) void tr_wgrad_reduce_kernel(long nw, in
 // gcat[2y+i][2x+j][c] (c < Cu), masked by u's ReLU (its only contribution)
 // into gu[y][x][c]; the skip part's, gcat[p][Cu+c], into ge[p][c] (its first
 // contribution: both overwrite)
-__global__ __launch_bounds__(kTrThreads) void tr_cat_bwd_kernel(int H, int W, int Cu, int Ce, const float *gcat,
-                                                                 const float *act_u, float *gu, float *ge)
+__global__ __launch_bounds__(kTrThreads) void tr_cat_bwd_kernel(int H, int W, int Cu, int Ce, int nf,
+                                                                 const float *gcat, const float *act_u, long sa,
+                                                                 float *gu, float *ge)
 {
     const int C = Cu + Ce;
     const int Hc = H / 2, Wc = W / 2;
     const long nu = (long)Hc * Wc * Cu, ne = (long)H * W * Ce;
     const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
-    if (i < nu) {
-        const int c = (int)(i % Cu);
-        const long q = i / Cu;
+    if (i >= (nu + ne) * nf) return;
+    const long f = i / (nu + ne), k = i - f * (nu + ne);
+    const float *gc = gcat + f * H * W * C;
+    if (k < nu) {
+        const int c = (int)(k % Cu);
+        const long q = k / Cu;
         const int y = (int)(q / Wc), x = (int)(q % Wc);
-        const float *s = gcat + ((long)(2 * y) * W + 2 * x) * C + c;
+        const float *s = gc + ((long)(2 * y) * W + 2 * x) * C + c;
         const float v = ((gload(s) + gload(s + C)) + gload(s + (long)W * C)) + gload(s + (long)W * C + C);
-        gstore(gu + i, gload(act_u + i) > 0.f ? v : 0.f);
-    } else if (i < nu + ne) {
-        const long j = i - nu;
+        gstore(gu + f * nu + k, gload(act_u + f * sa + k) > 0.f ? v : 0.f);
+    } else {
+        const long j = k - nu;
         const int c = (int)(j % Ce);
         const long p = j / Ce;
-        gstore(ge + j, gload(gcat + p * C + Cu + c));
+        gstore(ge + f * ne + j, gload(gc + p * C + Cu + c));
     }
 }
 
 // ge[p][c] = (act[p][c] > 0) (ge[p][c] + gp[p/2][c] / 4): the 2x2 mean's
 // adjoint added to what the concatenation's adjoint wrote, then the ReLU mask
 // of e (its last contribution)
-__global__ __launch_bounds__(kTrThreads) void tr_pool_bwd_kernel(int H, int W, int C, const float *gp,
-                                                                  const float *act, float *ge)
+__global__ __launch_bounds__(kTrThreads) void tr_pool_bwd_kernel(int H, int W, int C, int nf, const float *gp,
+                                                                  const float *act, long sa, float *ge)
 {
     const long n = (long)H * W * C;
     const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
-    if (i >= n) return;
-    const int c = (int)(i % C);
-    const long p = i / C;
+    if (i >= n * nf) return;
+    const long f = i / n, j = i - f * n;
+    const int c = (int)(j % C);
+    const long p = j / C;
     const int y = (int)(p / W), x = (int)(p % W);
-    const float v = gload(ge + i) + 0.25f * gload(gp + ((long)(y / 2) * (W / 2) + x / 2) * C + c);
-    gstore(ge + i, gload(act + i) > 0.f ? v : 0.f);
+    const long np = (long)(H / 2) * (W / 2) * C;
+    const float v = gload(ge + i) + 0.25f * gload(gp + f * np + ((long)(y / 2) * (W / 2) + x / 2) * C + c);
+    gstore(ge + i, gload(act + f * sa + j) > 0.f ? v : 0.f);
+}
+
+// frame table of an input-gradient conv over nf frames: e[0] = the gradient
+// it reads (frame stride ss), e[1] = the input gradient it writes (sd)
+__global__ void tr_frame_table_kernel(FrameDesc *tab, int nf, int H, int W, const float *src, long ss, float *dst,
+                                      long sd)
+{
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    FrameDesc d{};
+    d.H = H;
+    d.W = W;
+    d.e[0] = const_cast<float *>(src + f * ss);
+    d.e[1] = dst + f * sd;
+    tab[f] = d;
 }
 
 __global__ __launch_bounds__(kTrThreads) void tr_add_kernel(long n, const float *a, float *b)
@@ -447,14 +484,15 @@ hipError_t tr_pack(long P, const float *r, const float *a, const float *n, const
     TR_LAUNCH(tr_pack_kernel, P, P, r, a, n, d, inv_gamma, dnear, dinv, X);
     return hipGetLastError();
 }
-hipError_t tr_pool(int H, int W, int C, const float *in, float *out, hipStream_t s)
+hipError_t tr_pool(int H, int W, int C, int nf, const float *in, long sin, float *out, hipStream_t s)
 {
-    TR_LAUNCH(tr_pool_kernel, (long)(H / 2) * (W / 2) * C, H, W, C, in, out);
+    TR_LAUNCH(tr_pool_kernel, (long)(H / 2) * (W / 2) * C * nf, H, W, C, nf, in, sin, out);
     return hipGetLastError();
 }
-hipError_t tr_cat(int H, int W, int Cu, int Ce, const float *u, const float *e, float *out, hipStream_t s)
+hipError_t tr_cat(int H, int W, int Cu, int Ce, int nf, const float *u, long su, const float *e, long se, float *out,
+                  hipStream_t s)
 {
-    TR_LAUNCH(tr_cat_kernel, (long)H * W * (Cu + Ce), H, W, Cu, Ce, u, e, out);
+    TR_LAUNCH(tr_cat_kernel, (long)H * W * (Cu + Ce) * nf, H, W, Cu, Ce, nf, u, su, e, se, out);
     return hipGetLastError();
 }
 hipError_t tr_head_prep(long P, int M, const float *planar, const float *r, const float *a, float eps_a,
@@ -477,9 +515,9 @@ hipError_t tr_head_act_bwd(long P, int M, int ld, const float *grad_head, const 
     TR_LAUNCH(tr_head_act_bwd_kernel, P * ld, P, M, ld, grad_head, planar, dh);
     return hipGetLastError();
 }
-hipError_t tr_mask(long n, const float *g, const float *act, float *gm, hipStream_t s)
+hipError_t tr_mask(long n, int nf, const float *g, const float *act, long sa, float *gm, hipStream_t s)
 {
-    TR_LAUNCH(tr_mask_kernel, n, n, g, act, gm);
+    TR_LAUNCH(tr_mask_kernel, n * nf, n, nf, g, act, sa, gm);
     return hipGetLastError();
 }
 __global__ __launch_bounds__(kTrThreads) void tr_pack_dgrad_kernel(int Ci, int Co, int Co_pad, int Cout_pad,
@@ -502,36 +540,48 @@ hipError_t tr_pack_dgrad(int Ci, int Co, int Co_pad, int Cout_pad, const float *
 }
 
 int tr_wgrad_chunks(long P) { return (int)((P + kWgChunk - 1) / kWgChunk); }
-size_t tr_wgrad_part_floats(long P, int Ci, int Co) { return (size_t)tr_wgrad_chunks(P) * ((size_t)Co * Ci * 9 + Co); }
-hipError_t tr_wgrad(int H, int W, int Ci, int Co, int ldg, const float *gm, const float *in, float *part, float *dw,
-                    float *db, hipStream_t s)
+size_t tr_wgrad_part_floats(long P, int Ci, int Co, int nf)
+{
+    return (size_t)nf * tr_wgrad_chunks(P) * ((size_t)Co * Ci * 9 + Co);
+}
+hipError_t tr_wgrad(int H, int W, int Ci, int Co, int ldg, int nf, const float *gm, long sgm, const float *in,
+                    long sin, float *part, float *dw, float *db, hipStream_t s)
 {
     const long P = (long)H * W;
-    const int nch = tr_wgrad_chunks(P);
+    const int nch = tr_wgrad_chunks(P), nall = nf * nch;
     const long nw = (long)Co * Ci * 9;
-    float *partb = part + (size_t)nch * nw;
+    float *partb = part + (size_t)nall * nw;
     // the kernel's buffer windows and offsets stay below 2 GiB
     if ((double)(kWgChunk + 2.0 * W + 2.0) * std::max(Ci, ldg) * 4.0 >= 2147483648.0) return hipErrorInvalidValue;
     const unsigned cib = (unsigned)((Ci + 15) / 16), cob = (unsigned)((Co + 15) / 16);
     if (cob % 2 == 0)
-        hipLaunchKernelGGL(tr_wgrad_mfma_kernel<2>, dim3((unsigned)nch, cob / 2, cib), dim3(64 * kWgWaves), 0, s, H, W,
-                           Ci, Co, ldg, gm, in, part, partb);
+        hipLaunchKernelGGL(tr_wgrad_mfma_kernel<2>, dim3((unsigned)nall, cob / 2, cib), dim3(64 * kWgWaves), 0, s, H,
+                           W, Ci, Co, ldg, nch, gm, sgm, in, sin, part, partb);
     else
-        hipLaunchKernelGGL(tr_wgrad_mfma_kernel<1>, dim3((unsigned)nch, cob, cib), dim3(64 * kWgWaves), 0, s, H, W, Ci,
-                           Co, ldg, gm, in, part, partb);
+        hipLaunchKernelGGL(tr_wgrad_mfma_kernel<1>, dim3((unsigned)nall, cob, cib), dim3(64 * kWgWaves), 0, s, H, W,
+                           Ci, Co, ldg, nch, gm, sgm, in, sin, part, partb);
     hipLaunchKernelGGL(tr_wgrad_reduce_kernel, dim3((unsigned)((nw + Co + 63) / 64)), dim3(kTrThreads), 0, s, nw, Co,
-                       nch, part, partb, dw, db);
+                       nall, part, partb, dw, db);
     return hipGetLastError();
 }
-hipError_t tr_cat_bwd(int H, int W, int Cu, int Ce, const float *gcat, const float *act_u, float *gu, float *ge,
-                      hipStream_t s)
+hipError_t tr_cat_bwd(int H, int W, int Cu, int Ce, int nf, const float *gcat, const float *act_u, long sa, float *gu,
+                      float *ge, hipStream_t s)
 {
-    TR_LAUNCH(tr_cat_bwd_kernel, (long)(H / 2) * (W / 2) * Cu + (long)H * W * Ce, H, W, Cu, Ce, gcat, act_u, gu, ge);
+    TR_LAUNCH(tr_cat_bwd_kernel, ((long)(H / 2) * (W / 2) * Cu + (long)H * W * Ce) * nf, H, W, Cu, Ce, nf, gcat, act_u,
+              sa, gu, ge);
     return hipGetLastError();
 }
-hipError_t tr_pool_bwd(int H, int W, int C, const float *gp, const float *act, float *ge, hipStream_t s)
+hipError_t tr_pool_bwd(int H, int W, int C, int nf, const float *gp, const float *act, long sa, float *ge,
+                       hipStream_t s)
 {
-    TR_LAUNCH(tr_pool_bwd_kernel, (long)H * W * C, H, W, C, gp, act, ge);
+    TR_LAUNCH(tr_pool_bwd_kernel, (long)H * W * C * nf, H, W, C, nf, gp, act, sa, ge);
+    return hipGetLastError();
+}
+hipError_t tr_frame_table(FrameDesc *tab, int nf, int H, int W, const float *src, long ss, float *dst, long sd,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(tr_frame_table_kernel, dim3((unsigned)((nf + 63) / 64)), dim3(64), 0, s, tab, nf, H, W, src, ss,
+                       dst, sd);
     return hipGetLastError();
 }
 hipError_t tr_add(long n, const float *a, float *b, hipStream_t s)

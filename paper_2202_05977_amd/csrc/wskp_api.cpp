@@ -964,12 +964,14 @@ extern "C" wskp_status_t wskp_backward(wskp_handle_t h, void *stream, int N, int
 
 // ---------------------------------------------------------------------------
 // Training (fp32 handles with softplus weights): scratch of the backward
-// pass, sized for the largest frame of the batch.
+// pass for a group of nf frames of one size, each frame's tensors
+// contiguous after the previous frame's.
 struct TrainScratch {
     float *X, *head, *c, *mod, *gy, *gh, *gc, *dh, *dec, *partial, *in, *gin, *part;
     float *wpk[2 * kMaxLevels];   // packed weights of each input-gradient conv (blob order)
     float *zb;                    // zero bias
     float *ge[kMaxLevels], *gu[kMaxLevels];
+    FrameDesc *tab;               // frame table of the group's input-gradient convs
     size_t bytes;
 };
 
@@ -977,31 +979,32 @@ struct TrainScratch {
 // kernels' 16-channel chunk
 static int head_grad_stride(int M) { return (2 * M + 15) / 16 * 16; }
 
-static size_t train_plan(const wskp_ctx *h, int Hm, int Wm, char *base, TrainScratch *ts)
+static size_t train_plan(const wskp_ctx *h, int Hm, int Wm, int nf, char *base, TrainScratch *ts)
 {
     const int L = h->cfg.levels, M = h->cfg.num_kernels;
     const int *ch = h->cfg.channels;
     const long P = (long)Hm * Wm;
+    const size_t F = (size_t)nf;
     size_t o = 0;
     auto take = [&](size_t floats) {
         float *p = base ? reinterpret_cast<float *>(base + o) : nullptr;
         o += align_up(floats * sizeof(float));
         return p;
     };
-    size_t mx_in = 10 * (size_t)P, mx_part = tr_wgrad_part_floats(P, 10, ch[0]);
+    size_t mx_in = 10 * (size_t)P, mx_part = tr_wgrad_part_floats(P, 10, ch[0], nf);
     for (int l = 0; l < L; ++l) {
         const long Pl = (long)(Hm >> l) * (Wm >> l);
         if (l > 0) {
             mx_in = std::max(mx_in, (size_t)ch[l - 1] * Pl);
-            mx_part = std::max(mx_part, tr_wgrad_part_floats(Pl, ch[l - 1], ch[l]));
+            mx_part = std::max(mx_part, tr_wgrad_part_floats(Pl, ch[l - 1], ch[l], nf));
         }
         if (l + 1 < L) {
             mx_in = std::max(mx_in, (size_t)(ch[l + 1] + ch[l]) * Pl);
-            mx_part = std::max(mx_part, tr_wgrad_part_floats(Pl, ch[l + 1] + ch[l], ch[l]));
+            mx_part = std::max(mx_part, tr_wgrad_part_floats(Pl, ch[l + 1] + ch[l], ch[l], nf));
         }
     }
     mx_in = std::max(mx_in, (size_t)ch[0] * P);
-    mx_part = std::max(mx_part, tr_wgrad_part_floats(P, ch[0], 2 * M));
+    mx_part = std::max(mx_part, tr_wgrad_part_floats(P, ch[0], 2 * M, nf));
     const int ldh = head_grad_stride(M);
     // the input-gradient convs' packed weights (C_out of the forward conv
     // in, C_in out: encoders >= 1, decoders, the head) and the zero bias
@@ -1013,27 +1016,35 @@ static size_t train_plan(const wskp_ctx *h, int Hm, int Wm, char *base, TrainScr
     for (int l = 0; l + 1 < L; ++l) t.wpk[L + (L - 2 - l)] = take((size_t)ch[l] * 9 * r16(ch[l + 1] + ch[l]));
     t.wpk[2 * L - 1] = take((size_t)ldh * 9 * r16(ch[0]));
     t.zb = take(256);
-    t.X = take(10 * (size_t)P);
-    t.head = take((size_t)2 * M * P);
-    t.c = take(3 * (size_t)P);
-    t.mod = take(3 * (size_t)P);
-    t.gy = take(3 * (size_t)P);
-    t.gh = take((size_t)2 * M * P);
-    t.gc = take(3 * (size_t)P);
-    t.dh = take((size_t)ldh * P);
-    t.dec = take(decode_backward_scratch_bytes(h->dc, 1, Hm, Wm) / sizeof(float));
+    t.X = take(F * 10 * P);
+    t.head = take(F * 2 * M * P);
+    t.c = take(F * 3 * P);
+    t.mod = take(F * 3 * P);
+    t.gy = take(F * 3 * P);
+    t.gh = take(F * 2 * M * P);
+    t.gc = take(F * 3 * P);
+    t.dh = take(F * ldh * P);
+    t.dec = take(decode_backward_scratch_bytes(h->dc, nf, Hm, Wm) / sizeof(float));
     t.partial = take((size_t)tr_smape_blocks(3 * P));
-    t.in = take(mx_in);
-    t.gin = take(mx_in);
+    t.in = take(F * mx_in);
+    t.gin = take(F * mx_in);
     t.part = take(mx_part);
     for (int l = 0; l < L; ++l) {
-        const size_t n = (size_t)ch[l] * (Hm >> l) * (Wm >> l);
+        const size_t n = F * ch[l] * (Hm >> l) * (Wm >> l);
         t.ge[l] = take(n);
         t.gu[l] = l + 1 < L ? take(n) : nullptr;
     }
+    t.tab = reinterpret_cast<FrameDesc *>(take((F * sizeof(FrameDesc) + sizeof(float) - 1) / sizeof(float)));
     t.bytes = o;
     if (ts) *ts = t;
     return o;
+}
+
+static bool train_same_size(int n, const int *H, const int *W)
+{
+    for (int i = 1; i < n; ++i)
+        if (H[i] != H[0] || W[i] != W[0]) return false;
+    return true;
 }
 
 static wskp_status_t train_check(const wskp_ctx *h)
@@ -1061,10 +1072,13 @@ extern "C" wskp_status_t wskp_train_workspace_size(wskp_handle_t h, int n, const
             Hm = H[i];
             Wm = W[i];
         }
-    // the backward scratch holds levels of the largest frame; every frame's
-    // levels are no larger in pixels (sizes are multiples of 2^(L-1))
+    // frames of one size run their backward pass as one group; frames of
+    // mixed sizes one at a time, in scratch for the largest
     size_t mx = 0;
-    for (int i = 0; i < n; ++i) mx = std::max(mx, train_plan(h, H[i], W[i], nullptr, nullptr));
+    if (train_same_size(n, H, W))
+        mx = train_plan(h, H[0], W[0], n, nullptr, nullptr);
+    else
+        for (int i = 0; i < n; ++i) mx = std::max(mx, train_plan(h, H[i], W[i], 1, nullptr, nullptr));
     (void)Hm;
     (void)Wm;
     *bytes = align_up(fwd) + mx;
@@ -1109,8 +1123,9 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
     // forward kernel on the weights packed for it; gm has ldg >= Co channels
     // (the head's 2M padded with zeros to a multiple of 16, the kernel's
     // channel chunk; Ci, a network width, is one already)
-    auto dgrad = [&](const TrainScratch &t, size_t k, int Hl, int Wl, int Ci, int ldg, const float *gm,
-                     float *gin) -> hipError_t {
+    // gradients of nf frames, frame f's at gm + f sg, into gin + f si
+    auto dgrad = [&](const TrainScratch &t, size_t k, int Hl, int Wl, int Ci, int ldg, int nf, const float *gm,
+                     long sg, float *gin, long si) -> hipError_t {
         ConvLayer c{};
         c.level = 0;
         c.src0_kind = 0;
@@ -1135,16 +1150,23 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
         c.w = t.wpk[k];
         c.bias = t.zb;
         FrameArg fa{};
-        fa.n = 1;
-        fa.one.H = Hl;
-        fa.one.W = Wl;
-        fa.one.e[0] = const_cast<float *>(gm);
-        fa.one.e[1] = gin;
-        return launch_conv(c, CONV_PLAIN, EPI_LINEAR, WSKP_PREC_FP32, fa, conv_grid(c, 1, &Hl, &Wl), s);
+        fa.n = nf;
+        if (nf == 1) {
+            fa.one.H = Hl;
+            fa.one.W = Wl;
+            fa.one.e[0] = const_cast<float *>(gm);
+            fa.one.e[1] = gin;
+        } else {
+            hipError_t te = tr_frame_table(t.tab, nf, Hl, Wl, gm, sg, gin, si, s);
+            if (te != hipSuccess) return te;
+            fa.table = t.tab;
+        }
+        const std::vector<int> hv(nf, Hl), wv(nf, Wl);
+        return launch_conv(c, CONV_PLAIN, EPI_LINEAR, WSKP_PREC_FP32, fa, conv_grid(c, nf, hv.data(), wv.data()), s);
     };
     {
         TrainScratch t;
-        train_plan(h, Hs[0], Ws[0], static_cast<char *>(ws) + align_up(fwd), &t);
+        train_plan(h, Hs[0], Ws[0], 1, static_cast<char *>(ws) + align_up(fwd), &t);
         if (e == hipSuccess) e = tr_fill(256, 0.f, t.zb, s);
         if (e == hipSuccess) e = tr_pack_dgrad(ch[0], 2 * M, ldh, ch[0], wofs(head_k), t.wpk[head_k], s);
         for (int l = 0; l + 1 < L && e == hipSuccess; ++l) {
@@ -1154,25 +1176,40 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
         for (int l = 1; l < L && e == hipSuccess; ++l)
             e = tr_pack_dgrad(ch[l - 1], ch[l], ch[l], ch[l - 1], wofs(l), t.wpk[l], s);
     }
+    // Frames of one size run the backward pass as one group, every kernel
+    // over all of them (frame k's tensors at a constant stride: fs floats
+    // apart in the forward workspace, one frame's size apart in the
+    // scratch); frames of mixed sizes one at a time.
+    const int gsz = train_same_size(n, Hs.data(), Ws.data()) ? n : 1;
     char *fbase = static_cast<char *>(ws) + table_bytes(n);
-    for (int f = 0; f < n && e == hipSuccess; ++f) {
-        const int H = Hs[f], W = Ws[f];
+    for (int f0 = 0; f0 < n && e == hipSuccess; f0 += gsz) {
+        const int nf = gsz, H = Hs[f0], W = Ws[f0];
         const long P = (long)H * W;
+        const size_t fbytes = frame_bytes(h, H, W, nullptr, nullptr, nullptr);
+        const long fs = (long)(fbytes / sizeof(float));
         FrameDesc fd;
-        fill_frame(h, fd, fbase, frames[f]);
-        fbase += frame_bytes(h, H, W, nullptr, nullptr, nullptr);
+        fill_frame(h, fd, fbase, frames[f0]);
         TrainScratch t;
-        train_plan(h, H, W, static_cast<char *>(ws) + align_up(fwd), &t);
+        train_plan(h, H, W, nf, static_cast<char *>(ws) + align_up(fwd), &t);
         const float *e_[kMaxLevels], *u_[kMaxLevels];
         for (int l = 0; l < L; ++l) {
             e_[l] = static_cast<const float *>(fd.e[l]);
             u_[l] = static_cast<const float *>(fd.u[l]);
         }
-        // loss gradient, decode adjoint, weight activation
-        e = tr_head_prep(P, M, fd.head, fd.r, fd.a, h->cfg.eps_albedo, t.head, t.c, t.mod, s);
-        if (e == hipSuccess) e = tr_smape(3 * P, fd.out, targets[f], eps_smape, inv_n, t.gy, t.partial, loss, f > 0, s);
-        if (e == hipSuccess) e = launch_decode_backward(h->dc, 1, H, W, t.head, t.c, t.mod, t.gy, t.gh, t.gc, t.dec, s);
-        if (e == hipSuccess) e = tr_head_act_bwd(P, M, ldh, t.gh, fd.head, t.dh, s);
+        // per frame: the decode adjoint's inputs, the loss and its gradient
+        for (int k = 0; k < nf && e == hipSuccess; ++k) {
+            FrameDesc fk;
+            fill_frame(h, fk, fbase + k * fbytes, frames[f0 + k]);
+            e = tr_head_prep(P, M, fk.head, fk.r, fk.a, h->cfg.eps_albedo, t.head + k * 2 * M * P, t.c + k * 3 * P,
+                             t.mod + k * 3 * P, s);
+            if (e == hipSuccess)
+                e = tr_smape(3 * P, fk.out, targets[f0 + k], eps_smape, inv_n, t.gy + k * 3 * P, t.partial, loss,
+                             f0 + k > 0, s);
+        }
+        // decode adjoint over the group, then the weight activation's derivative
+        if (e == hipSuccess) e = launch_decode_backward(h->dc, nf, H, W, t.head, t.c, t.mod, t.gy, t.gh, t.gc, t.dec, s);
+        for (int k = 0; k < nf && e == hipSuccess; ++k)
+            e = tr_head_act_bwd(P, M, ldh, t.gh + k * 2 * M * P, fd.head + k * fs, t.dh + k * ldh * P, s);
         // Gradients of the activations, kept as gradients of their
         // pre-activations (the ReLU mask applied by the kernel that writes
         // the last contribution): gu[l] of u_l (l < L - 1; u_{L-1} is e_{L-1},
@@ -1180,12 +1217,14 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
         // contribution overwrites it, so none is cleared.
         auto gu_of = [&](int l) { return l == L - 1 ? t.ge[l] : t.gu[l]; };
         auto act_of = [&](int l) { return l == L - 1 ? e_[L - 1] : u_[l]; };
+        auto nel = [&](int l, int C) { return (long)C * (H >> l) * (W >> l); };   // one frame's floats
         // head conv: input u_0, output 2M channels, no ReLU; u_0's gradient
         // has one contribution, masked in place
         if (e == hipSuccess)
-            e = tr_wgrad(H, W, ch[0], 2 * M, ldh, t.dh, u_[0], t.part, gofs(head_k), bofs(head_k, ch[0], 2 * M), s);
-        if (e == hipSuccess) e = dgrad(t, head_k, H, W, ch[0], ldh, t.dh, gu_of(0));
-        if (e == hipSuccess) e = tr_mask((long)ch[0] * P, gu_of(0), act_of(0), gu_of(0), s);
+            e = tr_wgrad(H, W, ch[0], 2 * M, ldh, nf, t.dh, ldh * P, u_[0], fs, t.part, gofs(head_k),
+                         bofs(head_k, ch[0], 2 * M), s);
+        if (e == hipSuccess) e = dgrad(t, head_k, H, W, ch[0], ldh, nf, t.dh, ldh * P, gu_of(0), nel(0, ch[0]));
+        if (e == hipSuccess) e = tr_mask(nel(0, ch[0]), nf, gu_of(0), act_of(0), fs, gu_of(0), s);
         // decoders, finest first: dec_l is conv L + (L - 2 - l) in blob order;
         // the concatenation's adjoint writes u_{l+1}'s gradient (masked, its
         // only contribution) and the first part of e_l's
@@ -1193,27 +1232,38 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
             const size_t k = (size_t)L + (L - 2 - l);
             const int Hl = H >> l, Wl = W >> l, Ci = ch[l + 1] + ch[l], Co = ch[l];
             const float *gm = t.gu[l];
-            e = tr_cat(Hl, Wl, ch[l + 1], ch[l], u_[l + 1], e_[l], t.in, s);
-            if (e == hipSuccess) e = tr_wgrad(Hl, Wl, Ci, Co, Co, gm, t.in, t.part, gofs(k), bofs(k, Ci, Co), s);
-            if (e == hipSuccess) e = dgrad(t, k, Hl, Wl, Ci, Co, gm, t.gin);
+            e = tr_cat(Hl, Wl, ch[l + 1], ch[l], nf, u_[l + 1], fs, e_[l], fs, t.in, s);
             if (e == hipSuccess)
-                e = tr_cat_bwd(Hl, Wl, ch[l + 1], ch[l], t.gin, act_of(l + 1), gu_of(l + 1), t.ge[l], s);
+                e = tr_wgrad(Hl, Wl, Ci, Co, Co, nf, gm, nel(l, Co), t.in, nel(l, Ci), t.part, gofs(k),
+                             bofs(k, Ci, Co), s);
+            if (e == hipSuccess) e = dgrad(t, k, Hl, Wl, Ci, Co, nf, gm, nel(l, Co), t.gin, nel(l, Ci));
+            if (e == hipSuccess)
+                e = tr_cat_bwd(Hl, Wl, ch[l + 1], ch[l], nf, t.gin, act_of(l + 1), fs, gu_of(l + 1), t.ge[l], s);
         }
         // encoders, coarsest first: enc_l is conv l; the 2x2 mean's adjoint
         // adds the last part of e_{l-1}'s gradient and masks it
         for (int l = L - 1; l >= 1 && e == hipSuccess; --l) {
             const int Hl = H >> l, Wl = W >> l, Ci = ch[l - 1], Co = ch[l];
             const float *gm = t.ge[l];
-            e = tr_pool(H >> (l - 1), W >> (l - 1), Ci, e_[l - 1], t.in, s);
-            if (e == hipSuccess) e = tr_wgrad(Hl, Wl, Ci, Co, Co, gm, t.in, t.part, gofs(l), bofs(l, Ci, Co), s);
-            if (e == hipSuccess) e = dgrad(t, (size_t)l, Hl, Wl, Ci, Co, gm, t.gin);
-            if (e == hipSuccess) e = tr_pool_bwd(H >> (l - 1), W >> (l - 1), Ci, t.gin, e_[l - 1], t.ge[l - 1], s);
+            e = tr_pool(H >> (l - 1), W >> (l - 1), Ci, nf, e_[l - 1], fs, t.in, s);
+            if (e == hipSuccess)
+                e = tr_wgrad(Hl, Wl, Ci, Co, Co, nf, gm, nel(l, Co), t.in, nel(l, Ci), t.part, gofs(l),
+                             bofs(l, Ci, Co), s);
+            if (e == hipSuccess) e = dgrad(t, (size_t)l, Hl, Wl, Ci, Co, nf, gm, nel(l, Co), t.gin, nel(l, Ci));
+            if (e == hipSuccess)
+                e = tr_pool_bwd(H >> (l - 1), W >> (l - 1), Ci, nf, t.gin, e_[l - 1], fs, t.ge[l - 1], s);
         }
         // first encoder: the network input written out, weight gradient only
+        for (int k = 0; k < nf && e == hipSuccess; ++k) {
+            FrameDesc fk;
+            fill_frame(h, fk, fbase + k * fbytes, frames[f0 + k]);
+            e = tr_pack(P, fk.r, fk.a, fk.n, fk.d, 1.f / h->cfg.gamma, h->cfg.depth_near,
+                        1.f / (h->cfg.depth_far - h->cfg.depth_near), t.X + k * 10 * P, s);
+        }
         if (e == hipSuccess)
-            e = tr_pack(P, fd.r, fd.a, fd.n, fd.d, 1.f / h->cfg.gamma, h->cfg.depth_near,
-                        1.f / (h->cfg.depth_far - h->cfg.depth_near), t.X, s);
-        if (e == hipSuccess) e = tr_wgrad(H, W, 10, ch[0], ch[0], t.ge[0], t.X, t.part, gofs(0), bofs(0, 10, ch[0]), s);
+            e = tr_wgrad(H, W, 10, ch[0], ch[0], nf, t.ge[0], nel(0, ch[0]), t.X, 10 * P, t.part, gofs(0),
+                         bofs(0, 10, ch[0]), s);
+        fbase += nf * fbytes;
     }
     if (e != hipSuccess) return hip_fail(e, "training launch", WSKP_E_LAUNCH);
     return WSKP_OK;

@@ -233,10 +233,14 @@ hipError_t launch_decode_backward(const DecodeCfg &dc, int N, int H, int W, cons
                                   hipStream_t s);
 size_t decode_backward_scratch_bytes(const DecodeCfg &dc, int N, int H, int W);
 // Training kernels (train.hip): see the file's header for each operation.
+// Kernels with an nf argument run over nf frames of one size: frame f's
+// operand X is at X + f sX (strides in floats); their outputs are contiguous
+// per frame.
 hipError_t tr_pack(long P, const float *r, const float *a, const float *n, const float *d, float inv_gamma,
                    float dnear, float dinv, float *X, hipStream_t s);
-hipError_t tr_pool(int H, int W, int C, const float *in, float *out, hipStream_t s);
-hipError_t tr_cat(int H, int W, int Cu, int Ce, const float *u, const float *e, float *out, hipStream_t s);
+hipError_t tr_pool(int H, int W, int C, int nf, const float *in, long sin, float *out, hipStream_t s);
+hipError_t tr_cat(int H, int W, int Cu, int Ce, int nf, const float *u, long su, const float *e, long se, float *out,
+                  hipStream_t s);
 hipError_t tr_head_prep(long P, int M, const float *planar, const float *r, const float *a, float eps_a,
                         float *head, float *c, float *mod, hipStream_t s);
 int tr_smape_blocks(long n);
@@ -245,20 +249,27 @@ hipError_t tr_smape(long n, const float *y, const float *t, float eps, float inv
 // dh[p][j] for j < 2M, zero for 2M <= j < ld (rows ld floats apart)
 hipError_t tr_head_act_bwd(long P, int M, int ld, const float *grad_head, const float *planar, float *dh,
                            hipStream_t s);
-hipError_t tr_mask(long n, const float *g, const float *act, float *gm, hipStream_t s);
+// gm = (act > 0) g over nf frames of n values (gm may be g)
+hipError_t tr_mask(long n, int nf, const float *g, const float *act, long sa, float *gm, hipStream_t s);
 // Weights of the input-gradient conv in the fp32 forward kernels' packing
 // ([Co_pad/16][9][16][Cout_pad], 16-channel chunks): element (c, t, ci) is
 // w[c][ci][8 - t], zero beyond Co or Ci.
 hipError_t tr_pack_dgrad(int Ci, int Co, int Co_pad, int Cout_pad, const float *w, float *packed, hipStream_t s);
-size_t tr_wgrad_part_floats(long P, int Ci, int Co);
-// gm rows are ldg >= Co floats apart
-hipError_t tr_wgrad(int H, int W, int Ci, int Co, int ldg, const float *gm, const float *in, float *part, float *dw,
-                    float *db, hipStream_t s);
+// partial sums of a weight gradient over nf frames of P pixels
+size_t tr_wgrad_part_floats(long P, int Ci, int Co, int nf);
+// gm rows are ldg >= Co floats apart; dw and db accumulate the nf frames
+hipError_t tr_wgrad(int H, int W, int Ci, int Co, int ldg, int nf, const float *gm, long sgm, const float *in,
+                    long sin, float *part, float *dw, float *db, hipStream_t s);
 // gu = (act_u > 0) * (the upsampled part's gradient); ge = the skip part's
-hipError_t tr_cat_bwd(int H, int W, int Cu, int Ce, const float *gcat, const float *act_u, float *gu, float *ge,
-                      hipStream_t s);
+hipError_t tr_cat_bwd(int H, int W, int Cu, int Ce, int nf, const float *gcat, const float *act_u, long sa, float *gu,
+                      float *ge, hipStream_t s);
 // ge = (act > 0) * (ge + the 2x2 mean's adjoint of gp)
-hipError_t tr_pool_bwd(int H, int W, int C, const float *gp, const float *act, float *ge, hipStream_t s);
+hipError_t tr_pool_bwd(int H, int W, int C, int nf, const float *gp, const float *act, long sa, float *ge,
+                       hipStream_t s);
+// table of nf frames of H x W for an input-gradient conv: e[0] = src + f ss,
+// e[1] = dst + f sd
+hipError_t tr_frame_table(FrameDesc *tab, int nf, int H, int W, const float *src, long ss, float *dst, long sd,
+                          hipStream_t s);
 hipError_t tr_add(long n, const float *a, float *b, hipStream_t s);
 hipError_t tr_fill(long n, float v, float *b, hipStream_t s);
 hipError_t tr_adam(long n, float *w, const float *g, float *m, float *v, float lr, float b1, float b2, float c1,

@@ -44,7 +44,9 @@ def _oracle_batch(host, blob, cfg):
 
 
 # one- and two-level nets: the bottleneck's gradient is the head's input
-# gradient (one level) or comes from the only decoder (two levels)
+# gradient (one level) or comes from the only decoder (two levels).  Frames
+# of one size run the backward pass as one group (every kernel over all of
+# them), frames of mixed sizes one at a time: both are covered.
 ONE_LEVEL = synth.NetConfig(levels=1, channels=(16,), kernel_sizes=(3, 5))
 TWO_LEVEL = synth.NetConfig(levels=2, channels=(16, 32), kernel_sizes=(3, 5, 7))
 
@@ -52,8 +54,11 @@ TWO_LEVEL = synth.NetConfig(levels=2, channels=(16, 32), kernel_sizes=(3, 5, 7))
 @pytest.mark.parametrize("cfg_name,sizes", [("small", [(64, 96), (64, 96)]),
                                             ("small", [(48, 80), (32, 32), (72, 104)]),
                                             ("hd", [(64, 64)]),
+                                            ("hd", [(64, 64)] * 3),
                                             ("one_level", [(40, 56), (24, 32)]),
-                                            ("two_level", [(48, 64), (36, 44)])])
+                                            ("one_level", [(40, 56)] * 2),
+                                            ("two_level", [(48, 64), (36, 44)]),
+                                            ("two_level", [(48, 64)] * 3)])
 def test_train_grads_match_oracle(cfg_name, sizes):
     from paper_2202_05977_amd import wskp
     cfg = {"one_level": ONE_LEVEL, "two_level": TWO_LEVEL}.get(cfg_name) or synth.CONFIGS[cfg_name]
