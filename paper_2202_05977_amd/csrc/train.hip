@@ -27,9 +27,9 @@
 //          db[co] = sum_p gm[p][co]: a GEMM over pixels,
 //          tr_wgrad_mfma_kernel (v_mfma_f32_16x16x4f32, 4 pixels per step;
 //          channel counts that are not multiples of 16 are padded with
-//          zeros).  Each workgroup sums one chunk of 256 pixels and a
-//          second pass adds the chunks' partial sums in a fixed order, so
-//          the result does not depend on scheduling
+//          zeros).  Each workgroup sums one chunk of 256 to 1024 pixels
+//          and a second pass adds the chunks' partial sums in a fixed
+//          order, so the result does not depend on scheduling
 #include "wskp_internal.h"
 
 namespace wskp {
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(kTrThreads) void tr_mask_kernel(long n, int nf, con
 // pixels, D[co][ci] += sum_p gm[p][co] * in[p + off(tap)][ci] for each tap,
 // with v_mfma_f32_16x16x4f32 taking 4 pixels per step (lane (g, j): pixel
 // g of the step; A = gm[p_g][co0 + j] (gm rows ldg floats apart),
-// B = in[p_g + off][ci0 + j]).  One workgroup per (chunk of kWgChunk
+// B = in[p_g + off][ci0 + j]).  One workgroup per (chunk of `chunk`
 // pixels, CB output blocks of 16, one input block of 16); its kWgWaves waves
 // take consecutive quarters of the chunk, each loading the operands of its
 // next step before the MFMAs of the current one, and add their sums in LDS
@@ -200,11 +200,13 @@ __global__ __launch_bounds__(kTrThreads) void tr_mask_kernel(long n, int nf, con
 // so no load is conditional.  The workgroups of input block 0 also sum gm
 // (B = 1) for the bias.  Lane (g, j) ends with D[4g + r][j], r = 0..3.
 typedef float trf32x4 __attribute__((ext_vector_type(4)));
-constexpr int kWgChunk = 256, kWgWaves = 4;
+// Chunks are 256 pixels, doubled (up to kWgChunkMax) while a launch still
+// has kWgMinGroups workgroups: fewer partial sums to write and reduce.
+constexpr int kWgChunk = 256, kWgChunkMax = 1024, kWgMinGroups = 2048, kWgWaves = 4;
 constexpr unsigned kWgOut = 0x80000000u;   // beyond every window (windows are < 2 GiB)
 template <int CB>
 __global__ __launch_bounds__(64 * kWgWaves) void tr_wgrad_mfma_kernel(int H, int W, int Ci, int Co, int ldg,
-                                                                      int nch, const float *gm, long sgm,
+                                                                      int chunk, int nch, const float *gm, long sgm,
                                                                       const float *in, long sin, float *part,
                                                                       float *partb)
 {
@@ -216,8 +218,8 @@ __global__ __launch_bounds__(64 * kWgWaves) void tr_wgrad_mfma_kernel(int H, int
     const int fr = blockIdx.x / nch;
     gm += fr * sgm;
     in += fr * sin;
-    const long c0 = (long)(blockIdx.x - fr * nch) * kWgChunk;
-    const int n = (int)min((long)kWgChunk, P - c0);
+    const long c0 = (long)(blockIdx.x - fr * nch) * chunk;
+    const int n = (int)min((long)chunk, P - c0);
     const long lo = max(0L, c0 - W - 1), hi = min(P, c0 + n + W + 1);
     const rsrc_t rg = make_rsrc(gm + c0 * ldg, (unsigned)n * (unsigned)ldg * 4u);
     const rsrc_t ri = make_rsrc(in + lo * Ci, (unsigned)(hi - lo) * (unsigned)Ci * 4u);
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(64 * kWgWaves) void tr_wgrad_mfma_kernel(int H, int
 #pragma unroll
         for (int t = 0; t < 10; ++t) acc[c][t] = trf32x4{0.f, 0.f, 0.f, 0.f};
     // this wave's pixels qa .. qb - 1 of the chunk
-    const int qa = wave * (kWgChunk / kWgWaves), qb = min(n, qa + kWgChunk / kWgWaves);
+    const int qa = wave * (chunk / kWgWaves), qb = min(n, qa + chunk / kWgWaves);
     float a[CB], b[9];
     // operands of the step at chunk pixel q, for this lane's pixel q + g at
     // image position (y, x)
@@ -539,27 +541,41 @@ hipError_t tr_pack_dgrad(int Ci, int Co, int Co_pad, int Cout_pad, const float *
     return hipGetLastError();
 }
 
-int tr_wgrad_chunks(long P) { return (int)((P + kWgChunk - 1) / kWgChunk); }
+static int wgrad_blocks(int Ci, int Co)
+{
+    const int cib = (Ci + 15) / 16, cob = (Co + 15) / 16;
+    return cib * (cob % 2 == 0 ? cob / 2 : cob);
+}
+// pixels per chunk for nf frames of P pixels (a multiple of 16: four waves
+// of whole 4-pixel steps)
+static int wgrad_chunk(long P, int Ci, int Co, int nf)
+{
+    int c = kWgChunk;
+    while (c < kWgChunkMax && (long)nf * ((P + 2 * c - 1) / (2 * c)) * wgrad_blocks(Ci, Co) >= kWgMinGroups) c *= 2;
+    return c;
+}
 size_t tr_wgrad_part_floats(long P, int Ci, int Co, int nf)
 {
-    return (size_t)nf * tr_wgrad_chunks(P) * ((size_t)Co * Ci * 9 + Co);
+    const int c = wgrad_chunk(P, Ci, Co, nf);
+    return (size_t)nf * ((P + c - 1) / c) * ((size_t)Co * Ci * 9 + Co);
 }
 hipError_t tr_wgrad(int H, int W, int Ci, int Co, int ldg, int nf, const float *gm, long sgm, const float *in,
                     long sin, float *part, float *dw, float *db, hipStream_t s)
 {
     const long P = (long)H * W;
-    const int nch = tr_wgrad_chunks(P), nall = nf * nch;
+    const int chunk = wgrad_chunk(P, Ci, Co, nf);
+    const int nch = (int)((P + chunk - 1) / chunk), nall = nf * nch;
     const long nw = (long)Co * Ci * 9;
     float *partb = part + (size_t)nall * nw;
     // the kernel's buffer windows and offsets stay below 2 GiB
-    if ((double)(kWgChunk + 2.0 * W + 2.0) * std::max(Ci, ldg) * 4.0 >= 2147483648.0) return hipErrorInvalidValue;
+    if ((double)(chunk + 2.0 * W + 2.0) * std::max(Ci, ldg) * 4.0 >= 2147483648.0) return hipErrorInvalidValue;
     const unsigned cib = (unsigned)((Ci + 15) / 16), cob = (unsigned)((Co + 15) / 16);
     if (cob % 2 == 0)
         hipLaunchKernelGGL(tr_wgrad_mfma_kernel<2>, dim3((unsigned)nall, cob / 2, cib), dim3(64 * kWgWaves), 0, s, H,
-                           W, Ci, Co, ldg, nch, gm, sgm, in, sin, part, partb);
+                           W, Ci, Co, ldg, chunk, nch, gm, sgm, in, sin, part, partb);
     else
         hipLaunchKernelGGL(tr_wgrad_mfma_kernel<1>, dim3((unsigned)nall, cob, cib), dim3(64 * kWgWaves), 0, s, H, W,
-                           Ci, Co, ldg, nch, gm, sgm, in, sin, part, partb);
+                           Ci, Co, ldg, chunk, nch, gm, sgm, in, sin, part, partb);
     hipLaunchKernelGGL(tr_wgrad_reduce_kernel, dim3((unsigned)((nw + Co + 63) / 64)), dim3(kTrThreads), 0, s, nw, Co,
                        nall, part, partb, dw, db);
     return hipGetLastError();
