@@ -77,24 +77,6 @@ __global__ __launch_bounds__(kTrThreads) void tr_pool_kernel(int H, int W, int C
     gstore(out + i, 0.25f * (((gload(s) + gload(s + C)) + gload(s + (long)W * C)) + gload(s + (long)W * C + C)));
 }
 
-// out [nf][H][W][Cu + Ce] = [nearest x2 upsample of u [H/2][W/2][Cu],
-// e [H][W][Ce]] (frame strides su, se)
-__global__ __launch_bounds__(kTrThreads) void tr_cat_kernel(int H, int W, int Cu, int Ce, int nf, const float *u,
-                                                             long su, const float *e, long se, float *out)
-{
-    const int C = Cu + Ce;
-    const long n = (long)H * W * C;
-    const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
-    if (i >= n * nf) return;
-    const long f = i / n, j = i - f * n;
-    const int ch = (int)(j % C);
-    const long p = j / C;
-    const int y = (int)(p / W), x = (int)(p % W);
-    const float v = ch < Cu ? gload(u + f * su + ((long)(y / 2) * (W / 2) + x / 2) * Cu + ch)
-                            : gload(e + f * se + p * Ce + (ch - Cu));
-    gstore(out + i, v);
-}
-
 // interleaved head [P][2M] from the planar record [2M][P]; c = r/(a+eps_a),
 // mod = a + eps_a (the decode adjoint's inputs)
 __global__ __launch_bounds__(kTrThreads) void tr_head_prep_kernel(long P, int M, const float *planar, const float *r,
@@ -205,10 +187,11 @@ typedef float trf32x4 __attribute__((ext_vector_type(4)));
 constexpr int kWgChunk = 256, kWgChunkMax = 1024, kWgMinGroups = 2048, kWgWaves = 4;
 constexpr unsigned kWgOut = 0x80000000u;   // beyond every window (windows are < 2 GiB)
 template <int CB>
-__global__ __launch_bounds__(64 * kWgWaves) void tr_wgrad_mfma_kernel(int H, int W, int Ci, int Co, int ldg,
-                                                                      int chunk, int nch, const float *gm, long sgm,
-                                                                      const float *in, long sin, float *part,
-                                                                      float *partb)
+__global__ __launch_bounds__(64 * kWgWaves) void tr_wgrad_mfma_kernel(int H, int W, int Co, int ldg, int chunk,
+                                                                      int nch, const float *gm, long sgm,
+                                                                      const float *in, long sin, int Cf,
+                                                                      const float *up, long sup, int Cu,
+                                                                      float *part, float *partb)
 {
     __shared__ trf32x4 red[2][CB * 10][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
@@ -217,19 +200,28 @@ __global__ __launch_bounds__(64 * kWgWaves) void tr_wgrad_mfma_kernel(int H, int
     // workgroup x: frame f, chunk x - f nch of that frame; partial sum x
     const int fr = blockIdx.x / nch;
     gm += fr * sgm;
-    in += fr * sin;
     const long c0 = (long)(blockIdx.x - fr * nch) * chunk;
     const int n = (int)min((long)chunk, P - c0);
-    const long lo = max(0L, c0 - W - 1), hi = min(P, c0 + n + W + 1);
     const rsrc_t rg = make_rsrc(gm + c0 * ldg, (unsigned)n * (unsigned)ldg * 4u);
-    const rsrc_t ri = make_rsrc(in + lo * Ci, (unsigned)(hi - lo) * (unsigned)Ci * 4u);
+    // The input block's source: the map that the upsampling makes H x W
+    // (channels 0 .. Cu-1 of the layer's input, read at (y/2, x/2)) or the
+    // H x W map (channels Cu ..).  Its window: the source rows of image rows
+    // ylo .. yhi (the chunk's rows and one either side), whole rows.
+    const int Ci = Cu + Cf;
+    const bool coarse = ci0 < Cu;
+    const int sh = coarse ? 1 : 0, Cs = coarse ? Cu : Cf, cs0 = coarse ? ci0 : ci0 - Cu;
+    const int Wsrc = W >> sh;
+    const float *src = coarse ? up + fr * sup : in + fr * sin;
+    const int ylo = max(0, (int)(c0 / W) - 1), yhi = min(H - 1, (int)((c0 + n - 1) / W) + 1);
+    const int rlo = ylo >> sh, rhi = yhi >> sh;
+    const unsigned rowb = (unsigned)Wsrc * (unsigned)Cs * 4u, pixb = (unsigned)Cs * 4u;
+    const rsrc_t ri = make_rsrc(src + (long)rlo * Wsrc * Cs, (unsigned)(rhi - rlo + 1) * rowb);
     const bool bias = blockIdx.z == 0;
     bool cok[CB];
 #pragma unroll
     for (int c = 0; c < CB; ++c) cok[c] = co0 + c * 16 + j < Co;
-    const bool ciok = ci0 + j < Ci;
-    const int rel = (int)(c0 - lo);                 // the chunk's first pixel in the input window
-    const unsigned rowb = (unsigned)W * (unsigned)Ci * 4u, pixb = (unsigned)Ci * 4u;
+    const bool ciok = cs0 + j < Cs;
+    const unsigned chb = (unsigned)(cs0 + j) * 4u;
     trf32x4 acc[CB][10];
 #pragma unroll
     for (int c = 0; c < CB; ++c)
@@ -251,13 +243,20 @@ __global__ __launch_bounds__(64 * kWgWaves) void tr_wgrad_mfma_kernel(int H, int
             const unsigned off = ((unsigned)p * (unsigned)ldg + (unsigned)(co0 + c * 16 + j)) * 4u | out(valid & cok[c]);
             av[c] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rg, off, 0, 0));
         }
-        const unsigned ctr = ((unsigned)(rel + p) * (unsigned)Ci + (unsigned)(ci0 + j)) * 4u;
+        // tap (dy, dx) reads source row ((y + dy - 1) >> sh) - rlo, column
+        // (x + dx - 1) >> sh of the window (valid taps lie inside it)
         const bool vc = valid & ciok;
         const bool rok[3] = {y >= 1, true, y + 1 < H}, xok[3] = {x >= 1, true, x + 1 < W};
+        unsigned rt[3], ct[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            rt[d] = (unsigned)(((y + d - 1) >> sh) - rlo) * rowb + chb;
+            ct[d] = (unsigned)((x + d - 1) >> sh) * pixb;
+        }
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
             const int dy = t / 3, dx = t % 3;
-            const unsigned off = (ctr + (unsigned)(dy - 1) * rowb + (unsigned)(dx - 1) * pixb) | out(vc & rok[dy] & xok[dx]);
+            const unsigned off = (rt[dy] + ct[dx]) | out(vc & rok[dy] & xok[dx]);
             bv[t] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ri, off, 0, 0));
         }
     };
@@ -491,12 +490,6 @@ hipError_t tr_pool(int H, int W, int C, int nf, const float *in, long sin, float
     TR_LAUNCH(tr_pool_kernel, (long)(H / 2) * (W / 2) * C * nf, H, W, C, nf, in, sin, out);
     return hipGetLastError();
 }
-hipError_t tr_cat(int H, int W, int Cu, int Ce, int nf, const float *u, long su, const float *e, long se, float *out,
-                  hipStream_t s)
-{
-    TR_LAUNCH(tr_cat_kernel, (long)H * W * (Cu + Ce) * nf, H, W, Cu, Ce, nf, u, su, e, se, out);
-    return hipGetLastError();
-}
 hipError_t tr_head_prep(long P, int M, const float *planar, const float *r, const float *a, float eps_a,
                         float *head, float *c, float *mod, hipStream_t s)
 {
@@ -559,23 +552,25 @@ size_t tr_wgrad_part_floats(long P, int Ci, int Co, int nf)
     const int c = wgrad_chunk(P, Ci, Co, nf);
     return (size_t)nf * ((P + c - 1) / c) * ((size_t)Co * Ci * 9 + Co);
 }
-hipError_t tr_wgrad(int H, int W, int Ci, int Co, int ldg, int nf, const float *gm, long sgm, const float *in,
-                    long sin, float *part, float *dw, float *db, hipStream_t s)
+hipError_t tr_wgrad(int H, int W, int Co, int ldg, int nf, const float *gm, long sgm, const float *in, long sin,
+                    int Cf, const float *up, long sup, int Cu, float *part, float *dw, float *db, hipStream_t s)
 {
+    const int Ci = Cu + Cf;
     const long P = (long)H * W;
     const int chunk = wgrad_chunk(P, Ci, Co, nf);
     const int nch = (int)((P + chunk - 1) / chunk), nall = nf * nch;
     const long nw = (long)Co * Ci * 9;
     float *partb = part + (size_t)nall * nw;
     // the kernel's buffer windows and offsets stay below 2 GiB
-    if ((double)(chunk + 2.0 * W + 2.0) * std::max(Ci, ldg) * 4.0 >= 2147483648.0) return hipErrorInvalidValue;
+    if ((double)(chunk + 3.0 * W) * std::max(std::max(Cf, Cu), ldg) * 4.0 >= 2147483648.0) return hipErrorInvalidValue;
+    if (Cu % 16 || (Cu > 0 && (H % 2 || W % 2))) return hipErrorInvalidValue;   // whole blocks per source
     const unsigned cib = (unsigned)((Ci + 15) / 16), cob = (unsigned)((Co + 15) / 16);
     if (cob % 2 == 0)
         hipLaunchKernelGGL(tr_wgrad_mfma_kernel<2>, dim3((unsigned)nall, cob / 2, cib), dim3(64 * kWgWaves), 0, s, H,
-                           W, Ci, Co, ldg, chunk, nch, gm, sgm, in, sin, part, partb);
+                           W, Co, ldg, chunk, nch, gm, sgm, in, sin, Cf, up, sup, Cu, part, partb);
     else
         hipLaunchKernelGGL(tr_wgrad_mfma_kernel<1>, dim3((unsigned)nall, cob, cib), dim3(64 * kWgWaves), 0, s, H, W,
-                           Ci, Co, ldg, chunk, nch, gm, sgm, in, sin, part, partb);
+                           Co, ldg, chunk, nch, gm, sgm, in, sin, Cf, up, sup, Cu, part, partb);
     hipLaunchKernelGGL(tr_wgrad_reduce_kernel, dim3((unsigned)((nw + Co + 63) / 64)), dim3(kTrThreads), 0, s, nw, Co,
                        nall, part, partb, dw, db);
     return hipGetLastError();

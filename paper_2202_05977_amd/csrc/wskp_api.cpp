@@ -1221,7 +1221,7 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
         // head conv: input u_0, output 2M channels, no ReLU; u_0's gradient
         // has one contribution, masked in place
         if (e == hipSuccess)
-            e = tr_wgrad(H, W, ch[0], 2 * M, ldh, nf, t.dh, ldh * P, u_[0], fs, t.part, gofs(head_k),
+            e = tr_wgrad(H, W, 2 * M, ldh, nf, t.dh, ldh * P, u_[0], fs, ch[0], nullptr, 0, 0, t.part, gofs(head_k),
                          bofs(head_k, ch[0], 2 * M), s);
         if (e == hipSuccess) e = dgrad(t, head_k, H, W, ch[0], ldh, nf, t.dh, ldh * P, gu_of(0), nel(0, ch[0]));
         if (e == hipSuccess) e = tr_mask(nel(0, ch[0]), nf, gu_of(0), act_of(0), fs, gu_of(0), s);
@@ -1232,10 +1232,9 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
             const size_t k = (size_t)L + (L - 2 - l);
             const int Hl = H >> l, Wl = W >> l, Ci = ch[l + 1] + ch[l], Co = ch[l];
             const float *gm = t.gu[l];
-            e = tr_cat(Hl, Wl, ch[l + 1], ch[l], nf, u_[l + 1], fs, e_[l], fs, t.in, s);
-            if (e == hipSuccess)
-                e = tr_wgrad(Hl, Wl, Ci, Co, Co, nf, gm, nel(l, Co), t.in, nel(l, Ci), t.part, gofs(k),
-                             bofs(k, Ci, Co), s);
+            // the input [upsampled u_{l+1}, e_l] is read from its two sources
+            e = tr_wgrad(Hl, Wl, Co, Co, nf, gm, nel(l, Co), e_[l], fs, ch[l], u_[l + 1], fs, ch[l + 1], t.part,
+                         gofs(k), bofs(k, Ci, Co), s);
             if (e == hipSuccess) e = dgrad(t, k, Hl, Wl, Ci, Co, nf, gm, nel(l, Co), t.gin, nel(l, Ci));
             if (e == hipSuccess)
                 e = tr_cat_bwd(Hl, Wl, ch[l + 1], ch[l], nf, t.gin, act_of(l + 1), fs, gu_of(l + 1), t.ge[l], s);
@@ -1247,7 +1246,7 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
             const float *gm = t.ge[l];
             e = tr_pool(H >> (l - 1), W >> (l - 1), Ci, nf, e_[l - 1], fs, t.in, s);
             if (e == hipSuccess)
-                e = tr_wgrad(Hl, Wl, Ci, Co, Co, nf, gm, nel(l, Co), t.in, nel(l, Ci), t.part, gofs(l),
+                e = tr_wgrad(Hl, Wl, Co, Co, nf, gm, nel(l, Co), t.in, nel(l, Ci), Ci, nullptr, 0, 0, t.part, gofs(l),
                              bofs(l, Ci, Co), s);
             if (e == hipSuccess) e = dgrad(t, (size_t)l, Hl, Wl, Ci, Co, nf, gm, nel(l, Co), t.gin, nel(l, Ci));
             if (e == hipSuccess)
@@ -1261,8 +1260,8 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
                         1.f / (h->cfg.depth_far - h->cfg.depth_near), t.X + k * 10 * P, s);
         }
         if (e == hipSuccess)
-            e = tr_wgrad(H, W, 10, ch[0], ch[0], nf, t.ge[0], nel(0, ch[0]), t.X, 10 * P, t.part, gofs(0),
-                         bofs(0, 10, ch[0]), s);
+            e = tr_wgrad(H, W, ch[0], ch[0], nf, t.ge[0], nel(0, ch[0]), t.X, 10 * P, 10, nullptr, 0, 0, t.part,
+                         gofs(0), bofs(0, 10, ch[0]), s);
         fbase += nf * fbytes;
     }
     if (e != hipSuccess) return hip_fail(e, "training launch", WSKP_E_LAUNCH);

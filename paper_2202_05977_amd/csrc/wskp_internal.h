@@ -239,8 +239,6 @@ size_t decode_backward_scratch_bytes(const DecodeCfg &dc, int N, int H, int W);
 hipError_t tr_pack(long P, const float *r, const float *a, const float *n, const float *d, float inv_gamma,
                    float dnear, float dinv, float *X, hipStream_t s);
 hipError_t tr_pool(int H, int W, int C, int nf, const float *in, long sin, float *out, hipStream_t s);
-hipError_t tr_cat(int H, int W, int Cu, int Ce, int nf, const float *u, long su, const float *e, long se, float *out,
-                  hipStream_t s);
 hipError_t tr_head_prep(long P, int M, const float *planar, const float *r, const float *a, float eps_a,
                         float *head, float *c, float *mod, hipStream_t s);
 int tr_smape_blocks(long n);
@@ -257,9 +255,11 @@ hipError_t tr_mask(long n, int nf, const float *g, const float *act, long sa, fl
 hipError_t tr_pack_dgrad(int Ci, int Co, int Co_pad, int Cout_pad, const float *w, float *packed, hipStream_t s);
 // partial sums of a weight gradient over nf frames of P pixels
 size_t tr_wgrad_part_floats(long P, int Ci, int Co, int nf);
-// gm rows are ldg >= Co floats apart; dw and db accumulate the nf frames
-hipError_t tr_wgrad(int H, int W, int Ci, int Co, int ldg, int nf, const float *gm, long sgm, const float *in,
-                    long sin, float *part, float *dw, float *db, hipStream_t s);
+// The conv's input: Cu channels of `up` (H/2 x W/2) upsampled x2, then Cf
+// channels of `in` (H x W) (Cu = 0: `in` alone); gm rows are ldg >= Co
+// floats apart; dw and db accumulate the nf frames
+hipError_t tr_wgrad(int H, int W, int Co, int ldg, int nf, const float *gm, long sgm, const float *in, long sin,
+                    int Cf, const float *up, long sup, int Cu, float *part, float *dw, float *db, hipStream_t s);
 // gu = (act_u > 0) * (the upsampled part's gradient); ge = the skip part's
 hipError_t tr_cat_bwd(int H, int W, int Cu, int Ce, int nf, const float *gcat, const float *act_u, long sa, float *gu,
                       float *ge, hipStream_t s);
