@@ -39,12 +39,17 @@ constexpr int kTrThreads = 256;
 static inline int tr_blocks(long n) { return (int)((n + kTrThreads - 1) / kTrThreads); }
 
 // network input X [P][10] (Sec. 5.1), as the first conv's staging forms it
-__global__ __launch_bounds__(kTrThreads) void tr_pack_kernel(long P, const float *r, const float *a, const float *n,
-                                                              const float *d, float inv_gamma, float dnear, float dinv,
-                                                              float *X)
+// The per-frame kernels below run over a group of frames (blockIdx.y), the
+// frames' own buffers passed by pointer (TrFrames) and the group's scratch
+// contiguous per frame.
+__global__ __launch_bounds__(kTrThreads) void tr_pack_kernel(long P, TrFrames fr, float inv_gamma, float dnear,
+                                                              float dinv, float *X)
 {
     const long p = (long)blockIdx.x * kTrThreads + threadIdx.x;
     if (p >= P) return;
+    const int f = blockIdx.y;
+    const float *r = fr.r[f], *a = fr.a[f], *n = fr.n[f], *d = fr.d[f];
+    X += f * P * 10;
     float x[10];
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
@@ -79,12 +84,18 @@ __global__ __launch_bounds__(kTrThreads) void tr_pool_kernel(int H, int W, int C
 
 // interleaved head [P][2M] from the planar record [2M][P]; c = r/(a+eps_a),
 // mod = a + eps_a (the decode adjoint's inputs)
-__global__ __launch_bounds__(kTrThreads) void tr_head_prep_kernel(long P, int M, const float *planar, const float *r,
-                                                                   const float *a, float eps_a, float *head,
-                                                                   float *c, float *mod)
+__global__ __launch_bounds__(kTrThreads) void tr_head_prep_kernel(long P, int M, const float *planar, long sp,
+                                                                   TrFrames fr, float eps_a, float *head, float *c,
+                                                                   float *mod)
 {
     const long p = (long)blockIdx.x * kTrThreads + threadIdx.x;
     if (p >= P) return;
+    const int f = blockIdx.y;
+    const float *r = fr.r[f], *a = fr.a[f];
+    planar += f * sp;
+    head += f * P * 2 * M;
+    c += f * P * 3;
+    mod += f * P * 3;
     for (int j = 0; j < 2 * M; ++j) gstore(head + p * 2 * M + j, gload(planar + (long)j * P + p));
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
@@ -94,13 +105,18 @@ __global__ __launch_bounds__(kTrThreads) void tr_head_prep_kernel(long P, int M,
     }
 }
 
-// SMAPE (Eq. 6) gradient g = dL/dy for n values with mean weight inv_n, and
-// the block's share of the loss in partial[blockIdx.x]
-__global__ __launch_bounds__(kTrThreads) void tr_smape_kernel(long n, const float *y, const float *t, float eps,
-                                                               float inv_n, float *g, float *partial)
+// SMAPE (Eq. 6) gradient g = dL/dy for n values of each frame with mean
+// weight inv_n, and the block's share of the loss in
+// partial[frame * gridDim.x + blockIdx.x]
+__global__ __launch_bounds__(kTrThreads) void tr_smape_kernel(long n, TrFrames fr, float eps, float inv_n, float *g,
+                                                               float *partial)
 {
     __shared__ float red[kTrThreads];
     const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
+    const int f = blockIdx.y;
+    const float *y = fr.y[f], *t = fr.t[f];
+    g += f * n;
+    partial += (long)f * gridDim.x;
     float l = 0.f;
     if (i < n) {
         const float yv = gload(y + i), tv = gload(t + i);
@@ -139,10 +155,14 @@ __global__ __launch_bounds__(kTrThreads) void tr_sum_kernel(int nb, const float 
 // (the logistic of h, = 1 - e^{-W} = -expm1(-W) in terms of W = softplus(h),
 // accurate also where W is tiny); logits as is
 __global__ __launch_bounds__(kTrThreads) void tr_head_act_bwd_kernel(long P, int M, int ld, const float *grad_head,
-                                                                      const float *planar, float *dh)
+                                                                      const float *planar, long sp, float *dh)
 {
     const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
     if (i >= P * ld) return;
+    const int f = blockIdx.y;
+    grad_head += f * P * 2 * M;
+    planar += f * sp;
+    dh += f * P * ld;
     const int j = (int)(i % ld);
     const long p = i / ld;
     float g = 0.f;
@@ -479,10 +499,18 @@ __global__ __launch_bounds__(kTrThreads) void tr_repack_kernel(int Cin, int Cout
         if (n_ > 0) hipLaunchKernelGGL(kernel, dim3(tr_blocks(n_)), dim3(kTrThreads), 0, s, __VA_ARGS__); \
     } while (0)
 
-hipError_t tr_pack(long P, const float *r, const float *a, const float *n, const float *d, float inv_gamma,
-                   float dnear, float dinv, float *X, hipStream_t s)
+// grid of one frame's blocks (x) over the group's nf frames (y)
+#define TR_LAUNCH_F(kernel, n, nf, ...)                                                                    \
+    do {                                                                                                   \
+        const long n_ = (n);                                                                               \
+        if (n_ > 0 && (nf) > 0)                                                                            \
+            hipLaunchKernelGGL(kernel, dim3(tr_blocks(n_), (unsigned)(nf)), dim3(kTrThreads), 0, s, __VA_ARGS__); \
+    } while (0)
+
+hipError_t tr_pack(long P, int nf, const TrFrames &fr, float inv_gamma, float dnear, float dinv, float *X,
+                   hipStream_t s)
 {
-    TR_LAUNCH(tr_pack_kernel, P, P, r, a, n, d, inv_gamma, dnear, dinv, X);
+    TR_LAUNCH_F(tr_pack_kernel, P, nf, P, fr, inv_gamma, dnear, dinv, X);
     return hipGetLastError();
 }
 hipError_t tr_pool(int H, int W, int C, int nf, const float *in, long sin, float *out, hipStream_t s)
@@ -490,24 +518,24 @@ hipError_t tr_pool(int H, int W, int C, int nf, const float *in, long sin, float
     TR_LAUNCH(tr_pool_kernel, (long)(H / 2) * (W / 2) * C * nf, H, W, C, nf, in, sin, out);
     return hipGetLastError();
 }
-hipError_t tr_head_prep(long P, int M, const float *planar, const float *r, const float *a, float eps_a,
+hipError_t tr_head_prep(long P, int M, int nf, const float *planar, long sp, const TrFrames &fr, float eps_a,
                         float *head, float *c, float *mod, hipStream_t s)
 {
-    TR_LAUNCH(tr_head_prep_kernel, P, P, M, planar, r, a, eps_a, head, c, mod);
+    TR_LAUNCH_F(tr_head_prep_kernel, P, nf, P, M, planar, sp, fr, eps_a, head, c, mod);
     return hipGetLastError();
 }
 int tr_smape_blocks(long n) { return tr_blocks(n); }
-hipError_t tr_smape(long n, const float *y, const float *t, float eps, float inv_n, float *g, float *partial,
-                    float *loss, int accumulate, hipStream_t s)
+hipError_t tr_smape(long n, int nf, const TrFrames &fr, float eps, float inv_n, float *g, float *partial, float *loss,
+                    int accumulate, hipStream_t s)
 {
-    TR_LAUNCH(tr_smape_kernel, n, n, y, t, eps, inv_n, g, partial);
-    hipLaunchKernelGGL(tr_sum_kernel, dim3(1), dim3(kTrThreads), 0, s, tr_blocks(n), partial, loss, accumulate);
+    TR_LAUNCH_F(tr_smape_kernel, n, nf, n, fr, eps, inv_n, g, partial);
+    hipLaunchKernelGGL(tr_sum_kernel, dim3(1), dim3(kTrThreads), 0, s, tr_blocks(n) * nf, partial, loss, accumulate);
     return hipGetLastError();
 }
-hipError_t tr_head_act_bwd(long P, int M, int ld, const float *grad_head, const float *planar, float *dh,
-                           hipStream_t s)
+hipError_t tr_head_act_bwd(long P, int M, int ld, int nf, const float *grad_head, const float *planar, long sp,
+                           float *dh, hipStream_t s)
 {
-    TR_LAUNCH(tr_head_act_bwd_kernel, P * ld, P, M, ld, grad_head, planar, dh);
+    TR_LAUNCH_F(tr_head_act_bwd_kernel, P * ld, nf, P, M, ld, grad_head, planar, sp, dh);
     return hipGetLastError();
 }
 hipError_t tr_mask(long n, int nf, const float *g, const float *act, long sa, float *gm, hipStream_t s)

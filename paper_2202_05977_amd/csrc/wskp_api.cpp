@@ -1025,7 +1025,7 @@ static size_t train_plan(const wskp_ctx *h, int Hm, int Wm, int nf, char *base, 
     t.gc = take(F * 3 * P);
     t.dh = take(F * ldh * P);
     t.dec = take(decode_backward_scratch_bytes(h->dc, nf, Hm, Wm) / sizeof(float));
-    t.partial = take((size_t)tr_smape_blocks(3 * P));
+    t.partial = take((size_t)std::min(nf, kTrGroup) * tr_smape_blocks(3 * P));
     t.in = take(F * mx_in);
     t.gin = take(F * mx_in);
     t.part = take(mx_part);
@@ -1196,20 +1196,33 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
             e_[l] = static_cast<const float *>(fd.e[l]);
             u_[l] = static_cast<const float *>(fd.u[l]);
         }
-        // per frame: the decode adjoint's inputs, the loss and its gradient
-        for (int k = 0; k < nf && e == hipSuccess; ++k) {
-            FrameDesc fk;
-            fill_frame(h, fk, fbase + k * fbytes, frames[f0 + k]);
-            e = tr_head_prep(P, M, fk.head, fk.r, fk.a, h->cfg.eps_albedo, t.head + k * 2 * M * P, t.c + k * 3 * P,
-                             t.mod + k * 3 * P, s);
+        // the frames' own buffers, kTrGroup frames per launch of the
+        // per-frame kernels
+        auto frame_ptrs = [&](int k0, int kn) {
+            TrFrames fr{};
+            for (int k = 0; k < kn; ++k) {
+                const wskp_frame_t &q = frames[f0 + k0 + k];
+                fr.r[k] = q.radiance;
+                fr.a[k] = q.albedo;
+                fr.n[k] = q.normal;
+                fr.d[k] = q.depth;
+                fr.y[k] = q.out;
+                fr.t[k] = targets[f0 + k0 + k];
+            }
+            return fr;
+        };
+        // the decode adjoint's inputs, the loss and its gradient
+        for (int k0 = 0; k0 < nf && e == hipSuccess; k0 += kTrGroup) {
+            const int kn = std::min(kTrGroup, nf - k0);
+            const TrFrames fr = frame_ptrs(k0, kn);
+            e = tr_head_prep(P, M, kn, fd.head + k0 * fs, fs, fr, h->cfg.eps_albedo, t.head + k0 * 2 * M * P,
+                             t.c + k0 * 3 * P, t.mod + k0 * 3 * P, s);
             if (e == hipSuccess)
-                e = tr_smape(3 * P, fk.out, targets[f0 + k], eps_smape, inv_n, t.gy + k * 3 * P, t.partial, loss,
-                             f0 + k > 0, s);
+                e = tr_smape(3 * P, kn, fr, eps_smape, inv_n, t.gy + k0 * 3 * P, t.partial, loss, f0 + k0 > 0, s);
         }
         // decode adjoint over the group, then the weight activation's derivative
         if (e == hipSuccess) e = launch_decode_backward(h->dc, nf, H, W, t.head, t.c, t.mod, t.gy, t.gh, t.gc, t.dec, s);
-        for (int k = 0; k < nf && e == hipSuccess; ++k)
-            e = tr_head_act_bwd(P, M, ldh, t.gh + k * 2 * M * P, fd.head + k * fs, t.dh + k * ldh * P, s);
+        if (e == hipSuccess) e = tr_head_act_bwd(P, M, ldh, nf, t.gh, fd.head, fs, t.dh, s);
         // Gradients of the activations, kept as gradients of their
         // pre-activations (the ReLU mask applied by the kernel that writes
         // the last contribution): gu[l] of u_l (l < L - 1; u_{L-1} is e_{L-1},
@@ -1253,11 +1266,10 @@ extern "C" wskp_status_t wskp_train_grads(wskp_handle_t h, void *stream, int n, 
                 e = tr_pool_bwd(H >> (l - 1), W >> (l - 1), Ci, nf, t.gin, e_[l - 1], fs, t.ge[l - 1], s);
         }
         // first encoder: the network input written out, weight gradient only
-        for (int k = 0; k < nf && e == hipSuccess; ++k) {
-            FrameDesc fk;
-            fill_frame(h, fk, fbase + k * fbytes, frames[f0 + k]);
-            e = tr_pack(P, fk.r, fk.a, fk.n, fk.d, 1.f / h->cfg.gamma, h->cfg.depth_near,
-                        1.f / (h->cfg.depth_far - h->cfg.depth_near), t.X + k * 10 * P, s);
+        for (int k0 = 0; k0 < nf && e == hipSuccess; k0 += kTrGroup) {
+            const int kn = std::min(kTrGroup, nf - k0);
+            e = tr_pack(P, kn, frame_ptrs(k0, kn), 1.f / h->cfg.gamma, h->cfg.depth_near,
+                        1.f / (h->cfg.depth_far - h->cfg.depth_near), t.X + k0 * 10 * P, s);
         }
         if (e == hipSuccess)
             e = tr_wgrad(H, W, ch[0], ch[0], nf, t.ge[0], nel(0, ch[0]), t.X, 10 * P, 10, nullptr, 0, 0, t.part,

@@ -236,17 +236,26 @@ size_t decode_backward_scratch_bytes(const DecodeCfg &dc, int N, int H, int W);
 // Kernels with an nf argument run over nf frames of one size: frame f's
 // operand X is at X + f sX (strides in floats); their outputs are contiguous
 // per frame.
-hipError_t tr_pack(long P, const float *r, const float *a, const float *n, const float *d, float inv_gamma,
-                   float dnear, float dinv, float *X, hipStream_t s);
+// Up to kTrGroup frames' own buffers (radiance, albedo, normal, depth, the
+// denoised output, the reference) for the per-frame training kernels, which
+// run over the frames of a group in one launch
+constexpr int kTrGroup = 16;
+struct TrFrames {
+    const float *r[kTrGroup], *a[kTrGroup], *n[kTrGroup], *d[kTrGroup], *y[kTrGroup], *t[kTrGroup];
+};
+hipError_t tr_pack(long P, int nf, const TrFrames &fr, float inv_gamma, float dnear, float dinv, float *X,
+                   hipStream_t s);
 hipError_t tr_pool(int H, int W, int C, int nf, const float *in, long sin, float *out, hipStream_t s);
-hipError_t tr_head_prep(long P, int M, const float *planar, const float *r, const float *a, float eps_a,
+hipError_t tr_head_prep(long P, int M, int nf, const float *planar, long sp, const TrFrames &fr, float eps_a,
                         float *head, float *c, float *mod, hipStream_t s);
 int tr_smape_blocks(long n);
-hipError_t tr_smape(long n, const float *y, const float *t, float eps, float inv_n, float *g, float *partial,
-                    float *loss, int accumulate, hipStream_t s);
+// loss[0] (+)= the SMAPE of nf frames of n values (partial: nf x
+// tr_smape_blocks(n) floats)
+hipError_t tr_smape(long n, int nf, const TrFrames &fr, float eps, float inv_n, float *g, float *partial, float *loss,
+                    int accumulate, hipStream_t s);
 // dh[p][j] for j < 2M, zero for 2M <= j < ld (rows ld floats apart)
-hipError_t tr_head_act_bwd(long P, int M, int ld, const float *grad_head, const float *planar, float *dh,
-                           hipStream_t s);
+hipError_t tr_head_act_bwd(long P, int M, int ld, int nf, const float *grad_head, const float *planar, long sp,
+                           float *dh, hipStream_t s);
 // gm = (act > 0) g over nf frames of n values (gm may be g)
 hipError_t tr_mask(long n, int nf, const float *g, const float *act, long sa, float *gm, hipStream_t s);
 // Weights of the input-gradient conv in the fp32 forward kernels' packing
