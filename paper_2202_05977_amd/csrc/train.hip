@@ -13,8 +13,10 @@
 //   contribution to an activation's gradient also applies that activation's
 //   ReLU mask, and the first contribution overwrites, so no gradient buffer
 //   is cleared and no separate mask pass runs (except the head's input).
-// A layer's input (the network input, a 2x2 mean, an [upsampled, skip]
-// concatenation) is written out once for its two gradient kernels.
+// The weight gradient's input is written out where it is computed (the
+// network input, a 2x2 mean); a decoder's, the [upsampled, skip]
+// concatenation, is read from its two sources.  Frames of one size run the
+// backward pass together: every kernel once per layer over all of them.
 //
 // Gradient kernels (NHWC fp32, zero padding, conv = 3x3 cross-correlation):
 //   dgrad  gin[p][ci] = sum_{tap,co} gm[p - off(tap)][co] w[co][ci][tap]:
