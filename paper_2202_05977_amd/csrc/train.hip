@@ -443,12 +443,6 @@ __global__ void tr_frame_table_kernel(FrameDesc *tab, int nf, int H, int W, cons
     tab[f] = d;
 }
 
-__global__ __launch_bounds__(kTrThreads) void tr_add_kernel(long n, const float *a, float *b)
-{
-    const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
-    if (i < n) gstore(b + i, gload(b + i) + gload(a + i));
-}
-
 __global__ __launch_bounds__(kTrThreads) void tr_fill_kernel(long n, float v, float *b)
 {
     const long i = (long)blockIdx.x * kTrThreads + threadIdx.x;
@@ -623,11 +617,6 @@ hipError_t tr_frame_table(FrameDesc *tab, int nf, int H, int W, const float *src
 {
     hipLaunchKernelGGL(tr_frame_table_kernel, dim3((unsigned)((nf + 63) / 64)), dim3(64), 0, s, tab, nf, H, W, src, ss,
                        dst, sd);
-    return hipGetLastError();
-}
-hipError_t tr_add(long n, const float *a, float *b, hipStream_t s)
-{
-    TR_LAUNCH(tr_add_kernel, n, n, a, b);
     return hipGetLastError();
 }
 hipError_t tr_fill(long n, float v, float *b, hipStream_t s)

@@ -279,7 +279,6 @@ hipError_t tr_pool_bwd(int H, int W, int C, int nf, const float *gp, const float
 // e[1] = dst + f sd
 hipError_t tr_frame_table(FrameDesc *tab, int nf, int H, int W, const float *src, long ss, float *dst, long sd,
                           hipStream_t s);
-hipError_t tr_add(long n, const float *a, float *b, hipStream_t s);
 hipError_t tr_fill(long n, float v, float *b, hipStream_t s);
 hipError_t tr_adam(long n, float *w, const float *g, float *m, float *v, float lr, float b1, float b2, float c1,
                    float c2, float eps, hipStream_t s);
