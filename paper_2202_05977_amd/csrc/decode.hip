@@ -25,10 +25,9 @@
 
 namespace wskp {
 
-#ifndef WSKP_DECODE_TY
-#define WSKP_DECODE_TY 16
-#endif
-constexpr int kDTX = 32, kDTY = WSKP_DECODE_TY;
+// 32 x 16-centre tiles (8 row groups of kDTY/8 rows).  The adjoint's
+// results are validated at this height only.
+constexpr int kDTX = 32, kDTY = 16;
 static_assert(kDTY % 8 == 0, "8 row groups of kDTY/8 rows");
 // minimum resident workgroups per CU the forward kernel's registers must
 // allow (a build-time tuning knob)
