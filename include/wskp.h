@@ -252,7 +252,10 @@ wskp_status_t wskp_backward_workspace_size(wskp_handle_t h, int N, int H, int W,
  * WSKP_E_UNSUPPORTED).  The handle keeps the weight blob (the layout of
  * wskp_num_weights) on the device as the trained parameters.
  * wskp_train_workspace_size: workspace bytes of wskp_train_grads for n
- *   frames of sizes H[i] x W[i].
+ *   frames of sizes H[i] x W[i].  Frames of one size run the backward pass
+ *   together (every kernel once per layer over all n), so the workspace
+ *   grows with n; frames of mixed sizes run it one at a time in scratch for
+ *   the largest.
  * wskp_train_grads: forward pass of the n frames (each frame's `out`
  *   receives its reconstruction), loss = SMAPE(out, target) over all
  *   frames' values (Eq. 6 with eps_smape; N = all pixels of the batch) into
@@ -260,7 +263,10 @@ wskp_status_t wskp_backward_workspace_size(wskp_handle_t h, int N, int H, int W,
  *   and bias into grad (device, wskp_num_weights floats, overwritten).
  *   targets: HOST array of n device pointers to [H_i,W_i,3] references.
  *   Gradients are accumulated over frames in a fixed order (run-to-run
- *   identical).
+ *   identical).  Errors: WSKP_E_BUDGET when ws_bytes is below
+ *   wskp_train_workspace_size; WSKP_E_LAUNCH when a frame is too wide for
+ *   the 32-bit buffer windows of the weight-gradient kernel (about 10^6
+ *   pixels per row at 200 channels).
  * wskp_adam: one Adam step (step >= 1) on the handle's weights with the
  *   gradient grad and the moment buffers m, v (device, wskp_num_weights
  *   floats each, zero before step 1, updated in place); afterwards every
