@@ -350,6 +350,30 @@ __global__ __launch_bounds__(64 * kWgWaves) void tr_wgrad_mfma_kernel(int H, int
     }
 }
 
+// First level of a sliced reduce: out[y][i] = sum of part rows (chunks)
+// y S .. y S + S - 1 (fixed order: four interleaved sums added pairwise), for
+// the nw weights then the Co biases; blockIdx.y = slice y.  Used when a layer
+// has few weights and many chunks, so that more workgroups share the sums.
+__global__ __launch_bounds__(kTrThreads) void tr_wgrad_slice_kernel(long nw, int Co, int nchunk, int S,
+                                                                     const float *part, const float *partb,
+                                                                     float *out)
+{
+    __shared__ float sred[4][64];
+    const int li = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const long i = (long)blockIdx.x * 64 + li;
+    const bool inw = i < nw, in = i < nw + Co;
+    const float *src = inw ? part + i : partb + (in ? i - nw : 0);
+    const long stride = inw ? nw : Co;
+    const int c0 = blockIdx.y * S, c1 = min(nchunk, c0 + S);
+    float s0 = 0.f;
+    if (in)
+        for (int c = c0 + grp; c < c1; c += 4) s0 += gload(src + (long)c * stride);
+    sred[grp][li] = s0;
+    __syncthreads();
+    if (grp == 0 && in)
+        gstore(out + (long)blockIdx.y * (nw + Co) + i, (sred[0][li] + sred[1][li]) + (sred[2][li] + sred[3][li]));
+}
+
 // dw (+)= sum over chunks of part, likewise db: 64 weights per workgroup,
 // its four waves take the chunks c = wave (mod 4) and each sums them in
 // order on two alternating accumulators; the waves' sums are added in a
@@ -571,10 +595,20 @@ static int wgrad_chunk(long P, int Ci, int Co, int nf)
     while (c < kWgChunkMax && (long)nf * ((P + 2 * c - 1) / (2 * c)) * wgrad_blocks(Ci, Co) >= kWgMinGroups) c *= 2;
     return c;
 }
+// slices of the two-level reduce (at most kWgSlices)
+constexpr int kWgSlices = 64;
+static int wgrad_slices(long nw, int Co, int nall)
+{
+    const long gx = (nw + Co + 63) / 64;
+    int G = 1;
+    while (G < kWgSlices && gx * G < 1024 && nall / (2 * G) >= 32) G *= 2;
+    return G;
+}
 size_t tr_wgrad_part_floats(long P, int Ci, int Co, int nf)
 {
     const int c = wgrad_chunk(P, Ci, Co, nf);
-    return (size_t)nf * ((P + c - 1) / c) * ((size_t)Co * Ci * 9 + Co);
+    // the chunks' partial sums, then the slices' sums of the two-level reduce
+    return ((size_t)nf * ((P + c - 1) / c) + kWgSlices) * ((size_t)Co * Ci * 9 + Co);
 }
 hipError_t tr_wgrad(int H, int W, int Co, int ldg, int nf, const float *gm, long sgm, const float *in, long sin,
                     int Cf, const float *up, long sup, int Cu, float *part, float *dw, float *db, hipStream_t s)
@@ -595,8 +629,21 @@ hipError_t tr_wgrad(int H, int W, int Co, int ldg, int nf, const float *gm, long
     else
         hipLaunchKernelGGL(tr_wgrad_mfma_kernel<1>, dim3((unsigned)nall, cob, cib), dim3(64 * kWgWaves), 0, s, H, W,
                            Co, ldg, chunk, nch, gm, sgm, in, sin, Cf, up, sup, Cu, part, partb);
-    hipLaunchKernelGGL(tr_wgrad_reduce_kernel, dim3((unsigned)((nw + Co + 63) / 64)), dim3(kTrThreads), 0, s, nw, Co,
-                       nall, part, partb, dw, db);
+    const unsigned gx = (unsigned)((nw + Co + 63) / 64);
+    // (the second level treats the biases as weights nw .. nw + Co - 1, so
+    // db must follow dw, as in the weight blob)
+    const int G = db == dw + nw ? wgrad_slices(nw, Co, nall) : 1;
+    if (G == 1) {
+        hipLaunchKernelGGL(tr_wgrad_reduce_kernel, dim3(gx), dim3(kTrThreads), 0, s, nw, Co, nall, part, partb, dw, db);
+    } else {
+        // slice sums into the rows after the chunks' partials, then their sum
+        float *sl = partb + (size_t)nall * Co;
+        const int S = (nall + G - 1) / G;
+        hipLaunchKernelGGL(tr_wgrad_slice_kernel, dim3(gx, (unsigned)G), dim3(kTrThreads), 0, s, nw, Co, nall, S, part,
+                           partb, sl);
+        // rows of sl are nw + Co floats: weights, then biases
+        hipLaunchKernelGGL(tr_wgrad_reduce_kernel, dim3(gx), dim3(kTrThreads), 0, s, nw + Co, 0, G, sl, sl, dw, db);
+    }
     return hipGetLastError();
 }
 hipError_t tr_cat_bwd(int H, int W, int Cu, int Ce, int nf, const float *gcat, const float *act_u, long sa, float *gu,
