@@ -61,7 +61,10 @@ TWO_LEVEL = synth.NetConfig(levels=2, channels=(16, 32), kernel_sizes=(3, 5, 7))
                                             ("two_level", [(48, 64)] * 3),
                                             # 18 frames: the per-crop kernels take 16 frames'
                                             # buffers per launch, so two groups, one partial
-                                            ("small", [(16, 24)] * 18)])
+                                            ("small", [(16, 24)] * 18),
+                                            # 16 frames of 64x64: 256 chunk partials per
+                                            # weight of the input layer, summed in two levels
+                                            ("small", [(64, 64)] * 16)])
 def test_train_grads_match_oracle(cfg_name, sizes):
     from paper_2202_05977_amd import wskp
     cfg = {"one_level": ONE_LEVEL, "two_level": TWO_LEVEL}.get(cfg_name) or synth.CONFIGS[cfg_name]
