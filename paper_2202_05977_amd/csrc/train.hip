@@ -3,7 +3,7 @@
 // Eq. 6: the SMAPE loss; Sec. 5.3: Adam), FP32 throughout.
 //
 // The forward pass is the fp32 denoising path (its workspace keeps every
-// layer's output).  The backward pass, per frame:
+// layer's output).  The backward pass (the frames of one size together):
 //   SMAPE gradient at the output -> adjoint of decode and fusion (decode.hip)
 //   -> derivative of the weight activation -> for each conv, from the head
 //   back to the first encoder: the weight and bias gradient (accumulated
@@ -40,10 +40,11 @@ constexpr int kTrThreads = 256;
 
 static inline int tr_blocks(long n) { return (int)((n + kTrThreads - 1) / kTrThreads); }
 
-// network input X [P][10] (Sec. 5.1), as the first conv's staging forms it
 // The per-frame kernels below run over a group of frames (blockIdx.y), the
 // frames' own buffers passed by pointer (TrFrames) and the group's scratch
 // contiguous per frame.
+
+// network input X [P][10] (Sec. 5.1), as the first conv's staging forms it
 __global__ __launch_bounds__(kTrThreads) void tr_pack_kernel(long P, TrFrames fr, float inv_gamma, float dnear,
                                                               float dinv, float *X)
 {
@@ -197,11 +198,12 @@ __global__ __launch_bounds__(kTrThreads) void tr_mask_kernel(long n, int nf, con
 // take consecutive quarters of the chunk, each loading the operands of its
 // next step before the MFMAs of the current one, and add their sums in LDS
 // in a fixed order, (w0 + w2) + (w1 + w3).  Operands are raw buffer loads
-// over the chunk's window (its gm rows; its input rows and one image row
-// and pixel either side), 32-bit offsets from it: channels beyond Co or Ci
-// (the network input's 10, the head's 2M), taps outside the image and
-// pixels past the chunk take an offset beyond the window and read zeros,
-// so no load is conditional.  The workgroups of input block 0 also sum gm
+// with 32-bit offsets into windows: the chunk's gm rows, and the whole
+// source rows of the image rows the chunk touches and one either side (the
+// input block's source: the H x W map, or the half-size map the input
+// upsamples).  Channels beyond Co or Ci (the network input's 10, the
+// head's 2M), taps outside the image and pixels past the chunk take an
+// offset beyond the window and read zeros, so no load is conditional.  The workgroups of input block 0 also sum gm
 // (B = 1) for the bias.  Lane (g, j) ends with D[4g + r][j], r = 0..3.
 typedef float trf32x4 __attribute__((ext_vector_type(4)));
 // Chunks are 256 pixels, doubled (up to kWgChunkMax) while a launch still
