@@ -982,11 +982,14 @@ static bool uses_direct(int prec, int mode, int CK, int ks)
 bool conv_uses_direct(int prec, int mode, int CK, int ks) { return uses_direct(prec, mode, CK, ks); }
 
 // Tile rows per layer: the input layer uses kTHP; the direct-load kernel uses
-// kTHD, or 4 rows on the coarsest levels (>= WSKP_COARSE_LEVEL), which have
-// few pixels, so that they still spread over all CUs, unless the layer passes
-// on 2x2 means (that needs whole row pairs per wave, 8 rows).
+// kTHD, or 4 rows (and one output block per workgroup) on the levels from
+// WSKP_COARSE_LEVEL on, which have few pixels, so that they still spread
+// over all CUs, unless the layer passes on 2x2 means (that needs whole row
+// pairs per wave, 8 rows).  From level 4: with level 3 on 4-row tiles too
+// (the fourth level of the 720p net, 160 x 90) one frame's launch was
+// slightly faster alone but three-stream throughput 1 % lower.
 #ifndef WSKP_COARSE_LEVEL
-#define WSKP_COARSE_LEVEL 3
+#define WSKP_COARSE_LEVEL 4
 #endif
 int conv_tile_rows(int prec, int mode, int CK, int level, bool pool, int ks)
 {

@@ -125,6 +125,24 @@ def test_small_bf16_ragged():
     assert max_rel(out, y) <= TOL_BF16_MAX
 
 
+# five levels: from level 4 on the bf16 direct convs run on 4-row tiles with
+# one output block per workgroup (112 x 176: 7 x 11 pixels at level 4)
+FIVE_LEVEL = synth.NetConfig(levels=5, channels=(32, 32, 64, 64, 96), kernel_sizes=(3, 5, 7))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_five_level_net_against_oracle(prec):
+    fr = synth.make_frame(7, 112, 176)
+    blob = synth.make_weights(FIVE_LEVEL, 0)
+    y = oracle.denoise(fr, blob, FIVE_LEVEL)
+    out = _run(_denoiser(FIVE_LEVEL, prec), fr)
+    assert np.all(np.isfinite(out))
+    if prec == "fp32":
+        assert rel_l2(out, y) <= TOL_FP32 and max_rel(out, y) <= TOL_FP32
+    else:
+        assert rel_l2(out, y) <= TOL_BF16 and max_rel(out, y) <= TOL_BF16_MAX
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_three_stream_pipeline_matches_single_stream(prec):
     """The launch configuration of the throughput figure: 720p frames dealt
