@@ -569,9 +569,7 @@ constexpr int kFThreads = 512;
 constexpr int kFSlots = 6;          // halo pixels per thread: HXS * (TH + 2R) <= 3072
 constexpr int kNR = 5;              // row sums per thread (horizontal run)
 constexpr int kNC = 5;              // centres per thread (vertical run)
-constexpr int kTileW = 40;          // centres per tile row: kHRuns runs of kNR
-constexpr int kHRuns = kTileW / kNR;
-static_assert(kHRuns == 8, "the horizontal pass maps a row's runs to the low three bits of the thread id");
+constexpr int kTileW = 40;          // centres per tile row (multiple of kNR)
 constexpr int kSRow = kTileW + 1;   // row-sum buffer stride (float4): odd
 constexpr float kLog2e = 1.4426950408889634f;
 
@@ -588,8 +586,7 @@ __global__ __launch_bounds__(kFThreads, 4) void decode_tile_kernel(DecodeCfg dc,
 {
     extern __shared__ float4 lds4[];
     __shared__ float red[2][kFThreads / 64];
-    constexpr int TW = kTileW;
-    const int TH = dc.th, HXS = dc.hxs, R = dc.R;
+    const int TW = dc.tw, TH = dc.th, HXS = dc.hxs, R = dc.R;
     const int HX = TW + 2 * R, HY = TH + 2 * R, HXY = HXS * HY;
     const int tid = threadIdx.x;
 
@@ -769,7 +766,7 @@ __global__ __launch_bounds__(kFThreads, 4) void decode_tile_kernel(DecodeCfg dc,
                 const unsigned o = centre_off(q);
                 const auto a3 = __builtin_amdgcn_raw_buffer_load_b96(ra, o == kNoPixel ? kNoPixel : o * 3u, 0, 0);
 #pragma unroll
-                for (int ch = 0; ch < 3; ++ch) mv[q][ch] = __uint_as_float(a3[ch]);
+                for (int ch = 0; ch < 3; ++ch) mv[q][ch] = __uint_as_float(a3[ch]) + dc.eps_albedo;
             }
         }
         lds_sync();
@@ -778,9 +775,9 @@ __global__ __launch_bounds__(kFThreads, 4) void decode_tile_kernel(DecodeCfg dc,
         // reads), output columns x .. x + kNR - 1, into the row-sum buffer
         {
             const int nrows = TH + 2 * r;
-            if (tid < nrows * kHRuns) {
-                const int hrow = R - r + (tid >> 3);
-                const int hx = (tid & (kHRuns - 1)) * kNR;
+            if (tid < nrows * (TW / kNR)) {
+                const int hrow = R - r + tid % nrows;
+                const int hx = (tid / nrows) * kNR;
                 const int base = hrow * HXS + R - r + hx;
                 float4 hs[kNR];
 #define WSKP_H(KK) box_run<KK, kNR>([&](int j) { return pl[base + j]; }, hs)
@@ -827,7 +824,7 @@ __global__ __launch_bounds__(kFThreads, 4) void decode_tile_kernel(DecodeCfg dc,
         const float inv = 1.f / esum[q];
         float *op = io.out + centre_pix(q) * 3;
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) gstore(op + ch, (mv[q][ch] + dc.eps_albedo) * (F[q][ch] * inv));
+        for (int ch = 0; ch < 3; ++ch) gstore(op + ch, mv[q][ch] * (F[q][ch] * inv));
     }
 }
 
