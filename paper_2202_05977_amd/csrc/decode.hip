@@ -552,8 +552,13 @@ __global__ __launch_bounds__(kThreads, WSKP_DECODE_MIN_WG) void decode_fwd_kerne
 // The thread of step 3 owns those centres for the whole kernel: their
 // logits, fusion state and output.  Its lanes hold consecutive columns, so
 // the centres' global loads and stores are coalesced row segments.  The
-// irradiance c of the thread's halo pixels stays in registers; each size's
-// weight map is fetched one size ahead, its logits while its plane is built.
+// irradiance c of the thread's halo pixels stays in registers.  Each size's
+// weight map is fetched two sizes ahead and its logits one size ahead, with
+// the size loop unrolled so that the prefetched registers are never copied
+// (a copy would wait for its load): the loads of the next sizes stay in
+// flight across the barriers of this one.  With exp weights (whose halo
+// maximum takes more registers) the map is fetched one size ahead and the
+// logits while the plane is built, in a loop that is not unrolled.
 //
 // Fusion (Eq. 5) is an online softmax: the state of a centre is the largest
 // logit seen so far (m, in base-2 units), the sum of the numerators 2^(l-m)
@@ -657,12 +662,13 @@ __global__ __launch_bounds__(kFThreads, 4) void decode_tile_kernel(DecodeCfg dc,
     // reads zeros).  Map j of pixel q sits at (j P + q) * 4 (planar record).
     const unsigned hstride = 4u;
     auto map_rsrc = [&](int j) { return make_rsrc(io.head + (size_t)j * P, P * 4u); };
-    float cv[kFSlots][3], wv[kFSlots];
-    auto load_w = [&](int i) {
+    constexpr bool kAhead2 = !EXPW;     // weights two sizes ahead, logits one
+    float cv[kFSlots][3], wv[kFSlots], wn[kFSlots];
+    auto load_w = [&](int i, float *dst) {
         const rsrc_t rs = map_rsrc(i);
 #pragma unroll
         for (int k = 0; k < kFSlots; ++k)
-            wv[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+            dst[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
                 rs, gp[k] >= 0 ? (unsigned)gp[k] * hstride : kNoPixel, 0, 0));
     };
     auto load_logit = [&](int i, float *lg) {
@@ -689,8 +695,9 @@ __global__ __launch_bounds__(kFThreads, 4) void decode_tile_kernel(DecodeCfg dc,
                 av[k][ch] = __uint_as_float(a3[ch]);
             }
         }
-        load_w(0);
+        load_w(0, wv);
         load_logit(0, lg);
+        if (kAhead2 && M > 1) load_w(1, wn);
 #pragma unroll
         for (int k = 0; k < kFSlots; ++k)
 #pragma unroll
@@ -729,7 +736,8 @@ __global__ __launch_bounds__(kFThreads, 4) void decode_tile_kernel(DecodeCfg dc,
     }
     float mv[kNC][3];                   // remodulation factor of the centres
 
-#pragma unroll 1
+    constexpr int kUnroll = kAhead2 ? M : 1;
+#pragma unroll kUnroll
     for (int i = 0; i < M; ++i) {
         const int r = dc.radius[i];
         float eps = dc.eps_norm;
@@ -753,13 +761,17 @@ __global__ __launch_bounds__(kFThreads, 4) void decode_tile_kernel(DecodeCfg dc,
                 pl[p] = make_float4(w, w * cv[k][0], w * cv[k][1], w * cv[k][2]);
             }
         }
-        // this size's logits (used after the horizontal pass) and the next
-        // size's weights go out now; before the last size, the centres'
+        // the prefetches (see above); before the last size, the centres'
         // remodulation factors
-        if (i > 0) load_logit(i, lg);
-        if (i + 1 < M) {
-            load_w(i + 1);
+        float w2[kFSlots], l1[kNC];
+        if constexpr (kAhead2) {
+            if (i + 2 < M) load_w(i + 2, w2);
+            if (i + 1 < M) load_logit(i + 1, l1);
         } else {
+            if (i > 0) load_logit(i, lg);
+            if (i + 1 < M) load_w(i + 1, wv);
+        }
+        if (i + 1 == M) {
             const rsrc_t ra = make_rsrc(io.a, P * 12u);
 #pragma unroll
             for (int q = 0; q < kNC; ++q) {
@@ -813,6 +825,18 @@ __global__ __launch_bounds__(kFThreads, 4) void decode_tile_kernel(DecodeCfg dc,
                 F[q][0] = F[q][0] * sc + ei * acc[q].y;
                 F[q][1] = F[q][1] * sc + ei * acc[q].z;
                 F[q][2] = F[q][2] * sc + ei * acc[q].w;
+            }
+        }
+        if constexpr (kAhead2) {
+            // size i + 1 becomes current (no copies once unrolled)
+#pragma unroll
+            for (int k = 0; k < kFSlots; ++k) {
+                wv[k] = wn[k];
+                wn[k] = w2[k];
+            }
+            if (i + 1 < M) {
+#pragma unroll
+                for (int q = 0; q < kNC; ++q) lg[q] = l1[q];
             }
         }
     }
