@@ -143,6 +143,22 @@ def test_five_level_net_against_oracle(prec):
         assert rel_l2(out, y) <= TOL_BF16 and max_rel(out, y) <= TOL_BF16_MAX
 
 
+@pytest.mark.parametrize("ks", [(3,), (1, 5), (3, 5, 7, 9), (3, 5, 7, 9, 11, 13, 15), (1, 3, 5, 7, 9, 11, 13, 15)])
+def test_frames_decode_every_kernel_count_against_oracle(ks):
+    """The decode inside the per-frame path is compiled once per number of
+    kernel sizes M (its size loop unrolled, each weight map fetched two sizes
+    ahead): M = 1, 2, 4, 7 and 8, with k = 1 and k = 15 among them, through
+    the fp32 path on a frame of 2 x 3 decode tiles with ragged tails."""
+    import dataclasses
+    cfg = dataclasses.replace(synth.SMALL, kernel_sizes=ks)
+    fr = synth.make_frame(60 + len(ks), 52, 84)
+    blob = synth.make_weights(cfg, 0)
+    y = oracle.denoise(fr, blob, cfg)
+    out = _run(_denoiser(cfg, "fp32"), fr)
+    assert np.all(np.isfinite(out))
+    assert rel_l2(out, y) <= TOL_FP32 and max_rel(out, y) <= TOL_FP32
+
+
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 def test_three_stream_pipeline_matches_single_stream(prec):
     """The launch configuration of the throughput figure: 720p frames dealt
